@@ -1,0 +1,510 @@
+/*
+ * corde_oracle.c -- FP64 CPU oracle of the discrete CoRdE Cosserat rod stepper.
+ *
+ * TEST INFRASTRUCTURE ONLY (see corde_oracle.h).  Written for clarity, not speed: every
+ * quantity is recomputed from the material description where it is used, every gradient
+ * is the chain rule of the energy written out, and torques come from quaternion gradients
+ * through the B_k matrices exactly as eq. (6) defines the strain.
+ *
+ * Readings taken where the paper is silent or garbled (each is also listed in the design
+ * notes of the repository):
+ *   - bending/twist stiffness use the second moment of area: K_1 = K_2 = E pi r^4 / 4,
+ *     K_3 = G pi r^4 / 2 (eq. (3) prints r^2, which has the wrong dimension);
+ *   - K_p = G pi r^2 (eq. (8) only says it depends on the material);
+ *   - G = E / (2 (1 + nu)); point masses lump half of each adjacent element;
+ *   - frames are integrated as rigid cylinders, I = diag(m(3r^2+l^2)/12 twice, m r^2/2),
+ *     gyroscopic term included;
+ *   - joint j couples frames j and j+1 over lbar_j = (l_j + l_{j+1}) / 2 with the mean of
+ *     the two elements' stiffnesses;
+ *   - B_k are derived from (0, u) = 2 conj(q) (x) q' for scalar-first Hamilton quaternions
+ *     (the paper defers them to the appendix of its reference [17]);
+ *   - distance constraints: red-black Gauss-Seidel over segments (even, then odd), each
+ *     impulse linearised at the predicted positions p = x + dt v;
+ *   - semi-implicit Euler: v (and omega) first, then x (and q) with the new velocities,
+ *     followed by quaternion renormalisation;
+ *   - damping is plain velocity damping (a -= gamma v, alpha -= gamma omega); the paper's
+ *     internal friction terms are not given and are not modelled.
+ */
+#include "corde_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ---------------------------------------------------------------- quaternion algebra -- */
+
+/* B_k, eq. (6): B_k q = q (x) (0, e_k); skew-symmetric. */
+static const double BMAT[3][4][4] = {
+    {{0, -1, 0, 0}, {1, 0, 0, 0}, {0, 0, 0, 1}, {0, 0, -1, 0}},
+    {{0, 0, -1, 0}, {0, 0, 0, -1}, {1, 0, 0, 0}, {0, 1, 0, 0}},
+    {{0, 0, 0, -1}, {0, 0, 1, 0}, {0, -1, 0, 0}, {1, 0, 0, 0}},
+};
+
+void oracle_bmat(int32_t k, double* out16) {
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) out16[4 * r + c] = BMAT[k][r][c];
+}
+
+static void bmul(int k, const double* q, double* out) {
+    for (int r = 0; r < 4; ++r) {
+        out[r] = 0.0;
+        for (int c = 0; c < 4; ++c) out[r] += BMAT[k][r][c] * q[c];
+    }
+}
+
+static double dot4(const double* a, const double* b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
+}
+
+static double dot3(const double* a, const double* b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+static double norm3(const double* a) { return sqrt(dot3(a, a)); }
+
+static void cross3(const double* a, const double* b, double* r) {
+    double t0 = a[1] * b[2] - a[2] * b[1];
+    double t1 = a[2] * b[0] - a[0] * b[2];
+    double t2 = a[0] * b[1] - a[1] * b[0];
+    r[0] = t0;
+    r[1] = t1;
+    r[2] = t2;
+}
+
+void oracle_qmul(const double* a, const double* b, double* r) {
+    double w = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    double x = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    double y = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    double z = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+    r[0] = w;
+    r[1] = x;
+    r[2] = y;
+    r[3] = z;
+}
+
+/* Rotation matrix R(q) (body -> world), written for unit q; column k is director d_{k+1}. */
+static void rotmat(const double* q, double R[3][3]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0][0] = w * w + x * x - y * y - z * z;
+    R[0][1] = 2 * (x * y - w * z);
+    R[0][2] = 2 * (x * z + w * y);
+    R[1][0] = 2 * (x * y + w * z);
+    R[1][1] = w * w - x * x + y * y - z * z;
+    R[1][2] = 2 * (y * z - w * x);
+    R[2][0] = 2 * (x * z - w * y);
+    R[2][1] = 2 * (y * z + w * x);
+    R[2][2] = w * w - x * x - y * y + z * z;
+}
+
+void oracle_rotmat(const double* q, double* out9) {
+    double R[3][3];
+    rotmat(q, R);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) out9[3 * r + c] = R[r][c];
+}
+
+/* Third director d_3(q) and its Jacobian with respect to (w, x, y, z). */
+static void director3(const double* q, double* d3, double J[3][4]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    d3[0] = 2 * (x * z + w * y);
+    d3[1] = 2 * (y * z - w * x);
+    d3[2] = w * w - x * x - y * y + z * z;
+    if (J) {
+        J[0][0] = 2 * y;  J[0][1] = 2 * z;  J[0][2] = 2 * w;  J[0][3] = 2 * x;
+        J[1][0] = -2 * x; J[1][1] = -2 * w; J[1][2] = 2 * z;  J[1][3] = 2 * y;
+        J[2][0] = 2 * w;  J[2][1] = -2 * x; J[2][2] = -2 * y; J[2][3] = 2 * z;
+    }
+}
+
+/* ------------------------------------------------------------------ material model -- */
+
+typedef struct {
+    double l, r, E, G, A, m, Ks, Kp, K1, K3, I1, I3;
+} elem_t;
+
+static void element(const oracle_rod* rod, int j, elem_t* e) {
+    e->l = rod->seg_len[j];
+    e->r = rod->radius[j];
+    e->E = rod->young[j];
+    e->G = e->E / (2.0 * (1.0 + rod->poisson));
+    e->A = M_PI * e->r * e->r;
+    e->m = rod->density * e->A * e->l;
+    e->Ks = e->E * e->A;                                      /* eq. (2) */
+    e->Kp = rod->kp_scale * e->G * e->A;                      /* eq. (8) */
+    double r4 = e->r * e->r * e->r * e->r;
+    e->K1 = rod->bend_scale * e->E * M_PI * r4 / 4.0;          /* eq. (3), second moment */
+    e->K3 = rod->twist_scale * e->G * M_PI * r4 / 2.0;
+    e->I1 = e->m * (3.0 * e->r * e->r + e->l * e->l) / 12.0;  /* rigid cylinder */
+    e->I3 = e->m * e->r * e->r / 2.0;
+}
+
+static double point_mass(const oracle_rod* rod, int i) {
+    double M = 0.0;
+    elem_t e;
+    if (i > 0) {
+        element(rod, i - 1, &e);
+        M += 0.5 * e.m;
+    }
+    if (i < rod->n) {
+        element(rod, i, &e);
+        M += 0.5 * e.m;
+    }
+    return M;
+}
+
+typedef struct {
+    double lbar, K[3];
+    double uhat[3];
+} joint_t;
+
+static void joint(const oracle_rod* rod, int j, joint_t* jt) {
+    elem_t a, b;
+    element(rod, j, &a);
+    element(rod, j + 1, &b);
+    jt->lbar = 0.5 * (a.l + b.l);
+    jt->K[0] = 0.5 * (a.K1 + b.K1);
+    jt->K[1] = jt->K[0];
+    jt->K[2] = 0.5 * (a.K3 + b.K3);
+    for (int k = 0; k < 3; ++k) jt->uhat[k] = rod->u_hat ? rod->u_hat[3 * j + k] : 0.0;
+}
+
+int32_t oracle_check(const oracle_rod* rod) {
+    if (!rod || rod->n < 1) return -1;
+    if (!rod->seg_len || !rod->radius || !rod->young) return -2;
+    if (!(rod->dt > 0.0)) return -3;
+    if (rod->inextensible && rod->n_iter < 0) return -4;
+    for (int j = 0; j < rod->n; ++j)
+        if (!(rod->seg_len[j] > 0 && rod->radius[j] > 0 && rod->young[j] > 0)) return -5;
+    if (!(rod->density > 0)) return -6;
+    return 0;
+}
+
+/* ----------------------------------------------------------------- energy and forces -- */
+
+void oracle_darboux(const oracle_rod* rod, const double* q, int32_t j, double* u) {
+    joint_t jt;
+    joint(rod, j, &jt);
+    double Bq[4];
+    for (int k = 0; k < 3; ++k) {
+        bmul(k, q + 4 * j, Bq);
+        u[k] = (2.0 / jt.lbar) * dot4(Bq, q + 4 * (j + 1));  /* eq. (6) with eq. (5) */
+    }
+}
+
+double oracle_energy(const oracle_rod* rod, const double* x, const double* q) {
+    const int n = rod->n;
+    double V = 0.0;
+    for (int j = 0; j < n; ++j) {
+        elem_t e;
+        element(rod, j, &e);
+        double d[3], t[3], d3[3];
+        for (int c = 0; c < 3; ++c) d[c] = x[3 * (j + 1) + c] - x[3 * j + c];
+        double len = norm3(d);
+        for (int c = 0; c < 3; ++c) t[c] = d[c] / len;
+        if (!rod->inextensible) {
+            double s = len / e.l - 1.0;                        /* v_3 - 1, eq. (2) */
+            V += 0.5 * e.Ks * s * s * e.l;
+        }
+        director3(q + 4 * j, d3, NULL);
+        double diff[3] = {t[0] - d3[0], t[1] - d3[1], t[2] - d3[2]};
+        V += 0.5 * e.Kp * dot3(diff, diff) * e.l;              /* eq. (8) */
+    }
+    for (int j = 0; j + 1 < n; ++j) {
+        joint_t jt;
+        joint(rod, j, &jt);
+        double u[3];
+        oracle_darboux(rod, q, j, u);
+        for (int k = 0; k < 3; ++k) {
+            double du = u[k] - jt.uhat[k];
+            V += 0.5 * jt.K[k] * du * du * jt.lbar;            /* eq. (3) */
+        }
+    }
+    for (int i = 0; i <= n; ++i) {
+        double M = point_mass(rod, i);
+        V -= M * dot3(rod->gravity, x + 3 * i);
+        if (rod->f_ext) V -= dot3(rod->f_ext + 3 * i, x + 3 * i);
+    }
+    return V;
+}
+
+double oracle_kinetic(const oracle_rod* rod, const double* v, const double* w) {
+    double T = 0.0;
+    for (int i = 0; i <= rod->n; ++i) T += 0.5 * point_mass(rod, i) * dot3(v + 3 * i, v + 3 * i);
+    for (int j = 0; j < rod->n; ++j) {
+        elem_t e;
+        element(rod, j, &e);
+        const double* wj = w + 3 * j;
+        T += 0.5 * (e.I1 * wj[0] * wj[0] + e.I1 * wj[1] * wj[1] + e.I3 * wj[2] * wj[2]);
+    }
+    return T;
+}
+
+void oracle_forces(const oracle_rod* rod, const double* x, const double* q, double* F,
+                   double* tau) {
+    const int n = rod->n;
+    double* gq = (double*)calloc((size_t)4 * n, sizeof(double)); /* dV/dq */
+    memset(F, 0, sizeof(double) * 3 * (n + 1));
+
+    for (int j = 0; j < n; ++j) {
+        elem_t e;
+        element(rod, j, &e);
+        double d[3], t[3], d3[3], J[3][4];
+        for (int c = 0; c < 3; ++c) d[c] = x[3 * (j + 1) + c] - x[3 * j + c];
+        double len = norm3(d);
+        for (int c = 0; c < 3; ++c) t[c] = d[c] / len;
+        /* dV/dd for this segment */
+        double g[3] = {0, 0, 0};
+        if (!rod->inextensible) {
+            double s = len / e.l - 1.0;
+            for (int c = 0; c < 3; ++c) g[c] += e.Ks * s * t[c];  /* d/dd of 1/2 Ks l s^2 */
+        }
+        director3(q + 4 * j, d3, J);
+        double r[3] = {t[0] - d3[0], t[1] - d3[1], t[2] - d3[2]};
+        /* d/dd of 1/2 Kp l |t - d3|^2 = Kp l (I - t t^T) r / |d| */
+        double tr = dot3(t, r);
+        for (int c = 0; c < 3; ++c) g[c] += e.Kp * e.l * (r[c] - tr * t[c]) / len;
+        for (int c = 0; c < 3; ++c) {
+            F[3 * (j + 1) + c] -= g[c];
+            F[3 * j + c] += g[c];
+        }
+        /* d/dq of 1/2 Kp l |t - d3(q)|^2 = -Kp l J^T r */
+        for (int a = 0; a < 4; ++a) {
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c) s += J[c][a] * r[c];
+            gq[4 * j + a] -= e.Kp * e.l * s;
+        }
+    }
+    for (int j = 0; j + 1 < n; ++j) {
+        joint_t jt;
+        joint(rod, j, &jt);
+        double u[3];
+        oracle_darboux(rod, q, j, u);
+        for (int k = 0; k < 3; ++k) {
+            /* V_k = 1/2 K lbar (u_k - uhat)^2 with u_k = (2/lbar) q_j^T B_k^T q_{j+1} */
+            double mk = jt.K[k] * (u[k] - jt.uhat[k]);
+            double Bqj[4], Bqn[4];
+            bmul(k, q + 4 * j, Bqj);
+            bmul(k, q + 4 * (j + 1), Bqn);
+            for (int a = 0; a < 4; ++a) {
+                gq[4 * (j + 1) + a] += 2.0 * mk * Bqj[a];   /* B_k q_j */
+                gq[4 * j + a] -= 2.0 * mk * Bqn[a];         /* B_k^T q_{j+1} = -B_k q_{j+1} */
+            }
+        }
+    }
+    for (int i = 0; i <= n; ++i) {
+        double M = point_mass(rod, i);
+        for (int c = 0; c < 3; ++c) {
+            F[3 * i + c] += M * rod->gravity[c];
+            if (rod->f_ext) F[3 * i + c] += rod->f_ext[3 * i + c];
+        }
+    }
+    /* body torque about body axis a: virtual rotation q -> q (x) (1, eps e_a / 2) moves q by
+     * eps/2 B_a q, so tau_a = -1/2 (dV/dq) . (B_a q) */
+    for (int j = 0; j < n; ++j) {
+        for (int a = 0; a < 3; ++a) {
+            double Bq[4];
+            bmul(a, q + 4 * j, Bq);
+            tau[3 * j + a] = -0.5 * dot4(gq + 4 * j, Bq);
+        }
+    }
+    free(gq);
+}
+
+/* -------------------------------------------------------------------------- clamp -- */
+
+void oracle_clamp_pose(const oracle_rod* rod, double t, double* xc, double* qc, double* wc) {
+    const double two_pi_f = 2.0 * M_PI * rod->clamp_freq;
+    double sx = sin(two_pi_f * t + rod->clamp_phase_x);
+    for (int c = 0; c < 3; ++c) xc[c] = rod->clamp_x0[c] + rod->clamp_amp[c] * sx;
+    double psi = rod->clamp_twist_amp * sin(two_pi_f * t + rod->clamp_phase_twist);
+    double psidot = rod->clamp_twist_amp * two_pi_f * cos(two_pi_f * t + rod->clamp_phase_twist);
+    const double* ax = rod->clamp_twist_axis;
+    double an = norm3(ax);
+    double axis[3] = {0, 0, 0};
+    if (an > 0) for (int c = 0; c < 3; ++c) axis[c] = ax[c] / an;
+    double rq[4] = {cos(0.5 * psi), sin(0.5 * psi) * axis[0], sin(0.5 * psi) * axis[1],
+                    sin(0.5 * psi) * axis[2]};
+    oracle_qmul(rq, rod->clamp_q0, qc);
+    /* world rate psidot * axis, expressed in the body axes of q_c: R(q_c)^T (psidot axis) */
+    double R[3][3];
+    rotmat(qc, R);
+    for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (int c = 0; c < 3; ++c) s += R[c][a] * psidot * axis[c];
+        wc[a] = s;
+    }
+}
+
+/* --------------------------------------------------------------------------- step -- */
+
+static void project_segment(const oracle_rod* rod, int j, const double* x, double* v,
+                            const double* winv) {
+    const double dt = rod->dt;
+    double p0[3], p1[3], d[3];
+    for (int c = 0; c < 3; ++c) {
+        p0[c] = x[3 * j + c] + dt * v[3 * j + c];
+        p1[c] = x[3 * (j + 1) + c] + dt * v[3 * (j + 1) + c];
+        d[c] = p1[c] - p0[c];
+    }
+    double len = norm3(d);
+    double wsum = winv[j] + winv[j + 1];
+    if (!(wsum > 0.0) || !(len > 0.0)) return;
+    double C = len - rod->seg_len[j];                  /* C_d: length error */
+    double lambda = C / (dt * wsum);                   /* J M^-1 J^T = w_j + w_{j+1} */
+    for (int c = 0; c < 3; ++c) {
+        double nc = d[c] / len;
+        v[3 * j + c] += winv[j] * lambda * nc;
+        v[3 * (j + 1) + c] -= winv[j + 1] * lambda * nc;
+    }
+}
+
+void oracle_step(const oracle_rod* rod, double t, double* x, double* v, double* q, double* w) {
+    const int n = rod->n;
+    const double dt = rod->dt;
+    double* F = (double*)malloc(sizeof(double) * 3 * (n + 1));
+    double* tau = (double*)malloc(sizeof(double) * 3 * n);
+    double* winv = (double*)malloc(sizeof(double) * (n + 1));
+
+    /* forces and torques from the start-of-step configuration */
+    oracle_forces(rod, x, q, F, tau);
+
+    /* integrate forces: points as particles */
+    for (int i = 0; i <= n; ++i) {
+        double M = point_mass(rod, i);
+        winv[i] = (rod->clamp && i == 0) ? 0.0 : 1.0 / M;
+        if (rod->clamp && i == 0) continue;
+        for (int c = 0; c < 3; ++c) {
+            double a = F[3 * i + c] / M - rod->damp_lin * v[3 * i + c];
+            v[3 * i + c] += dt * a;
+        }
+    }
+    /* integrate torques: frames as rigid bodies, Euler's equations in body axes */
+    for (int j = 0; j < n; ++j) {
+        if (rod->clamp && j == 0) continue;
+        elem_t e;
+        element(rod, j, &e);
+        double I[3] = {e.I1, e.I1, e.I3};
+        double* wj = w + 3 * j;
+        double Iw[3] = {I[0] * wj[0], I[1] * wj[1], I[2] * wj[2]};
+        double gyro[3];
+        cross3(wj, Iw, gyro);
+        double tq[3];
+        for (int a = 0; a < 3; ++a) {
+            tq[a] = tau[3 * j + a] - gyro[a];
+            if (rod->tau_ext) tq[a] += rod->tau_ext[3 * j + a];
+        }
+        for (int a = 0; a < 3; ++a) wj[a] += dt * (tq[a] / I[a] - rod->damp_ang * wj[a]);
+    }
+    double xc[3], qc[4], wc[3];
+    if (rod->clamp) {
+        oracle_clamp_pose(rod, t + dt, xc, qc, wc);
+        for (int c = 0; c < 3; ++c) {
+            v[c] = (xc[c] - x[c]) / dt;
+            w[c] = wc[c];
+        }
+    }
+    /* inextensible variant: red-black Gauss-Seidel over the distance constraints */
+    if (rod->inextensible) {
+        for (int it = 0; it < rod->n_iter; ++it)
+            for (int parity = 0; parity < 2; ++parity)
+                for (int j = parity; j < n; j += 2) project_segment(rod, j, x, v, winv);
+    }
+    /* integrate velocities */
+    for (int i = 0; i <= n; ++i)
+        for (int c = 0; c < 3; ++c) x[3 * i + c] += dt * v[3 * i + c];
+    for (int j = 0; j < n; ++j) {
+        double* qj = q + 4 * j;
+        double om[4] = {0.0, w[3 * j], w[3 * j + 1], w[3 * j + 2]};
+        double dq[4];
+        oracle_qmul(qj, om, dq);                       /* dq/dt = 1/2 q (x) (0, omega) */
+        double nq = 0.0;
+        for (int a = 0; a < 4; ++a) {
+            qj[a] += 0.5 * dt * dq[a];
+            nq += qj[a] * qj[a];
+        }
+        nq = sqrt(nq);
+        for (int a = 0; a < 4; ++a) qj[a] /= nq;
+    }
+    if (rod->clamp) {
+        for (int c = 0; c < 3; ++c) x[c] = xc[c];
+        for (int a = 0; a < 4; ++a) q[a] = qc[a];
+    }
+    free(F);
+    free(tau);
+    free(winv);
+}
+
+void oracle_rollout(const oracle_rod* rod, double t0, int32_t n_steps, double* x, double* v,
+                    double* q, double* w, double* tip) {
+    for (int s = 0; s < n_steps; ++s) {
+        oracle_step(rod, t0 + s * rod->dt, x, v, q, w);
+        if (tip)
+            for (int c = 0; c < 3; ++c) tip[3 * s + c] = x[3 * rod->n + c];
+    }
+}
+
+double oracle_max_strain(const oracle_rod* rod, const double* x) {
+    double m = 0.0;
+    for (int j = 0; j < rod->n; ++j) {
+        double d[3];
+        for (int c = 0; c < 3; ++c) d[c] = x[3 * (j + 1) + c] - x[3 * j + c];
+        double s = fabs(norm3(d) / rod->seg_len[j] - 1.0);
+        if (!(s == s)) return INFINITY;
+        if (s > m) m = s;
+    }
+    return m;
+}
+
+int32_t oracle_stable(const oracle_rod* rod, double t0, int32_t n_steps, const double* x0,
+                      const double* v0, const double* q0, const double* w0,
+                      double energy_factor) {
+    const int n = rod->n;
+    double* x = (double*)malloc(sizeof(double) * 3 * (n + 1));
+    double* v = (double*)malloc(sizeof(double) * 3 * (n + 1));
+    double* q = (double*)malloc(sizeof(double) * 4 * n);
+    double* w = (double*)malloc(sizeof(double) * 3 * n);
+    memcpy(x, x0, sizeof(double) * 3 * (n + 1));
+    memcpy(v, v0, sizeof(double) * 3 * (n + 1));
+    memcpy(q, q0, sizeof(double) * 4 * n);
+    memcpy(w, w0, sizeof(double) * 3 * n);
+    double E0 = oracle_kinetic(rod, v, w) + oracle_energy(rod, x, q);
+    int ok = 1;
+    for (int s = 0; s < n_steps && ok; ++s) {
+        oracle_step(rod, t0 + s * rod->dt, x, v, q, w);
+        double E = oracle_kinetic(rod, v, w) + oracle_energy(rod, x, q);
+        if (!(E == E) || !isfinite(E)) ok = 0;
+        else if (E > E0 + (energy_factor - 1.0) * fabs(E0) + 1e-9) ok = 0;
+        else if (!(oracle_max_strain(rod, x) < 0.5)) ok = 0;
+    }
+    free(x);
+    free(v);
+    free(q);
+    free(w);
+    return ok;
+}
+
+double oracle_dt_rule(const oracle_rod* rod) {
+    double best = INFINITY;
+    for (int j = 0; j < rod->n; ++j) {
+        elem_t e;
+        element(rod, j, &e);
+        double om[5];
+        int nm = 0;
+        /* one-element mode frequencies of a uniform chain: 2 sqrt(k / m) for the
+         * alternating translational modes, sqrt(k_rot / I) for the rotational ones */
+        if (!rod->inextensible) om[nm++] = 2.0 * sqrt(e.Ks / e.l / e.m);
+        om[nm++] = 2.0 * sqrt(e.Kp / e.l / e.m);
+        om[nm++] = sqrt(e.l * e.Kp / e.I1);
+        om[nm++] = sqrt(4.0 * e.K1 / (e.l * e.I1));
+        om[nm++] = sqrt(4.0 * e.K3 / (e.l * e.I3));
+        for (int k = 0; k < nm; ++k) {
+            double dt = 2.0 / om[k];
+            if (dt < best) best = dt;
+        }
+    }
+    return 0.5 * best;
+}

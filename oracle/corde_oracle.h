@@ -1,0 +1,131 @@
+/*
+ * corde_oracle.h -- FP64 CPU oracle of the discrete CoRdE Cosserat rod stepper.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This header and corde_oracle.c are the slow, plainly written
+ * reference that the GPU library is checked against.  Only the test-suite, the package smoke
+ * check and the CPU-baseline leg of the benchmark may build, load or call it.  It shares no
+ * code, header, table or constant with the product library under paper_2509_04277_amd/.
+ *
+ * Model (Korzeniowski, Hald, Bello: "Massively-Parallel Implementation of Inextensible
+ * Elastic Rods Using Inter-block GPU Synchronization", Sec. 2.1):
+ *   - N elements (segments), N+1 mass points x_0..x_N, N material frames q_0..q_{N-1}
+ *     stored as unit quaternions (w, x, y, z), Hamilton product, body -> world.
+ *   - stretch energy, eq. (2), extensible variant only;
+ *   - bend/twist energy, eq. (3), with the discrete Darboux vector of eqs. (5)-(6);
+ *   - parallel-constraint penalty energy, eqs. (7)-(8);
+ *   - inextensible variant: eq. (2) dropped, segment lengths enforced by iterative local
+ *     velocity impulses (the J M^-1 J^T projection of Sec. 2.1, "Constraints");
+ *   - time integration: forces -> velocities -> impulses -> positions, semi-implicit Euler
+ *     (Sec. 2.1 last paragraph and the step loop of Fig. 5, without collision, self-collision
+ *     and binding lines).
+ *
+ * Array layouts (all row-major, contiguous):
+ *   x, v          : (N+1) x 3   world positions [m] and velocities [m/s]
+ *   q             : N x 4       (w, x, y, z) unit quaternions, body -> world
+ *   w (omega)     : N x 3       angular velocities in each frame's body axes [rad/s]
+ *   seg_len, radius, young : N  per element rest length [m], radius [m], Young modulus [Pa]
+ *   u_hat         : (N-1) x 3   intrinsic Darboux vector per joint [1/m] (NULL = zero)
+ *   f_ext         : (N+1) x 3   constant external world force per point [N] (NULL = none)
+ *   tau_ext       : N x 3       constant external body-frame torque per frame [N m] (NULL)
+ */
+#ifndef CORDE_ORACLE_H
+#define CORDE_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct oracle_rod {
+    int32_t n;             /* number of elements N >= 1 */
+    int32_t inextensible;  /* 0: stretch energy eq. (2); 1: distance constraints */
+    int32_t n_iter;        /* constraint iterations per step (inextensible only) */
+    int32_t clamp;         /* 1: point 0 and frame 0 follow the prescribed clamp motion */
+    double dt;             /* time step [s] */
+    double gravity[3];     /* [m/s^2] */
+    double damp_lin;       /* linear velocity damping gamma [1/s]: a -= gamma v */
+    double damp_ang;       /* angular velocity damping [1/s]: alpha -= gamma omega */
+    double poisson;        /* G = E / (2 (1 + nu)) */
+    double density;        /* [kg/m^3] */
+    double kp_scale;       /* K_p = kp_scale * G * pi r^2 */
+    double bend_scale;     /* multiplies K_1 = K_2 (1 = E pi r^4 / 4) */
+    double twist_scale;    /* multiplies K_3 (1 = G pi r^4 / 2) */
+    const double* seg_len;
+    const double* radius;
+    const double* young;
+    const double* u_hat;
+    const double* f_ext;
+    const double* tau_ext;
+    /* clamp trajectory: x_c(t) = clamp_x0 + clamp_amp * sin(2 pi f t + phase_x);
+     * q_c(t) = (cos(psi/2), sin(psi/2) axis) (x) clamp_q0, psi = twist_amp sin(2 pi f t + phase_tw) */
+    double clamp_x0[3];
+    double clamp_q0[4];
+    double clamp_amp[3];
+    double clamp_twist_amp;
+    double clamp_twist_axis[3];
+    double clamp_freq;
+    double clamp_phase_x;
+    double clamp_phase_twist;
+} oracle_rod;
+
+/* 0 if the description is usable, else a negative code. */
+int32_t oracle_check(const oracle_rod* rod);
+
+/* Total potential energy V(x, q): stretch (extensible only) + penalty + bend/twist
+ * - sum_i M_i g . x_i - sum_i f_ext_i . x_i.  [J] */
+double oracle_energy(const oracle_rod* rod, const double* x, const double* q);
+
+/* Kinetic energy 1/2 sum M v^2 + 1/2 sum w^T I w over all points and frames. [J] */
+double oracle_kinetic(const oracle_rod* rod, const double* v, const double* w);
+
+/* Conservative forces F = -dV/dx on every point (includes gravity and f_ext), and body
+ * torques tau_a = -1/2 (dV/dq) . (B_a q) on every frame (without tau_ext). */
+void oracle_forces(const oracle_rod* rod, const double* x, const double* q,
+                   double* F, double* tau);
+
+/* Discrete Darboux vector of joint j, eq. (6): u_k = (2 / lbar_j) (B_k q_j) . q_{j+1}. */
+void oracle_darboux(const oracle_rod* rod, const double* q, int32_t j, double* u);
+
+/* Prescribed clamp pose and body-frame angular rate at time t. */
+void oracle_clamp_pose(const oracle_rod* rod, double t, double* xc, double* qc, double* wc);
+
+/* One step from time t to t + dt, in place. */
+void oracle_step(const oracle_rod* rod, double t, double* x, double* v, double* q, double* w);
+
+/* n_steps steps starting at time t0, in place.  If tip != NULL it receives x_N after every
+ * step (n_steps x 3). */
+void oracle_rollout(const oracle_rod* rod, double t0, int32_t n_steps,
+                    double* x, double* v, double* q, double* w, double* tip);
+
+/* Same as oracle_rollout, on a private copy of the state, and returns 1 if every step is
+ * stable: all values finite, max_j | |e_j| / l_j - 1 | < 0.5, and total energy
+ * (kinetic + V) <= E_0 + (energy_factor - 1) |E_0| + 1e-9 J at every step (for E_0 > 0 this
+ * is E <= energy_factor E_0 + 1e-9; the |E_0| form stays meaningful when the gravity
+ * potential makes E_0 negative); 0 otherwise. */
+int32_t oracle_stable(const oracle_rod* rod, double t0, int32_t n_steps,
+                      const double* x, const double* v, const double* q, const double* w,
+                      double energy_factor);
+
+/* Time-step stability rule: 0.5 * min over elements and modes of 2 / omega_mode, with
+ * omega from the axial (extensible only), penalty-shear, penalty-rotation, bending and
+ * twisting one-element modes. */
+double oracle_dt_rule(const oracle_rod* rod);
+
+/* Largest relative segment-length error max_j | |x_{j+1} - x_j| / l_j - 1 |. */
+double oracle_max_strain(const oracle_rod* rod, const double* x);
+
+/* The constant skew-symmetric matrix B_k (k = 0, 1, 2), row-major 4x4, of eq. (6). */
+void oracle_bmat(int32_t k, double* out16);
+
+/* Rotation matrix R(q), row-major 3x3, body -> world: column k is director d_{k+1}. */
+void oracle_rotmat(const double* q, double* out9);
+
+/* Hamilton product r = a (x) b of (w, x, y, z) quaternions. */
+void oracle_qmul(const double* a, const double* b, double* r);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,247 @@
+"""ctypes binding of the FP64 CPU oracle (corde_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the package smoke check and the CPU-baseline leg of
+the benchmark use this module; the product library never imports it.  It shares no code with
+the GPU path.  A rod is described by a ``RodSpec`` and a ``RodState`` from
+``paper_2509_04277_amd.workloads`` (plain data, no method arithmetic).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "corde_oracle.c")
+LIB = os.path.join(HERE, "libcorde_oracle.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile corde_oracle.c with gcc (FP64, -O2, no fast-math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+             "-ffp-contract=off", "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Rod(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("inextensible", C.c_int32), ("n_iter", C.c_int32),
+        ("clamp", C.c_int32), ("dt", C.c_double), ("gravity", C.c_double * 3),
+        ("damp_lin", C.c_double), ("damp_ang", C.c_double), ("poisson", C.c_double),
+        ("density", C.c_double), ("kp_scale", C.c_double), ("bend_scale", C.c_double),
+        ("twist_scale", C.c_double),
+        ("seg_len", C.POINTER(C.c_double)), ("radius", C.POINTER(C.c_double)),
+        ("young", C.POINTER(C.c_double)), ("u_hat", C.POINTER(C.c_double)),
+        ("f_ext", C.POINTER(C.c_double)), ("tau_ext", C.POINTER(C.c_double)),
+        ("clamp_x0", C.c_double * 3), ("clamp_q0", C.c_double * 4),
+        ("clamp_amp", C.c_double * 3), ("clamp_twist_amp", C.c_double),
+        ("clamp_twist_axis", C.c_double * 3), ("clamp_freq", C.c_double),
+        ("clamp_phase_x", C.c_double), ("clamp_phase_twist", C.c_double),
+    ]
+
+
+_lib = None
+_DP = C.POINTER(C.c_double)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = C.CDLL(build())
+        L.oracle_check.restype = C.c_int32
+        L.oracle_check.argtypes = [C.POINTER(_Rod)]
+        L.oracle_energy.restype = C.c_double
+        L.oracle_energy.argtypes = [C.POINTER(_Rod), _DP, _DP]
+        L.oracle_kinetic.restype = C.c_double
+        L.oracle_kinetic.argtypes = [C.POINTER(_Rod), _DP, _DP]
+        L.oracle_forces.restype = None
+        L.oracle_forces.argtypes = [C.POINTER(_Rod), _DP, _DP, _DP, _DP]
+        L.oracle_darboux.restype = None
+        L.oracle_darboux.argtypes = [C.POINTER(_Rod), _DP, C.c_int32, _DP]
+        L.oracle_clamp_pose.restype = None
+        L.oracle_clamp_pose.argtypes = [C.POINTER(_Rod), C.c_double, _DP, _DP, _DP]
+        L.oracle_step.restype = None
+        L.oracle_step.argtypes = [C.POINTER(_Rod), C.c_double, _DP, _DP, _DP, _DP]
+        L.oracle_rollout.restype = None
+        L.oracle_rollout.argtypes = [C.POINTER(_Rod), C.c_double, C.c_int32,
+                                     _DP, _DP, _DP, _DP, _DP]
+        L.oracle_stable.restype = C.c_int32
+        L.oracle_stable.argtypes = [C.POINTER(_Rod), C.c_double, C.c_int32,
+                                    _DP, _DP, _DP, _DP, C.c_double]
+        L.oracle_rotmat.restype = None
+        L.oracle_rotmat.argtypes = [_DP, _DP]
+        L.oracle_dt_rule.restype = C.c_double
+        L.oracle_dt_rule.argtypes = [C.POINTER(_Rod)]
+        L.oracle_max_strain.restype = C.c_double
+        L.oracle_max_strain.argtypes = [C.POINTER(_Rod), _DP]
+        L.oracle_bmat.restype = None
+        L.oracle_bmat.argtypes = [C.c_int32, _DP]
+        L.oracle_qmul.restype = None
+        L.oracle_qmul.argtypes = [_DP, _DP, _DP]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(_DP)
+
+
+def _f64(a, shape=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+class Rod:
+    """An oracle rod: holds the C description and keeps its arrays alive."""
+
+    def __init__(self, spec):
+        n = int(spec.n)
+        self.spec = spec
+        self.n = n
+        self._keep = dict(
+            seg_len=_f64(spec.seg_len, (n,)), radius=_f64(spec.radius, (n,)),
+            young=_f64(spec.young, (n,)),
+            u_hat=_f64(spec.u_hat, (max(n - 1, 0), 3)) if spec.u_hat is not None else None,
+            f_ext=_f64(spec.f_ext, (n + 1, 3)) if spec.f_ext is not None else None,
+            tau_ext=_f64(spec.tau_ext, (n, 3)) if spec.tau_ext is not None else None)
+        r = _Rod()
+        r.n = n
+        r.inextensible = int(bool(spec.inextensible))
+        r.n_iter = int(spec.n_iter)
+        r.clamp = int(bool(spec.clamp))
+        r.dt = float(spec.dt)
+        r.gravity[:] = [float(g) for g in spec.gravity]
+        r.damp_lin = float(spec.damp_lin)
+        r.damp_ang = float(spec.damp_ang)
+        r.poisson = float(spec.poisson)
+        r.density = float(spec.density)
+        r.kp_scale = float(spec.kp_scale)
+        r.bend_scale = float(spec.bend_scale)
+        r.twist_scale = float(spec.twist_scale)
+        for k in ("seg_len", "radius", "young", "u_hat", "f_ext", "tau_ext"):
+            setattr(r, k, _p(self._keep[k]))
+        r.clamp_x0[:] = [float(c) for c in spec.clamp_x0]
+        r.clamp_q0[:] = [float(c) for c in spec.clamp_q0]
+        r.clamp_amp[:] = [float(c) for c in spec.clamp_amp]
+        r.clamp_twist_amp = float(spec.clamp_twist_amp)
+        r.clamp_twist_axis[:] = [float(c) for c in spec.clamp_twist_axis]
+        r.clamp_freq = float(spec.clamp_freq)
+        r.clamp_phase_x = float(spec.clamp_phase_x)
+        r.clamp_phase_twist = float(spec.clamp_phase_twist)
+        self.c = r
+        rc = lib().oracle_check(C.byref(r))
+        if rc != 0:
+            raise ValueError("oracle rejected rod description (code %d)" % rc)
+
+    def with_dt(self, dt):
+        import dataclasses
+        return Rod(dataclasses.replace(self.spec, dt=float(dt)))
+
+    # --- queries -------------------------------------------------------------------
+    def energy(self, x, q):
+        x, q = _f64(x, (self.n + 1, 3)), _f64(q, (self.n, 4))
+        return lib().oracle_energy(C.byref(self.c), _p(x), _p(q))
+
+    def kinetic(self, v, w):
+        v, w = _f64(v, (self.n + 1, 3)), _f64(w, (self.n, 3))
+        return lib().oracle_kinetic(C.byref(self.c), _p(v), _p(w))
+
+    def forces(self, x, q):
+        x, q = _f64(x, (self.n + 1, 3)), _f64(q, (self.n, 4))
+        F = np.zeros((self.n + 1, 3))
+        tau = np.zeros((self.n, 3))
+        lib().oracle_forces(C.byref(self.c), _p(x), _p(q), _p(F), _p(tau))
+        return F, tau
+
+    def darboux(self, q, j):
+        q = _f64(q, (self.n, 4))
+        u = np.zeros(3)
+        lib().oracle_darboux(C.byref(self.c), _p(q), int(j), _p(u))
+        return u
+
+    def clamp_pose(self, t):
+        xc, qc, wc = np.zeros(3), np.zeros(4), np.zeros(3)
+        lib().oracle_clamp_pose(C.byref(self.c), float(t), _p(xc), _p(qc), _p(wc))
+        return xc, qc, wc
+
+    def max_strain(self, x):
+        x = _f64(x, (self.n + 1, 3))
+        return lib().oracle_max_strain(C.byref(self.c), _p(x))
+
+    def dt_rule(self):
+        return lib().oracle_dt_rule(C.byref(self.c))
+
+    # --- time stepping ---------------------------------------------------------------
+    def rollout(self, state, n_steps, t0=0.0, tip=False):
+        """Returns (new_state, tip trajectory or None); ``state`` is not modified."""
+        st = state.copy()
+        x, v = _f64(st.x, (self.n + 1, 3)).copy(), _f64(st.v, (self.n + 1, 3)).copy()
+        q, w = _f64(st.q, (self.n, 4)).copy(), _f64(st.w, (self.n, 3)).copy()
+        tr = np.zeros((int(n_steps), 3)) if tip else None
+        lib().oracle_rollout(C.byref(self.c), float(t0), int(n_steps), _p(x), _p(v), _p(q),
+                             _p(w), _p(tr))
+        st.x, st.v, st.q, st.w = x, v, q, w
+        return st, tr
+
+    def stable(self, state, n_steps, t0=0.0, energy_factor=1.01):
+        x, v = _f64(state.x, (self.n + 1, 3)), _f64(state.v, (self.n + 1, 3))
+        q, w = _f64(state.q, (self.n, 4)), _f64(state.w, (self.n, 3))
+        return bool(lib().oracle_stable(C.byref(self.c), float(t0), int(n_steps), _p(x),
+                                        _p(v), _p(q), _p(w), float(energy_factor)))
+
+
+def bmat(k):
+    out = np.zeros(16)
+    lib().oracle_bmat(int(k), _p(out))
+    return out.reshape(4, 4)
+
+
+def rotmat(q):
+    q = _f64(q, (4,))
+    out = np.zeros(9)
+    lib().oracle_rotmat(_p(q), _p(out))
+    return out.reshape(3, 3)
+
+
+def qmul(a, b):
+    a, b = _f64(a, (4,)), _f64(b, (4,))
+    r = np.zeros(4)
+    lib().oracle_qmul(_p(a), _p(b), _p(r))
+    return r
+
+
+def rollout_many(specs_states, n_steps, t0=0.0, tip=False):
+    """Roll out several independent rods (one oracle call each)."""
+    return [Rod(s).rollout(st, n_steps, t0, tip) for s, st in specs_states]
+
+
+def bisect_dt_max(spec, state, n_steps, lo=1e-9, hi=1e-1, rel=1e-3, t0=0.0):
+    """Largest stable dt by bisection in log space (stability as in ``Rod.stable``).
+
+    ``lo`` must be stable and ``hi`` unstable; the interval is halved in log(dt) until
+    hi / lo <= 1 + rel.  Returns the stable end ``lo``.
+    """
+    import dataclasses
+    import math
+    mk = lambda dt: Rod(dataclasses.replace(spec, dt=float(dt)))
+    if not mk(lo).stable(state, n_steps, t0):
+        raise ValueError("lower bracket is not stable")
+    if mk(hi).stable(state, n_steps, t0):
+        return hi
+    while hi / lo > 1.0 + rel:
+        mid = math.exp(0.5 * (math.log(lo) + math.log(hi)))
+        if mk(mid).stable(state, n_steps, t0):
+            lo = mid
+        else:
+            hi = mid
+    return lo
