@@ -1,0 +1,149 @@
+"""Benchmark of the CoRdE rod stepper on one MI355X.
+
+Workload: two inextensible 512-element rods (catheter / guidewire-like: rod A r = 0.5 mm,
+E = 2 GPa; rod B r = 0.2 mm, E = 50 GPa with a 5 GPa tip), driven clamps, 10 constraint
+iterations, 10 time steps per kernel launch.  A benchmark "step" is one time step of both
+rods (forces, force integration, constraint impulses, velocity integration).
+
+Prints one JSON line: element-steps/s over the timed steps (device state resident in HBM),
+microseconds per step, the roofline of the step kernel (HBM, 104 algorithmic bytes per
+element-step: the 52-byte FP32 state read and written) with the kernel duration measured by
+HIP events on the library's stream, and the FP64 CPU oracle timed on the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+REPO = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, REPO)
+
+BYTES_PER_ELEMENT_STEP = 104          # 13 FP32 state values read + written per element
+HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("paper_2509_04277_amd/csrc/rod_kernels.hpp", "paper_2509_04277_amd/csrc/rod_lib.hip"):
+        h.update(open(os.path.join(REPO, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_name, elements, spl):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they match this source."""
+    path = os.path.join(REPO, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    e = d.get(kernel_name)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    if e.get("elements") != elements or e.get("steps_per_launch") != spl:
+        return None
+    return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+
+
+def cpu_baseline(wl, n_steps):
+    from oracle import oracle as O
+    t = time.perf_counter()
+    for spec, st in wl.rods:
+        O.Rod(spec).rollout(st, n_steps)
+    dt = time.perf_counter() - t
+    return {"value": wl.n_elements * n_steps / dt, "unit": "element-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "FP64 C oracle, both 512-element rods of the same workload, %d steps "
+                      "(%.1f s), one thread" % (n_steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--steps-per-launch", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=20000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the rods of this workload are independent and a "
+              "multi-GPU run would only shard rods across devices; run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2509_04277_amd import rod as R
+    from paper_2509_04277_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    spl = args.steps_per_launch
+    wl = W.config1()
+    specs = [s for s, _ in wl.rods]
+    b = R.RodBatch(specs)
+    b.set_state_rods([st for _, st in wl.rods])
+    tune = b.autotune(probe_steps=1000, steps_per_launch=spl)
+    print("autotune: %s" % tune, file=sys.stderr, flush=True)
+    b.set_state_rods([st for _, st in wl.rods])
+    if args.warmup:
+        b.step(args.warmup, spl)
+    b.sync()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    b.step(args.steps, spl)
+    b.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    ms_dev, launches = b.last_step_time()
+    elements = wl.n_elements
+    value = elements * args.steps / wall
+    # host-visible latency of one 10-step update including the position read-back (Sec. 3.1)
+    pos = torch.empty(3 * b.n_points, dtype=torch.float32).pin_memory()
+    lat = []
+    for _ in range(200):
+        t1 = time.perf_counter()
+        b.step(spl, spl)
+        b.get_positions(pos.numpy())
+        lat.append(time.perf_counter() - t1)
+    b.sync()
+    b.close()
+    kernel = "rod_resident_kernel<%d,%d>" % (tune["waves"], tune["elems_per_lane"])
+    launch_s = ms_dev / 1e3 / launches
+    bytes_per_launch = BYTES_PER_ELEMENT_STEP * elements * spl
+    achieved = bytes_per_launch / launch_s / 1e9
+    traffic = measured_traffic(kernel, elements, spl)
+    out = {
+        "metric": "element-steps/s",
+        "value": value,
+        "unit": "element-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2x512-element inextensible rods (catheter/guidewire pair, "
+                               "no contact), driven clamps, 10 constraint iterations, "
+                               "%d steps per launch" % spl,
+                   "rods": 2, "elements": elements, "steps_per_launch": spl,
+                   "kernel": kernel},
+        "us_per_step": 1e6 * wall / args.steps,
+        "us_per_step_device": 1e3 * ms_dev / args.steps,
+        "host_visible_ms_per_update": {"steps": spl, "median": 1e3 * float(np.median(lat)),
+                                       "p99": 1e3 * float(np.percentile(lat, 99))},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,158 @@
+/*
+ * rod.h -- C ABI of the MI355X (gfx950) CoRdE Cosserat-rod stepper, libcorde_rod.so.
+ *
+ * Method: Korzeniowski, Hald, Bello, "Massively-Parallel Implementation of Inextensible
+ * Elastic Rods Using Inter-block GPU Synchronization".
+ *   - Model: discrete Cosserat rod of Sec. 2.1 -- N elements, N+1 mass points, N material
+ *     frames as unit quaternions; stretch energy eq. (2) (extensible variant), bend/twist
+ *     energy eq. (3) with the discrete Darboux vector of eqs. (5)-(6), parallel-constraint
+ *     penalty eqs. (7)-(8); the inextensible variant drops eq. (2) and enforces segment
+ *     lengths with iterative local velocity impulses (J M^-1 J^T projection, Sec. 2.1
+ *     "Constraints").
+ *   - Step (Sec. 2.1 last paragraph, Fig. 5 without collision/self-collision/binding):
+ *     external + elastic forces and torques -> integrate forces -> n_iter constraint
+ *     iterations -> integrate velocities (semi-implicit Euler), quaternion renormalisation.
+ *   - The paper's kernel takes the number of time-steps, the number of constraint
+ *     iterations, material properties and the user input (Sec. 2.2): rod_step() takes the
+ *     step count, the handle carries the rest; rod_set_clamp() is the user (haptic) input.
+ *
+ * Conventions
+ *   - Every call returns a rod_status; ROD_OK == 0, errors are negative.  No C++ exception
+ *     crosses the ABI.  On error, output buffers are left untouched and rod_last_error()
+ *     describes the failure.
+ *   - A handle (rod_ctx) holds R >= 1 independent rods ("batch"); all its device memory is
+ *     owned by the library and freed by rod_destroy().  Caller buffers are never retained.
+ *   - State layout, concatenated over the rods of a handle in rod order (FP32, row-major):
+ *       x, v : sum_r (N_r + 1) x 3     point positions [m] / velocities [m/s], world axes
+ *       q    : sum_r N_r x 4           frame quaternions (w, x, y, z), body -> world
+ *       w    : sum_r N_r x 3           frame angular velocities in body axes [rad/s]
+ *   - on_device = 1: pointers are device pointers on the handle's device (e.g. a torch
+ *     tensor's data_ptr()); the copy is enqueued on the handle's stream and the call returns
+ *     without waiting.  on_device = 0: host pointers; the call synchronises the stream.
+ *   - All work is enqueued on the HIP stream given at creation (NULL = default stream) and is
+ *     stream-ordered.  Calls on one handle must not be made concurrently from two threads.
+ *   - Non-finite state seen by a kernel is latched on the device; the next call that
+ *     synchronises (rod_sync, host rod_get_state) returns ROD_E_UNSTABLE.
+ */
+#ifndef CORDE_ROD_H
+#define CORDE_ROD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rod_status {
+    ROD_OK = 0,
+    ROD_E_INVALID = -1,     /* bad argument (null pointer, size, value out of range) */
+    ROD_E_NOMEM = -2,       /* device or host allocation failed */
+    ROD_E_DEVICE = -3,      /* a HIP call failed */
+    ROD_E_UNSTABLE = -4,    /* a kernel saw a non-finite state value */
+    ROD_E_ORDER = -5,       /* call made in the wrong order */
+    ROD_E_UNSUPPORTED = -6  /* valid request this build cannot run (e.g. rod too long) */
+} rod_status;
+
+/* Description of one rod, SI units.  Arrays are read during rod_create() only. */
+typedef struct rod_params {
+    int32_t n_elements;          /* N >= 1: N+1 points, N frames */
+    int32_t inextensible;        /* 0: stretch energy eq. (2); 1: distance impulses */
+    int32_t n_constraint_iters;  /* iterations per step (inextensible only, paper: 10) */
+    int32_t clamp_end0;          /* 1: point 0 and frame 0 follow the clamp trajectory */
+    double dt;                   /* time step [s] > 0 */
+    double gravity[3];           /* [m/s^2] */
+    double damping_lin;          /* gamma [1/s]: acceleration -= gamma * v */
+    double damping_ang;          /* [1/s]: angular acceleration -= gamma * omega */
+    double poisson;              /* nu, G = E / (2 (1 + nu)) */
+    double density;              /* rho [kg/m^3] */
+    double kp_scale;             /* penalty eq. (8): K_p = kp_scale * G * pi r^2 */
+    double bend_scale;           /* K_1 = K_2 = bend_scale * E * pi r^4 / 4, eq. (3) */
+    double twist_scale;          /* K_3 = twist_scale * G * pi r^4 / 2, eq. (3) */
+    const double* seg_len;       /* [N] rest length of each element [m] (required) */
+    const double* radius;        /* [N] cross-section radius [m] (required) */
+    const double* young;         /* [N] Young modulus [Pa] (required) */
+    const double* u_hat;         /* [(N-1) x 3] intrinsic Darboux vector per joint, or NULL */
+    const double* f_ext;         /* [(N+1) x 3] constant world force per point [N], or NULL */
+    const double* tau_ext;       /* [N x 3] constant body torque per frame [N m], or NULL */
+    /* clamp trajectory (used when clamp_end0 = 1):
+     *   x_c(t) = clamp_x0 + clamp_amp * sin(2 pi f t + phase_x)
+     *   q_c(t) = (cos(psi/2), sin(psi/2) axis) (x) clamp_q0,  psi = twist_amp sin(2 pi f t + phase_tw) */
+    double clamp_x0[3];
+    double clamp_q0[4];
+    double clamp_amp[3];
+    double clamp_twist_amp;
+    double clamp_twist_axis[3];
+    double clamp_freq;
+    double clamp_phase_x;
+    double clamp_phase_twist;
+} rod_params;
+
+typedef struct rod_ctx rod_ctx;
+
+/* Kernel shape used for a handle: waves per workgroup and elements per lane. */
+typedef struct rod_tuning {
+    int32_t waves;            /* wavefronts (64 lanes) per rod */
+    int32_t elems_per_lane;   /* consecutive elements held in each lane's registers */
+    int32_t steps_per_launch; /* time steps run inside one kernel launch */
+    float us_per_step;        /* measured device time per step (autotune), else 0 */
+} rod_tuning;
+
+/* Create a handle for n_rods rods described by params[0..n_rods-1] on the current HIP device,
+ * enqueuing work on hip_stream (a hipStream_t, NULL = default).  Derives all per-element
+ * coefficients (masses, inertias, stiffnesses of eqs. (2), (3), (8)) in FP64 on the host.
+ * The state is zero until rod_set_state().  Errors: INVALID (bad sizes/values), NOMEM,
+ * DEVICE, UNSUPPORTED (a rod longer than the single-workgroup kernel holds). */
+rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream, rod_ctx** out);
+
+/* Free all device and host memory of the handle (after finishing its stream's work). */
+rod_status rod_destroy(rod_ctx* ctx);
+
+/* Copy a full state in (layouts above).  Resets the simulation time to t0 [s]. */
+rod_status rod_set_state(rod_ctx* ctx, const float* x, const float* v, const float* q,
+                         const float* w, int32_t on_device, double t0);
+
+/* Copy the full state out into caller-owned buffers (any pointer may be NULL to skip). */
+rod_status rod_get_state(rod_ctx* ctx, float* x, float* v, float* q, float* w, int32_t on_device);
+
+/* Advance every rod by n_steps time steps, steps_per_launch steps per kernel launch
+ * (0 = the handle's tuned value).  Each launch loads the state once, keeps it in registers
+ * across its steps and stores it once. */
+rod_status rod_step(rod_ctx* ctx, int32_t n_steps, int32_t steps_per_launch);
+
+/* Override the static clamp pose of rod `rod` (haptic input, Sec. 2.2); takes effect at the
+ * next step.  x0[3], q0[4] as in rod_params; the sinusoidal amplitudes are kept. */
+rod_status rod_set_clamp(rod_ctx* ctx, int32_t rod, const double* x0, const double* q0);
+
+/* Wait for the handle's stream; returns ROD_E_UNSTABLE if a non-finite state was seen. */
+rod_status rod_sync(rod_ctx* ctx);
+
+/* Simulation time [s] and number of steps taken since rod_set_state(). */
+rod_status rod_get_time(const rod_ctx* ctx, double* t, int64_t* steps);
+
+/* Select the kernel shape; waves in {1,2,4,8,16}, elems_per_lane in {1,2,4,8} as built.
+ * ROD_E_UNSUPPORTED if that shape is not built or cannot hold the longest rod. */
+rod_status rod_set_tuning(rod_ctx* ctx, const rod_tuning* t);
+rod_status rod_get_tuning(const rod_ctx* ctx, rod_tuning* t);
+
+/* Time every built kernel shape that holds the handle's rods on probe_steps steps (state is
+ * saved and restored) and keep the fastest; out (nullable) receives the choice. */
+rod_status rod_autotune(rod_ctx* ctx, int32_t probe_steps, int32_t steps_per_launch,
+                        rod_tuning* out);
+
+/* Stability rule for one rod: 0.5 * min over elements and one-element modes (axial for the
+ * extensible variant, penalty shear, penalty rotation, bending, twisting) of 2 / omega. */
+rod_status rod_stable_dt(const rod_params* p, double* dt_out);
+
+/* Device time of the last rod_step() call measured with HIP events on the handle's stream
+ * [ms], and the number of kernel launches it made. */
+rod_status rod_last_step_time(rod_ctx* ctx, float* ms, int32_t* launches);
+
+const char* rod_status_str(rod_status s);
+/* Detail of the last error on this handle (never NULL; "" if none; NULL ctx = global). */
+const char* rod_last_error(const rod_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,429 @@
+// rod_kernels.hpp -- gfx950 kernels of the CoRdE Cosserat-rod stepper.
+//
+// One workgroup of W wavefronts steps one rod for k time steps per launch with the whole rod
+// state held in registers.  Lane g (0 <= g < 64 W) owns E consecutive "slots"; slot j holds
+// material frame j (q_j, omega_j) and mass point j+1 (x_{j+1}, v_{j+1}), i.e. segment j's
+// right end.  Point 0 (the clamped base) is held separately by lane 0.  With this split a rod
+// of N elements needs exactly N slots.
+//
+// Neighbour data moves between lanes of a wavefront with DPP whole-wave shifts (wave_shr:1,
+// wave_shl:1), and between wavefronts through a double-buffered LDS mailbox with one
+// s_barrier per exchange.  One time step needs, in order (Sec. 2.1, Fig. 5 of the paper):
+//   A  exchange x of the left point and q of the right frame,
+//   F  segment forces (stretch eq. (2), penalty eq. (8)), joint torques (bend/twist eq. (3)
+//      with the Darboux vector of eqs. (5)-(6)),
+//   B  exchange each segment's force on its left point and each joint's torque on its right
+//      frame (and, inextensible, the right neighbour's segment vector),
+//   V  integrate forces: points as particles, frames as rigid bodies (Euler's equations),
+//   C  inextensible: n_iter x {even segments, odd segments} velocity impulses; with an even
+//      number of slots per lane only the even half-sweep crosses lanes,
+//   X  integrate velocities (semi-implicit Euler) and renormalise the quaternions.
+// No barrier is needed inside a wavefront; a workgroup of W > 1 waves pays one barrier per
+// exchange (A, B and one per constraint iteration).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace corde {
+
+// Per-slot coefficient rows (FP32, derived in FP64 on the host), stored row-major:
+// prm[row * stride + slot].
+enum PrmRow : int {
+  P_WINV = 0,    // inverse mass of point j+1
+  P_WINV_PREV,   // inverse mass of point j (0 for a clamped base)
+  P_WINV_NEXT,   // inverse mass of point j+2 (0 if j = N-1)
+  P_LEN,         // rest length l_j
+  P_LEN_NEXT,    // rest length l_{j+1} (0 if j = N-1: no segment)
+  P_KS_L,        // K_s / l_j, stretch, eq. (2) (0 for the inextensible variant)
+  P_LKP,         // l_j K_p, penalty, eq. (8)
+  P_IINV1,       // 1 / I_1 of frame j
+  P_IINV3,       // 1 / I_3
+  P_GYRO,        // (I_3 - I_1) / I_1
+  P_C1,          // joint j: 2 K_1 / lbar_j (0 if j = N-1: no joint)
+  P_C3,          // joint j: 2 K_3 / lbar_j
+  P_D0,          // joint j: K_k uhat_k
+  P_D1,
+  P_D2,
+  P_NROWS
+};
+
+struct RodDev {
+  int32_t n;          // elements
+  int32_t slot_off;   // first slot in the coefficient rows
+  int32_t pt_off;     // first point in x, v
+  int32_t fr_off;     // first frame in q, w
+  int32_t n_iter;     // constraint iterations (0: extensible)
+  int32_t clamp;      // 1: base point and frame 0 kinematic
+  int32_t driven;     // 1: clamp trajectory has non-zero amplitudes
+  int32_t has_ext;    // 1: read f_ext / tau_ext
+  float dt, damp_lin, damp_ang, winv0;
+  float g[3];
+  float ctw;          // twist amplitude
+  float cx0[3], camp[3], caxis[3];
+  float cq0[4];
+  double dt_d, t0, omega, ph_x, ph_t;
+};
+
+struct V3 {
+  float x, y, z;
+};
+struct Q4 {
+  float w, x, y, z;
+};
+
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ V3 operator*(float s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ V3 sel(bool c, V3 a, V3 b) {
+  return {c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
+}
+
+// DPP whole-wavefront shifts; the lane without a source receives 0.
+__device__ __forceinline__ float from_lower_lane(float v) {  // lane i <- lane i-1
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_upper_lane(float v) {  // lane i <- lane i+1
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+// Neighbour exchange across the rod's lanes.  `lo` receives the KL values `mine_hi` of the
+// lane below (its last slot), `hi` receives the KH values `mine_lo` of the lane above (its
+// first slot).  Global lane 0 and the last lane receive 0 (the caller substitutes).
+template <int W>
+struct Mailbox {
+  float buf[2][W][2][8];
+};
+
+template <int W, int KL, int KH>
+__device__ __forceinline__ void exchange(const float (&mine_hi)[KL], float (&lo)[KL],
+                                         const float (&mine_lo)[KH], float (&hi)[KH],
+                                         Mailbox<W>& mb, int& parity) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < KL; ++k) lo[k] = from_lower_lane(mine_hi[k]);
+#pragma unroll
+  for (int k = 0; k < KH; ++k) hi[k] = from_upper_lane(mine_lo[k]);
+  if constexpr (W > 1) {
+    const int wave = threadIdx.x >> 6;
+    if (lane == 63) {
+#pragma unroll
+      for (int k = 0; k < KL; ++k) mb.buf[parity][wave][1][k] = mine_hi[k];
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < KH; ++k) mb.buf[parity][wave][0][k] = mine_lo[k];
+    }
+    __syncthreads();
+    if (lane == 0 && wave > 0) {
+#pragma unroll
+      for (int k = 0; k < KL; ++k) lo[k] = mb.buf[parity][wave - 1][1][k];
+    }
+    if (lane == 63 && wave < W - 1) {
+#pragma unroll
+      for (int k = 0; k < KH; ++k) hi[k] = mb.buf[parity][wave + 1][0][k];
+    }
+    parity ^= 1;
+  }
+}
+
+// Velocity impulse of one distance constraint (Sec. 2.1, "Constraints"), linearised at the
+// predicted positions p = x + dt v.  e = x_hi - x_lo; returns lambda n with
+// lambda = C / (dt (w_lo + w_hi)), C = |p_hi - p_lo| - l.  Both owners of a segment call it
+// with identical operands.
+__device__ __forceinline__ V3 impulse(V3 e, V3 vhi, V3 vlo, float dt, float l, float wsum) {
+  V3 d = e + dt * (vhi - vlo);
+  float len2 = dot(d, d);
+  float il = rsqrtf(len2);
+  float len = len2 * il;
+  float lam = (len - l) / (dt * wsum);
+  return (lam * il) * d;
+}
+
+__device__ __forceinline__ Q4 qmul(Q4 a, Q4 b) {
+  return {a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z,
+          a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y,
+          a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x,
+          a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w};
+}
+
+// Prescribed clamp pose at time t: position, orientation, body angular rate.
+__device__ __forceinline__ void clamp_pose(const RodDev& rd, double t, V3& xc, Q4& qc, V3& wc) {
+  const double two_pi = 6.283185307179586;
+  double px = rd.omega * t + rd.ph_x;
+  double pt = rd.omega * t + rd.ph_t;
+  px -= two_pi * rint(px * (1.0 / two_pi));
+  pt -= two_pi * rint(pt * (1.0 / two_pi));
+  float sx = sinf((float)px);
+  float st, ct;
+  sincosf((float)pt, &st, &ct);
+  xc = {rd.cx0[0] + rd.camp[0] * sx, rd.cx0[1] + rd.camp[1] * sx, rd.cx0[2] + rd.camp[2] * sx};
+  float psi = rd.ctw * st;
+  float psidot = rd.ctw * (float)rd.omega * ct;
+  float sh, ch;
+  sincosf(0.5f * psi, &sh, &ch);
+  Q4 r = {ch, sh * rd.caxis[0], sh * rd.caxis[1], sh * rd.caxis[2]};
+  Q4 q0 = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
+  qc = qmul(r, q0);
+  // body rate = R(qc)^T (psidot axis): rotate by the conjugate
+  V3 a = {psidot * rd.caxis[0], psidot * rd.caxis[1], psidot * rd.caxis[2]};
+  V3 u = {-qc.x, -qc.y, -qc.z};
+  V3 tt = 2.0f * cross(u, a);
+  wc = a + qc.w * tt + cross(u, tt);
+}
+
+template <int W, int E>
+__global__ __launch_bounds__(64 * W) void rod_resident_kernel(
+    const RodDev* __restrict__ rods, const float* __restrict__ prm, int prm_stride,
+    float* __restrict__ gx, float* __restrict__ gv, float* __restrict__ gq,
+    float* __restrict__ gw, const float* __restrict__ fext, const float* __restrict__ text,
+    int n_steps, long long steps_done, int* __restrict__ status) {
+  __shared__ Mailbox<W> mb;
+  const RodDev rd = rods[blockIdx.x];
+  const int g = threadIdx.x;
+  const int n = rd.n;
+  const int j0 = g * E;
+  const float dt = rd.dt;
+  const bool inext = rd.n_iter > 0;
+  const V3 grav = {rd.g[0], rd.g[1], rd.g[2]};
+  int par = 0;
+
+  // ---- load state (once per launch)
+  V3 X[E], Vv[E], Om[E];
+  Q4 Qf[E];
+  float P[P_NROWS][E];
+  bool ok[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = j0 + e;
+    ok[e] = j < n;
+    if (ok[e]) {
+      const float* px = gx + 3 * (rd.pt_off + j + 1);
+      const float* pv = gv + 3 * (rd.pt_off + j + 1);
+      const float* pq = gq + 4 * (rd.fr_off + j);
+      const float* pw = gw + 3 * (rd.fr_off + j);
+      X[e] = {px[0], px[1], px[2]};
+      Vv[e] = {pv[0], pv[1], pv[2]};
+      Qf[e] = {pq[0], pq[1], pq[2], pq[3]};
+      Om[e] = {pw[0], pw[1], pw[2]};
+#pragma unroll
+      for (int r = 0; r < P_NROWS; ++r) P[r][e] = prm[r * prm_stride + rd.slot_off + j];
+    } else {
+      X[e] = {0.f, 0.f, 0.f};
+      Vv[e] = {0.f, 0.f, 0.f};
+      Qf[e] = {1.f, 0.f, 0.f, 0.f};
+      Om[e] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < P_NROWS; ++r) P[r][e] = 0.f;
+    }
+  }
+  V3 bx = {0.f, 0.f, 0.f}, bv = {0.f, 0.f, 0.f};  // base point (lane 0)
+  if (g == 0) {
+    const float* px = gx + 3 * rd.pt_off;
+    const float* pv = gv + 3 * rd.pt_off;
+    bx = {px[0], px[1], px[2]};
+    bv = {pv[0], pv[1], pv[2]};
+  }
+  V3 xc = {rd.cx0[0], rd.cx0[1], rd.cx0[2]}, wc = {0.f, 0.f, 0.f};
+  Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
+
+  for (int s = 0; s < n_steps; ++s) {
+    // ---------------- A: left point x (from below), right frame q (from above)
+    V3 xl;
+    Q4 qn;
+    {
+      float mh[3] = {X[E - 1].x, X[E - 1].y, X[E - 1].z};
+      float ml[4] = {Qf[0].w, Qf[0].x, Qf[0].y, Qf[0].z};
+      float lo[3], hi[4];
+      exchange<W, 3, 4>(mh, lo, ml, hi, mb, par);
+      xl = {lo[0], lo[1], lo[2]};
+      if (g == 0) xl = bx;
+      qn = {hi[0], hi[1], hi[2], hi[3]};
+    }
+    // ---------------- F: segment forces and joint torques, accumulated per slot
+    V3 F[E], T[E], Ev[E];
+    V3 fs_first = {0.f, 0.f, 0.f}, tn_prev = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const V3 xa = (e == 0) ? xl : X[e - 1];
+      const V3 d = X[e] - xa;
+      Ev[e] = d;
+      const float len2 = dot(d, d);
+      const float il = rsqrtf(len2);
+      const V3 t = il * d;
+      const Q4 q = Qf[e];
+      const float ww = q.w * q.w, xx = q.x * q.x, yy = q.y * q.y, zz = q.z * q.z;
+      const float xy = q.x * q.y, xz = q.x * q.z, yz = q.y * q.z;
+      const float wx = q.w * q.x, wy = q.w * q.y, wz = q.w * q.z;
+      const V3 d1 = {ww + xx - yy - zz, 2.f * (xy + wz), 2.f * (xz - wy)};
+      const V3 d2 = {2.f * (xy - wz), ww - xx + yy - zz, 2.f * (yz + wx)};
+      const V3 d3 = {2.f * (xz + wy), 2.f * (yz - wx), ww - xx - yy + zz};
+      const float lkp = P[P_LKP][e];
+      const float td3 = dot(t, d3);
+      V3 f = (lkp * il) * (d3 - td3 * t);                       // penalty, eq. (8)
+      const float len = len2 * il;
+      f = f - (P[P_KS_L][e] * (len - P[P_LEN][e])) * t;         // stretch, eq. (2)
+      f = sel(ok[e], f, V3{0.f, 0.f, 0.f});                     // force on point j+1
+      const V3 tpen = {-lkp * dot(d2, t), lkp * dot(d1, t), 0.f};  // l K_p e_3 x R^T t
+      // joint j: frames j and j+1 (eq. (6) with q' = (q_{j+1} - q_j) / lbar)
+      const Q4 qb = (e == E - 1) ? qn : Qf[e + 1];
+      const Q4 dq = {qb.w - q.w, qb.x - q.x, qb.y - q.y, qb.z - q.z};
+      const float rw = q.w * qb.w + q.x * qb.x + q.y * qb.y + q.z * qb.z;
+      const V3 va = {q.x, q.y, q.z}, dv = {dq.x, dq.y, dq.z};
+      const V3 rv = q.w * dv - dq.w * va - cross(va, dv);       // vec(conj(q_j) (x) q_{j+1})
+      const V3 m = {P[P_C1][e] * rv.x - P[P_D0][e], P[P_C1][e] * rv.y - P[P_D1][e],
+                    P[P_C3][e] * rv.z - P[P_D2][e]};            // K (u - uhat)
+      const V3 rxm = cross(rv, m);
+      const V3 tj = sel(ok[e], rw * m + rxm, V3{0.f, 0.f, 0.f});  // on frame j
+      const V3 tn = sel(ok[e], rxm - rw * m, V3{0.f, 0.f, 0.f});  // on frame j+1
+      F[e] = f;
+      if (e == 0) fs_first = f;
+      else F[e - 1] = F[e - 1] - f;                             // reaction on point j
+      T[e] = (tpen + tj) + tn_prev;
+      tn_prev = tn;
+    }
+    // ---------------- B: next segment's force, previous joint's torque, next segment vector
+    V3 enext;
+    {
+      float mh[3] = {tn_prev.x, tn_prev.y, tn_prev.z};
+      float ml[6] = {fs_first.x, fs_first.y, fs_first.z, Ev[0].x, Ev[0].y, Ev[0].z};
+      float lo[3], hi[6];
+      exchange<W, 3, 6>(mh, lo, ml, hi, mb, par);
+      T[0] = T[0] + V3{lo[0], lo[1], lo[2]};
+      F[E - 1] = F[E - 1] - V3{hi[0], hi[1], hi[2]};
+      enext = {hi[3], hi[4], hi[5]};
+    }
+    // ---------------- V: integrate forces and torques
+    if (rd.driven && rd.clamp) clamp_pose(rd, rd.t0 + (double)(steps_done + s + 1) * rd.dt_d, xc, qc, wc);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      V3 Fe = F[e];
+      V3 tau = T[e];
+      if (rd.has_ext && ok[e]) {
+        const float* pf = fext + 3 * (rd.pt_off + j0 + e + 1);
+        const float* pt = text + 3 * (rd.fr_off + j0 + e);
+        Fe = Fe + V3{pf[0], pf[1], pf[2]};
+        tau = tau + V3{pt[0], pt[1], pt[2]};
+      }
+      const V3 a = P[P_WINV][e] * Fe + grav - rd.damp_lin * Vv[e];
+      Vv[e] = Vv[e] + dt * a;
+      const V3 o = Om[e];
+      const float i1 = P[P_IINV1][e], i3 = P[P_IINV3][e], kg = P[P_GYRO][e];
+      const V3 al = {i1 * tau.x - kg * o.y * o.z - rd.damp_ang * o.x,
+                     i1 * tau.y + kg * o.x * o.z - rd.damp_ang * o.y,
+                     i3 * tau.z - rd.damp_ang * o.z};
+      Om[e] = o + dt * al;
+    }
+    if (g == 0) {
+      if (rd.clamp) {
+        bv = (1.0f / dt) * (xc - bx);
+        Om[0] = wc;
+      } else {
+        V3 Fb = V3{0.f, 0.f, 0.f} - fs_first;
+        if (rd.has_ext) {
+          const float* pf = fext + 3 * rd.pt_off;
+          Fb = Fb + V3{pf[0], pf[1], pf[2]};
+        }
+        bv = bv + dt * (rd.winv0 * Fb + grav - rd.damp_lin * bv);
+      }
+    }
+    // ---------------- C: distance impulses, red-black over segments
+    if (inext) {
+      for (int it = 0; it < rd.n_iter; ++it) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const bool cross_lanes = (E % 2 == 1) || (h == 0);
+          V3 vlo = {0.f, 0.f, 0.f}, vhi = {0.f, 0.f, 0.f};
+          if (cross_lanes) {
+            float mh[3] = {Vv[E - 1].x, Vv[E - 1].y, Vv[E - 1].z};
+            float ml[3] = {Vv[0].x, Vv[0].y, Vv[0].z};
+            float lo[3], hi[3];
+            exchange<W, 3, 3>(mh, lo, ml, hi, mb, par);
+            vlo = {lo[0], lo[1], lo[2]};
+            vhi = {hi[0], hi[1], hi[2]};
+            if (g == 0) vlo = bv;
+          }
+          V3 dvb = {0.f, 0.f, 0.f};
+          V3 nv[E];
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int j = j0 + e;
+            const bool is_hi = ((j & 1) == h);   // slot is the right end of segment j
+            // as right end of segment j: partner is point j
+            const V3 v_lo = (e == 0) ? vlo : Vv[e - 1];
+            const float w_lo = P[P_WINV_PREV][e];
+            // as left end of segment j+1: partner is point j+2
+            const V3 v_hi = (e == E - 1) ? vhi : Vv[e + 1];
+            const V3 e_next = (e == E - 1) ? enext : Ev[e + 1];
+            const float w_hi = P[P_WINV_NEXT][e];
+            const float w_me = P[P_WINV][e];
+            const V3 im_hi = impulse(Ev[e], Vv[e], v_lo, dt, P[P_LEN][e], w_me + w_lo);
+            const V3 im_lo = impulse(e_next, v_hi, Vv[e], dt, P[P_LEN_NEXT][e], w_hi + w_me);
+            const V3 newv = sel(is_hi, Vv[e] - w_me * im_hi, Vv[e] + w_me * im_lo);
+            if (e == 0) dvb = w_lo * im_hi;   // base point: left end of segment 0
+            const bool apply = ok[e] && (is_hi || P[P_LEN_NEXT][e] > 0.f);
+            nv[e] = sel(apply, newv, Vv[e]);
+          }
+#pragma unroll
+          for (int e = 0; e < E; ++e) Vv[e] = nv[e];
+          if (g == 0 && h == 0 && !rd.clamp) bv = bv + dvb;
+        }
+      }
+    }
+    // ---------------- X: integrate velocities, renormalise
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      X[e] = X[e] + dt * Vv[e];
+      const Q4 q = Qf[e];
+      const V3 o = Om[e];
+      const float hdt = 0.5f * dt;
+      Q4 qq = {q.w + hdt * (-q.x * o.x - q.y * o.y - q.z * o.z),
+               q.x + hdt * (q.w * o.x + q.y * o.z - q.z * o.y),
+               q.y + hdt * (q.w * o.y - q.x * o.z + q.z * o.x),
+               q.z + hdt * (q.w * o.z + q.x * o.y - q.y * o.x)};
+      const float inrm = rsqrtf(qq.w * qq.w + qq.x * qq.x + qq.y * qq.y + qq.z * qq.z);
+      Qf[e] = {qq.w * inrm, qq.x * inrm, qq.y * inrm, qq.z * inrm};
+    }
+    if (g == 0) {
+      if (rd.clamp) {
+        bx = xc;
+        Qf[0] = qc;
+      } else {
+        bx = bx + dt * bv;
+      }
+    }
+  }
+
+  // ---- store state (once per launch), latch non-finite values
+  float chk = 0.f;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = j0 + e;
+    if (ok[e]) {
+      float* px = gx + 3 * (rd.pt_off + j + 1);
+      float* pv = gv + 3 * (rd.pt_off + j + 1);
+      float* pq = gq + 4 * (rd.fr_off + j);
+      float* pw = gw + 3 * (rd.fr_off + j);
+      px[0] = X[e].x; px[1] = X[e].y; px[2] = X[e].z;
+      pv[0] = Vv[e].x; pv[1] = Vv[e].y; pv[2] = Vv[e].z;
+      pq[0] = Qf[e].w; pq[1] = Qf[e].x; pq[2] = Qf[e].y; pq[3] = Qf[e].z;
+      pw[0] = Om[e].x; pw[1] = Om[e].y; pw[2] = Om[e].z;
+      chk += X[e].x + X[e].y + X[e].z + Vv[e].x + Vv[e].y + Vv[e].z + Qf[e].w + Om[e].x +
+             Om[e].y + Om[e].z;
+    }
+  }
+  if (g == 0) {
+    float* px = gx + 3 * rd.pt_off;
+    float* pv = gv + 3 * rd.pt_off;
+    px[0] = bx.x; px[1] = bx.y; px[2] = bx.z;
+    pv[0] = bv.x; pv[1] = bv.y; pv[2] = bv.z;
+    chk += bx.x + bx.y + bx.z + bv.x + bv.y + bv.z;
+  }
+  if (!__builtin_isfinite(chk)) atomicOr(status, 1);
+}
+
+}  // namespace corde

@@ -1,0 +1,598 @@
+// rod_lib.hip -- host side of libcorde_rod.so: the C ABI declared in include/rod.h.
+//
+// rod_create() derives every per-element coefficient of the discrete Cosserat rod (Sec. 2.1
+// of the paper) in FP64 on the host and stores it as FP32 rows on the device; rod_step()
+// launches the register-resident kernel of rod_kernels.hpp, one workgroup per rod, running
+// steps_per_launch time steps per launch.  Everything is enqueued on the handle's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rod.h"
+#include "rod_kernels.hpp"
+
+using corde::RodDev;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+using KernelFn = void (*)(const RodDev*, const float*, int, float*, float*, float*, float*,
+                          const float*, const float*, int, long long, int*);
+
+struct KernelEntry {
+  int waves, elems;
+  KernelFn fn;
+};
+
+// Built kernel shapes: (waves per rod, elements per lane).  Capacity = 64 * waves * elems.
+const KernelEntry kKernels[] = {
+    {1, 1, corde::rod_resident_kernel<1, 1>},   {1, 2, corde::rod_resident_kernel<1, 2>},
+    {1, 4, corde::rod_resident_kernel<1, 4>},   {1, 8, corde::rod_resident_kernel<1, 8>},
+    {2, 1, corde::rod_resident_kernel<2, 1>},   {2, 2, corde::rod_resident_kernel<2, 2>},
+    {2, 4, corde::rod_resident_kernel<2, 4>},   {4, 1, corde::rod_resident_kernel<4, 1>},
+    {4, 2, corde::rod_resident_kernel<4, 2>},   {4, 4, corde::rod_resident_kernel<4, 4>},
+    {4, 8, corde::rod_resident_kernel<4, 8>},   {8, 1, corde::rod_resident_kernel<8, 1>},
+    {8, 2, corde::rod_resident_kernel<8, 2>},   {8, 4, corde::rod_resident_kernel<8, 4>},
+    {16, 1, corde::rod_resident_kernel<16, 1>},
+};
+
+const KernelEntry* find_kernel(int w, int e) {
+  for (const auto& k : kKernels)
+    if (k.waves == w && k.elems == e) return &k;
+  return nullptr;
+}
+
+int max_capacity() {
+  int c = 0;
+  for (const auto& k : kKernels) c = std::max(c, 64 * k.waves * k.elems);
+  return c;
+}
+
+thread_local std::string g_last_error;
+
+}  // namespace
+
+struct rod_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n_rods = 0;
+  int max_n = 0;
+  int total_pts = 0, total_frames = 0;
+  std::vector<int> n;
+  std::vector<RodDev> rods;
+  RodDev* d_rods = nullptr;
+  float* d_prm = nullptr;
+  int prm_stride = 0;
+  float *d_x = nullptr, *d_v = nullptr, *d_q = nullptr, *d_w = nullptr;
+  float *d_fext = nullptr, *d_text = nullptr;
+  int* d_status = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool have_state = false;
+  long long steps_done = 0;
+  double t0 = 0.0;
+  rod_tuning tuning{};
+  float last_ms = 0.f;
+  int last_launches = 0;
+  bool timed = false;
+  std::string err;
+};
+
+namespace {
+
+rod_status fail(rod_ctx* c, rod_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  g_last_error = msg;
+  return s;
+}
+
+rod_status hip_fail(rod_ctx* c, hipError_t e, const char* what) {
+  return fail(c, ROD_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, call)                                   \
+  do {                                                       \
+    hipError_t _e = (call);                                  \
+    if (_e != hipSuccess) return hip_fail((ctx), _e, #call); \
+  } while (0)
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Validates one rod description; returns "" or a message.
+std::string check_params(const rod_params& p, int idx) {
+  char buf[256];
+  auto bad = [&](const char* what) {
+    std::snprintf(buf, sizeof buf, "rod %d: %s", idx, what);
+    return std::string(buf);
+  };
+  if (p.n_elements < 1) return bad("n_elements must be >= 1");
+  if (p.inextensible != 0 && p.inextensible != 1) return bad("inextensible must be 0 or 1");
+  if (p.inextensible && (p.n_constraint_iters < 0 || p.n_constraint_iters > 100000))
+    return bad("n_constraint_iters out of range");
+  if (!finite_pos(p.dt)) return bad("dt must be finite and > 0");
+  if (!finite_pos(p.density)) return bad("density must be > 0");
+  if (!(std::isfinite(p.poisson) && p.poisson > -1.0 && p.poisson < 0.5 + 1e-12))
+    return bad("poisson must be in (-1, 0.5]");
+  if (!(std::isfinite(p.kp_scale) && p.kp_scale >= 0) || !(std::isfinite(p.bend_scale) && p.bend_scale >= 0) ||
+      !(std::isfinite(p.twist_scale) && p.twist_scale >= 0))
+    return bad("stiffness scales must be finite and >= 0");
+  if (!(std::isfinite(p.damping_lin) && p.damping_lin >= 0 && std::isfinite(p.damping_ang) &&
+        p.damping_ang >= 0))
+    return bad("damping must be finite and >= 0");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(p.gravity[k])) return bad("gravity must be finite");
+  if (!p.seg_len || !p.radius || !p.young) return bad("seg_len, radius and young are required");
+  for (int j = 0; j < p.n_elements; ++j)
+    if (!finite_pos(p.seg_len[j]) || !finite_pos(p.radius[j]) || !finite_pos(p.young[j]))
+      return bad("seg_len, radius and young must be finite and > 0");
+  if (p.clamp_end0 != 0 && p.clamp_end0 != 1) return bad("clamp_end0 must be 0 or 1");
+  if (p.clamp_end0) {
+    double qn = 0;
+    for (int k = 0; k < 4; ++k) qn += p.clamp_q0[k] * p.clamp_q0[k];
+    if (!(std::fabs(qn - 1.0) < 1e-6)) return bad("clamp_q0 must be a unit quaternion");
+    double an = 0;
+    for (int k = 0; k < 3; ++k) an += p.clamp_twist_axis[k] * p.clamp_twist_axis[k];
+    if (p.clamp_twist_amp != 0.0 && !(an > 0)) return bad("clamp_twist_axis must be non-zero");
+    if (!std::isfinite(p.clamp_freq)) return bad("clamp_freq must be finite");
+  }
+  return "";
+}
+
+// Material coefficients of element j (FP64): Sec. 2.1, with the second moment of area in
+// eq. (3), K_p = kp_scale G pi r^2 in eq. (8), rigid-cylinder frame inertia.
+struct Elem {
+  double l, m, Ks, Kp, K1, K3, I1, I3;
+};
+
+Elem element(const rod_params& p, int j) {
+  Elem e;
+  const double r = p.radius[j], E = p.young[j];
+  const double G = E / (2.0 * (1.0 + p.poisson));
+  const double A = kPi * r * r;
+  e.l = p.seg_len[j];
+  e.m = p.density * A * e.l;
+  e.Ks = E * A;
+  e.Kp = p.kp_scale * G * A;
+  e.K1 = p.bend_scale * E * kPi * r * r * r * r / 4.0;
+  e.K3 = p.twist_scale * G * kPi * r * r * r * r / 2.0;
+  e.I1 = e.m * (3.0 * r * r + e.l * e.l) / 12.0;
+  e.I3 = e.m * r * r / 2.0;
+  return e;
+}
+
+// Per-slot coefficient rows of one rod into rows[r * stride + off + j].
+void fill_rows(const rod_params& p, std::vector<float>& rows, int stride, int off, double* winv0) {
+  const int n = p.n_elements;
+  std::vector<Elem> el(n);
+  for (int j = 0; j < n; ++j) el[j] = element(p, j);
+  std::vector<double> winv(n + 1);
+  for (int i = 0; i <= n; ++i) {
+    double M = 0.0;
+    if (i > 0) M += 0.5 * el[i - 1].m;
+    if (i < n) M += 0.5 * el[i].m;
+    winv[i] = 1.0 / M;
+  }
+  if (p.clamp_end0) winv[0] = 0.0;
+  *winv0 = winv[0];
+  auto put = [&](int row, int j, double v) { rows[(size_t)row * stride + off + j] = (float)v; };
+  for (int j = 0; j < n; ++j) {
+    const Elem& e = el[j];
+    put(corde::P_WINV, j, winv[j + 1]);
+    put(corde::P_WINV_PREV, j, winv[j]);
+    put(corde::P_WINV_NEXT, j, j + 2 <= n ? winv[j + 2] : 0.0);
+    put(corde::P_LEN, j, e.l);
+    put(corde::P_LEN_NEXT, j, j + 1 < n ? el[j + 1].l : 0.0);
+    put(corde::P_KS_L, j, p.inextensible ? 0.0 : e.Ks / e.l);
+    put(corde::P_LKP, j, e.l * e.Kp);
+    put(corde::P_IINV1, j, 1.0 / e.I1);
+    put(corde::P_IINV3, j, 1.0 / e.I3);
+    put(corde::P_GYRO, j, (e.I3 - e.I1) / e.I1);
+    if (j + 1 < n) {
+      const Elem& f = el[j + 1];
+      const double lbar = 0.5 * (e.l + f.l);
+      const double K1 = 0.5 * (e.K1 + f.K1), K3 = 0.5 * (e.K3 + f.K3);
+      put(corde::P_C1, j, 2.0 * K1 / lbar);
+      put(corde::P_C3, j, 2.0 * K3 / lbar);
+      const double* uh = p.u_hat ? p.u_hat + 3 * j : nullptr;
+      put(corde::P_D0, j, uh ? K1 * uh[0] : 0.0);
+      put(corde::P_D1, j, uh ? K1 * uh[1] : 0.0);
+      put(corde::P_D2, j, uh ? K3 * uh[2] : 0.0);
+    } else {
+      put(corde::P_C1, j, 0.0);
+      put(corde::P_C3, j, 0.0);
+      put(corde::P_D0, j, 0.0);
+      put(corde::P_D1, j, 0.0);
+      put(corde::P_D2, j, 0.0);
+    }
+  }
+}
+
+RodDev make_dev(const rod_params& p, int slot_off, int pt_off, int fr_off, double winv0) {
+  RodDev d{};
+  d.n = p.n_elements;
+  d.slot_off = slot_off;
+  d.pt_off = pt_off;
+  d.fr_off = fr_off;
+  d.n_iter = p.inextensible ? p.n_constraint_iters : 0;
+  d.clamp = p.clamp_end0;
+  d.has_ext = (p.f_ext || p.tau_ext) ? 1 : 0;
+  d.dt = (float)p.dt;
+  d.dt_d = p.dt;
+  d.damp_lin = (float)p.damping_lin;
+  d.damp_ang = (float)p.damping_ang;
+  d.winv0 = (float)winv0;
+  for (int k = 0; k < 3; ++k) d.g[k] = (float)p.gravity[k];
+  double an = 0;
+  for (int k = 0; k < 3; ++k) an += p.clamp_twist_axis[k] * p.clamp_twist_axis[k];
+  an = an > 0 ? std::sqrt(an) : 1.0;
+  bool moving = p.clamp_twist_amp != 0.0;
+  for (int k = 0; k < 3; ++k) {
+    d.cx0[k] = (float)p.clamp_x0[k];
+    d.camp[k] = (float)p.clamp_amp[k];
+    d.caxis[k] = (float)(p.clamp_twist_axis[k] / an);
+    moving = moving || p.clamp_amp[k] != 0.0;
+  }
+  for (int k = 0; k < 4; ++k) d.cq0[k] = (float)p.clamp_q0[k];
+  d.ctw = (float)p.clamp_twist_amp;
+  d.driven = (p.clamp_end0 && moving) ? 1 : 0;
+  d.omega = 2.0 * kPi * p.clamp_freq;
+  d.ph_x = p.clamp_phase_x;
+  d.ph_t = p.clamp_phase_twist;
+  d.t0 = 0.0;
+  return d;
+}
+
+// Default kernel shape for the longest rod: one wavefront while it fits, then up to four
+// (one per SIMD), then more elements per lane.
+void default_tuning(int max_n, rod_tuning* t) {
+  static const int order[][2] = {{1, 1}, {1, 2}, {2, 2}, {4, 2}, {4, 4}, {8, 4}, {4, 8}};
+  for (const auto& o : order) {
+    if (64 * o[0] * o[1] >= max_n) {
+      t->waves = o[0];
+      t->elems_per_lane = o[1];
+      break;
+    }
+  }
+  t->steps_per_launch = 10;
+  t->us_per_step = 0.f;
+}
+
+rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it) {
+  const KernelEntry* k = find_kernel(c->tuning.waves, c->tuning.elems_per_lane);
+  if (!k) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
+  if (time_it) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+  int launches = 0;
+  for (int done = 0; done < n_steps; done += spl) {
+    const int ks = std::min(spl, n_steps - done);
+    hipLaunchKernelGGL(k->fn, dim3(c->n_rods), dim3(64 * k->waves), 0, c->stream, c->d_rods,
+                       c->d_prm, c->prm_stride, c->d_x, c->d_v, c->d_q, c->d_w, c->d_fext,
+                       c->d_text, ks, c->steps_done + done, c->d_status);
+    HIP_TRY(c, hipGetLastError());
+    ++launches;
+  }
+  if (time_it) HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+  c->timed = time_it;
+  c->last_launches = launches;
+  c->steps_done += n_steps;
+  return ROD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rod_status_str(rod_status s) {
+  switch (s) {
+    case ROD_OK: return "ROD_OK";
+    case ROD_E_INVALID: return "ROD_E_INVALID: invalid argument";
+    case ROD_E_NOMEM: return "ROD_E_NOMEM: out of memory";
+    case ROD_E_DEVICE: return "ROD_E_DEVICE: HIP runtime error";
+    case ROD_E_UNSTABLE: return "ROD_E_UNSTABLE: non-finite state";
+    case ROD_E_ORDER: return "ROD_E_ORDER: call out of order";
+    case ROD_E_UNSUPPORTED: return "ROD_E_UNSUPPORTED: not supported by this build";
+  }
+  return "unknown rod_status";
+}
+
+const char* rod_last_error(const rod_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_last_error.c_str();
+}
+
+rod_status rod_stable_dt(const rod_params* p, double* dt_out) {
+  if (!p || !dt_out) return fail(nullptr, ROD_E_INVALID, "null argument");
+  rod_params q = *p;
+  q.dt = 1.0;  // dt itself is not needed for the rule
+  std::string msg = check_params(q, 0);
+  if (!msg.empty()) return fail(nullptr, ROD_E_INVALID, msg);
+  double best = INFINITY;
+  for (int j = 0; j < p->n_elements; ++j) {
+    const Elem e = element(*p, j);
+    // one-element modes: alternating translation 2 sqrt(k/m) with k = K/l, rotation
+    // sqrt(k_rot / I) with k_rot = l K_p (penalty), 4 K_1 / l (bend), 4 K_3 / l (twist)
+    double w[5];
+    int nw = 0;
+    if (!p->inextensible) w[nw++] = 2.0 * std::sqrt(e.Ks / (e.l * e.m));
+    w[nw++] = 2.0 * std::sqrt(e.Kp / (e.l * e.m));
+    w[nw++] = std::sqrt(e.l * e.Kp / e.I1);
+    w[nw++] = std::sqrt(4.0 * e.K1 / (e.l * e.I1));
+    w[nw++] = std::sqrt(4.0 * e.K3 / (e.l * e.I3));
+    for (int k = 0; k < nw; ++k)
+      if (w[k] > 0) best = std::min(best, 2.0 / w[k]);
+  }
+  if (!std::isfinite(best)) return fail(nullptr, ROD_E_INVALID, "rod has no elastic mode");
+  *dt_out = 0.5 * best;
+  return ROD_OK;
+}
+
+rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream, rod_ctx** out) {
+  if (!params || !out) return fail(nullptr, ROD_E_INVALID, "null argument");
+  if (n_rods < 1 || n_rods > (1 << 24)) return fail(nullptr, ROD_E_INVALID, "n_rods out of range");
+  long long pts = 0, frames = 0;
+  int max_n = 0;
+  for (int r = 0; r < n_rods; ++r) {
+    std::string msg = check_params(params[r], r);
+    if (!msg.empty()) return fail(nullptr, ROD_E_INVALID, msg);
+    pts += params[r].n_elements + 1;
+    frames += params[r].n_elements;
+    max_n = std::max(max_n, params[r].n_elements);
+  }
+  if (frames > (1LL << 30)) return fail(nullptr, ROD_E_INVALID, "too many elements");
+  if (max_n > max_capacity())
+    return fail(nullptr, ROD_E_UNSUPPORTED,
+                "rod of " + std::to_string(max_n) + " elements exceeds the single-workgroup kernel (" +
+                    std::to_string(max_capacity()) + ")");
+  rod_ctx* c = new (std::nothrow) rod_ctx();
+  if (!c) return fail(nullptr, ROD_E_NOMEM, "host allocation failed");
+  auto cleanup = [&](rod_status s) {
+    rod_destroy(c);
+    return s;
+  };
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) return cleanup(hip_fail(nullptr, e, "hipGetDevice"));
+  c->stream = (hipStream_t)hip_stream;
+  c->n_rods = n_rods;
+  c->max_n = max_n;
+  c->total_pts = (int)pts;
+  c->total_frames = (int)frames;
+  c->prm_stride = (int)frames;
+  std::vector<float> rows((size_t)corde::P_NROWS * c->prm_stride, 0.f);
+  std::vector<float> fext, text;
+  bool any_ext = false;
+  for (int r = 0; r < n_rods; ++r) any_ext = any_ext || params[r].f_ext || params[r].tau_ext;
+  if (any_ext) {
+    fext.assign((size_t)3 * pts, 0.f);
+    text.assign((size_t)3 * frames, 0.f);
+  }
+  int slot = 0, pt = 0, fr = 0;
+  for (int r = 0; r < n_rods; ++r) {
+    const rod_params& p = params[r];
+    double winv0 = 0;
+    fill_rows(p, rows, c->prm_stride, slot, &winv0);
+    c->rods.push_back(make_dev(p, slot, pt, fr, winv0));
+    c->n.push_back(p.n_elements);
+    if (p.f_ext)
+      for (int i = 0; i < 3 * (p.n_elements + 1); ++i) fext[(size_t)3 * pt + i] = (float)p.f_ext[i];
+    if (p.tau_ext)
+      for (int i = 0; i < 3 * p.n_elements; ++i) text[(size_t)3 * fr + i] = (float)p.tau_ext[i];
+    slot += p.n_elements;
+    pt += p.n_elements + 1;
+    fr += p.n_elements;
+  }
+  auto dmalloc = [&](void** ptr, size_t bytes) -> bool {
+    return hipMalloc(ptr, std::max<size_t>(bytes, 4)) == hipSuccess;
+  };
+  if (!dmalloc((void**)&c->d_rods, sizeof(RodDev) * n_rods) ||
+      !dmalloc((void**)&c->d_prm, sizeof(float) * rows.size()) ||
+      !dmalloc((void**)&c->d_x, sizeof(float) * 3 * pts) ||
+      !dmalloc((void**)&c->d_v, sizeof(float) * 3 * pts) ||
+      !dmalloc((void**)&c->d_q, sizeof(float) * 4 * frames) ||
+      !dmalloc((void**)&c->d_w, sizeof(float) * 3 * frames) ||
+      !dmalloc((void**)&c->d_status, sizeof(int)))
+    return cleanup(fail(nullptr, ROD_E_NOMEM, "device allocation failed"));
+  if (any_ext && (!dmalloc((void**)&c->d_fext, sizeof(float) * fext.size()) ||
+                  !dmalloc((void**)&c->d_text, sizeof(float) * text.size())))
+    return cleanup(fail(nullptr, ROD_E_NOMEM, "device allocation failed"));
+  e = hipMemcpy(c->d_rods, c->rods.data(), sizeof(RodDev) * n_rods, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_prm, rows.data(), sizeof(float) * rows.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && any_ext) {
+    e = hipMemcpy(c->d_fext, fext.data(), sizeof(float) * fext.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_text, text.data(), sizeof(float) * text.size(), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMemset(c->d_x, 0, sizeof(float) * 3 * pts);
+  if (e == hipSuccess) e = hipMemset(c->d_v, 0, sizeof(float) * 3 * pts);
+  if (e == hipSuccess) e = hipMemset(c->d_q, 0, sizeof(float) * 4 * frames);
+  if (e == hipSuccess) e = hipMemset(c->d_w, 0, sizeof(float) * 3 * frames);
+  if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(int));
+  if (e == hipSuccess) e = hipEventCreate(&c->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev1);
+  if (e != hipSuccess) return cleanup(hip_fail(nullptr, e, "rod_create device setup"));
+  default_tuning(max_n, &c->tuning);
+  *out = c;
+  return ROD_OK;
+}
+
+rod_status rod_destroy(rod_ctx* c) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  for (void* p : {(void*)c->d_rods, (void*)c->d_prm, (void*)c->d_x, (void*)c->d_v,
+                  (void*)c->d_q, (void*)c->d_w, (void*)c->d_fext, (void*)c->d_text,
+                  (void*)c->d_status})
+    if (p) (void)hipFree(p);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+  return ROD_OK;
+}
+
+rod_status rod_set_state(rod_ctx* c, const float* x, const float* v, const float* q,
+                         const float* w, int32_t on_device, double t0) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (!x || !v || !q || !w) return fail(c, ROD_E_INVALID, "null state pointer");
+  if (!std::isfinite(t0)) return fail(c, ROD_E_INVALID, "t0 must be finite");
+  const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HIP_TRY(c, hipMemcpyAsync(c->d_x, x, sizeof(float) * 3 * c->total_pts, k, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_v, v, sizeof(float) * 3 * c->total_pts, k, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_q, q, sizeof(float) * 4 * c->total_frames, k, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_w, w, sizeof(float) * 3 * c->total_frames, k, c->stream));
+  if (!on_device) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->t0 = t0;
+  c->steps_done = 0;
+  for (auto& r : c->rods) r.t0 = t0;
+  HIP_TRY(c, hipMemcpyAsync(c->d_rods, c->rods.data(), sizeof(RodDev) * c->n_rods,
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));  // c->rods is host memory read by the copy
+  c->have_state = true;
+  return ROD_OK;
+}
+
+rod_status rod_get_state(rod_ctx* c, float* x, float* v, float* q, float* w, int32_t on_device) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (!c->have_state) return fail(c, ROD_E_ORDER, "rod_get_state before rod_set_state");
+  const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (x) HIP_TRY(c, hipMemcpyAsync(x, c->d_x, sizeof(float) * 3 * c->total_pts, k, c->stream));
+  if (v) HIP_TRY(c, hipMemcpyAsync(v, c->d_v, sizeof(float) * 3 * c->total_pts, k, c->stream));
+  if (q) HIP_TRY(c, hipMemcpyAsync(q, c->d_q, sizeof(float) * 4 * c->total_frames, k, c->stream));
+  if (w) HIP_TRY(c, hipMemcpyAsync(w, c->d_w, sizeof(float) * 3 * c->total_frames, k, c->stream));
+  if (!on_device) return rod_sync(c);
+  return ROD_OK;
+}
+
+rod_status rod_step(rod_ctx* c, int32_t n_steps, int32_t steps_per_launch) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (!c->have_state) return fail(c, ROD_E_ORDER, "rod_step before rod_set_state");
+  if (n_steps < 0) return fail(c, ROD_E_INVALID, "n_steps must be >= 0");
+  if (steps_per_launch < 0) return fail(c, ROD_E_INVALID, "steps_per_launch must be >= 0");
+  if (n_steps == 0) return ROD_OK;
+  const int spl = steps_per_launch > 0 ? steps_per_launch : std::max(1, c->tuning.steps_per_launch);
+  return launch_steps(c, n_steps, spl, true);
+}
+
+rod_status rod_set_clamp(rod_ctx* c, int32_t rod, const double* x0, const double* q0) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (rod < 0 || rod >= c->n_rods) return fail(c, ROD_E_INVALID, "rod index out of range");
+  if (!x0 || !q0) return fail(c, ROD_E_INVALID, "null clamp pose");
+  double qn = 0;
+  for (int k = 0; k < 4; ++k) qn += q0[k] * q0[k];
+  if (!(std::fabs(qn - 1.0) < 1e-6)) return fail(c, ROD_E_INVALID, "q0 must be a unit quaternion");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(x0[k])) return fail(c, ROD_E_INVALID, "x0 must be finite");
+  RodDev& d = c->rods[rod];
+  for (int k = 0; k < 3; ++k) d.cx0[k] = (float)x0[k];
+  for (int k = 0; k < 4; ++k) d.cq0[k] = (float)q0[k];
+  HIP_TRY(c, hipMemcpyAsync(c->d_rods + rod, &d, sizeof(RodDev), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return ROD_OK;
+}
+
+rod_status rod_sync(rod_ctx* c) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int st = 0;
+  HIP_TRY(c, hipMemcpy(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost));
+  if (st) return fail(c, ROD_E_UNSTABLE, "non-finite state detected by the step kernel");
+  return ROD_OK;
+}
+
+rod_status rod_get_time(const rod_ctx* c, double* t, int64_t* steps) {
+  if (!c || !t || !steps) return fail(nullptr, ROD_E_INVALID, "null argument");
+  *steps = c->steps_done;
+  *t = c->t0 + (double)c->steps_done * c->rods[0].dt_d;
+  return ROD_OK;
+}
+
+rod_status rod_set_tuning(rod_ctx* c, const rod_tuning* t) {
+  if (!c || !t) return fail(nullptr, ROD_E_INVALID, "null argument");
+  if (t->steps_per_launch < 1) return fail(c, ROD_E_INVALID, "steps_per_launch must be >= 1");
+  const KernelEntry* k = find_kernel(t->waves, t->elems_per_lane);
+  if (!k) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
+  if (64 * k->waves * k->elems < c->max_n) return fail(c, ROD_E_UNSUPPORTED, "shape cannot hold the longest rod");
+  c->tuning = *t;
+  return ROD_OK;
+}
+
+rod_status rod_get_tuning(const rod_ctx* c, rod_tuning* t) {
+  if (!c || !t) return fail(nullptr, ROD_E_INVALID, "null argument");
+  *t = c->tuning;
+  return ROD_OK;
+}
+
+rod_status rod_last_step_time(rod_ctx* c, float* ms, int32_t* launches) {
+  if (!c || !ms || !launches) return fail(nullptr, ROD_E_INVALID, "null argument");
+  if (!c->timed) return fail(c, ROD_E_ORDER, "no timed rod_step yet");
+  HIP_TRY(c, hipEventSynchronize(c->ev1));
+  HIP_TRY(c, hipEventElapsedTime(&c->last_ms, c->ev0, c->ev1));
+  *ms = c->last_ms;
+  *launches = c->last_launches;
+  return ROD_OK;
+}
+
+rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launch, rod_tuning* out) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (!c->have_state) return fail(c, ROD_E_ORDER, "rod_autotune before rod_set_state");
+  if (probe_steps < 1 || steps_per_launch < 1) return fail(c, ROD_E_INVALID, "probe sizes must be >= 1");
+  // save the state, probe every shape that holds the rods, restore
+  const size_t bx = sizeof(float) * 3 * c->total_pts, bq = sizeof(float) * 4 * c->total_frames,
+               bw = sizeof(float) * 3 * c->total_frames;
+  float *sx = nullptr, *sv = nullptr, *sq = nullptr, *sw = nullptr;
+  if (hipMalloc(&sx, bx) != hipSuccess || hipMalloc(&sv, bx) != hipSuccess ||
+      hipMalloc(&sq, bq) != hipSuccess || hipMalloc(&sw, bw) != hipSuccess) {
+    for (float* p : {sx, sv, sq, sw}) if (p) (void)hipFree(p);
+    return fail(c, ROD_E_NOMEM, "autotune scratch allocation failed");
+  }
+  auto free_all = [&]() { for (float* p : {sx, sv, sq, sw}) (void)hipFree(p); };
+  auto copy = [&](float* d, const float* s, size_t b) {
+    return hipMemcpyAsync(d, s, b, hipMemcpyDeviceToDevice, c->stream);
+  };
+  if (copy(sx, c->d_x, bx) || copy(sv, c->d_v, bx) || copy(sq, c->d_q, bq) || copy(sw, c->d_w, bw)) {
+    free_all();
+    return fail(c, ROD_E_DEVICE, "autotune state save failed");
+  }
+  const long long saved_steps = c->steps_done;
+  rod_tuning best = c->tuning;
+  float best_us = INFINITY;
+  rod_status st = ROD_OK;
+  for (const auto& k : kKernels) {
+    if (64 * k.waves * k.elems < c->max_n) continue;
+    if (64 * k.waves * k.elems >= 4 * std::max(c->max_n, 64)) continue;  // mostly idle lanes
+    c->tuning.waves = k.waves;
+    c->tuning.elems_per_lane = k.elems;
+    float ms_best = INFINITY;
+    for (int rep = 0; rep < 2 && st == ROD_OK; ++rep) {
+      st = launch_steps(c, probe_steps, steps_per_launch, true);
+      float ms = 0;
+      int nl = 0;
+      if (st == ROD_OK) st = rod_last_step_time(c, &ms, &nl);
+      ms_best = std::min(ms_best, ms);
+    }
+    if (st != ROD_OK) break;
+    const float us = 1000.f * ms_best / probe_steps;
+    if (us < best_us) {
+      best_us = us;
+      best.waves = k.waves;
+      best.elems_per_lane = k.elems;
+    }
+  }
+  best.steps_per_launch = steps_per_launch;
+  best.us_per_step = best_us;
+  c->tuning = best;
+  c->steps_done = saved_steps;
+  if (copy(c->d_x, sx, bx) || copy(c->d_v, sv, bx) || copy(c->d_q, sq, bq) || copy(c->d_w, sw, bw)) {
+    free_all();
+    return fail(c, ROD_E_DEVICE, "autotune state restore failed");
+  }
+  (void)hipStreamSynchronize(c->stream);
+  free_all();
+  if (st != ROD_OK) return st;
+  if (out) *out = best;
+  return ROD_OK;
+}
+
+}  // extern "C"

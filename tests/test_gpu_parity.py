@@ -1,0 +1,268 @@
+"""GPU parity: the HIP stepper (through the C ABI) against the FP64 oracle on the same seeded
+inputs.  Tolerance from the method's target: tip within 1e-4 x rod length after the workload's
+step count; every point within the same bound; quaternions unit to FP32 precision.
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2509_04277_amd import rod as R
+from paper_2509_04277_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _say(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    assert os.path.exists(R.LIB_PATH), "libcorde_rod.so must be built before the GPU tests"
+    torch.cuda.init()
+    yield
+
+
+def run_gpu(rods, n_steps, spl, shape=None, t0=0.0):
+    b = R.RodBatch([s for s, _ in rods])
+    if shape is not None:
+        b.set_tuning(shape[0], shape[1], spl)
+    b.set_state_rods([st for _, st in rods], t0=t0)
+    if n_steps:
+        b.step(n_steps, spl)
+    b.sync()
+    out = b.get_state_rods()
+    b.close()
+    return out
+
+
+def run_oracle(oracle, rods, n_steps, t0=0.0):
+    return [oracle.Rod(s).rollout(st, n_steps, t0=t0)[0] for s, st in rods]
+
+
+def compare(gpu, ref, specs, label):
+    worst = 0.0
+    for (x, v, q, w), o, s in zip(gpu, ref, specs):
+        L = float(np.sum(s.seg_len))
+        ex = np.abs(x - o.x).max()
+        tip = np.linalg.norm(x[-1] - o.x[-1])
+        qn = np.abs(np.linalg.norm(q.astype(np.float64), axis=1) - 1).max()
+        eq = np.abs(q - o.q).max()
+        _say("%s N=%d: max|dx|=%.2e tip=%.2e (tol %.1e) max|dq|=%.2e |q|-1=%.1e max|dv|=%.2e"
+             % (label, s.n, ex, tip, 1e-4 * L, eq, qn, np.abs(v - o.v).max()))
+        assert np.isfinite(x).all() and np.isfinite(q).all()
+        assert tip <= 1e-4 * L
+        assert ex <= 1e-4 * L
+        assert qn <= 1e-6
+        worst = max(worst, ex / L)
+    return worst
+
+
+def test_c0_full_run(oracle):
+    wl = W.config0()
+    _say("c0 full: 1x64 extensible, %d steps, %d per launch" % (wl.n_steps, wl.steps_per_launch))
+    gpu = run_gpu(wl.rods, wl.n_steps, wl.steps_per_launch)
+    ref = run_oracle(oracle, wl.rods, wl.n_steps)
+    compare(gpu, ref, [s for s, _ in wl.rods], "c0")
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 2), (1, 4), (2, 1), (2, 2), (4, 1), (8, 1)])
+def test_c0_every_kernel_shape(oracle, shape):
+    wl = W.config0(dt=1e-4)
+    _say("c0 dt=1e-4 (large swing), 3000 steps, shape waves=%d elems=%d" % shape)
+    gpu = run_gpu(wl.rods, 3000, 50, shape)
+    ref = run_oracle(oracle, wl.rods, 3000)
+    compare(gpu, ref, [s for s, _ in wl.rods], "c0-swing %s" % (shape,))
+
+
+def test_c1_reduced_vs_oracle(oracle):
+    wl = W.config1()
+    _say("c1 2x512 inextensible, 2000 steps, 10 per launch, shape (4,2)")
+    gpu = run_gpu(wl.rods, 2000, 10, (4, 2))
+    ref = run_oracle(oracle, wl.rods, 2000)
+    compare(gpu, ref, [s for s, _ in wl.rods], "c1-2000")
+
+
+def test_c1_full_run_against_stored_oracle():
+    """Full 20000-step run in the benchmark's launch configuration vs the stored FP64 oracle."""
+    g = json.load(open(os.path.join(HERE, "golden", "c1_oracle.json")))
+    wl = W.config1()
+    assert g["n_steps"] == wl.n_steps and g["dt"] == wl.rods[0][0].dt
+    _say("c1 full: 2x512, 20000 steps at 10 per launch, shape (4,2)")
+    b = R.RodBatch([s for s, _ in wl.rods])
+    b.set_tuning(4, 2, 10)
+    b.set_state_rods([st for _, st in wl.rods])
+    tips = []
+    for k in range(wl.n_steps // 1000):
+        b.step(1000, 10)
+        tips.append([x[-1].copy() for x, _, _, _ in b.get_state_rods()])
+    b.sync()
+    final = b.get_state_rods()
+    b.close()
+    for r, (spec, _) in enumerate(wl.rods):
+        ref_tip = np.array(g["rods"][r]["tip"])
+        got = np.array([t[r] for t in tips])
+        err = np.linalg.norm(got - ref_tip, axis=1)
+        _say("c1 rod %d: tip error every 1000 steps max %.2e final %.2e" % (r, err.max(), err[-1]))
+        assert err.max() <= 1e-4 * 1.0
+        sp = g["rods"][r]["sample_points"]
+        ex = np.abs(final[r][0][sp] - np.array(g["rods"][r]["x"])).max()
+        _say("c1 rod %d: sample points max|dx| %.2e" % (r, ex))
+        assert ex <= 1e-4
+        x = final[r][0].astype(np.float64)
+        strain = np.abs(np.linalg.norm(np.diff(x, axis=0), axis=1) / spec.seg_len - 1).max()
+        _say("c1 rod %d: max strain gpu %.2e oracle %.2e" % (r, strain, g["rods"][r]["max_strain"]))
+        assert strain <= max(10 * g["rods"][r]["max_strain"], 1e-4)
+
+
+def _edge_rods(oracle):
+    rng = np.random.default_rng(40)
+    rods = []
+    for n, inext, clamp in ((1, False, True), (2, True, True), (3, False, False), (65, True, True),
+                            (130, False, True), (200, True, False)):
+        x, q = W.curved_rod(n, 0.02, rng, sigma=0.2, twist_sigma=0.1)
+        spec = W.RodSpec(
+            n=n, inextensible=inext, n_iter=7 if inext else 0, clamp=clamp, dt=2e-5,
+            gravity=(0.5, -2.0, -9.81), damp_lin=0.3, damp_ang=0.2, poisson=0.35, density=1100.0,
+            seg_len=rng.uniform(0.015, 0.025, n), radius=rng.uniform(0.004, 0.006, n),
+            young=rng.uniform(2e5, 1e6, n), kp_scale=0.8, bend_scale=1.2, twist_scale=0.9,
+            u_hat=rng.normal(0, 1.0, (n - 1, 3)) if n > 1 else None,
+            f_ext=rng.normal(0, 1e-3, (n + 1, 3)), tau_ext=rng.normal(0, 1e-5, (n, 3)),
+            clamp_x0=tuple(x[0]), clamp_q0=tuple(q[0]),
+            clamp_amp=(0.0, 1e-3, 5e-4) if clamp else (0, 0, 0), clamp_twist_amp=0.1 if clamp else 0,
+            clamp_twist_axis=(0.2, 0.0, 1.0), clamp_freq=7.0, clamp_phase_x=0.3,
+            clamp_phase_twist=1.3)
+        st = W.RodState(x, rng.normal(0, 1e-2, (n + 1, 3)), q, rng.normal(0, 0.1, (n, 3)))
+        if clamp:
+            xc, qc, _ = oracle.Rod(spec).clamp_pose(0.0)
+            st.x = st.x - st.x[0] + xc
+            st.q[0] = qc
+        rods.append((spec, st))
+    return rods
+
+
+def test_edge_cases_mixed_batch(oracle):
+    """One handle with ragged rods (N = 1, 2, 3, 65, 130, 200), both variants, clamped and
+    free, driven clamps, external loads, intrinsic shape, non-uniform material."""
+    rods = _edge_rods(oracle)
+    for shape in ((4, 1), (2, 2), (1, 4)):
+        _say("edge batch, 400 steps, shape %s" % (shape,))
+        gpu = run_gpu(rods, 400, 37, shape)
+        ref = run_oracle(oracle, rods, 400)
+        compare(gpu, ref, [s for s, _ in rods], "edge %s" % (shape,))
+
+
+def test_zero_steps_and_roundtrip():
+    wl = W.config0()
+    _say("state round trip")
+    gpu = run_gpu(wl.rods, 0, 10)
+    spec, st = wl.rods[0]
+    x, v, q, w = gpu[0]
+    assert np.array_equal(x, st.x.astype(np.float32)) and np.array_equal(q, st.q.astype(np.float32))
+
+
+def test_launch_split_and_determinism_are_bitwise():
+    wl = W.config1(n_steps=200)
+    _say("c1 200 steps: 1x200 vs 20x10 vs 200x1 launches, repeated")
+    a = run_gpu(wl.rods, 200, 200, (4, 2))
+    b = run_gpu(wl.rods, 200, 10, (4, 2))
+    c = run_gpu(wl.rods, 200, 1, (4, 2))
+    d = run_gpu(wl.rods, 200, 10, (4, 2))
+    for ra, rb, rc, rd in zip(a, b, c, d):
+        for k in range(4):
+            assert np.array_equal(ra[k], rb[k]) and np.array_equal(ra[k], rc[k])
+            assert np.array_equal(rb[k], rd[k])
+
+
+def _resume(rods, n1, n2, spl, shape):
+    b = R.RodBatch([s for s, _ in rods])
+    b.set_tuning(shape[0], shape[1], spl)
+    b.set_state_rods([st for _, st in rods])
+    b.step(n1, spl)
+    x, v, q, w = b.get_state()
+    t, steps = b.time()
+    b.close()
+    b = R.RodBatch([s for s, _ in rods])
+    b.set_tuning(shape[0], shape[1], spl)
+    b.set_state(x, v, q, w, t0=t)
+    b.step(n2, spl)
+    res = b.get_state_rods()
+    b.close()
+    return res
+
+
+def test_checkpoint_resume():
+    """get_state / set_state round trip mid-run: bitwise for a static clamp; with a driven
+    clamp the resumed time t0 + k dt rounds differently from k' dt, so 1e-6 there."""
+    wl = W.config0()
+    _say("c0: 300 steps straight vs 120 + get/set + 180")
+    full = run_gpu(wl.rods, 300, 10, (1, 1))
+    res = _resume(wl.rods, 120, 180, 10, (1, 1))
+    for ra, rb in zip(full, res):
+        for k in range(4):
+            assert np.array_equal(ra[k], rb[k])
+    wl = W.config1(n_steps=300)
+    _say("c1: 300 steps straight vs 120 + get/set + 180")
+    full = run_gpu(wl.rods, 300, 10, (4, 2))
+    res = _resume(wl.rods, 120, 180, 10, (4, 2))
+    for ra, rb in zip(full, res):
+        assert np.abs(ra[0] - rb[0]).max() < 1e-6
+
+
+def test_device_pointer_state_io():
+    import torch
+    wl = W.config0()
+    spec, st = wl.rods[0]
+    _say("device tensors in/out")
+    b = R.RodBatch([spec])
+    dev = [torch.tensor(a.astype(np.float32).ravel(), device="cuda") for a in (st.x, st.v, st.q, st.w)]
+    b.set_state(*dev)
+    b.step(50, 10)
+    out = [torch.empty_like(t) for t in dev]
+    b.get_state(out)
+    torch.cuda.synchronize()
+    host = b.get_state()
+    b.close()
+    for a, t in zip(host, out):
+        assert np.array_equal(a, t.cpu().numpy())
+
+
+def test_non_finite_state_is_reported():
+    wl = W.config0()
+    spec, st = wl.rods[0]
+    _say("NaN in the state -> ROD_E_UNSTABLE")
+    b = R.RodBatch([spec])
+    x = st.x.astype(np.float32).ravel().copy()
+    x[30] = np.nan
+    b.set_state(x, st.v.astype(np.float32).ravel(), st.q.astype(np.float32).ravel(),
+                st.w.astype(np.float32).ravel())
+    b.step(10, 10)
+    with pytest.raises(R.RodError) as e:
+        b.sync()
+    assert e.value.status == -4
+    b.close()
+
+
+def test_autotune_keeps_state_and_picks_a_shape():
+    wl = W.config1(n_steps=100)
+    _say("autotune on c1")
+    b = R.RodBatch([s for s, _ in wl.rods])
+    b.set_state_rods([st for _, st in wl.rods])
+    before = b.get_state()
+    t = b.autotune(probe_steps=100, steps_per_launch=10)
+    after = b.get_state()
+    assert b.time()[1] == 0
+    b.close()
+    _say("autotune chose %s" % t)
+    assert 64 * t["waves"] * t["elems_per_lane"] >= 512 and t["us_per_step"] > 0
+    for a, c in zip(before, after):
+        assert np.array_equal(a, c)
