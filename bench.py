@@ -65,6 +65,7 @@ def main():
     ap.add_argument("--steps-per-launch", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20000)
+    ap.add_argument("--shape", default="", help="W,E kernel shape (default: autotune)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the rods of this workload are independent and a "
@@ -84,8 +85,13 @@ def main():
     specs = [s for s, _ in wl.rods]
     b = R.RodBatch(specs)
     b.set_state_rods([st for _, st in wl.rods])
-    tune = b.autotune(probe_steps=1000, steps_per_launch=spl)
-    print("autotune: %s" % tune, file=sys.stderr, flush=True)
+    if args.shape:
+        w, e = (int(v) for v in args.shape.split(","))
+        b.set_tuning(w, e, spl)
+        tune = b.tuning
+    else:
+        tune = b.autotune(probe_steps=1000, steps_per_launch=spl)
+    print("kernel shape: %s" % tune, file=sys.stderr, flush=True)
     b.set_state_rods([st for _, st in wl.rods])
     if args.warmup:
         b.step(args.warmup, spl)

@@ -32,9 +32,11 @@ namespace corde {
 enum PrmRow : int {
   P_WINV = 0,    // inverse mass of point j+1
   P_WINV_PREV,   // inverse mass of point j (0 for a clamped base)
-  P_WINV_NEXT,   // inverse mass of point j+2 (0 if j = N-1)
+  P_CI,          // segment j: 1 / (dt (w_j + w_{j+1}))   (J M^-1 J^T of the distance constraint)
+  P_CIL,         // segment j: l_j / (dt (w_j + w_{j+1}))
+  P_CI_NEXT,     // the same for segment j+1 (0 if j = N-1: no segment)
+  P_CIL_NEXT,
   P_LEN,         // rest length l_j
-  P_LEN_NEXT,    // rest length l_{j+1} (0 if j = N-1: no segment)
   P_KS_L,        // K_s / l_j, stretch, eq. (2) (0 for the inextensible variant)
   P_LKP,         // l_j K_p, penalty, eq. (8)
   P_IINV1,       // 1 / I_1 of frame j
@@ -47,6 +49,9 @@ enum PrmRow : int {
   P_D2,
   P_NROWS
 };
+
+// Clamp poses are evaluated for up to kClampChunk steps at a time, one step per lane, into LDS.
+constexpr int kClampChunk = 64;
 
 struct RodDev {
   int32_t n;          // elements
@@ -119,29 +124,36 @@ __device__ __forceinline__ void exchange(const float (&mine_hi)[KL], float (&lo)
       for (int k = 0; k < KH; ++k) mb.buf[parity][wave][0][k] = mine_lo[k];
     }
     __syncthreads();
-    if (lane == 0 && wave > 0) {
+    // every lane reads the same (broadcast) word; only the wave's edge lanes keep it
+    const int wl = wave > 0 ? wave - 1 : 0;
+    const int wh = wave < W - 1 ? wave + 1 : W - 1;
+    const bool take_lo = (lane == 0) && (wave > 0);
+    const bool take_hi = (lane == 63) && (wave < W - 1);
 #pragma unroll
-      for (int k = 0; k < KL; ++k) lo[k] = mb.buf[parity][wave - 1][1][k];
+    for (int k = 0; k < KL; ++k) {
+      const float t = mb.buf[parity][wl][1][k];
+      lo[k] = take_lo ? t : lo[k];
     }
-    if (lane == 63 && wave < W - 1) {
 #pragma unroll
-      for (int k = 0; k < KH; ++k) hi[k] = mb.buf[parity][wave + 1][0][k];
+    for (int k = 0; k < KH; ++k) {
+      const float t = mb.buf[parity][wh][0][k];
+      hi[k] = take_hi ? t : hi[k];
     }
     parity ^= 1;
   }
 }
 
 // Velocity impulse of one distance constraint (Sec. 2.1, "Constraints"), linearised at the
-// predicted positions p = x + dt v.  e = x_hi - x_lo; returns lambda n with
-// lambda = C / (dt (w_lo + w_hi)), C = |p_hi - p_lo| - l.  Both owners of a segment call it
-// with identical operands.
-__device__ __forceinline__ V3 impulse(V3 e, V3 vhi, V3 vlo, float dt, float l, float wsum) {
-  V3 d = e + dt * (vhi - vlo);
-  float len2 = dot(d, d);
-  float il = rsqrtf(len2);
-  float len = len2 * il;
-  float lam = (len - l) / (dt * wsum);
-  return (lam * il) * d;
+// predicted positions p = x + dt v, returned as lambda n:
+//   d = p_hi - p_lo = e + dt (v_hi - v_lo),  C = |d| - l,  lambda = C / (dt (w_lo + w_hi)),
+//   lambda n = ci (1 - l / |d|) d   with ci = 1 / (dt (w_lo + w_hi)), cil = ci l.
+// Both owners of a segment call it with identical operands, so both apply the same impulse.
+// A missing segment has ci = cil = 0 and yields 0 (the max keeps the reciprocal finite).
+__device__ __forceinline__ V3 impulse(V3 e, V3 vhi, V3 vlo, float dt, float ci, float cil) {
+  const V3 d = e + dt * (vhi - vlo);
+  const float il = rsqrtf(fmaxf(dot(d, d), 1e-30f));
+  const float s = ci - cil * il;
+  return s * d;
 }
 
 __device__ __forceinline__ Q4 qmul(Q4 a, Q4 b) {
@@ -183,6 +195,7 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
     float* __restrict__ gw, const float* __restrict__ fext, const float* __restrict__ text,
     int n_steps, long long steps_done, int* __restrict__ status) {
   __shared__ Mailbox<W> mb;
+  __shared__ float cbuf[kClampChunk][10];
   const RodDev rd = rods[blockIdx.x];
   const int g = threadIdx.x;
   const int n = rd.n;
@@ -298,7 +311,27 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
       enext = {hi[3], hi[4], hi[5]};
     }
     // ---------------- V: integrate forces and torques
-    if (rd.driven && rd.clamp) clamp_pose(rd, rd.t0 + (double)(steps_done + s + 1) * rd.dt_d, xc, qc, wc);
+    if (rd.driven && rd.clamp) {
+      // prescribed clamp pose: evaluated for kClampChunk steps at once, one step per lane
+      const int cs = s % kClampChunk;
+      if (cs == 0) {
+        __syncthreads();
+        if (g < kClampChunk && s + g < n_steps) {
+          V3 pxc, pwc;
+          Q4 pqc;
+          clamp_pose(rd, rd.t0 + (double)(steps_done + s + g + 1) * rd.dt_d, pxc, pqc, pwc);
+          float* c = cbuf[g];
+          c[0] = pxc.x; c[1] = pxc.y; c[2] = pxc.z;
+          c[3] = pqc.w; c[4] = pqc.x; c[5] = pqc.y; c[6] = pqc.z;
+          c[7] = pwc.x; c[8] = pwc.y; c[9] = pwc.z;
+        }
+        __syncthreads();
+      }
+      const float* c = cbuf[cs];
+      xc = {c[0], c[1], c[2]};
+      qc = {c[3], c[4], c[5], c[6]};
+      wc = {c[7], c[8], c[9]};
+    }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       V3 Fe = F[e];
@@ -353,20 +386,16 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
           for (int e = 0; e < E; ++e) {
             const int j = j0 + e;
             const bool is_hi = ((j & 1) == h);   // slot is the right end of segment j
-            // as right end of segment j: partner is point j
+            const float w_me = P[P_WINV][e];
+            // as right end of segment j (partner: point j) or left end of segment j+1
+            // (partner: point j+2); only one of the two is live for even E
             const V3 v_lo = (e == 0) ? vlo : Vv[e - 1];
-            const float w_lo = P[P_WINV_PREV][e];
-            // as left end of segment j+1: partner is point j+2
             const V3 v_hi = (e == E - 1) ? vhi : Vv[e + 1];
             const V3 e_next = (e == E - 1) ? enext : Ev[e + 1];
-            const float w_hi = P[P_WINV_NEXT][e];
-            const float w_me = P[P_WINV][e];
-            const V3 im_hi = impulse(Ev[e], Vv[e], v_lo, dt, P[P_LEN][e], w_me + w_lo);
-            const V3 im_lo = impulse(e_next, v_hi, Vv[e], dt, P[P_LEN_NEXT][e], w_hi + w_me);
-            const V3 newv = sel(is_hi, Vv[e] - w_me * im_hi, Vv[e] + w_me * im_lo);
-            if (e == 0) dvb = w_lo * im_hi;   // base point: left end of segment 0
-            const bool apply = ok[e] && (is_hi || P[P_LEN_NEXT][e] > 0.f);
-            nv[e] = sel(apply, newv, Vv[e]);
+            const V3 im_hi = impulse(Ev[e], Vv[e], v_lo, dt, P[P_CI][e], P[P_CIL][e]);
+            const V3 im_lo = impulse(e_next, v_hi, Vv[e], dt, P[P_CI_NEXT][e], P[P_CIL_NEXT][e]);
+            nv[e] = sel(is_hi, Vv[e] - w_me * im_hi, Vv[e] + w_me * im_lo);
+            if (e == 0) dvb = P[P_WINV_PREV][e] * im_hi;   // base point: left end of segment 0
           }
 #pragma unroll
           for (int e = 0; e < E; ++e) Vv[e] = nv[e];

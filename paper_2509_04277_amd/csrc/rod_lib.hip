@@ -182,13 +182,17 @@ void fill_rows(const rod_params& p, std::vector<float>& rows, int stride, int of
   if (p.clamp_end0) winv[0] = 0.0;
   *winv0 = winv[0];
   auto put = [&](int row, int j, double v) { rows[(size_t)row * stride + off + j] = (float)v; };
+  // distance-constraint coefficients of segment k: 1 / (dt (w_k + w_{k+1})) and l_k times it
+  auto ci = [&](int k) { return 1.0 / (p.dt * (winv[k] + winv[k + 1])); };
   for (int j = 0; j < n; ++j) {
     const Elem& e = el[j];
     put(corde::P_WINV, j, winv[j + 1]);
     put(corde::P_WINV_PREV, j, winv[j]);
-    put(corde::P_WINV_NEXT, j, j + 2 <= n ? winv[j + 2] : 0.0);
+    put(corde::P_CI, j, p.inextensible ? ci(j) : 0.0);
+    put(corde::P_CIL, j, p.inextensible ? ci(j) * e.l : 0.0);
+    put(corde::P_CI_NEXT, j, p.inextensible && j + 1 < n ? ci(j + 1) : 0.0);
+    put(corde::P_CIL_NEXT, j, p.inextensible && j + 1 < n ? ci(j + 1) * el[j + 1].l : 0.0);
     put(corde::P_LEN, j, e.l);
-    put(corde::P_LEN_NEXT, j, j + 1 < n ? el[j + 1].l : 0.0);
     put(corde::P_KS_L, j, p.inextensible ? 0.0 : e.Ks / e.l);
     put(corde::P_LKP, j, e.l * e.Kp);
     put(corde::P_IINV1, j, 1.0 / e.I1);
