@@ -57,6 +57,68 @@ def cpu_baseline(wl, n_steps):
                       "(%.1f s), one thread" % (n_steps, dt)}
 
 
+def batch_extras(R, W):
+    """c3: 4096 uneven rods, per-rod dt, 1000 steps in one launch per kernel-shape bucket,
+    against one launch per rod (same kernel) on every 32nd rod, extrapolated by rod count."""
+    import numpy as np
+    wl = W.config3()
+    rods = [(s.replace(dt=R.stable_dt(s)), st) for s, st in wl.rods]
+    b = R.RodBatch([s for s, _ in rods])
+    b.set_state_rods([st for _, st in rods])
+    tune = b.autotune(probe_steps=50, steps_per_launch=1000)
+    b.set_state_rods([st for _, st in rods])
+    b.step(wl.n_steps, wl.n_steps)
+    b.sync()
+    ms, launches = b.last_step_time()
+    buckets = b.buckets()
+    b.close()
+    elements = wl.n_elements
+    value = elements * wl.n_steps / (ms / 1e3)
+    sample = rods[::32]
+    per_rod_ms = []
+    for spec, st in sample:
+        h = R.RodBatch([spec])
+        h.set_state_rods([st])
+        h.step(wl.n_steps, wl.n_steps)
+        h.sync()
+        per_rod_ms.append(h.last_step_time()[0])
+        h.close()
+    single_ms = float(np.mean(per_rod_ms)) * len(rods)
+    achieved = BYTES_PER_ELEMENT_STEP * elements * wl.n_steps / (ms / 1e3) / 1e9
+    return {
+        "workload": "4096 rods, N log-uniform [32, 2048] (sum %d), half inextensible, per-rod dt, "
+                    "%d steps" % (elements, wl.n_steps),
+        "element_steps_per_s": value, "ms": ms, "launches": launches,
+        "buckets": [{"waves": w, "elems_per_lane": e, "rods": n} for w, e, n, _ in buckets],
+        "hbm_roofline_frac": achieved / HBM_PEAK_GBS,
+        "one_rod_per_launch": {"element_steps_per_s": elements * wl.n_steps / (single_ms / 1e3),
+                               "ms_extrapolated": single_ms, "sampled_rods": len(sample),
+                               "hbm_roofline_frac": BYTES_PER_ELEMENT_STEP * elements * wl.n_steps
+                               / (single_ms / 1e3) / 1e9 / HBM_PEAK_GBS},
+        "speedup_vs_one_rod_per_launch": single_ms / ms,
+    }
+
+
+def long_rod_extras(R, W):
+    """c2 at the lengths one workgroup holds: us/step vs steps per launch."""
+    out = []
+    for n in (1024, 2048):
+        for inext in (False, True):
+            wl = W.config2(n, inext)
+            spec, st = wl.rods[0]
+            for spl in (1, 10, 100):
+                b = R.RodBatch([spec])
+                b.set_state_rods([st])
+                b.step(200, spl)
+                b.step(1000, spl)
+                b.sync()
+                ms, launches = b.last_step_time()
+                b.close()
+                out.append({"n": n, "inextensible": inext, "steps_per_launch": spl,
+                            "us_per_step": 1e3 * ms / 1000, "element_steps_per_s": n * 1000 / (ms / 1e3)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +128,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20000)
     ap.add_argument("--shape", default="", help="W,E kernel shape (default: autotune)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (4096 rods) and long-rod measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the rods of this workload are independent and a "
@@ -146,6 +210,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic},
     }
+    if not args.no_extras:
+        out["extras"] = {"batch": batch_extras(R, W), "long_rod": long_rod_extras(R, W)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -129,13 +129,21 @@ rod_status rod_sync(rod_ctx* ctx);
 /* Simulation time [s] and number of steps taken since rod_set_state(). */
 rod_status rod_get_time(const rod_ctx* ctx, double* t, int64_t* steps);
 
-/* Select the kernel shape; waves in {1,2,4,8,16}, elems_per_lane in {1,2,4,8} as built.
- * ROD_E_UNSUPPORTED if that shape is not built or cannot hold the longest rod. */
+/* Rods of a handle are grouped into buckets that share one kernel shape (by default the
+ * smallest shape that holds each rod); rod_step() launches every bucket per chunk of steps.
+ * rod_set_tuning() puts all rods into one bucket of the given shape (waves in {1,2,4,8,16},
+ * elems_per_lane in {1,2,4,8} as built; ROD_E_UNSUPPORTED if not built or too small for the
+ * longest rod).  rod_get_tuning() reports the first bucket's shape and the summed per-step
+ * time of all buckets measured by rod_autotune(). */
 rod_status rod_set_tuning(rod_ctx* ctx, const rod_tuning* t);
 rod_status rod_get_tuning(const rod_ctx* ctx, rod_tuning* t);
 
-/* Time every built kernel shape that holds the handle's rods on probe_steps steps (state is
- * saved and restored) and keep the fastest; out (nullable) receives the choice. */
+/* Shape, measured time and rod count of bucket `bucket` (0-based); ROD_E_INVALID past the end. */
+rod_status rod_bucket_info(const rod_ctx* ctx, int32_t bucket, rod_tuning* t, int32_t* n_rods);
+
+/* Per bucket, time every built shape that holds its longest rod on probe_steps steps (the
+ * state is saved and restored, the step counter unchanged) and keep the fastest; sets the
+ * handle's steps_per_launch.  out (nullable) receives rod_get_tuning(). */
 rod_status rod_autotune(rod_ctx* ctx, int32_t probe_steps, int32_t steps_per_launch,
                         rod_tuning* out);
 

@@ -190,13 +190,14 @@ __device__ __forceinline__ void clamp_pose(const RodDev& rd, double t, V3& xc, Q
 
 template <int W, int E>
 __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
-    const RodDev* __restrict__ rods, const float* __restrict__ prm, int prm_stride,
+    const RodDev* __restrict__ rods, const int* __restrict__ rod_ids, const float* __restrict__ prm,
+    int prm_stride,
     float* __restrict__ gx, float* __restrict__ gv, float* __restrict__ gq,
     float* __restrict__ gw, const float* __restrict__ fext, const float* __restrict__ text,
     int n_steps, long long steps_done, int* __restrict__ status) {
   __shared__ Mailbox<W> mb;
   __shared__ float cbuf[kClampChunk][10];
-  const RodDev rd = rods[blockIdx.x];
+  const RodDev rd = rods[rod_ids[blockIdx.x]];
   const int g = threadIdx.x;
   const int n = rd.n;
   const int j0 = g * E;

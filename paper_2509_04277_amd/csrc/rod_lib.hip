@@ -24,8 +24,8 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-using KernelFn = void (*)(const RodDev*, const float*, int, float*, float*, float*, float*,
-                          const float*, const float*, int, long long, int*);
+using KernelFn = void (*)(const RodDev*, const int*, const float*, int, float*, float*, float*,
+                          float*, const float*, const float*, int, long long, int*);
 
 struct KernelEntry {
   int waves, elems;
@@ -78,7 +78,15 @@ struct rod_ctx {
   bool have_state = false;
   long long steps_done = 0;
   double t0 = 0.0;
-  rod_tuning tuning{};
+  // rods grouped by kernel shape; rod_ids lists the rods bucket by bucket (longest first)
+  struct Bucket {
+    int waves, elems, first, count, max_n;
+    float us_per_step;
+  };
+  std::vector<Bucket> buckets;
+  std::vector<int> rod_ids;
+  int* d_rod_ids = nullptr;
+  int steps_per_launch = 10;
   float last_ms = 0.f;
   int last_launches = 0;
   bool timed = false;
@@ -253,33 +261,72 @@ RodDev make_dev(const rod_params& p, int slot_off, int pt_off, int fr_off, doubl
   return d;
 }
 
-// Default kernel shape for the longest rod: one wavefront while it fits, then up to four
+// Default kernel shape for a rod of n elements: one wavefront while it fits, then up to four
 // (one per SIMD), then more elements per lane.
-void default_tuning(int max_n, rod_tuning* t) {
+void default_shape(int n, int* w, int* e) {
   static const int order[][2] = {{1, 1}, {1, 2}, {2, 2}, {4, 2}, {4, 4}, {8, 4}, {4, 8}};
   for (const auto& o : order) {
-    if (64 * o[0] * o[1] >= max_n) {
-      t->waves = o[0];
-      t->elems_per_lane = o[1];
-      break;
+    if (64 * o[0] * o[1] >= n) {
+      *w = o[0];
+      *e = o[1];
+      return;
     }
   }
-  t->steps_per_launch = 10;
-  t->us_per_step = 0.f;
+  *w = 4;
+  *e = 8;
 }
 
-rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it) {
-  const KernelEntry* k = find_kernel(c->tuning.waves, c->tuning.elems_per_lane);
+// Groups the rods into buckets of equal kernel shape (shape(r) gives it), longest rod first
+// within a bucket, and uploads the resulting rod order.
+template <class ShapeFn>
+rod_status make_buckets(rod_ctx* c, ShapeFn shape) {
+  std::vector<std::pair<long long, int>> key(c->n_rods);
+  for (int r = 0; r < c->n_rods; ++r) {
+    int w, e;
+    shape(r, &w, &e);
+    key[r] = {((long long)(w * 16 + e) << 32) | (long long)(0x7fffffff - c->n[r]), r};
+  }
+  std::sort(key.begin(), key.end());
+  c->buckets.clear();
+  c->rod_ids.assign(c->n_rods, 0);
+  for (int i = 0; i < c->n_rods; ++i) {
+    const int r = key[i].second;
+    int w, e;
+    shape(r, &w, &e);
+    c->rod_ids[i] = r;
+    if (c->buckets.empty() || c->buckets.back().waves != w || c->buckets.back().elems != e)
+      c->buckets.push_back({w, e, i, 0, 0, 0.f});
+    c->buckets.back().count++;
+    c->buckets.back().max_n = std::max(c->buckets.back().max_n, c->n[r]);
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->d_rod_ids, c->rod_ids.data(), sizeof(int) * c->n_rods,
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return ROD_OK;
+}
+
+rod_status launch_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long long done) {
+  const KernelEntry* k = find_kernel(b.waves, b.elems);
   if (!k) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
+  hipLaunchKernelGGL(k->fn, dim3(b.count), dim3(64 * k->waves), 0, c->stream, c->d_rods,
+                     c->d_rod_ids + b.first, c->d_prm, c->prm_stride, c->d_x, c->d_v, c->d_q,
+                     c->d_w, c->d_fext, c->d_text, ks, done, c->d_status);
+  HIP_TRY(c, hipGetLastError());
+  return ROD_OK;
+}
+
+// n_steps steps of every rod, spl steps per launch; bucket < 0: all buckets, else that one.
+rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it, int bucket = -1) {
   if (time_it) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
   int launches = 0;
   for (int done = 0; done < n_steps; done += spl) {
     const int ks = std::min(spl, n_steps - done);
-    hipLaunchKernelGGL(k->fn, dim3(c->n_rods), dim3(64 * k->waves), 0, c->stream, c->d_rods,
-                       c->d_prm, c->prm_stride, c->d_x, c->d_v, c->d_q, c->d_w, c->d_fext,
-                       c->d_text, ks, c->steps_done + done, c->d_status);
-    HIP_TRY(c, hipGetLastError());
-    ++launches;
+    for (int b = 0; b < (int)c->buckets.size(); ++b) {
+      if (bucket >= 0 && b != bucket) continue;
+      rod_status st = launch_bucket(c, c->buckets[b], ks, c->steps_done + done);
+      if (st != ROD_OK) return st;
+      ++launches;
+    }
   }
   if (time_it) HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
   c->timed = time_it;
@@ -398,7 +445,8 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
       !dmalloc((void**)&c->d_v, sizeof(float) * 3 * pts) ||
       !dmalloc((void**)&c->d_q, sizeof(float) * 4 * frames) ||
       !dmalloc((void**)&c->d_w, sizeof(float) * 3 * frames) ||
-      !dmalloc((void**)&c->d_status, sizeof(int)))
+      !dmalloc((void**)&c->d_status, sizeof(int)) ||
+      !dmalloc((void**)&c->d_rod_ids, sizeof(int) * n_rods))
     return cleanup(fail(nullptr, ROD_E_NOMEM, "device allocation failed"));
   if (any_ext && (!dmalloc((void**)&c->d_fext, sizeof(float) * fext.size()) ||
                   !dmalloc((void**)&c->d_text, sizeof(float) * text.size())))
@@ -417,7 +465,10 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
   if (e == hipSuccess) e = hipEventCreate(&c->ev0);
   if (e == hipSuccess) e = hipEventCreate(&c->ev1);
   if (e != hipSuccess) return cleanup(hip_fail(nullptr, e, "rod_create device setup"));
-  default_tuning(max_n, &c->tuning);
+  {
+    rod_status st = make_buckets(c, [&](int r, int* w, int* e) { default_shape(c->n[r], w, e); });
+    if (st != ROD_OK) return cleanup(st);
+  }
   *out = c;
   return ROD_OK;
 }
@@ -428,7 +479,7 @@ rod_status rod_destroy(rod_ctx* c) {
   else (void)hipDeviceSynchronize();
   for (void* p : {(void*)c->d_rods, (void*)c->d_prm, (void*)c->d_x, (void*)c->d_v,
                   (void*)c->d_q, (void*)c->d_w, (void*)c->d_fext, (void*)c->d_text,
-                  (void*)c->d_status})
+                  (void*)c->d_status, (void*)c->d_rod_ids})
     if (p) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -475,7 +526,7 @@ rod_status rod_step(rod_ctx* c, int32_t n_steps, int32_t steps_per_launch) {
   if (n_steps < 0) return fail(c, ROD_E_INVALID, "n_steps must be >= 0");
   if (steps_per_launch < 0) return fail(c, ROD_E_INVALID, "steps_per_launch must be >= 0");
   if (n_steps == 0) return ROD_OK;
-  const int spl = steps_per_launch > 0 ? steps_per_launch : std::max(1, c->tuning.steps_per_launch);
+  const int spl = steps_per_launch > 0 ? steps_per_launch : std::max(1, c->steps_per_launch);
   return launch_steps(c, n_steps, spl, true);
 }
 
@@ -518,13 +569,34 @@ rod_status rod_set_tuning(rod_ctx* c, const rod_tuning* t) {
   const KernelEntry* k = find_kernel(t->waves, t->elems_per_lane);
   if (!k) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
   if (64 * k->waves * k->elems < c->max_n) return fail(c, ROD_E_UNSUPPORTED, "shape cannot hold the longest rod");
-  c->tuning = *t;
+  rod_status st = make_buckets(c, [&](int, int* w, int* e) { *w = t->waves; *e = t->elems_per_lane; });
+  if (st != ROD_OK) return st;
+  c->steps_per_launch = t->steps_per_launch;
   return ROD_OK;
 }
 
 rod_status rod_get_tuning(const rod_ctx* c, rod_tuning* t) {
   if (!c || !t) return fail(nullptr, ROD_E_INVALID, "null argument");
-  *t = c->tuning;
+  const auto& b = c->buckets.front();
+  t->waves = b.waves;
+  t->elems_per_lane = b.elems;
+  t->steps_per_launch = c->steps_per_launch;
+  float us = 0.f;
+  for (const auto& bb : c->buckets) us += bb.us_per_step;
+  t->us_per_step = us;
+  return ROD_OK;
+}
+
+rod_status rod_bucket_info(const rod_ctx* c, int32_t bucket, rod_tuning* t, int32_t* n_rods) {
+  if (!c || !t || !n_rods) return fail(nullptr, ROD_E_INVALID, "null argument");
+  if (bucket < 0 || bucket >= (int)c->buckets.size())
+    return fail(const_cast<rod_ctx*>(c), ROD_E_INVALID, "bucket index out of range");
+  const auto& b = c->buckets[bucket];
+  t->waves = b.waves;
+  t->elems_per_lane = b.elems;
+  t->steps_per_launch = c->steps_per_launch;
+  t->us_per_step = b.us_per_step;
+  *n_rods = b.count;
   return ROD_OK;
 }
 
@@ -542,7 +614,7 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
   if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
   if (!c->have_state) return fail(c, ROD_E_ORDER, "rod_autotune before rod_set_state");
   if (probe_steps < 1 || steps_per_launch < 1) return fail(c, ROD_E_INVALID, "probe sizes must be >= 1");
-  // save the state, probe every shape that holds the rods, restore
+  // save the state, probe the candidate shapes of every bucket, restore
   const size_t bx = sizeof(float) * 3 * c->total_pts, bq = sizeof(float) * 4 * c->total_frames,
                bw = sizeof(float) * 3 * c->total_frames;
   float *sx = nullptr, *sv = nullptr, *sq = nullptr, *sw = nullptr;
@@ -560,33 +632,50 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
     return fail(c, ROD_E_DEVICE, "autotune state save failed");
   }
   const long long saved_steps = c->steps_done;
-  rod_tuning best = c->tuning;
-  float best_us = INFINITY;
   rod_status st = ROD_OK;
-  for (const auto& k : kKernels) {
-    if (64 * k.waves * k.elems < c->max_n) continue;
-    if (64 * k.waves * k.elems >= 4 * std::max(c->max_n, 64)) continue;  // mostly idle lanes
-    c->tuning.waves = k.waves;
-    c->tuning.elems_per_lane = k.elems;
-    float ms_best = INFINITY;
-    for (int rep = 0; rep < 2 && st == ROD_OK; ++rep) {
-      st = launch_steps(c, probe_steps, steps_per_launch, true);
-      float ms = 0;
-      int nl = 0;
-      if (st == ROD_OK) st = rod_last_step_time(c, &ms, &nl);
-      ms_best = std::min(ms_best, ms);
-    }
-    if (st != ROD_OK) break;
-    const float us = 1000.f * ms_best / probe_steps;
-    if (us < best_us) {
-      best_us = us;
-      best.waves = k.waves;
-      best.elems_per_lane = k.elems;
+  // per bucket: time every built shape that holds its longest rod without idling most lanes
+  std::vector<rod_ctx::Bucket> chosen = c->buckets;
+  for (size_t bi = 0; bi < chosen.size() && st == ROD_OK; ++bi) {
+    rod_ctx::Bucket& best = chosen[bi];
+    best.us_per_step = INFINITY;
+    for (const auto& k : kKernels) {
+      const int cap = 64 * k.waves * k.elems;
+      if (cap < best.max_n || cap >= 4 * std::max(best.max_n, 64)) continue;
+      c->buckets[bi].waves = k.waves;
+      c->buckets[bi].elems = k.elems;
+      float ms_best = INFINITY;
+      for (int rep = 0; rep < 2 && st == ROD_OK; ++rep) {
+        st = launch_steps(c, probe_steps, steps_per_launch, true, (int)bi);
+        float ms = 0;
+        int nl = 0;
+        if (st == ROD_OK) st = rod_last_step_time(c, &ms, &nl);
+        ms_best = std::min(ms_best, ms);
+      }
+      if (st != ROD_OK) break;
+      const float us = 1000.f * ms_best / probe_steps;
+      if (us < best.us_per_step) {
+        best.us_per_step = us;
+        best.waves = k.waves;
+        best.elems = k.elems;
+      }
     }
   }
-  best.steps_per_launch = steps_per_launch;
-  best.us_per_step = best_us;
-  c->tuning = best;
+  if (st == ROD_OK) {
+    // re-bucket: rods keep their bucket's chosen shape (equal shapes merge)
+    std::vector<int> shape_of(c->n_rods);
+    for (size_t bi = 0; bi < chosen.size(); ++bi)
+      for (int i = 0; i < chosen[bi].count; ++i)
+        shape_of[c->rod_ids[chosen[bi].first + i]] = chosen[bi].waves * 16 + chosen[bi].elems;
+    std::vector<std::pair<int, float>> us_of;
+    for (const auto& b : chosen) us_of.push_back({b.waves * 16 + b.elems, b.us_per_step});
+    st = make_buckets(c, [&](int r, int* w, int* e) { *w = shape_of[r] / 16; *e = shape_of[r] % 16; });
+    for (auto& b : c->buckets) {
+      b.us_per_step = 0.f;
+      for (const auto& u : us_of)
+        if (u.first == b.waves * 16 + b.elems) b.us_per_step += u.second;
+    }
+  }
+  c->steps_per_launch = steps_per_launch;
   c->steps_done = saved_steps;
   if (copy(c->d_x, sx, bx) || copy(c->d_v, sv, bx) || copy(c->d_q, sq, bq) || copy(c->d_w, sw, bw)) {
     free_all();
@@ -595,7 +684,7 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
   (void)hipStreamSynchronize(c->stream);
   free_all();
   if (st != ROD_OK) return st;
-  if (out) *out = best;
+  if (out) rod_get_tuning(c, out);
   return ROD_OK;
 }
 

@@ -66,6 +66,7 @@ _SIGS = {
     "rod_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(rod_tuning)]),
     "rod_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(rod_tuning)]),
     "rod_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(rod_tuning)]),
+    "rod_bucket_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rod_tuning), C.POINTER(C.c_int32)]),
     "rod_stable_dt": (C.c_int, [C.POINTER(rod_params), _DP]),
     "rod_last_step_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     "rod_status_str": (C.c_char_p, [C.c_int]),
@@ -272,6 +273,16 @@ class RodBatch:
     def set_tuning(self, waves: int, elems_per_lane: int, steps_per_launch: int = 10):
         t = rod_tuning(int(waves), int(elems_per_lane), int(steps_per_launch), 0.0)
         _check(lib().rod_set_tuning(self.h, C.byref(t)), self.h)
+
+    def buckets(self):
+        """[(waves, elems_per_lane, n_rods, us_per_step)] of the handle's kernel-shape buckets."""
+        out, b = [], 0
+        while True:
+            t, n = rod_tuning(), C.c_int32()
+            if lib().rod_bucket_info(self.h, b, C.byref(t), C.byref(n)) != ROD_OK:
+                return out
+            out.append((t.waves, t.elems_per_lane, n.value, t.us_per_step))
+            b += 1
 
     def autotune(self, probe_steps: int = 200, steps_per_launch: int = 10):
         t = rod_tuning()

@@ -167,6 +167,65 @@ def curved_rod(n: int, l: float, rng, sigma: float, twist_sigma: float = 0.0,
     return x, q
 
 
+def curved_rods(ns, l: float, rng, sigma: float, twist_sigma: float = 0.0, q0=Q_ALONG_X):
+    """Many curved rods at once (same construction as ``curved_rod``, vectorised over rods).
+
+    Per rod, in order: body-axis angles theta ~ N(0, sigma^2) for axes 1-2 (and N(0,
+    twist_sigma^2) for axis 3), one triple per element; rods of similar length are grown
+    together."""
+    ns = [int(n) for n in ns]
+    angles = []
+    for n in ns:
+        th = np.zeros((n, 3))
+        th[:, :2] = rng.normal(0.0, sigma, size=(n, 2))
+        if twist_sigma > 0:
+            th[:, 2] = rng.normal(0.0, twist_sigma, size=n)
+        angles.append(th)
+    out = [None] * len(ns)
+    order = np.argsort(ns, kind="stable")
+    for k in range(0, len(ns), 256):
+        idx = order[k:k + 256]
+        res = _grow_rods([angles[i] for i in idx], l, q0)
+        for i, rq in zip(idx, res):
+            out[i] = rq
+    return out
+
+
+def _grow_rods(angles, l, q0):
+    ns = [a.shape[0] for a in angles]
+    R, nmax = len(ns), max(ns)
+    th = np.zeros((R, nmax, 3))
+    for r, a in enumerate(angles):
+        th[r, :a.shape[0]] = a
+    th = np.ascontiguousarray(th.transpose(1, 0, 2))          # element-major: (nmax, R, 3)
+    ang = np.linalg.norm(th, axis=2)
+    safe = np.where(ang > 0, ang, 1.0)
+    rot = np.concatenate([np.cos(0.5 * ang)[..., None],
+                          (np.sin(0.5 * ang) / safe)[..., None] * th], axis=2)
+    q = np.zeros((nmax, R, 4))
+    x = np.zeros((nmax + 1, R, 3))
+    q[0] = np.asarray(q0, dtype=np.float64)
+    for j in range(nmax):
+        w_, x_, y_, z_ = q[j, :, 0], q[j, :, 1], q[j, :, 2], q[j, :, 3]
+        x[j + 1, :, 0] = x[j, :, 0] + l * (2 * (x_ * z_ + w_ * y_))
+        x[j + 1, :, 1] = x[j, :, 1] + l * (2 * (y_ * z_ - w_ * x_))
+        x[j + 1, :, 2] = x[j, :, 2] + l * (w_ * w_ - x_ * x_ - y_ * y_ + z_ * z_)
+        if j + 1 < nmax:
+            bw, bx, by, bz = rot[j, :, 0], rot[j, :, 1], rot[j, :, 2], rot[j, :, 3]
+            nw = w_ * bw - x_ * bx - y_ * by - z_ * bz
+            nx = w_ * bx + x_ * bw + y_ * bz - z_ * by
+            ny = w_ * by - x_ * bz + y_ * bw + z_ * bx
+            nz = w_ * bz + x_ * by - y_ * bx + z_ * bw
+            inv = 1.0 / np.sqrt(nw * nw + nx * nx + ny * ny + nz * nz)
+            q[j + 1, :, 0] = nw * inv
+            q[j + 1, :, 1] = nx * inv
+            q[j + 1, :, 2] = ny * inv
+            q[j + 1, :, 3] = nz * inv
+    x = x.transpose(1, 0, 2)
+    q = q.transpose(1, 0, 2)
+    return [(x[r, :n + 1].copy(), q[r, :n].copy()) for r, n in enumerate(ns)]
+
+
 def _zero_state(x, q) -> RodState:
     n = q.shape[0]
     return RodState(np.ascontiguousarray(x, dtype=np.float64), np.zeros((n + 1, 3)),
@@ -267,9 +326,10 @@ def config3(n_rods: int = 4096, n_min: int = 32, n_max: int = 2048) -> Workload:
     inext[rng.permutation(n_rods)[: n_rods // 2]] = True
     l = 1.0 / 64.0
     rods = []
+    geo = curved_rods(ns, l, rng, sigma=0.05)
     for r in range(n_rods):
         n = int(ns[r])
-        x, q = curved_rod(n, l, rng, sigma=0.05)
+        x, q = geo[r]
         spec = RodSpec(n=n, inextensible=bool(inext[r]), n_iter=10 if inext[r] else 0,
                        clamp=True, dt=0.0, gravity=(0.0, 0.0, -9.81), damp_lin=0.1,
                        damp_ang=0.1, poisson=0.5, density=1000.0, seg_len=np.full(n, l),
@@ -287,8 +347,7 @@ def config4(n_rods: int = 256, n: int = 256, dt: Optional[float] = None) -> Work
     if dt is None:
         dt = load_dt_golden()["c0"]["dt"]
     rods = []
-    for _ in range(n_rods):
-        x, q = curved_rod(n, l, rng, sigma=0.05, twist_sigma=0.05)
+    for x, q in curved_rods([n] * n_rods, l, rng, sigma=0.05, twist_sigma=0.05):
         spec = RodSpec(n=n, inextensible=True, n_iter=10, clamp=True, dt=float(dt),
                        clamp_x0=tuple(x[0]), clamp_q0=tuple(q[0]), **_c0_material(n, n * l))
         rods.append((spec, _zero_state(x, q)))

@@ -266,3 +266,29 @@ def test_autotune_keeps_state_and_picks_a_shape():
     assert 64 * t["waves"] * t["elems_per_lane"] >= 512 and t["us_per_step"] > 0
     for a, c in zip(before, after):
         assert np.array_equal(a, c)
+
+
+def test_batch_buckets_and_autotune_vs_oracle(oracle):
+    """Uneven batch (per-rod dt from the stability rule, mixed variants) in several kernel-shape
+    buckets, before and after autotuning, against the oracle rod by rod."""
+    wl = W.config3(n_rods=48, n_min=8, n_max=700)
+    rods = []
+    for spec, st in wl.rods:
+        spec = spec.replace(dt=R.stable_dt(spec))
+        rods.append((spec, st))
+    b = R.RodBatch([s for s, _ in rods])
+    bk = b.buckets()
+    _say("batch of 48 rods (N 8..700) in buckets %s" % (bk,))
+    assert len(bk) >= 3
+    b.set_state_rods([st for _, st in rods])
+    b.step(150, 50)
+    got = b.get_state_rods()
+    b.set_state_rods([st for _, st in rods])
+    t = b.autotune(probe_steps=20, steps_per_launch=50)
+    _say("after autotune: %s, buckets %s" % (t, b.buckets()))
+    b.step(150, 0)
+    got2 = b.get_state_rods()
+    b.close()
+    ref = run_oracle(oracle, rods, 150)
+    compare(got, ref, [s for s, _ in rods], "batch")
+    compare(got2, ref, [s for s, _ in rods], "batch-tuned")
