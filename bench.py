@@ -99,6 +99,38 @@ def batch_extras(R, W):
     }
 
 
+def adjoint_extras(R, W):
+    """c4: 256 rods x 256 elements, 400 steps: plain forward vs checkpointed adjoint."""
+    import numpy as np
+    import torch
+    wl = W.config4()
+    rods = [(s.replace(dt=R.stable_dt(s)), st) for s, st in wl.rods]
+    n_steps, ckpt = wl.n_steps, 20
+    b = R.RodBatch([s for s, _ in rods])
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, 1e3 * (time.perf_counter() - t)
+
+    b.set_state_rods([st for _, st in rods])
+    b.step(n_steps, ckpt)                      # warm-up
+    b.set_state_rods([st for _, st in rods])
+    _, fwd_ms = timed(lambda: (b.step(n_steps, ckpt), b.sync()))
+    b.set_state_rods([st for _, st in rods])
+    tips, afwd_ms = timed(lambda: b.adjoint_forward(n_steps, ckpt))
+    rng = np.random.default_rng(4)
+    dtips = rng.normal(0, 1.0, tips.shape).astype(np.float32)
+    _, bwd_ms = timed(lambda: b.adjoint_backward(dtips))
+    b.close()
+    return {"workload": "256 rods x 256 elements, inextensible, %d steps, checkpoints every %d"
+                        % (n_steps, ckpt),
+            "forward_ms": fwd_ms, "adjoint_forward_ms": afwd_ms, "adjoint_backward_ms": bwd_ms,
+            "adjoint_over_forward": (afwd_ms + bwd_ms) / fwd_ms}
+
+
 def long_rod_extras(R, W):
     """c2 at the lengths one workgroup holds: us/step vs steps per launch."""
     out = []
@@ -211,7 +243,8 @@ def main():
                      "traffic": traffic},
     }
     if not args.no_extras:
-        out["extras"] = {"batch": batch_extras(R, W), "long_rod": long_rod_extras(R, W)}
+        out["extras"] = {"batch": batch_extras(R, W), "long_rod": long_rod_extras(R, W),
+                         "adjoint": adjoint_extras(R, W)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(out), flush=True)

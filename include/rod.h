@@ -155,6 +155,33 @@ rod_status rod_stable_dt(const rod_params* p, double* dt_out);
  * [ms], and the number of kernel launches it made. */
 rod_status rod_last_step_time(rod_ctx* ctx, float* ms, int32_t* launches);
 
+/* ---- Adjoint (reverse-mode gradients of a rollout) ------------------------------------
+ * Differentiates the rollout of rod_step() with respect to the per-rod multipliers of the
+ * bend stiffness (K_1 = K_2 of eq. (3)) and twist stiffness (K_3), and the initial state.
+ * The loss is any function of the tip trajectory tip(s) = x_N after step s; the caller passes
+ * dL/dtip.  Supported: at most 10 constraint iterations, rods of at most 512 elements. */
+
+/* Set the stiffness multipliers m_b[r], m_t[r] >= 0 (host arrays of n_rods; default 1).
+ * Invalidates a recorded adjoint rollout. */
+rod_status rod_set_stiffness_mult(rod_ctx* ctx, const float* bend, const float* twist);
+
+/* Advance every rod by n_steps steps from the current state (like rod_step), recording a
+ * checkpoint of the whole state every ckpt_every steps (ckpt_every = 1 stores every step and
+ * needs no recomputation), and write the tip trajectory to tips (n_rods x n_steps x 3, rod
+ * major; nullable).  Device memory: ceil(n_steps / ckpt_every) + ckpt_every states. */
+rod_status rod_adjoint_forward(rod_ctx* ctx, int32_t n_steps, int32_t ckpt_every, float* tips,
+                               int32_t on_device);
+
+/* Reverse pass of the last rod_adjoint_forward() (ROD_E_ORDER without one).  dl_dtips:
+ * n_rods x n_steps x 3.  Outputs (any may be NULL): dL/dm_b, dL/dm_t (n_rods each), and
+ * dL/d(initial state) in the state layout; dl_dq is the gradient with respect to the four
+ * quaternion components as stored (not projected on the unit sphere).  Each checkpoint
+ * segment is recomputed forward, then reversed by one kernel launch per bucket.  Synchronises
+ * the stream; ROD_E_UNSTABLE if a non-finite adjoint appears. */
+rod_status rod_adjoint_backward(rod_ctx* ctx, const float* dl_dtips, float* dl_dbend,
+                                float* dl_dtwist, float* dl_dx, float* dl_dv, float* dl_dq,
+                                float* dl_dw, int32_t on_device);
+
 const char* rod_status_str(rod_status s);
 /* Detail of the last error on this handle (never NULL; "" if none; NULL ctx = global). */
 const char* rod_last_error(const rod_ctx* ctx);

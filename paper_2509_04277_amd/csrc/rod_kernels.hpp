@@ -67,6 +67,8 @@ struct RodDev {
   float ctw;          // twist amplitude
   float cx0[3], camp[3], caxis[3];
   float cq0[4];
+  float mult_bend;    // learnable multipliers of the bend (K_1 = K_2) and twist (K_3) stiffness
+  float mult_twist;
   double dt_d, t0, omega, ph_x, ph_t;
 };
 
@@ -86,6 +88,9 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b) {
 }
 __device__ __forceinline__ V3 sel(bool c, V3 a, V3 b) {
   return {c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
+}
+__device__ __forceinline__ Q4 sel4(bool c, Q4 a, Q4 b) {
+  return {c ? a.w : b.w, c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
 }
 
 // DPP whole-wavefront shifts; the lane without a source receives 0.
@@ -147,13 +152,23 @@ __device__ __forceinline__ void exchange(const float (&mine_hi)[KL], float (&lo)
 // predicted positions p = x + dt v, returned as lambda n:
 //   d = p_hi - p_lo = e + dt (v_hi - v_lo),  C = |d| - l,  lambda = C / (dt (w_lo + w_hi)),
 //   lambda n = ci (1 - l / |d|) d   with ci = 1 / (dt (w_lo + w_hi)), cil = ci l.
-// Both owners of a segment call it with identical operands, so both apply the same impulse.
+// Both owners of a segment compute it from identical operands, so both apply the same impulse.
 // A missing segment has ci = cil = 0 and yields 0 (the max keeps the reciprocal finite).
-__device__ __forceinline__ V3 impulse(V3 e, V3 vhi, V3 vlo, float dt, float ci, float cil) {
-  const V3 d = e + dt * (vhi - vlo);
+__device__ __forceinline__ V3 impulse_d(V3 d, float ci, float cil) {
   const float il = rsqrtf(fmaxf(dot(d, d), 1e-30f));
   const float s = ci - cil * il;
   return s * d;
+}
+
+// q <- normalize(q + dt/2 q (x) (0, omega)).
+__device__ __forceinline__ Q4 advance_quat(Q4 q, V3 o, float dt) {
+  const float hdt = 0.5f * dt;
+  const Q4 qq = {q.w + hdt * (-q.x * o.x - q.y * o.y - q.z * o.z),
+                 q.x + hdt * (q.w * o.x + q.y * o.z - q.z * o.y),
+                 q.y + hdt * (q.w * o.y - q.x * o.z + q.z * o.x),
+                 q.z + hdt * (q.w * o.z + q.x * o.y - q.y * o.x)};
+  const float inrm = rsqrtf(qq.w * qq.w + qq.x * qq.x + qq.y * qq.y + qq.z * qq.z);
+  return {qq.w * inrm, qq.x * inrm, qq.y * inrm, qq.z * inrm};
 }
 
 __device__ __forceinline__ Q4 qmul(Q4 a, Q4 b) {
@@ -188,79 +203,126 @@ __device__ __forceinline__ void clamp_pose(const RodDev& rd, double t, V3& xc, Q
   wc = a + qc.w * tt + cross(u, tt);
 }
 
-template <int W, int E>
-__global__ __launch_bounds__(64 * W) void rod_resident_kernel(
-    const RodDev* __restrict__ rods, const int* __restrict__ rod_ids, const float* __restrict__ prm,
-    int prm_stride,
-    float* __restrict__ gx, float* __restrict__ gv, float* __restrict__ gq,
-    float* __restrict__ gw, const float* __restrict__ fext, const float* __restrict__ text,
-    int n_steps, long long steps_done, int* __restrict__ status) {
-  __shared__ Mailbox<W> mb;
-  __shared__ float cbuf[kClampChunk][10];
-  const RodDev rd = rods[rod_ids[blockIdx.x]];
-  const int g = threadIdx.x;
-  const int n = rd.n;
-  const int j0 = g * E;
-  const float dt = rd.dt;
-  const bool inext = rd.n_iter > 0;
-  const V3 grav = {rd.g[0], rd.g[1], rd.g[2]};
-  int par = 0;
 
-  // ---- load state (once per launch)
+// Registers of one lane of a rod's workgroup: E slots (frame j, point j+1) plus, in lane 0,
+// the base point.  The member functions are the phases of one time step; the forward kernel
+// and the adjoint kernel call the same functions, so a recomputed step is bit-identical.
+template <int W, int E>
+struct RodLane {
   V3 X[E], Vv[E], Om[E];
   Q4 Qf[E];
   float P[P_NROWS][E];
   bool ok[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int j = j0 + e;
-    ok[e] = j < n;
-    if (ok[e]) {
-      const float* px = gx + 3 * (rd.pt_off + j + 1);
-      const float* pv = gv + 3 * (rd.pt_off + j + 1);
-      const float* pq = gq + 4 * (rd.fr_off + j);
-      const float* pw = gw + 3 * (rd.fr_off + j);
-      X[e] = {px[0], px[1], px[2]};
-      Vv[e] = {pv[0], pv[1], pv[2]};
-      Qf[e] = {pq[0], pq[1], pq[2], pq[3]};
-      Om[e] = {pw[0], pw[1], pw[2]};
-#pragma unroll
-      for (int r = 0; r < P_NROWS; ++r) P[r][e] = prm[r * prm_stride + rd.slot_off + j];
-    } else {
-      X[e] = {0.f, 0.f, 0.f};
-      Vv[e] = {0.f, 0.f, 0.f};
-      Qf[e] = {1.f, 0.f, 0.f, 0.f};
-      Om[e] = {0.f, 0.f, 0.f};
-#pragma unroll
-      for (int r = 0; r < P_NROWS; ++r) P[r][e] = 0.f;
-    }
-  }
-  V3 bx = {0.f, 0.f, 0.f}, bv = {0.f, 0.f, 0.f};  // base point (lane 0)
-  if (g == 0) {
-    const float* px = gx + 3 * rd.pt_off;
-    const float* pv = gv + 3 * rd.pt_off;
-    bx = {px[0], px[1], px[2]};
-    bv = {pv[0], pv[1], pv[2]};
-  }
-  V3 xc = {rd.cx0[0], rd.cx0[1], rd.cx0[2]}, wc = {0.f, 0.f, 0.f};
-  Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
+  V3 bx, bv;
+  int g, j0, n;
+  float dt;
 
-  for (int s = 0; s < n_steps; ++s) {
-    // ---------------- A: left point x (from below), right frame q (from above)
-    V3 xl;
-    Q4 qn;
-    {
-      float mh[3] = {X[E - 1].x, X[E - 1].y, X[E - 1].z};
-      float ml[4] = {Qf[0].w, Qf[0].x, Qf[0].y, Qf[0].z};
-      float lo[3], hi[4];
-      exchange<W, 3, 4>(mh, lo, ml, hi, mb, par);
-      xl = {lo[0], lo[1], lo[2]};
-      if (g == 0) xl = bx;
-      qn = {hi[0], hi[1], hi[2], hi[3]};
+  __device__ __forceinline__ void load_params(const RodDev& rd, const float* __restrict__ prm,
+                                              int prm_stride) {
+    g = threadIdx.x;
+    n = rd.n;
+    j0 = g * E;
+    dt = rd.dt;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = j0 + e;
+      ok[e] = j < n;
+#pragma unroll
+      for (int r = 0; r < P_NROWS; ++r) P[r][e] = ok[e] ? prm[r * prm_stride + rd.slot_off + j] : 0.f;
+      // learnable stiffness multipliers scale the joint coefficients
+      P[P_C1][e] *= rd.mult_bend;
+      P[P_D0][e] *= rd.mult_bend;
+      P[P_D1][e] *= rd.mult_bend;
+      P[P_C3][e] *= rd.mult_twist;
+      P[P_D2][e] *= rd.mult_twist;
     }
-    // ---------------- F: segment forces and joint torques, accumulated per slot
-    V3 F[E], T[E], Ev[E];
-    V3 fs_first = {0.f, 0.f, 0.f}, tn_prev = {0.f, 0.f, 0.f};
+  }
+
+  __device__ __forceinline__ void load_state(const RodDev& rd, const float* __restrict__ gx,
+                                             const float* __restrict__ gv,
+                                             const float* __restrict__ gq,
+                                             const float* __restrict__ gw) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = j0 + e;
+      if (ok[e]) {
+        const float* px = gx + 3 * (rd.pt_off + j + 1);
+        const float* pv = gv + 3 * (rd.pt_off + j + 1);
+        const float* pq = gq + 4 * (rd.fr_off + j);
+        const float* pw = gw + 3 * (rd.fr_off + j);
+        X[e] = {px[0], px[1], px[2]};
+        Vv[e] = {pv[0], pv[1], pv[2]};
+        Qf[e] = {pq[0], pq[1], pq[2], pq[3]};
+        Om[e] = {pw[0], pw[1], pw[2]};
+      } else {
+        X[e] = {0.f, 0.f, 0.f};
+        Vv[e] = {0.f, 0.f, 0.f};
+        Qf[e] = {1.f, 0.f, 0.f, 0.f};
+        Om[e] = {0.f, 0.f, 0.f};
+      }
+    }
+    bx = {0.f, 0.f, 0.f};
+    bv = {0.f, 0.f, 0.f};
+    if (g == 0) {
+      const float* px = gx + 3 * rd.pt_off;
+      const float* pv = gv + 3 * rd.pt_off;
+      bx = {px[0], px[1], px[2]};
+      bv = {pv[0], pv[1], pv[2]};
+    }
+  }
+
+  // Writes the state; returns a sum of the written values (non-finite if any value is).
+  __device__ __forceinline__ float store_state(const RodDev& rd, float* __restrict__ gx,
+                                               float* __restrict__ gv, float* __restrict__ gq,
+                                               float* __restrict__ gw) const {
+    float chk = 0.f;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = j0 + e;
+      if (ok[e]) {
+        float* px = gx + 3 * (rd.pt_off + j + 1);
+        float* pv = gv + 3 * (rd.pt_off + j + 1);
+        float* pq = gq + 4 * (rd.fr_off + j);
+        float* pw = gw + 3 * (rd.fr_off + j);
+        px[0] = X[e].x; px[1] = X[e].y; px[2] = X[e].z;
+        pv[0] = Vv[e].x; pv[1] = Vv[e].y; pv[2] = Vv[e].z;
+        pq[0] = Qf[e].w; pq[1] = Qf[e].x; pq[2] = Qf[e].y; pq[3] = Qf[e].z;
+        pw[0] = Om[e].x; pw[1] = Om[e].y; pw[2] = Om[e].z;
+        chk += X[e].x + X[e].y + X[e].z + Vv[e].x + Vv[e].y + Vv[e].z + Qf[e].w + Om[e].x +
+               Om[e].y + Om[e].z;
+      }
+    }
+    if (g == 0) {
+      float* px = gx + 3 * rd.pt_off;
+      float* pv = gv + 3 * rd.pt_off;
+      px[0] = bx.x; px[1] = bx.y; px[2] = bx.z;
+      pv[0] = bv.x; pv[1] = bv.y; pv[2] = bv.z;
+      chk += bx.x + bx.y + bx.z + bv.x + bv.y + bv.z;
+    }
+    return chk;
+  }
+
+  // A: x of each slot's left point (from the lane below; the base point for lane 0) and q of
+  // the right frame (from the lane above).
+  __device__ __forceinline__ void exchange_a(Mailbox<W>& mb, int& par, V3& xl, Q4& qn) const {
+    float mh[3] = {X[E - 1].x, X[E - 1].y, X[E - 1].z};
+    float ml[4] = {Qf[0].w, Qf[0].x, Qf[0].y, Qf[0].z};
+    float lo[3], hi[4];
+    exchange<W, 3, 4>(mh, lo, ml, hi, mb, par);
+    xl = {lo[0], lo[1], lo[2]};
+    if (g == 0) xl = bx;
+    qn = {hi[0], hi[1], hi[2], hi[3]};
+  }
+
+  // F: segment forces (stretch eq. (2), penalty eq. (8)) and joint torques (eq. (3) with the
+  // discrete Darboux vector of eqs. (5)-(6)), accumulated per slot; then exchange B.
+  // F[e]: force on point j+1; T[e]: body torque on frame j; Ev[e]: segment vector e_j;
+  // fs0: force of the lane's first segment on its left point (negated); enext: e_{j+1} of the
+  // last slot.
+  __device__ __forceinline__ void forces(Mailbox<W>& mb, int& par, V3 xl, Q4 qn, V3 (&F)[E],
+                                         V3 (&T)[E], V3 (&Ev)[E], V3& fs0, V3& enext) const {
+    V3 tn_prev = {0.f, 0.f, 0.f};
+    fs0 = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const V3 xa = (e == 0) ? xl : X[e - 1];
@@ -278,61 +340,42 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
       const V3 d3 = {2.f * (xz + wy), 2.f * (yz - wx), ww - xx - yy + zz};
       const float lkp = P[P_LKP][e];
       const float td3 = dot(t, d3);
-      V3 f = (lkp * il) * (d3 - td3 * t);                       // penalty, eq. (8)
+      V3 f = (lkp * il) * (d3 - td3 * t);                        // penalty, eq. (8)
       const float len = len2 * il;
-      f = f - (P[P_KS_L][e] * (len - P[P_LEN][e])) * t;         // stretch, eq. (2)
-      f = sel(ok[e], f, V3{0.f, 0.f, 0.f});                     // force on point j+1
+      f = f - (P[P_KS_L][e] * (len - P[P_LEN][e])) * t;          // stretch, eq. (2)
+      f = sel(ok[e], f, V3{0.f, 0.f, 0.f});                      // force on point j+1
       const V3 tpen = {-lkp * dot(d2, t), lkp * dot(d1, t), 0.f};  // l K_p e_3 x R^T t
-      // joint j: frames j and j+1 (eq. (6) with q' = (q_{j+1} - q_j) / lbar)
       const Q4 qb = (e == E - 1) ? qn : Qf[e + 1];
       const Q4 dq = {qb.w - q.w, qb.x - q.x, qb.y - q.y, qb.z - q.z};
       const float rw = q.w * qb.w + q.x * qb.x + q.y * qb.y + q.z * qb.z;
       const V3 va = {q.x, q.y, q.z}, dv = {dq.x, dq.y, dq.z};
-      const V3 rv = q.w * dv - dq.w * va - cross(va, dv);       // vec(conj(q_j) (x) q_{j+1})
+      const V3 rv = q.w * dv - dq.w * va - cross(va, dv);        // vec(conj(q_j) (x) q_{j+1})
       const V3 m = {P[P_C1][e] * rv.x - P[P_D0][e], P[P_C1][e] * rv.y - P[P_D1][e],
-                    P[P_C3][e] * rv.z - P[P_D2][e]};            // K (u - uhat)
+                    P[P_C3][e] * rv.z - P[P_D2][e]};             // K (u - uhat)
       const V3 rxm = cross(rv, m);
       const V3 tj = sel(ok[e], rw * m + rxm, V3{0.f, 0.f, 0.f});  // on frame j
       const V3 tn = sel(ok[e], rxm - rw * m, V3{0.f, 0.f, 0.f});  // on frame j+1
       F[e] = f;
-      if (e == 0) fs_first = f;
-      else F[e - 1] = F[e - 1] - f;                             // reaction on point j
+      if (e == 0) fs0 = f;
+      else F[e - 1] = F[e - 1] - f;                              // reaction on point j
       T[e] = (tpen + tj) + tn_prev;
       tn_prev = tn;
     }
-    // ---------------- B: next segment's force, previous joint's torque, next segment vector
-    V3 enext;
-    {
-      float mh[3] = {tn_prev.x, tn_prev.y, tn_prev.z};
-      float ml[6] = {fs_first.x, fs_first.y, fs_first.z, Ev[0].x, Ev[0].y, Ev[0].z};
-      float lo[3], hi[6];
-      exchange<W, 3, 6>(mh, lo, ml, hi, mb, par);
-      T[0] = T[0] + V3{lo[0], lo[1], lo[2]};
-      F[E - 1] = F[E - 1] - V3{hi[0], hi[1], hi[2]};
-      enext = {hi[3], hi[4], hi[5]};
-    }
-    // ---------------- V: integrate forces and torques
-    if (rd.driven && rd.clamp) {
-      // prescribed clamp pose: evaluated for kClampChunk steps at once, one step per lane
-      const int cs = s % kClampChunk;
-      if (cs == 0) {
-        __syncthreads();
-        if (g < kClampChunk && s + g < n_steps) {
-          V3 pxc, pwc;
-          Q4 pqc;
-          clamp_pose(rd, rd.t0 + (double)(steps_done + s + g + 1) * rd.dt_d, pxc, pqc, pwc);
-          float* c = cbuf[g];
-          c[0] = pxc.x; c[1] = pxc.y; c[2] = pxc.z;
-          c[3] = pqc.w; c[4] = pqc.x; c[5] = pqc.y; c[6] = pqc.z;
-          c[7] = pwc.x; c[8] = pwc.y; c[9] = pwc.z;
-        }
-        __syncthreads();
-      }
-      const float* c = cbuf[cs];
-      xc = {c[0], c[1], c[2]};
-      qc = {c[3], c[4], c[5], c[6]};
-      wc = {c[7], c[8], c[9]};
-    }
+    float mh[3] = {tn_prev.x, tn_prev.y, tn_prev.z};
+    float ml[6] = {fs0.x, fs0.y, fs0.z, Ev[0].x, Ev[0].y, Ev[0].z};
+    float lo[3], hi[6];
+    exchange<W, 3, 6>(mh, lo, ml, hi, mb, par);
+    T[0] = T[0] + V3{lo[0], lo[1], lo[2]};
+    F[E - 1] = F[E - 1] - V3{hi[0], hi[1], hi[2]};
+    enext = {hi[3], hi[4], hi[5]};
+  }
+
+  // V: integrate forces (points as particles) and torques (frames as rigid bodies).
+  __device__ __forceinline__ void integrate_forces(const RodDev& rd, const V3 (&F)[E],
+                                                   const V3 (&T)[E], V3 fs0, V3 xc, V3 wc,
+                                                   const float* __restrict__ fext,
+                                                   const float* __restrict__ text) {
+    const V3 grav = {rd.g[0], rd.g[1], rd.g[2]};
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       V3 Fe = F[e];
@@ -357,7 +400,7 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
         bv = (1.0f / dt) * (xc - bx);
         Om[0] = wc;
       } else {
-        V3 Fb = V3{0.f, 0.f, 0.f} - fs_first;
+        V3 Fb = V3{0.f, 0.f, 0.f} - fs0;
         if (rd.has_ext) {
           const float* pf = fext + 3 * rd.pt_off;
           Fb = Fb + V3{pf[0], pf[1], pf[2]};
@@ -365,58 +408,54 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
         bv = bv + dt * (rd.winv0 * Fb + grav - rd.damp_lin * bv);
       }
     }
-    // ---------------- C: distance impulses, red-black over segments
-    if (inext) {
-      for (int it = 0; it < rd.n_iter; ++it) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const bool cross_lanes = (E % 2 == 1) || (h == 0);
-          V3 vlo = {0.f, 0.f, 0.f}, vhi = {0.f, 0.f, 0.f};
-          if (cross_lanes) {
-            float mh[3] = {Vv[E - 1].x, Vv[E - 1].y, Vv[E - 1].z};
-            float ml[3] = {Vv[0].x, Vv[0].y, Vv[0].z};
-            float lo[3], hi[3];
-            exchange<W, 3, 3>(mh, lo, ml, hi, mb, par);
-            vlo = {lo[0], lo[1], lo[2]};
-            vhi = {hi[0], hi[1], hi[2]};
-            if (g == 0) vlo = bv;
-          }
-          V3 dvb = {0.f, 0.f, 0.f};
-          V3 nv[E];
-#pragma unroll
-          for (int e = 0; e < E; ++e) {
-            const int j = j0 + e;
-            const bool is_hi = ((j & 1) == h);   // slot is the right end of segment j
-            const float w_me = P[P_WINV][e];
-            // as right end of segment j (partner: point j) or left end of segment j+1
-            // (partner: point j+2); only one of the two is live for even E
-            const V3 v_lo = (e == 0) ? vlo : Vv[e - 1];
-            const V3 v_hi = (e == E - 1) ? vhi : Vv[e + 1];
-            const V3 e_next = (e == E - 1) ? enext : Ev[e + 1];
-            const V3 im_hi = impulse(Ev[e], Vv[e], v_lo, dt, P[P_CI][e], P[P_CIL][e]);
-            const V3 im_lo = impulse(e_next, v_hi, Vv[e], dt, P[P_CI_NEXT][e], P[P_CIL_NEXT][e]);
-            nv[e] = sel(is_hi, Vv[e] - w_me * im_hi, Vv[e] + w_me * im_lo);
-            if (e == 0) dvb = P[P_WINV_PREV][e] * im_hi;   // base point: left end of segment 0
-          }
-#pragma unroll
-          for (int e = 0; e < E; ++e) Vv[e] = nv[e];
-          if (g == 0 && h == 0 && !rd.clamp) bv = bv + dvb;
-        }
-      }
+  }
+
+  // One red-black half-sweep h of the distance impulses.  If dsnap is given, the segment
+  // vector d of the slot's segment in this half-sweep is saved (for the adjoint).
+  __device__ __forceinline__ void half_sweep(const RodDev& rd, Mailbox<W>& mb, int& par, int h,
+                                             const V3 (&Ev)[E], V3 enext, V3* dsnap) {
+    const bool cross_lanes = (E % 2 == 1) || (h == 0);
+    V3 vlo = {0.f, 0.f, 0.f}, vhi = {0.f, 0.f, 0.f};
+    if (cross_lanes) {
+      float mh[3] = {Vv[E - 1].x, Vv[E - 1].y, Vv[E - 1].z};
+      float ml[3] = {Vv[0].x, Vv[0].y, Vv[0].z};
+      float lo[3], hi[3];
+      exchange<W, 3, 3>(mh, lo, ml, hi, mb, par);
+      vlo = {lo[0], lo[1], lo[2]};
+      vhi = {hi[0], hi[1], hi[2]};
+      if (g == 0) vlo = bv;
     }
-    // ---------------- X: integrate velocities, renormalise
+    V3 dvb = {0.f, 0.f, 0.f};
+    V3 nv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = j0 + e;
+      const bool is_hi = ((j & 1) == h);   // slot is the right end of segment j
+      const float w_me = P[P_WINV][e];
+      // as right end of segment j (partner: point j) or left end of segment j+1
+      // (partner: point j+2); only one of the two is live for even E
+      const V3 v_lo = (e == 0) ? vlo : Vv[e - 1];
+      const V3 v_hi = (e == E - 1) ? vhi : Vv[e + 1];
+      const V3 e_next = (e == E - 1) ? enext : Ev[e + 1];
+      const V3 d_hi = Ev[e] + dt * (Vv[e] - v_lo);
+      const V3 d_lo = e_next + dt * (v_hi - Vv[e]);
+      const V3 im_hi = impulse_d(d_hi, P[P_CI][e], P[P_CIL][e]);
+      const V3 im_lo = impulse_d(d_lo, P[P_CI_NEXT][e], P[P_CIL_NEXT][e]);
+      nv[e] = sel(is_hi, Vv[e] - w_me * im_hi, Vv[e] + w_me * im_lo);
+      if (dsnap) dsnap[e] = sel(is_hi, d_hi, d_lo);
+      if (e == 0) dvb = P[P_WINV_PREV][e] * im_hi;   // base point: left end of segment 0
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) Vv[e] = nv[e];
+    if (g == 0 && h == 0 && !rd.clamp) bv = bv + dvb;
+  }
+
+  // X: integrate velocities (semi-implicit Euler), renormalise, impose the clamp pose.
+  __device__ __forceinline__ void integrate_velocities(const RodDev& rd, V3 xc, Q4 qc) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       X[e] = X[e] + dt * Vv[e];
-      const Q4 q = Qf[e];
-      const V3 o = Om[e];
-      const float hdt = 0.5f * dt;
-      Q4 qq = {q.w + hdt * (-q.x * o.x - q.y * o.y - q.z * o.z),
-               q.x + hdt * (q.w * o.x + q.y * o.z - q.z * o.y),
-               q.y + hdt * (q.w * o.y - q.x * o.z + q.z * o.x),
-               q.z + hdt * (q.w * o.z + q.x * o.y - q.y * o.x)};
-      const float inrm = rsqrtf(qq.w * qq.w + qq.x * qq.x + qq.y * qq.y + qq.z * qq.z);
-      Qf[e] = {qq.w * inrm, qq.x * inrm, qq.y * inrm, qq.z * inrm};
+      Qf[e] = advance_quat(Qf[e], Om[e], dt);
     }
     if (g == 0) {
       if (rd.clamp) {
@@ -427,32 +466,87 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
       }
     }
   }
+};
 
-  // ---- store state (once per launch), latch non-finite values
-  float chk = 0.f;
+// Prescribed clamp pose of step s (global step index steps_done + s), evaluated kClampChunk
+// steps at a time, one step per lane, into LDS.  Must be reached by every thread.
+template <int W>
+__device__ __forceinline__ void clamp_for_step(const RodDev& rd, float (*cbuf)[10], int s,
+                                               int n_steps, long long steps_done, V3& xc, Q4& qc,
+                                               V3& wc) {
+  if (!(rd.driven && rd.clamp)) return;
+  const int cs = s % kClampChunk;
+  if (cs == 0) {
+    __syncthreads();
+    const int g = threadIdx.x;
+    if (g < kClampChunk && s + g < n_steps) {
+      V3 pxc, pwc;
+      Q4 pqc;
+      clamp_pose(rd, rd.t0 + (double)(steps_done + s + g + 1) * rd.dt_d, pxc, pqc, pwc);
+      float* c = cbuf[g];
+      c[0] = pxc.x; c[1] = pxc.y; c[2] = pxc.z;
+      c[3] = pqc.w; c[4] = pqc.x; c[5] = pqc.y; c[6] = pqc.z;
+      c[7] = pwc.x; c[8] = pwc.y; c[9] = pwc.z;
+    }
+    __syncthreads();
+  }
+  const float* c = cbuf[cs];
+  xc = {c[0], c[1], c[2]};
+  qc = {c[3], c[4], c[5], c[6]};
+  wc = {c[7], c[8], c[9]};
+}
+
+// Forward kernel: steps one rod per workgroup n_steps times with the state in registers.
+// traj (nullable): the whole-handle state at the start of every step s is written to
+// traj + s * traj_stride, laid out as [x (3 n_pts) | v (3 n_pts) | q (4 n_frames) | w (3 n_frames)].
+// tips (nullable): x_N after step s goes to tips[(rod * tip_steps + steps_done - tip_base + s) * 3].
+template <int W, int E>
+__global__ __launch_bounds__(64 * W) void rod_resident_kernel(
+    const RodDev* __restrict__ rods, const int* __restrict__ rod_ids, const float* __restrict__ prm,
+    int prm_stride, float* __restrict__ gx, float* __restrict__ gv, float* __restrict__ gq,
+    float* __restrict__ gw, const float* __restrict__ fext, const float* __restrict__ text,
+    int n_steps, long long steps_done, int* __restrict__ status, float* __restrict__ traj,
+    long long traj_stride, int n_pts, int n_frames, float* __restrict__ tips, int tip_steps,
+    long long tip_base) {
+  __shared__ Mailbox<W> mb;
+  __shared__ float cbuf[kClampChunk][10];
+  const int rod = rod_ids[blockIdx.x];
+  const RodDev rd = rods[rod];
+  RodLane<W, E> L;
+  L.load_params(rd, prm, prm_stride);
+  L.load_state(rd, gx, gv, gq, gw);
+  int par = 0;
+  V3 xc = {rd.cx0[0], rd.cx0[1], rd.cx0[2]}, wc = {0.f, 0.f, 0.f};
+  Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
+  const int tip_lane = (rd.n - 1) / E, tip_e = (rd.n - 1) % E;
+
+  for (int s = 0; s < n_steps; ++s) {
+    if (traj) {
+      float* base = traj + (long long)s * traj_stride;
+      L.store_state(rd, base, base + 3 * n_pts, base + 6 * n_pts, base + 6 * n_pts + 4 * n_frames);
+    }
+    V3 xl;
+    Q4 qn;
+    L.exchange_a(mb, par, xl, qn);
+    V3 F[E], T[E], Ev[E], fs0, enext;
+    L.forces(mb, par, xl, qn, F, T, Ev, fs0, enext);
+    clamp_for_step<W>(rd, cbuf, s, n_steps, steps_done, xc, qc, wc);
+    L.integrate_forces(rd, F, T, fs0, xc, wc, fext, text);
+    for (int it = 0; it < rd.n_iter; ++it) {
+      L.half_sweep(rd, mb, par, 0, Ev, enext, nullptr);
+      L.half_sweep(rd, mb, par, 1, Ev, enext, nullptr);
+    }
+    L.integrate_velocities(rd, xc, qc);
+    if (tips && (int)threadIdx.x == tip_lane) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int j = j0 + e;
-    if (ok[e]) {
-      float* px = gx + 3 * (rd.pt_off + j + 1);
-      float* pv = gv + 3 * (rd.pt_off + j + 1);
-      float* pq = gq + 4 * (rd.fr_off + j);
-      float* pw = gw + 3 * (rd.fr_off + j);
-      px[0] = X[e].x; px[1] = X[e].y; px[2] = X[e].z;
-      pv[0] = Vv[e].x; pv[1] = Vv[e].y; pv[2] = Vv[e].z;
-      pq[0] = Qf[e].w; pq[1] = Qf[e].x; pq[2] = Qf[e].y; pq[3] = Qf[e].z;
-      pw[0] = Om[e].x; pw[1] = Om[e].y; pw[2] = Om[e].z;
-      chk += X[e].x + X[e].y + X[e].z + Vv[e].x + Vv[e].y + Vv[e].z + Qf[e].w + Om[e].x +
-             Om[e].y + Om[e].z;
+      for (int e = 0; e < E; ++e)
+        if (e == tip_e) {
+          float* pt = tips + ((long long)rod * tip_steps + steps_done - tip_base + s) * 3;
+          pt[0] = L.X[e].x; pt[1] = L.X[e].y; pt[2] = L.X[e].z;
+        }
     }
   }
-  if (g == 0) {
-    float* px = gx + 3 * rd.pt_off;
-    float* pv = gv + 3 * rd.pt_off;
-    px[0] = bx.x; px[1] = bx.y; px[2] = bx.z;
-    pv[0] = bv.x; pv[1] = bv.y; pv[2] = bv.z;
-    chk += bx.x + bx.y + bx.z + bv.x + bv.y + bv.z;
-  }
+  const float chk = L.store_state(rd, gx, gv, gq, gw);
   if (!__builtin_isfinite(chk)) atomicOr(status, 1);
 }
 

@@ -16,7 +16,7 @@
 #include <vector>
 
 #include "../../include/rod.h"
-#include "rod_kernels.hpp"
+#include "rod_adjoint.hpp"
 
 using corde::RodDev;
 
@@ -25,7 +25,25 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 
 using KernelFn = void (*)(const RodDev*, const int*, const float*, int, float*, float*, float*,
-                          float*, const float*, const float*, int, long long, int*);
+                          float*, const float*, const float*, int, long long, int*, float*,
+                          long long, int, int, float*, int, long long);
+using AdjointFn = void (*)(const RodDev*, const int*, const float*, int, const float*, long long,
+                           int, int, int, long long, int, const float*, int, float*, float*,
+                           float*, float*, float*, const float*, const float*, int*);
+
+struct AdjointEntry {
+  int waves, elems;
+  AdjointFn fn;
+};
+
+// Adjoint kernel shapes (one or two elements per lane: the reverse keeps 60 snapshot values
+// per element in registers).
+const AdjointEntry kAdjoints[] = {
+    {1, 1, corde::rod_adjoint_kernel<1, 1>}, {1, 2, corde::rod_adjoint_kernel<1, 2>},
+    {2, 1, corde::rod_adjoint_kernel<2, 1>}, {2, 2, corde::rod_adjoint_kernel<2, 2>},
+    {4, 1, corde::rod_adjoint_kernel<4, 1>}, {4, 2, corde::rod_adjoint_kernel<4, 2>},
+    {8, 1, corde::rod_adjoint_kernel<8, 1>},
+};
 
 struct KernelEntry {
   int waves, elems;
@@ -87,6 +105,17 @@ struct rod_ctx {
   std::vector<int> rod_ids;
   int* d_rod_ids = nullptr;
   int steps_per_launch = 10;
+  // adjoint rollout (rod_adjoint_forward / rod_adjoint_backward)
+  bool adj_ready = false;
+  int adj_steps = 0, adj_ckpt = 0, adj_nckpt = 0;
+  long long adj_step0 = 0;
+  float* d_ckpt = nullptr;   // adj_nckpt whole-handle states (checkpoints)
+  float* d_traj = nullptr;   // states at the start of each step of a segment (or of all steps)
+  float* d_tips = nullptr;   // n_rods x adj_steps x 3
+  float* d_dtips = nullptr;
+  float* d_adj = nullptr;    // adjoint state, whole-handle state layout
+  float* d_work = nullptr;   // recompute state
+  float* d_gmult = nullptr;  // n_rods x adj_steps x 2: per-step multiplier gradients
   float last_ms = 0.f;
   int last_launches = 0;
   bool timed = false;
@@ -196,6 +225,7 @@ void fill_rows(const rod_params& p, std::vector<float>& rows, int stride, int of
     const Elem& e = el[j];
     put(corde::P_WINV, j, winv[j + 1]);
     put(corde::P_WINV_PREV, j, winv[j]);
+    put(corde::P_WINV_NEXT, j, j + 2 <= n ? winv[j + 2] : 0.0);
     put(corde::P_CI, j, p.inextensible ? ci(j) : 0.0);
     put(corde::P_CIL, j, p.inextensible ? ci(j) * e.l : 0.0);
     put(corde::P_CI_NEXT, j, p.inextensible && j + 1 < n ? ci(j + 1) : 0.0);
@@ -258,6 +288,8 @@ RodDev make_dev(const rod_params& p, int slot_off, int pt_off, int fr_off, doubl
   d.ph_x = p.clamp_phase_x;
   d.ph_t = p.clamp_phase_twist;
   d.t0 = 0.0;
+  d.mult_bend = 1.f;
+  d.mult_twist = 1.f;
   return d;
 }
 
@@ -310,7 +342,8 @@ rod_status launch_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long long
   if (!k) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
   hipLaunchKernelGGL(k->fn, dim3(b.count), dim3(64 * k->waves), 0, c->stream, c->d_rods,
                      c->d_rod_ids + b.first, c->d_prm, c->prm_stride, c->d_x, c->d_v, c->d_q,
-                     c->d_w, c->d_fext, c->d_text, ks, done, c->d_status);
+                     c->d_w, c->d_fext, c->d_text, ks, done, c->d_status, nullptr, 0LL,
+                     c->total_pts, c->total_frames, nullptr, 0, 0LL);
   HIP_TRY(c, hipGetLastError());
   return ROD_OK;
 }
@@ -332,6 +365,44 @@ rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it, int buck
   c->timed = time_it;
   c->last_launches = launches;
   c->steps_done += n_steps;
+  return ROD_OK;
+}
+
+// Adjoint shape for a bucket: the bucket's forward shape when it is built (an even number of
+// elements per lane halves the constraint work), else the smallest one that holds the rods.
+const AdjointEntry* adjoint_shape(int max_n, int waves = 0, int elems = 0) {
+  for (const auto& a : kAdjoints)
+    if (a.waves == waves && a.elems == elems && 64 * a.waves * a.elems >= max_n) return &a;
+  for (const auto& a : kAdjoints)
+    if (64 * a.waves * a.elems >= max_n) return &a;
+  return nullptr;
+}
+
+// floats of one whole-handle state: x, v (3 per point), q (4 per frame), w (3 per frame)
+size_t state_floats(const rod_ctx* c) { return (size_t)6 * c->total_pts + (size_t)7 * c->total_frames; }
+
+void free_adjoint(rod_ctx* c) {
+  for (float** p : {&c->d_ckpt, &c->d_traj, &c->d_tips, &c->d_dtips, &c->d_adj, &c->d_work,
+                    &c->d_gmult}) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+  c->adj_ready = false;
+}
+
+// Launches the forward kernel of every bucket on the given state arrays.
+rod_status launch_forward_on(rod_ctx* c, float* x, float* v, float* q, float* w, int ks,
+                             long long step, float* traj, float* tips, long long tip_base) {
+  const long long S = (long long)state_floats(c);
+  for (const auto& b : c->buckets) {
+    const KernelEntry* k = find_kernel(b.waves, b.elems);
+    if (!k) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
+    hipLaunchKernelGGL(k->fn, dim3(b.count), dim3(64 * k->waves), 0, c->stream, c->d_rods,
+                       c->d_rod_ids + b.first, c->d_prm, c->prm_stride, x, v, q, w, c->d_fext,
+                       c->d_text, ks, step, c->d_status, traj, S, c->total_pts, c->total_frames,
+                       tips, c->adj_steps, tip_base);
+    HIP_TRY(c, hipGetLastError());
+  }
   return ROD_OK;
 }
 
@@ -413,7 +484,7 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
   c->total_pts = (int)pts;
   c->total_frames = (int)frames;
   c->prm_stride = (int)frames;
-  std::vector<float> rows((size_t)corde::P_NROWS * c->prm_stride, 0.f);
+  std::vector<float> rows((size_t)(corde::P_NROWS + 1) * c->prm_stride, 0.f);
   std::vector<float> fext, text;
   bool any_ext = false;
   for (int r = 0; r < n_rods; ++r) any_ext = any_ext || params[r].f_ext || params[r].tau_ext;
@@ -479,7 +550,9 @@ rod_status rod_destroy(rod_ctx* c) {
   else (void)hipDeviceSynchronize();
   for (void* p : {(void*)c->d_rods, (void*)c->d_prm, (void*)c->d_x, (void*)c->d_v,
                   (void*)c->d_q, (void*)c->d_w, (void*)c->d_fext, (void*)c->d_text,
-                  (void*)c->d_status, (void*)c->d_rod_ids})
+                  (void*)c->d_status, (void*)c->d_rod_ids, (void*)c->d_ckpt, (void*)c->d_traj,
+                  (void*)c->d_tips, (void*)c->d_dtips, (void*)c->d_adj, (void*)c->d_work,
+                  (void*)c->d_gmult})
     if (p) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -685,6 +758,141 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
   free_all();
   if (st != ROD_OK) return st;
   if (out) rod_get_tuning(c, out);
+  return ROD_OK;
+}
+
+rod_status rod_set_stiffness_mult(rod_ctx* c, const float* bend, const float* twist) {
+  if (!c || !bend || !twist) return fail(c, ROD_E_INVALID, "null argument");
+  for (int r = 0; r < c->n_rods; ++r)
+    if (!(std::isfinite(bend[r]) && bend[r] >= 0.f && std::isfinite(twist[r]) && twist[r] >= 0.f))
+      return fail(c, ROD_E_INVALID, "multipliers must be finite and >= 0");
+  for (int r = 0; r < c->n_rods; ++r) {
+    c->rods[r].mult_bend = bend[r];
+    c->rods[r].mult_twist = twist[r];
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->d_rods, c->rods.data(), sizeof(RodDev) * c->n_rods,
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->adj_ready = false;
+  return ROD_OK;
+}
+
+rod_status rod_adjoint_forward(rod_ctx* c, int32_t n_steps, int32_t ckpt_every, float* tips,
+                               int32_t on_device) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (!c->have_state) return fail(c, ROD_E_ORDER, "rod_adjoint_forward before rod_set_state");
+  if (n_steps < 1 || ckpt_every < 1) return fail(c, ROD_E_INVALID, "n_steps and ckpt_every must be >= 1");
+  for (const auto& r : c->rods)
+    if (r.n_iter > corde::kAdjointMaxIter)
+      return fail(c, ROD_E_UNSUPPORTED, "adjoint supports at most 10 constraint iterations");
+  for (const auto& b : c->buckets)
+    if (!adjoint_shape(b.max_n)) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
+  free_adjoint(c);
+  const size_t S = state_floats(c);
+  const int ck = std::min(ckpt_every, n_steps);
+  const int nck = (n_steps + ck - 1) / ck;
+  const size_t traj_states = ck == 1 ? (size_t)n_steps : (size_t)ck;
+  auto dm = [&](float** p, size_t n) { return hipMalloc((void**)p, sizeof(float) * std::max<size_t>(n, 1)) == hipSuccess; };
+  if (!dm(&c->d_ckpt, ck == 1 ? 1 : nck * S) || !dm(&c->d_traj, traj_states * S) ||
+      !dm(&c->d_tips, (size_t)3 * c->n_rods * n_steps) || !dm(&c->d_dtips, (size_t)3 * c->n_rods * n_steps) ||
+      !dm(&c->d_adj, S) || !dm(&c->d_work, S) ||
+      !dm(&c->d_gmult, 2 * (size_t)c->n_rods * n_steps)) {
+    free_adjoint(c);
+    return fail(c, ROD_E_NOMEM, "adjoint buffers do not fit");
+  }
+  c->adj_steps = n_steps;
+  c->adj_ckpt = ck;
+  c->adj_nckpt = nck;
+  c->adj_step0 = c->steps_done;
+  const size_t P3 = (size_t)3 * c->total_pts, F4 = (size_t)4 * c->total_frames;
+  for (int seg = 0; seg < nck; ++seg) {
+    const int len = std::min(ck, n_steps - seg * ck);
+    float* traj = nullptr;
+    if (ck == 1) {
+      traj = c->d_traj + (size_t)seg * S;
+    } else {
+      float* dst = c->d_ckpt + (size_t)seg * S;
+      HIP_TRY(c, hipMemcpyAsync(dst, c->d_x, sizeof(float) * P3, hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(c, hipMemcpyAsync(dst + P3, c->d_v, sizeof(float) * P3, hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(c, hipMemcpyAsync(dst + 2 * P3, c->d_q, sizeof(float) * F4, hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(c, hipMemcpyAsync(dst + 2 * P3 + F4, c->d_w, sizeof(float) * 3 * c->total_frames,
+                                hipMemcpyDeviceToDevice, c->stream));
+    }
+    rod_status st = launch_forward_on(c, c->d_x, c->d_v, c->d_q, c->d_w, len, c->steps_done, traj,
+                                      c->d_tips, c->adj_step0);
+    if (st != ROD_OK) return st;
+    c->steps_done += len;
+  }
+  if (tips) {
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIP_TRY(c, hipMemcpyAsync(tips, c->d_tips, sizeof(float) * 3 * c->n_rods * n_steps, k, c->stream));
+    if (!on_device) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  c->adj_ready = true;
+  return ROD_OK;
+}
+
+rod_status rod_adjoint_backward(rod_ctx* c, const float* dl_dtips, float* dl_dbend,
+                                float* dl_dtwist, float* dl_dx, float* dl_dv, float* dl_dq,
+                                float* dl_dw, int32_t on_device) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (!c->adj_ready) return fail(c, ROD_E_ORDER, "rod_adjoint_backward without rod_adjoint_forward");
+  if (!dl_dtips) return fail(c, ROD_E_INVALID, "null dL/dtip");
+  const size_t S = state_floats(c);
+  const size_t P3 = (size_t)3 * c->total_pts, F4 = (size_t)4 * c->total_frames;
+  const hipMemcpyKind kin = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HIP_TRY(c, hipMemcpyAsync(c->d_dtips, dl_dtips, sizeof(float) * 3 * c->n_rods * c->adj_steps, kin, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_adj, 0, sizeof(float) * S, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_gmult, 0, sizeof(float) * 2 * c->n_rods * c->adj_steps, c->stream));
+  const long long Sl = (long long)S;
+  for (int seg = c->adj_nckpt - 1; seg >= 0; --seg) {
+    const int len = std::min(c->adj_ckpt, c->adj_steps - seg * c->adj_ckpt);
+    const long long tstep0 = c->adj_step0 + (long long)seg * c->adj_ckpt;
+    const float* traj;
+    if (c->adj_ckpt == 1) {
+      traj = c->d_traj + (size_t)seg * S;
+    } else {
+      // recompute the segment from its checkpoint, storing the state at every step start
+      HIP_TRY(c, hipMemcpyAsync(c->d_work, c->d_ckpt + (size_t)seg * S, sizeof(float) * S,
+                                hipMemcpyDeviceToDevice, c->stream));
+      rod_status st = launch_forward_on(c, c->d_work, c->d_work + P3, c->d_work + 2 * P3,
+                                        c->d_work + 2 * P3 + F4, len, tstep0, c->d_traj, nullptr, 0);
+      if (st != ROD_OK) return st;
+      traj = c->d_traj;
+    }
+    for (const auto& b : c->buckets) {
+      const AdjointEntry* a = adjoint_shape(b.max_n, b.waves, b.elems);
+      hipLaunchKernelGGL(a->fn, dim3(b.count), dim3(64 * a->waves), 0, c->stream, c->d_rods,
+                         c->d_rod_ids + b.first, c->d_prm, c->prm_stride, traj, Sl, c->total_pts,
+                         c->total_frames, len, tstep0, seg * c->adj_ckpt, c->d_dtips, c->adj_steps,
+                         c->d_adj, c->d_adj + P3, c->d_adj + 2 * P3, c->d_adj + 2 * P3 + F4,
+                         c->d_gmult, c->d_fext, c->d_text, c->d_status);
+      HIP_TRY(c, hipGetLastError());
+    }
+  }
+  const hipMemcpyKind kout = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (dl_dx) HIP_TRY(c, hipMemcpyAsync(dl_dx, c->d_adj, sizeof(float) * P3, kout, c->stream));
+  if (dl_dv) HIP_TRY(c, hipMemcpyAsync(dl_dv, c->d_adj + P3, sizeof(float) * P3, kout, c->stream));
+  if (dl_dq) HIP_TRY(c, hipMemcpyAsync(dl_dq, c->d_adj + 2 * P3, sizeof(float) * F4, kout, c->stream));
+  if (dl_dw) HIP_TRY(c, hipMemcpyAsync(dl_dw, c->d_adj + 2 * P3 + F4, sizeof(float) * 3 * c->total_frames, kout, c->stream));
+  std::vector<float> gm(2 * (size_t)c->n_rods * c->adj_steps);
+  HIP_TRY(c, hipMemcpyAsync(gm.data(), c->d_gmult, sizeof(float) * gm.size(), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<float> gb(c->n_rods), gt(c->n_rods);
+  for (int r = 0; r < c->n_rods; ++r) {   // fixed summation order over the steps, in FP64
+    double sb = 0.0, st = 0.0;
+    for (int s = 0; s < c->adj_steps; ++s) {
+      sb += gm[((size_t)r * c->adj_steps + s) * 2];
+      st += gm[((size_t)r * c->adj_steps + s) * 2 + 1];
+    }
+    gb[r] = (float)sb;
+    gt[r] = (float)st;
+  }
+  if (dl_dbend) HIP_TRY(c, hipMemcpy(dl_dbend, gb.data(), sizeof(float) * c->n_rods, on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+  if (dl_dtwist) HIP_TRY(c, hipMemcpy(dl_dtwist, gt.data(), sizeof(float) * c->n_rods, on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+  int stt = 0;
+  HIP_TRY(c, hipMemcpy(&stt, c->d_status, sizeof(int), hipMemcpyDeviceToHost));
+  if (stt) return fail(c, ROD_E_UNSTABLE, "non-finite value in the adjoint");
   return ROD_OK;
 }
 

@@ -69,6 +69,9 @@ _SIGS = {
     "rod_bucket_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rod_tuning), C.POINTER(C.c_int32)]),
     "rod_stable_dt": (C.c_int, [C.POINTER(rod_params), _DP]),
     "rod_last_step_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
+    "rod_set_stiffness_mult": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "rod_adjoint_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _FP, C.c_int32]),
+    "rod_adjoint_backward": (C.c_int, [C.c_void_p, _FP, _FP, _FP, _FP, _FP, _FP, _FP, C.c_int32]),
     "rod_status_str": (C.c_char_p, [C.c_int]),
     "rod_last_error": (C.c_char_p, [C.c_void_p]),
 }
@@ -262,6 +265,38 @@ class RodBatch:
         _check(lib().rod_set_clamp(self.h, int(rod), a.ctypes.data_as(_DP), b.ctypes.data_as(_DP)),
                self.h)
 
+    # ---- adjoint --------------------------------------------------------------------
+    def set_stiffness_mult(self, bend, twist):
+        b = np.ascontiguousarray(np.asarray(bend, dtype=np.float32).ravel())
+        t = np.ascontiguousarray(np.asarray(twist, dtype=np.float32).ravel())
+        if b.size != len(self.n) or t.size != len(self.n):
+            raise ValueError("one multiplier per rod expected")
+        _check(lib().rod_set_stiffness_mult(self.h, b.ctypes.data_as(C.POINTER(C.c_float)),
+                                            t.ctypes.data_as(C.POINTER(C.c_float))), self.h)
+
+    def adjoint_forward(self, n_steps: int, ckpt_every: int = 20, tips=None):
+        """Rollout with checkpoints; returns the tip trajectory (rods, n_steps, 3)."""
+        if tips is None:
+            tips = np.empty((len(self.n), int(n_steps), 3), np.float32)
+        p, dev = _ptr(tips)
+        _check(lib().rod_adjoint_forward(self.h, int(n_steps), int(ckpt_every), C.c_void_p(p),
+                                         dev), self.h)
+        return tips
+
+    def adjoint_backward(self, dl_dtips, out=None):
+        """Gradients for dL/dtip: dict bend, twist (per rod) and x, v, q, w (state layout)."""
+        if out is None:
+            out = dict(bend=np.empty(len(self.n), np.float32), twist=np.empty(len(self.n), np.float32),
+                       x=np.empty(3 * self.n_points, np.float32), v=np.empty(3 * self.n_points, np.float32),
+                       q=np.empty(4 * self.n_frames, np.float32), w=np.empty(3 * self.n_frames, np.float32))
+        pd, dev = _ptr(dl_dtips)
+        ptrs = [_ptr(out[k]) for k in ("bend", "twist", "x", "v", "q", "w")]
+        if any(d != dev for _, d in ptrs):
+            raise ValueError("dL/dtip and the outputs must be on the same side")
+        _check(lib().rod_adjoint_backward(self.h, C.c_void_p(pd), *[C.c_void_p(p) for p, _ in ptrs],
+                                          dev), self.h)
+        return out
+
     # ---- kernel shape ---------------------------------------------------------------
     @property
     def tuning(self):
@@ -298,3 +333,38 @@ def header_functions(path: Optional[str] = None):
     path = path or os.path.join(os.path.dirname(HERE), "include", "rod.h")
     src = open(path).read()
     return sorted(set(re.findall(r"^\s*(?:rod_status|const char\*)\s+(rod_\w+)\s*\(", src, re.M)))
+
+
+def rollout_function():
+    """torch.autograd.Function over the library's adjoint: tips = RodRollout.apply(batch,
+    bend_mult, twist_mult, x0, v0, q0, w0, n_steps, ckpt_every).
+
+    Inputs are device float32 tensors: bend_mult, twist_mult (n_rods,), initial state in the
+    handle's layout.  Output: tip trajectory (n_rods, n_steps, 3).  backward() runs
+    rod_adjoint_backward and returns gradients for the multipliers and the initial state."""
+    import torch
+
+    class RodRollout(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, batch, bend, twist, x0, v0, q0, w0, n_steps, ckpt_every):
+            batch.set_stiffness_mult(bend.detach().cpu().numpy(), twist.detach().cpu().numpy())
+            batch.set_state(x0.detach().contiguous(), v0.detach().contiguous(),
+                            q0.detach().contiguous(), w0.detach().contiguous())
+            tips = torch.empty((len(batch.n), int(n_steps), 3), dtype=torch.float32, device=x0.device)
+            batch.adjoint_forward(int(n_steps), int(ckpt_every), tips)
+            torch.cuda.synchronize(x0.device)
+            ctx.batch = batch
+            return tips
+
+        @staticmethod
+        def backward(ctx, grad_tips):
+            b = ctx.batch
+            dev = grad_tips.device
+            out = dict(bend=torch.empty(len(b.n), device=dev), twist=torch.empty(len(b.n), device=dev),
+                       x=torch.empty(3 * b.n_points, device=dev), v=torch.empty(3 * b.n_points, device=dev),
+                       q=torch.empty(4 * b.n_frames, device=dev), w=torch.empty(3 * b.n_frames, device=dev))
+            b.adjoint_backward(grad_tips.contiguous().float(), out)
+            torch.cuda.synchronize(dev)
+            return (None, out["bend"], out["twist"], out["x"], out["v"], out["q"], out["w"], None, None)
+
+    return RodRollout

@@ -20,7 +20,8 @@ the anatomy meshes, which are not available):
   c3  4096 rods, N log-uniform in [32, 2048], E log-uniform in [1e6, 1e10] Pa, r uniform in
       [0.1, 1] mm, element length 1/64 m, half extensible / half inextensible, each with its
       own dt (left 0 here: set from the stability rule by the caller).
-  c4  256 rods x 256 elements, inextensible, c0 material, L = 4 m, curvature and twist noise.
+  c4  256 rods x 256 elements, inextensible, c0 material, L = 4 m, curvature and twist noise,
+      dt from the stability rule (left 0 here), 400 steps, checkpoints every 20 steps.
 """
 from __future__ import annotations
 
@@ -340,12 +341,12 @@ def config3(n_rods: int = 4096, n_min: int = 32, n_max: int = 2048) -> Workload:
                     rods, n_steps=1000, steps_per_launch=1000)
 
 
-def config4(n_rods: int = 256, n: int = 256, dt: Optional[float] = None) -> Workload:
-    """Adjoint workload: curved and twisted inextensible rods of c0 material, L = 4 m."""
+def config4(n_rods: int = 256, n: int = 256, dt: float = 0.0) -> Workload:
+    """Adjoint workload: curved and twisted inextensible rods of c0 material, L = 4 m.
+
+    dt = 0 means "set from the stability rule by the caller" (as for c3)."""
     rng = np.random.default_rng(4)
     l = 4.0 / n
-    if dt is None:
-        dt = load_dt_golden()["c0"]["dt"]
     rods = []
     for x, q in curved_rods([n] * n_rods, l, rng, sigma=0.05, twist_sigma=0.05):
         spec = RodSpec(n=n, inextensible=True, n_iter=10, clamp=True, dt=float(dt),
