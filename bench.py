@@ -132,22 +132,31 @@ def adjoint_extras(R, W):
 
 
 def long_rod_extras(R, W):
-    """c2 at the lengths one workgroup holds: us/step vs steps per launch."""
+    """c2: us/step vs rod length and steps per launch.  Rods up to 2048 elements run in one
+    workgroup ("single") and, for comparison, split over several ("chunked"); longer rods are
+    always chunked (one workgroup per ~500 elements, halo exchange through HBM every step)."""
     out = []
-    for n in (1024, 2048):
+    for n in (1024, 2048, 4096, 16384, 65536):
         for inext in (False, True):
             wl = W.config2(n, inext)
             spec, st = wl.rods[0]
-            for spl in (1, 10, 100):
-                b = R.RodBatch([spec])
-                b.set_state_rods([st])
-                b.step(200, spl)
-                b.step(1000, spl)
-                b.sync()
-                ms, launches = b.last_step_time()
-                b.close()
-                out.append({"n": n, "inextensible": inext, "steps_per_launch": spl,
-                            "us_per_step": 1e3 * ms / 1000, "element_steps_per_s": n * 1000 / (ms / 1e3)})
+            for mode in (("single", "chunked") if n <= 2048 else ("chunked",)):
+                for spl in (1, 10, 100):
+                    b = R.RodBatch([spec])
+                    if mode == "chunked" and n <= 2048:
+                        b.set_chunking(n - 1)
+                    b.set_state_rods([st])
+                    b.step(200, spl)
+                    b.step(1000, spl)
+                    b.sync()
+                    ms, launches = b.last_step_time()
+                    b.close()
+                    out.append({"n": n, "inextensible": inext, "mode": mode,
+                                "steps_per_launch": spl, "us_per_step": 1e3 * ms / 1000,
+                                "element_steps_per_s": n * 1000 / (ms / 1e3)})
+                    print("[bench] long rod n=%d %s %s k=%d: %.2f us/step" % (
+                        n, "inext" if inext else "ext", mode, spl, 1e3 * ms / 1000),
+                        file=sys.stderr, flush=True)
     return out
 
 

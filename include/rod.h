@@ -50,7 +50,8 @@ typedef enum rod_status {
     ROD_E_DEVICE = -3,      /* a HIP call failed */
     ROD_E_UNSTABLE = -4,    /* a kernel saw a non-finite state value */
     ROD_E_ORDER = -5,       /* call made in the wrong order */
-    ROD_E_UNSUPPORTED = -6  /* valid request this build cannot run (e.g. rod too long) */
+    ROD_E_UNSUPPORTED = -6, /* valid request this build cannot run */
+    ROD_E_TIMEOUT = -7      /* a long-rod workgroup waited too long for a neighbour */
 } rod_status;
 
 /* Description of one rod, SI units.  Arrays are read during rod_create() only. */
@@ -100,8 +101,12 @@ typedef struct rod_tuning {
 /* Create a handle for n_rods rods described by params[0..n_rods-1] on the current HIP device,
  * enqueuing work on hip_stream (a hipStream_t, NULL = default).  Derives all per-element
  * coefficients (masses, inertias, stiffnesses of eqs. (2), (3), (8)) in FP64 on the host.
+ * Rods of up to 2048 elements are stepped by one workgroup each; longer rods are split into
+ * chunks of about 500 elements, one workgroup per chunk, that exchange halos once per step
+ * (all chunks of a handle must be resident on the device at once: ROD_E_UNSUPPORTED if not,
+ * and for any rod longer than 131072 elements).
  * The state is zero until rod_set_state().  Errors: INVALID (bad sizes/values), NOMEM,
- * DEVICE, UNSUPPORTED (a rod longer than the single-workgroup kernel holds). */
+ * DEVICE, UNSUPPORTED. */
 rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream, rod_ctx** out);
 
 /* Free all device and host memory of the handle (after finishing its stream's work). */
@@ -131,15 +136,29 @@ rod_status rod_get_time(const rod_ctx* ctx, double* t, int64_t* steps);
 
 /* Rods of a handle are grouped into buckets that share one kernel shape (by default the
  * smallest shape that holds each rod); rod_step() launches every bucket per chunk of steps.
- * rod_set_tuning() puts all rods into one bucket of the given shape (waves in {1,2,4,8,16},
- * elems_per_lane in {1,2,4,8} as built; ROD_E_UNSUPPORTED if not built or too small for the
- * longest rod).  rod_get_tuning() reports the first bucket's shape and the summed per-step
- * time of all buckets measured by rod_autotune(). */
+ * Rods longer than 2048 elements form one last bucket stepped by the chunked kernel (shape
+ * 4 waves x 2 elements per lane per chunk), which tuning does not change.
+ * rod_set_tuning() puts all other rods into one bucket of the given shape (waves in
+ * {1,2,4,8,16}, elems_per_lane in {1,2,4,8} as built; ROD_E_UNSUPPORTED if not built or too
+ * small for the longest of them).  rod_get_tuning() reports the first bucket's shape and the
+ * summed per-step time of the buckets measured by rod_autotune(). */
 rod_status rod_set_tuning(rod_ctx* ctx, const rod_tuning* t);
 rod_status rod_get_tuning(const rod_ctx* ctx, rod_tuning* t);
 
-/* Shape, measured time and rod count of bucket `bucket` (0-based); ROD_E_INVALID past the end. */
+/* Shape, measured time (0 if not measured) and rod count of bucket `bucket` (0-based; the
+ * long-rod bucket, if any, is last); ROD_E_INVALID past the end. */
 rod_status rod_bucket_info(const rod_ctx* ctx, int32_t bucket, rod_tuning* t, int32_t* n_rods);
+
+/* Step every rod longer than min_elements (1..2048; default 2048) with the chunked long-rod
+ * kernel: one workgroup per chunk, neighbouring chunks trading H = 2 n_constraint_iters + 4
+ * (rounded up to even) halo elements per side once per step, so a rod of up to 2048
+ * elements can also be spread over several compute units.  chunk_elements sets the owned
+ * elements per chunk (0 = the most a 512-element window holds, 512 - 2 H; otherwise clamped to
+ * [2 H + 2, 512 - 2 H]; chunk sizes are even and about equal).  The other rods return to their
+ * default shapes (as after rod_create).  A held adjoint rollout is dropped if any rod ends up
+ * chunked.  Errors: INVALID, UNSUPPORTED (too many constraint iterations to split a rod, or
+ * more chunks than the device holds at once; the default split is then restored), DEVICE. */
+rod_status rod_set_chunking(rod_ctx* ctx, int32_t min_elements, int32_t chunk_elements);
 
 /* Per bucket, time every built shape that holds its longest rod on probe_steps steps (the
  * state is saved and restored, the step counter unchanged) and keep the fastest; sets the

@@ -11,6 +11,10 @@ DEPS = SOURCES + [os.path.join(HERE, "csrc", "rod_kernels.hpp"),
                   os.path.join(REPO, "include", "rod.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+         # multiply-adds fuse only within one source expression, so an element's arithmetic
+         # does not depend on the kernel shape or the code around it: every kernel shape and
+         # the chunked long-rod kernel produce bitwise-identical states
+         "-ffp-contract=on",
          # packed FP32 VALU forms are kept out of the generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(REPO, "include")]

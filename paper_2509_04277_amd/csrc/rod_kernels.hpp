@@ -215,26 +215,43 @@ struct RodLane {
   bool ok[E];
   V3 bx, bv;
   int g, j0, n;
+  int off, nloc;   // window of the rod held by this workgroup: slots [off, off + nloc)
+  bool ghost;      // off > 0: lane 0's "base point" is point `off`, held fixed (a halo edge)
   float dt;
 
+  // Loads the coefficients of slots [off, off + nloc) (the whole rod by default).  A window
+  // that does not reach the rod's end drops its last slot's outward segment and joint; one
+  // that does not start at the rod's base sees point `off` as a fixed (infinite-mass) point.
+  // Both only perturb slots within one step's dependency radius of the window edges.
   __device__ __forceinline__ void load_params(const RodDev& rd, const float* __restrict__ prm,
-                                              int prm_stride) {
+                                              int prm_stride, int win_off = 0, int win_n = -1) {
     g = threadIdx.x;
     n = rd.n;
+    off = win_off;
+    nloc = win_n < 0 ? rd.n : win_n;
+    ghost = off > 0;
     j0 = g * E;
     dt = rd.dt;
+    const bool cut_right = off + nloc < n;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int j = j0 + e;
-      ok[e] = j < n;
+      const int jl = j0 + e;
+      ok[e] = jl < nloc;
 #pragma unroll
-      for (int r = 0; r < P_NROWS; ++r) P[r][e] = ok[e] ? prm[r * prm_stride + rd.slot_off + j] : 0.f;
+      for (int r = 0; r < P_NROWS; ++r)
+        P[r][e] = ok[e] ? prm[r * prm_stride + rd.slot_off + off + jl] : 0.f;
       // learnable stiffness multipliers scale the joint coefficients
       P[P_C1][e] *= rd.mult_bend;
       P[P_D0][e] *= rd.mult_bend;
       P[P_D1][e] *= rd.mult_bend;
       P[P_C3][e] *= rd.mult_twist;
       P[P_D2][e] *= rd.mult_twist;
+      if (ghost && jl == 0) P[P_WINV_PREV][e] = 0.f;
+      if (cut_right && jl == nloc - 1) {
+        P[P_CI_NEXT][e] = 0.f;
+        P[P_CIL_NEXT][e] = 0.f;
+        P[P_C1][e] = P[P_C3][e] = P[P_D0][e] = P[P_D1][e] = P[P_D2][e] = 0.f;
+      }
     }
   }
 
@@ -244,7 +261,7 @@ struct RodLane {
                                              const float* __restrict__ gw) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int j = j0 + e;
+      const int j = off + j0 + e;
       if (ok[e]) {
         const float* px = gx + 3 * (rd.pt_off + j + 1);
         const float* pv = gv + 3 * (rd.pt_off + j + 1);
@@ -264,22 +281,25 @@ struct RodLane {
     bx = {0.f, 0.f, 0.f};
     bv = {0.f, 0.f, 0.f};
     if (g == 0) {
-      const float* px = gx + 3 * rd.pt_off;
-      const float* pv = gv + 3 * rd.pt_off;
+      const float* px = gx + 3 * (rd.pt_off + off);
+      const float* pv = gv + 3 * (rd.pt_off + off);
       bx = {px[0], px[1], px[2]};
       bv = {pv[0], pv[1], pv[2]};
     }
   }
 
-  // Writes the state; returns a sum of the written values (non-finite if any value is).
+  // Writes the slots [own_lo, own_hi) of the window (all by default) and, for a window at the
+  // rod's base, the base point; returns a sum of the written values (non-finite if any is).
   __device__ __forceinline__ float store_state(const RodDev& rd, float* __restrict__ gx,
                                                float* __restrict__ gv, float* __restrict__ gq,
-                                               float* __restrict__ gw) const {
+                                               float* __restrict__ gw, int own_lo = 0,
+                                               int own_hi = 1 << 30) const {
     float chk = 0.f;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int j = j0 + e;
-      if (ok[e]) {
+      const int jl = j0 + e;
+      const int j = off + jl;
+      if (ok[e] && jl >= own_lo && jl < own_hi) {
         float* px = gx + 3 * (rd.pt_off + j + 1);
         float* pv = gv + 3 * (rd.pt_off + j + 1);
         float* pq = gq + 4 * (rd.fr_off + j);
@@ -292,7 +312,7 @@ struct RodLane {
                Om[e].y + Om[e].z;
       }
     }
-    if (g == 0) {
+    if (g == 0 && off == 0) {
       float* px = gx + 3 * rd.pt_off;
       float* pv = gv + 3 * rd.pt_off;
       px[0] = bx.x; px[1] = bx.y; px[2] = bx.z;
@@ -381,8 +401,8 @@ struct RodLane {
       V3 Fe = F[e];
       V3 tau = T[e];
       if (rd.has_ext && ok[e]) {
-        const float* pf = fext + 3 * (rd.pt_off + j0 + e + 1);
-        const float* pt = text + 3 * (rd.fr_off + j0 + e);
+        const float* pf = fext + 3 * (rd.pt_off + off + j0 + e + 1);
+        const float* pt = text + 3 * (rd.fr_off + off + j0 + e);
         Fe = Fe + V3{pf[0], pf[1], pf[2]};
         tau = tau + V3{pt[0], pt[1], pt[2]};
       }
@@ -396,7 +416,9 @@ struct RodLane {
       Om[e] = o + dt * al;
     }
     if (g == 0) {
-      if (rd.clamp) {
+      if (ghost) {
+        bv = {0.f, 0.f, 0.f};                                  // fixed halo-edge point
+      } else if (rd.clamp) {
         bv = (1.0f / dt) * (xc - bx);
         Om[0] = wc;
       } else {
@@ -447,7 +469,7 @@ struct RodLane {
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) Vv[e] = nv[e];
-    if (g == 0 && h == 0 && !rd.clamp) bv = bv + dvb;
+    if (g == 0 && h == 0 && !rd.clamp && !ghost) bv = bv + dvb;
   }
 
   // X: integrate velocities (semi-implicit Euler), renormalise, impose the clamp pose.
@@ -457,7 +479,7 @@ struct RodLane {
       X[e] = X[e] + dt * Vv[e];
       Qf[e] = advance_quat(Qf[e], Om[e], dt);
     }
-    if (g == 0) {
+    if (g == 0 && !ghost) {
       if (rd.clamp) {
         bx = xc;
         Qf[0] = qc;
@@ -547,6 +569,139 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
     }
   }
   const float chk = L.store_state(rd, gx, gv, gq, gw);
+  if (!__builtin_isfinite(chk)) atomicOr(status, 1);
+}
+
+// ---------------------------------------------------------------------------------------
+// Long rods: several workgroups per rod.  Chunk k owns slots [s0, s0 + c) and holds the window
+// [win0, win0 + nwin) = owned slots plus a halo of H slots on each side (fewer at the rod
+// ends).  Every step is computed on the whole window; slots farther than one step's dependency
+// radius (2 n_iter + 2) from a window edge are exact, so with H at least that radius the owned
+// slots are exact.  After each step the chunk publishes its first H owned slots (for the left
+// neighbour's right halo) and its last H + 1 owned slots (for the right neighbour's left halo
+// and halo-edge point) to a double-buffered mailbox in global memory, raises its flag to the
+// step count with release semantics, waits for both neighbours' flags (acquire) and refills
+// its halos: one exchange per step instead of one per phase.
+struct GridChunk {
+  int32_t rod;             // rod index
+  int32_t s0, c;           // owned slots
+  int32_t win0, nwin;      // window slots
+  int32_t left, right;     // neighbour chunk indices (-1 at the rod's ends)
+  int32_t halo;            // H
+};
+
+constexpr int kPubSlotFloats = 13;   // x, v (point j+1), q, w (frame j)
+
+template <int W, int E>
+__global__ __launch_bounds__(64 * W) void rod_grid_kernel(
+    const RodDev* __restrict__ rods, const GridChunk* __restrict__ chunks,
+    const int* __restrict__ block_chunk, const float* __restrict__ prm, int prm_stride,
+    float* __restrict__ gx, float* __restrict__ gv, float* __restrict__ gq, float* __restrict__ gw,
+    const float* __restrict__ fext, const float* __restrict__ text, int n_steps,
+    long long steps_done, int* __restrict__ status, float* pub, int pub_slots, int n_chunks,
+    int* flags, int spin_limit) {
+  __shared__ Mailbox<W> mb;
+  __shared__ float cbuf[kClampChunk][10];
+  __shared__ int abort_flag;
+  const int ci = block_chunk[blockIdx.x];
+  const GridChunk ck = chunks[ci];
+  const RodDev rd = rods[ck.rod];
+  RodLane<W, E> L;
+  L.load_params(rd, prm, prm_stride, ck.win0, ck.nwin);
+  L.load_state(rd, gx, gv, gq, gw);
+  int par = 0;
+  V3 xc = {rd.cx0[0], rd.cx0[1], rd.cx0[2]}, wc = {0.f, 0.f, 0.f};
+  Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
+  const int own_lo = ck.s0 - ck.win0, own_hi = own_lo + ck.c;
+  const int H = ck.halo;
+  if (threadIdx.x == 0) abort_flag = 0;
+  __syncthreads();
+
+  for (int s = 0; s < n_steps; ++s) {
+    const long long gs = steps_done + s;
+    V3 xl;
+    Q4 qn;
+    L.exchange_a(mb, par, xl, qn);
+    V3 F[E], T[E], Ev[E], fs0, enext;
+    L.forces(mb, par, xl, qn, F, T, Ev, fs0, enext);
+    if (ck.win0 == 0) clamp_for_step<W>(rd, cbuf, s, n_steps, steps_done, xc, qc, wc);
+    L.integrate_forces(rd, F, T, fs0, xc, wc, fext, text);
+    for (int it = 0; it < rd.n_iter; ++it) {
+      L.half_sweep(rd, mb, par, 0, Ev, enext, nullptr);
+      L.half_sweep(rd, mb, par, 1, Ev, enext, nullptr);
+    }
+    L.integrate_velocities(rd, xc, qc);
+
+    // ---- publish boundary slots: part 0 = owned [0, H), part 1 = owned [c - H - 1, c)
+    const int pp = (int)(gs & 1);
+    float* mine = pub + ((long long)(pp * n_chunks + ci) * 2) * pub_slots * kPubSlotFloats;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int o = L.j0 + e - own_lo;   // owned index
+      const bool p0 = L.ok[e] && o >= 0 && o < H && ck.left >= 0;
+      const bool p1 = L.ok[e] && o >= ck.c - H - 1 && o < ck.c && ck.right >= 0;
+      if (p0 || p1) {
+        float* d = mine + (p0 ? o : pub_slots + o - (ck.c - H - 1)) * kPubSlotFloats;
+        d[0] = L.X[e].x; d[1] = L.X[e].y; d[2] = L.X[e].z;
+        d[3] = L.Vv[e].x; d[4] = L.Vv[e].y; d[5] = L.Vv[e].z;
+        d[6] = L.Qf[e].w; d[7] = L.Qf[e].x; d[8] = L.Qf[e].y; d[9] = L.Qf[e].z;
+        d[10] = L.Om[e].x; d[11] = L.Om[e].y; d[12] = L.Om[e].z;
+        if (p0 && p1) {   // a slot in both parts (c < 2 H + 1)
+          float* d1 = mine + (pub_slots + o - (ck.c - H - 1)) * kPubSlotFloats;
+          for (int k = 0; k < kPubSlotFloats; ++k) d1[k] = d[k];
+        }
+      }
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(&flags[ci], (int)(gs + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      // wait for both neighbours to have published this step (bounded spin)
+      int spins = 0;
+      for (int side = 0; side < 2; ++side) {
+        const int nb = side == 0 ? ck.left : ck.right;
+        if (nb < 0) continue;
+        while (__hip_atomic_load(&flags[nb], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (int)(gs + 1)) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > spin_limit) {
+            abort_flag = 1;
+            break;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (abort_flag) {
+      if (threadIdx.x == 0) atomicOr(status, 4);
+      break;
+    }
+    // ---- refill the halos from the neighbours' parts
+    const float* lp = ck.left >= 0
+        ? pub + ((long long)(pp * n_chunks + ck.left) * 2 + 1) * pub_slots * kPubSlotFloats
+        : nullptr;
+    const float* rp = ck.right >= 0
+        ? pub + ((long long)(pp * n_chunks + ck.right) * 2) * pub_slots * kPubSlotFloats
+        : nullptr;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int o = L.j0 + e - own_lo;
+      const float* src = nullptr;
+      if (L.ok[e] && o < 0 && lp) src = lp + (o + H + 1) * kPubSlotFloats;   // slot s0 + o
+      if (L.ok[e] && o >= ck.c && rp) src = rp + (o - ck.c) * kPubSlotFloats;
+      if (src) {
+        L.X[e] = {src[0], src[1], src[2]};
+        L.Vv[e] = {src[3], src[4], src[5]};
+        L.Qf[e] = {src[6], src[7], src[8], src[9]};
+        L.Om[e] = {src[10], src[11], src[12]};
+      }
+    }
+    if (L.g == 0 && L.ghost && lp) {   // halo-edge point: point win0 = point of slot win0 - 1
+      L.bx = {lp[0], lp[1], lp[2]};
+      L.bv = {lp[3], lp[4], lp[5]};
+    }
+  }
+  const float chk = L.store_state(rd, gx, gv, gq, gw, own_lo, own_hi);
   if (!__builtin_isfinite(chk)) atomicOr(status, 1);
 }
 

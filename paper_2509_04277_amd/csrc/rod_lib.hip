@@ -27,6 +27,14 @@ constexpr double kPi = 3.14159265358979323846;
 using KernelFn = void (*)(const RodDev*, const int*, const float*, int, float*, float*, float*,
                           float*, const float*, const float*, int, long long, int*, float*,
                           long long, int, int, float*, int, long long);
+using GridFn = void (*)(const RodDev*, const corde::GridChunk*, const int*, const float*, int,
+                        float*, float*, float*, float*, const float*, const float*, int, long long,
+                        int*, float*, int, int, int*, int);
+// Long-rod kernel shape: 4 wavefronts (one per SIMD) x 2 elements per lane = 512-slot windows.
+constexpr int kGridWaves = 4, kGridElems = 2;
+constexpr int kResidentMax = 2048;   // longest rod stepped by a single workgroup
+constexpr int kLongMax = 1 << 17;    // longest rod accepted (its chunks must be co-resident)
+
 using AdjointFn = void (*)(const RodDev*, const int*, const float*, int, const float*, long long,
                            int, int, int, long long, int, const float*, int, float*, float*,
                            float*, float*, float*, const float*, const float*, int*);
@@ -68,11 +76,7 @@ const KernelEntry* find_kernel(int w, int e) {
   return nullptr;
 }
 
-int max_capacity() {
-  int c = 0;
-  for (const auto& k : kKernels) c = std::max(c, 64 * k.waves * k.elems);
-  return c;
-}
+GridFn grid_kernel() { return corde::rod_grid_kernel<kGridWaves, kGridElems>; }
 
 thread_local std::string g_last_error;
 
@@ -101,6 +105,15 @@ struct rod_ctx {
     int waves, elems, first, count, max_n;
     float us_per_step;
   };
+  // long rods (more than chunk_above elements): chunked, one workgroup per chunk
+  int chunk_above = kResidentMax;
+  int chunk_target = 0;   // owned elements per chunk (0: as many as a window holds)
+  std::vector<int> long_rods;
+  int n_chunks = 0, pub_slots = 0;
+  corde::GridChunk* d_chunks = nullptr;
+  int* d_block_chunk = nullptr;
+  float* d_pub = nullptr;
+  int* d_flags = nullptr;
   std::vector<Bucket> buckets;
   std::vector<int> rod_ids;
   int* d_rod_ids = nullptr;
@@ -312,16 +325,17 @@ void default_shape(int n, int* w, int* e) {
 // within a bucket, and uploads the resulting rod order.
 template <class ShapeFn>
 rod_status make_buckets(rod_ctx* c, ShapeFn shape) {
-  std::vector<std::pair<long long, int>> key(c->n_rods);
+  std::vector<std::pair<long long, int>> key;
   for (int r = 0; r < c->n_rods; ++r) {
+    if (c->n[r] > c->chunk_above) continue;   // long rods run chunked
     int w, e;
     shape(r, &w, &e);
-    key[r] = {((long long)(w * 16 + e) << 32) | (long long)(0x7fffffff - c->n[r]), r};
+    key.push_back({((long long)(w * 16 + e) << 32) | (long long)(0x7fffffff - c->n[r]), r});
   }
   std::sort(key.begin(), key.end());
   c->buckets.clear();
-  c->rod_ids.assign(c->n_rods, 0);
-  for (int i = 0; i < c->n_rods; ++i) {
+  c->rod_ids.assign(std::max(c->n_rods, 1), 0);
+  for (int i = 0; i < (int)key.size(); ++i) {
     const int r = key[i].second;
     int w, e;
     shape(r, &w, &e);
@@ -334,6 +348,114 @@ rod_status make_buckets(rod_ctx* c, ShapeFn shape) {
   HIP_TRY(c, hipMemcpyAsync(c->d_rod_ids, c->rod_ids.data(), sizeof(int) * c->n_rods,
                             hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return ROD_OK;
+}
+
+// Splits every rod longer than chunk_above into chunks owning c slots (even, at least 2 H + 2
+// when there are several, about chunk_target if set) with windows of at most
+// 64 kGridWaves kGridElems slots, H = 2 n_iter + 4 (rounded up to even) halo slots per side;
+// maps chunks to blocks so that neighbours share an XCD.
+rod_status setup_long_rods(rod_ctx* c) {
+  std::vector<corde::GridChunk> ch;
+  int hmax = 0;
+  const int K = 64 * kGridWaves * kGridElems;
+  for (int r = 0; r < c->n_rods; ++r) {
+    const int n = c->n[r];
+    if (n <= c->chunk_above) continue;
+    c->long_rods.push_back(r);
+    int H = 2 * c->rods[r].n_iter + 4;
+    H += H & 1;
+    hmax = std::max(hmax, H);
+    int cmax = (K - 2 * H) & ~1;
+    if (c->chunk_target > 0) cmax = std::min(cmax, std::max(c->chunk_target, 2 * H + 2) & ~1);
+    int G = (n + cmax - 1) / cmax;
+    while (G > 1 && ((n / G) & ~1) < 2 * H + 2) --G;
+    int base = (n / G) & ~1;
+    int rem = n - base * G;   // distributed two slots at a time
+    int s0 = 0;
+    const int first = (int)ch.size();
+    for (int k = 0; k < G; ++k) {
+      int cc = base;
+      if (rem >= 2) { cc += 2; rem -= 2; }
+      if (k == G - 1) cc = n - s0;
+      corde::GridChunk g{};
+      g.rod = r;
+      g.s0 = s0;
+      g.c = cc;
+      g.win0 = std::max(0, s0 - H);
+      g.nwin = std::min(n, s0 + cc + H) - g.win0;
+      g.left = k > 0 ? first + k - 1 : -1;
+      g.right = k < G - 1 ? first + k + 1 : -1;
+      g.halo = H;
+      if (g.nwin > K || (G > 1 && cc < 2 * H + 2))
+        return fail(c, ROD_E_UNSUPPORTED, "rod " + std::to_string(r) +
+                    ": too many constraint iterations to split it into chunks");
+      ch.push_back(g);
+      s0 += cc;
+    }
+  }
+  c->n_chunks = (int)ch.size();
+  if (!c->n_chunks) return ROD_OK;
+  c->pub_slots = hmax + 1;
+  // blocks are dealt to the 8 XCDs round-robin: give XCD x the chunks [x G / 8, (x+1) G / 8)
+  const int G = c->n_chunks;
+  std::vector<int> block_chunk(G);
+  {
+    std::vector<int> per_xcd(8, 0), start(9, 0);
+    for (int x = 0; x < 8; ++x) start[x + 1] = (int)((long long)G * (x + 1) / 8);
+    std::vector<int> next(start.begin(), start.end() - 1);
+    for (int b = 0; b < G; ++b) {
+      int x = b % 8;
+      // fall back to any XCD with chunks left if this one is exhausted
+      for (int t = 0; t < 8 && next[x] >= start[x + 1]; ++t) x = (x + 1) % 8;
+      block_chunk[b] = next[x]++;
+    }
+  }
+  auto dm = [&](void** p, size_t n) { return hipMalloc(p, std::max<size_t>(n, 4)) == hipSuccess; };
+  if (!dm((void**)&c->d_chunks, sizeof(corde::GridChunk) * G) ||
+      !dm((void**)&c->d_block_chunk, sizeof(int) * G) ||
+      !dm((void**)&c->d_pub, sizeof(float) * 2 * (size_t)G * 2 * c->pub_slots * corde::kPubSlotFloats) ||
+      !dm((void**)&c->d_flags, sizeof(int) * G))
+    return fail(c, ROD_E_NOMEM, "long-rod buffers");
+  HIP_TRY(c, hipMemcpy(c->d_chunks, ch.data(), sizeof(corde::GridChunk) * G, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->d_block_chunk, block_chunk.data(), sizeof(int) * G, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemset(c->d_flags, 0, sizeof(int) * G));
+  // every chunk must be resident at once (the chunks wait on each other)
+  int per_cu = 0, cus = 0, dev = 0;
+  HIP_TRY(c, hipGetDevice(&dev));
+  HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, grid_kernel(), 64 * kGridWaves, 0));
+  if ((long long)per_cu * cus < G)
+    return fail(c, ROD_E_UNSUPPORTED, "long rods need " + std::to_string(G) +
+                " resident workgroups, the device holds " + std::to_string(per_cu * cus));
+  return ROD_OK;
+}
+
+// Chunked long rods: one cooperative launch of ks steps.
+rod_status launch_long(rod_ctx* c, float* x, float* v, float* q, float* w, int ks, long long done) {
+  if (!c->n_chunks) return ROD_OK;
+  int spin = 1 << 22;
+  const RodDev* rods = c->d_rods;
+  const corde::GridChunk* chunks = c->d_chunks;
+  const int* bc = c->d_block_chunk;
+  const float* prm = c->d_prm;
+  int stride = c->prm_stride;
+  const float* fe = c->d_fext;
+  const float* te = c->d_text;
+  int* st = c->d_status;
+  float* pub = c->d_pub;
+  int ps = c->pub_slots, nc = c->n_chunks;
+  int* fl = c->d_flags;
+  void* args[] = {&rods, &chunks, &bc, &prm, &stride, &x, &v, &q, &w, &fe, &te, &ks, &done,
+                  &st, &pub, &ps, &nc, &fl, &spin};
+  HIP_TRY(c, hipLaunchCooperativeKernel((const void*)grid_kernel(), dim3(c->n_chunks),
+                                        dim3(64 * kGridWaves), args, 0, c->stream));
+  return ROD_OK;
+}
+
+// Zeroes the long-rod step flags (whenever the step counter restarts).
+rod_status reset_flags(rod_ctx* c) {
+  if (c->d_flags) HIP_TRY(c, hipMemsetAsync(c->d_flags, 0, sizeof(int) * c->n_chunks, c->stream));
   return ROD_OK;
 }
 
@@ -357,6 +479,11 @@ rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it, int buck
     for (int b = 0; b < (int)c->buckets.size(); ++b) {
       if (bucket >= 0 && b != bucket) continue;
       rod_status st = launch_bucket(c, c->buckets[b], ks, c->steps_done + done);
+      if (st != ROD_OK) return st;
+      ++launches;
+    }
+    if (bucket < 0 && c->n_chunks) {
+      rod_status st = launch_long(c, c->d_x, c->d_v, c->d_q, c->d_w, ks, c->steps_done + done);
       if (st != ROD_OK) return st;
       ++launches;
     }
@@ -419,6 +546,7 @@ const char* rod_status_str(rod_status s) {
     case ROD_E_UNSTABLE: return "ROD_E_UNSTABLE: non-finite state";
     case ROD_E_ORDER: return "ROD_E_ORDER: call out of order";
     case ROD_E_UNSUPPORTED: return "ROD_E_UNSUPPORTED: not supported by this build";
+    case ROD_E_TIMEOUT: return "ROD_E_TIMEOUT: long-rod workgroups lost step synchronisation";
   }
   return "unknown rod_status";
 }
@@ -465,11 +593,10 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
     frames += params[r].n_elements;
     max_n = std::max(max_n, params[r].n_elements);
   }
+  if (max_n > kLongMax)
+    return fail(nullptr, ROD_E_UNSUPPORTED, "rod of " + std::to_string(max_n) +
+                " elements exceeds the longest supported (" + std::to_string(kLongMax) + ")");
   if (frames > (1LL << 30)) return fail(nullptr, ROD_E_INVALID, "too many elements");
-  if (max_n > max_capacity())
-    return fail(nullptr, ROD_E_UNSUPPORTED,
-                "rod of " + std::to_string(max_n) + " elements exceeds the single-workgroup kernel (" +
-                    std::to_string(max_capacity()) + ")");
   rod_ctx* c = new (std::nothrow) rod_ctx();
   if (!c) return fail(nullptr, ROD_E_NOMEM, "host allocation failed");
   auto cleanup = [&](rod_status s) {
@@ -537,7 +664,9 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
   if (e == hipSuccess) e = hipEventCreate(&c->ev1);
   if (e != hipSuccess) return cleanup(hip_fail(nullptr, e, "rod_create device setup"));
   {
-    rod_status st = make_buckets(c, [&](int r, int* w, int* e) { default_shape(c->n[r], w, e); });
+    rod_status st = setup_long_rods(c);
+    if (st != ROD_OK) return cleanup(st);
+    st = make_buckets(c, [&](int r, int* w, int* e) { default_shape(c->n[r], w, e); });
     if (st != ROD_OK) return cleanup(st);
   }
   *out = c;
@@ -552,7 +681,8 @@ rod_status rod_destroy(rod_ctx* c) {
                   (void*)c->d_q, (void*)c->d_w, (void*)c->d_fext, (void*)c->d_text,
                   (void*)c->d_status, (void*)c->d_rod_ids, (void*)c->d_ckpt, (void*)c->d_traj,
                   (void*)c->d_tips, (void*)c->d_dtips, (void*)c->d_adj, (void*)c->d_work,
-                  (void*)c->d_gmult})
+                  (void*)c->d_gmult, (void*)c->d_chunks, (void*)c->d_block_chunk, (void*)c->d_pub,
+                  (void*)c->d_flags})
     if (p) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -573,6 +703,10 @@ rod_status rod_set_state(rod_ctx* c, const float* x, const float* v, const float
   if (!on_device) HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->t0 = t0;
   c->steps_done = 0;
+  {
+    rod_status st = reset_flags(c);
+    if (st != ROD_OK) return st;
+  }
   for (auto& r : c->rods) r.t0 = t0;
   HIP_TRY(c, hipMemcpyAsync(c->d_rods, c->rods.data(), sizeof(RodDev) * c->n_rods,
                             hipMemcpyHostToDevice, c->stream));
@@ -625,6 +759,7 @@ rod_status rod_sync(rod_ctx* c) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   int st = 0;
   HIP_TRY(c, hipMemcpy(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost));
+  if (st & 4) return fail(c, ROD_E_TIMEOUT, "a long-rod chunk waited too long for a neighbour");
   if (st) return fail(c, ROD_E_UNSTABLE, "non-finite state detected by the step kernel");
   return ROD_OK;
 }
@@ -641,7 +776,10 @@ rod_status rod_set_tuning(rod_ctx* c, const rod_tuning* t) {
   if (t->steps_per_launch < 1) return fail(c, ROD_E_INVALID, "steps_per_launch must be >= 1");
   const KernelEntry* k = find_kernel(t->waves, t->elems_per_lane);
   if (!k) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
-  if (64 * k->waves * k->elems < c->max_n) return fail(c, ROD_E_UNSUPPORTED, "shape cannot hold the longest rod");
+  int max_res = 0;
+  for (int r = 0; r < c->n_rods; ++r)
+    if (c->n[r] <= c->chunk_above) max_res = std::max(max_res, c->n[r]);
+  if (64 * k->waves * k->elems < max_res) return fail(c, ROD_E_UNSUPPORTED, "shape cannot hold the longest rod");
   rod_status st = make_buckets(c, [&](int, int* w, int* e) { *w = t->waves; *e = t->elems_per_lane; });
   if (st != ROD_OK) return st;
   c->steps_per_launch = t->steps_per_launch;
@@ -650,9 +788,8 @@ rod_status rod_set_tuning(rod_ctx* c, const rod_tuning* t) {
 
 rod_status rod_get_tuning(const rod_ctx* c, rod_tuning* t) {
   if (!c || !t) return fail(nullptr, ROD_E_INVALID, "null argument");
-  const auto& b = c->buckets.front();
-  t->waves = b.waves;
-  t->elems_per_lane = b.elems;
+  t->waves = c->buckets.empty() ? kGridWaves : c->buckets.front().waves;
+  t->elems_per_lane = c->buckets.empty() ? kGridElems : c->buckets.front().elems;
   t->steps_per_launch = c->steps_per_launch;
   float us = 0.f;
   for (const auto& bb : c->buckets) us += bb.us_per_step;
@@ -662,7 +799,16 @@ rod_status rod_get_tuning(const rod_ctx* c, rod_tuning* t) {
 
 rod_status rod_bucket_info(const rod_ctx* c, int32_t bucket, rod_tuning* t, int32_t* n_rods) {
   if (!c || !t || !n_rods) return fail(nullptr, ROD_E_INVALID, "null argument");
-  if (bucket < 0 || bucket >= (int)c->buckets.size())
+  const int nb = (int)c->buckets.size();
+  if (bucket == nb && c->n_chunks) {
+    t->waves = kGridWaves;
+    t->elems_per_lane = kGridElems;
+    t->steps_per_launch = c->steps_per_launch;
+    t->us_per_step = 0.f;
+    *n_rods = (int)c->long_rods.size();
+    return ROD_OK;
+  }
+  if (bucket < 0 || bucket >= nb)
     return fail(const_cast<rod_ctx*>(c), ROD_E_INVALID, "bucket index out of range");
   const auto& b = c->buckets[bucket];
   t->waves = b.waves;
@@ -670,6 +816,43 @@ rod_status rod_bucket_info(const rod_ctx* c, int32_t bucket, rod_tuning* t, int3
   t->steps_per_launch = c->steps_per_launch;
   t->us_per_step = b.us_per_step;
   *n_rods = b.count;
+  return ROD_OK;
+}
+
+rod_status rod_set_chunking(rod_ctx* c, int32_t min_elements, int32_t chunk_elements) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (min_elements < 1 || min_elements > kResidentMax)
+    return fail(c, ROD_E_INVALID, "min_elements must be in [1, 2048]");
+  if (chunk_elements < 0) return fail(c, ROD_E_INVALID, "chunk_elements must be >= 0");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (void** p : {(void**)&c->d_chunks, (void**)&c->d_block_chunk, (void**)&c->d_pub,
+                   (void**)&c->d_flags}) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+  c->long_rods.clear();
+  c->n_chunks = 0;
+  c->pub_slots = 0;
+  c->chunk_above = min_elements;
+  c->chunk_target = chunk_elements;
+  rod_status st = setup_long_rods(c);
+  if (st == ROD_OK) st = make_buckets(c, [&](int r, int* w, int* e) { default_shape(c->n[r], w, e); });
+  if (st != ROD_OK) {   // back to the default split, which rod_create accepted
+    for (void** p : {(void**)&c->d_chunks, (void**)&c->d_block_chunk, (void**)&c->d_pub,
+                     (void**)&c->d_flags}) {
+      if (*p) (void)hipFree(*p);
+      *p = nullptr;
+    }
+    c->long_rods.clear();
+    c->n_chunks = 0;
+    c->chunk_above = kResidentMax;
+    c->chunk_target = 0;
+    const std::string err = c->err;
+    if (setup_long_rods(c) == ROD_OK)
+      (void)make_buckets(c, [&](int r, int* w, int* e) { default_shape(c->n[r], w, e); });
+    return fail(c, st, err);
+  }
+  if (c->n_chunks) c->adj_ready = false;   // the adjoint does not step chunked rods
   return ROD_OK;
 }
 
@@ -750,6 +933,7 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
   }
   c->steps_per_launch = steps_per_launch;
   c->steps_done = saved_steps;
+  (void)reset_flags(c);
   if (copy(c->d_x, sx, bx) || copy(c->d_v, sv, bx) || copy(c->d_q, sq, bq) || copy(c->d_w, sw, bw)) {
     free_all();
     return fail(c, ROD_E_DEVICE, "autotune state restore failed");
@@ -787,6 +971,7 @@ rod_status rod_adjoint_forward(rod_ctx* c, int32_t n_steps, int32_t ckpt_every, 
       return fail(c, ROD_E_UNSUPPORTED, "adjoint supports at most 10 constraint iterations");
   for (const auto& b : c->buckets)
     if (!adjoint_shape(b.max_n)) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
+  if (c->n_chunks) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
   free_adjoint(c);
   const size_t S = state_floats(c);
   const int ck = std::min(ckpt_every, n_steps);
@@ -837,6 +1022,7 @@ rod_status rod_adjoint_backward(rod_ctx* c, const float* dl_dtips, float* dl_dbe
                                 float* dl_dw, int32_t on_device) {
   if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
   if (!c->adj_ready) return fail(c, ROD_E_ORDER, "rod_adjoint_backward without rod_adjoint_forward");
+  if (c->n_chunks) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
   if (!dl_dtips) return fail(c, ROD_E_INVALID, "null dL/dtip");
   const size_t S = state_floats(c);
   const size_t P3 = (size_t)3 * c->total_pts, F4 = (size_t)4 * c->total_frames;

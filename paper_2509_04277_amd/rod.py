@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libcorde_rod.so")
 
 ROD_OK = 0
 STATUS = {0: "ROD_OK", -1: "ROD_E_INVALID", -2: "ROD_E_NOMEM", -3: "ROD_E_DEVICE",
-          -4: "ROD_E_UNSTABLE", -5: "ROD_E_ORDER", -6: "ROD_E_UNSUPPORTED"}
+          -4: "ROD_E_UNSTABLE", -5: "ROD_E_ORDER", -6: "ROD_E_UNSUPPORTED", -7: "ROD_E_TIMEOUT"}
 
 
 class RodError(RuntimeError):
@@ -67,6 +67,7 @@ _SIGS = {
     "rod_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(rod_tuning)]),
     "rod_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(rod_tuning)]),
     "rod_bucket_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rod_tuning), C.POINTER(C.c_int32)]),
+    "rod_set_chunking": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "rod_stable_dt": (C.c_int, [C.POINTER(rod_params), _DP]),
     "rod_last_step_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     "rod_set_stiffness_mult": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
@@ -318,6 +319,11 @@ class RodBatch:
                 return out
             out.append((t.waves, t.elems_per_lane, n.value, t.us_per_step))
             b += 1
+
+    def set_chunking(self, min_elements: int, chunk_elements: int = 0):
+        """Step rods longer than min_elements with the chunked multi-workgroup kernel, about
+        chunk_elements owned elements per workgroup (0: the largest chunk)."""
+        _check(lib().rod_set_chunking(self.h, int(min_elements), int(chunk_elements)), self.h)
 
     def autotune(self, probe_steps: int = 200, steps_per_launch: int = 10):
         t = rod_tuning()

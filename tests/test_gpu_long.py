@@ -1,0 +1,182 @@
+"""GPU parity of the chunked long-rod kernel (one workgroup per chunk of about 500 elements,
+halo exchange through HBM once per step) against the FP64 oracle and against the
+single-workgroup kernel on the same rod.  Tolerance from the method's target: tip (and every
+point) within 1e-4 x rod length after the workload's step count.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2509_04277_amd import rod as R
+from paper_2509_04277_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    torch.cuda.init()
+    yield
+
+
+def _run(rods, n_steps, spl, chunk_above=None, chunk=0, splits=None, shape=None):
+    b = R.RodBatch([s for s, _ in rods])
+    if shape is not None:
+        b.set_tuning(shape[0], shape[1], spl)
+    if chunk_above is not None:
+        b.set_chunking(chunk_above, chunk)
+    b.set_state_rods([st for _, st in rods])
+    for k in (splits or [n_steps]):
+        b.step(k, spl)
+    b.sync()
+    out = b.get_state_rods()
+    info = b.buckets()
+    b.close()
+    return out, info
+
+
+def _vs_oracle(oracle, rods, gpu, n_steps, label):
+    for (s, st), (x, v, q, w) in zip(rods, gpu):
+        o = oracle.Rod(s).rollout(st, n_steps)[0]
+        L = float(np.sum(s.seg_len))
+        tip = float(np.linalg.norm(x[-1] - o.x[-1]))
+        ex = float(np.abs(x - o.x).max())
+        qn = float(np.abs(np.linalg.norm(q.astype(np.float64), axis=1) - 1).max())
+        _say("%s N=%d %s: tip=%.2e max|dx|=%.2e (tol %.1e) max|dv|=%.2e (|v|max %.2e) |q|-1=%.1e"
+             % (label, s.n, "inext" if s.inextensible else "ext", tip, ex, 1e-4 * L,
+                np.abs(v - o.v).max(), np.abs(o.v).max(), qn))
+        assert np.isfinite(x).all() and np.isfinite(q).all() and np.isfinite(v).all()
+        assert tip <= 1e-4 * L
+        assert ex <= 1e-4 * L
+        assert qn <= 1e-6
+
+
+@pytest.mark.parametrize("case", ["c2-500-inext", "c2-500-ext", "c1-2x512-driven"])
+def test_chunked_is_bitwise_single_workgroup(case):
+    """Chunked and single-workgroup kernels of the same shape (4 waves x 2 elements per lane)
+    on the same rods: windows start at even elements, so every owned element is computed by
+    the same instructions from the same operands, and the halo (2 n_iter + 4 elements per
+    side) covers one step's dependency radius.  Any halo shortfall breaks bitwise equality."""
+    if case == "c1-2x512-driven":
+        rods, chunk = W.config1().rods, 128
+    else:
+        rods, chunk = W.config2(500, case.endswith("-inext")).rods, 64
+    n_steps = 300
+    one, info1 = _run(rods, n_steps, 10, shape=(4, 2))
+    many, info2 = _run(rods, n_steps, 10, chunk_above=1, chunk=chunk)
+    _say("%s: %d steps; buckets single %s, chunked %s" % (case, n_steps, info1, info2))
+    assert info1 == [(4, 2, len(rods), 0.0)] and info2 == [(4, 2, len(rods), 0.0)]
+    for r, (a, b) in enumerate(zip(one, many)):
+        d = [float(np.abs(u - v).max()) for u, v in zip(a, b)]
+        _say("  rod %d max diffs x %.2e v %.2e q %.2e w %.2e" % (r, *d))
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("inext", [True, False])
+def test_chunked_matches_wider_single_workgroup(oracle, inext):
+    """A 2000-element rod in 5 chunks against the same rod in one 8-wave x 4-element
+    workgroup: multiply-adds are fused only within a source expression, so the grouping of
+    elements into lanes does not change any element's arithmetic."""
+    wl = W.config2(2000, inext)
+    L = float(np.sum(wl.rods[0][0].seg_len))
+    n_steps = 300
+    one, info1 = _run(wl.rods, n_steps, 10)
+    many, info2 = _run(wl.rods, n_steps, 10, chunk_above=1024)
+    _say("1x2000 %s, %d steps; buckets single %s, chunked %s"
+         % ("inext" if inext else "ext", n_steps, info1, info2))
+    assert info2 == [(4, 2, 1, 0.0)]
+    (x1, v1, q1, w1), (x2, v2, q2, w2) = one[0], many[0]
+    dx, dq = np.abs(x1 - x2).max(), np.abs(q1 - q2).max()
+    _say("  max diffs: x %.2e (L %.1f) q %.2e v %.2e w %.2e" % (
+        dx, L, dq, np.abs(v1 - v2).max(), np.abs(w1 - w2).max()))
+    for u, v in zip(one[0], many[0]):
+        assert np.array_equal(u, v)
+    _vs_oracle(oracle, wl.rods, many, n_steps, "chunked-2000")
+
+
+def test_every_kernel_shape_is_bitwise():
+    """The two c1 rods (512 elements, driven clamp) in every built shape that holds them and
+    in 4 chunks: identical states after 300 steps."""
+    rods = W.config1().rods
+    ref, _ = _run(rods, 300, 10, shape=(4, 2))
+    for shape in [(1, 8), (2, 4), (8, 1), (4, 4), (8, 2), (4, 8), (8, 4), (16, 1)]:
+        got, _ = _run(rods, 300, 10, shape=shape)
+        same = all(np.array_equal(u, v) for a, b in zip(ref, got) for u, v in zip(a, b))
+        _say("shape %s bitwise equal to (4, 2): %s" % (shape, same))
+        assert same
+    got, _ = _run(rods, 300, 10, chunk_above=1, chunk=128)
+    assert all(np.array_equal(u, v) for a, b in zip(ref, got) for u, v in zip(a, b))
+
+
+@pytest.mark.parametrize("inext", [True, False])
+def test_c2_4096_full_run(oracle, inext):
+    wl = W.config2(4096, inext)
+    _say("c2 full: 1x4096 %s, %d steps at %d per launch"
+         % ("inext" if inext else "ext", wl.n_steps, wl.steps_per_launch))
+    gpu, info = _run(wl.rods, wl.n_steps, wl.steps_per_launch)
+    assert info == [(4, 2, 1, 0.0)]
+    _vs_oracle(oracle, wl.rods, gpu, wl.n_steps, "c2-4096")
+
+
+def test_c2_65536_short_run(oracle):
+    """Largest rod of the long-rod workload (142 chunks), 200 steps at 100 per launch."""
+    wl = W.config2(65536, True)
+    _say("c2 largest: 1x65536 inext, 200 steps at 100 per launch")
+    gpu, _ = _run(wl.rods, 200, 100)
+    _vs_oracle(oracle, wl.rods, gpu, 200, "c2-65536")
+
+
+def test_launch_split_and_restart_are_bitwise():
+    """Chunk flags carry absolute step numbers across launches; rod_set_state restarts them."""
+    wl = W.config2(4096, True)
+    _say("c2 1x4096 inext: 100 steps as 1x100 (k=100), 100x1 (k=1), 10x10 (k=10), restarted")
+    b = R.RodBatch([s for s, _ in wl.rods])
+    res = []
+    for spl in (100, 1, 10):
+        b.set_state_rods([st for _, st in wl.rods])
+        b.step(100, spl)
+        b.sync()
+        res.append(b.get_state_rods()[0])
+        _say("  k=%d done" % spl)
+    b.close()
+    for other in res[1:]:
+        for a, c in zip(res[0], other):
+            assert np.array_equal(a, c)
+
+
+def test_mixed_handle_long_and_short(oracle):
+    """One handle holding resident rods and a chunked rod: one rod_step advances all."""
+    rods = W.config0().rods + W.config2(3000, True).rods + W.config2(700, False).rods
+    _say("mixed handle: N=64 ext, N=3000 inext (chunked), N=700 ext; 500 steps")
+    gpu, info = _run(rods, 500, 10)
+    _say("buckets %s" % info)
+    assert info[-1][:3] == (4, 2, 1)
+    _vs_oracle(oracle, rods, gpu, 500, "mixed")
+
+
+def test_set_chunking_arguments():
+    wl = W.config2(1000, True)
+    b = R.RodBatch([s for s, _ in wl.rods])
+    for bad in (0, -1, 2049):
+        with pytest.raises(R.RodError):
+            b.set_chunking(bad)
+    with pytest.raises(R.RodError):
+        b.set_chunking(10, -1)
+    b.set_chunking(2048)
+    assert b.buckets()[-1][2] == 1 and len(b.buckets()) == 1
+    b.set_chunking(999)
+    assert b.buckets() == [(4, 2, 1, 0.0)]
+    b.set_chunking(999, 1)   # clamped up to the smallest chunk, 2 H + 2 = 50
+    b.set_state_rods([st for _, st in wl.rods])
+    b.step(10, 10)
+    b.sync()
+    b.close()
