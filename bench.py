@@ -26,7 +26,8 @@ HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("paper_2509_04277_amd/csrc/rod_kernels.hpp", "paper_2509_04277_amd/csrc/rod_lib.hip"):
+    for f in ("paper_2509_04277_amd/csrc/rod_kernels.hpp", "paper_2509_04277_amd/csrc/rod_lib.hip",
+              "paper_2509_04277_amd/build.py"):
         h.update(open(os.path.join(REPO, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -43,6 +44,28 @@ def measured_traffic(kernel_name, elements, spl):
     if e.get("elements") != elements or e.get("steps_per_launch") != spl:
         return None
     return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+
+
+COPY_FLOATS = 64 << 20                # 256 MiB FP32 copy: 512 MiB of HBM traffic per dispatch
+
+
+def copy_bandwidth(torch, reps=20):
+    """STREAM-style copy (one elementwise copy kernel of 256 MiB read + 256 MiB written): the
+    measured HBM rate, and the dispatch whose FETCH_SIZE / WRITE_SIZE calibrate the counters."""
+    src = torch.ones(COPY_FLOATS, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 2 * 4 * COPY_FLOATS
+    del src, dst
+    return {"bytes_per_dispatch": nbytes, "ms": ms, "GB/s": nbytes / (ms / 1e3) / 1e9}
 
 
 def cpu_baseline(wl, n_steps):
@@ -185,6 +208,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    copy = copy_bandwidth(torch)
+    print("copy: %.0f GB/s" % copy["GB/s"], file=sys.stderr, flush=True)
     spl = args.steps_per_launch
     wl = W.config1()
     specs = [s for s, _ in wl.rods]
@@ -249,7 +274,9 @@ def main():
                                        "p99": 1e3 * float(np.percentile(lat, 99))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     "measured_copy_GBs": copy["GB/s"],
+                     "frac_of_measured_copy": achieved / copy["GB/s"]},
     }
     if not args.no_extras:
         out["extras"] = {"batch": batch_extras(R, W), "long_rod": long_rod_extras(R, W),

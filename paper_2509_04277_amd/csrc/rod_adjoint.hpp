@@ -25,6 +25,10 @@ constexpr int P_WINV_NEXT = P_NROWS;  // extra coefficient row: inverse mass of 
 __device__ __forceinline__ Q4 q_add(Q4 a, Q4 b) { return {a.w + b.w, a.x + b.x, a.y + b.y, a.z + b.z}; }
 __device__ __forceinline__ Q4 q_scale(float s, Q4 a) { return {s * a.w, s * a.x, s * a.y, s * a.z}; }
 __device__ __forceinline__ float q_dot(Q4 a, Q4 b) { return a.w * b.w + a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ Q4 qfma(float s, Q4 a, Q4 b) {   // s a + b, fused per component
+  return {__builtin_fmaf(s, a.w, b.w), __builtin_fmaf(s, a.x, b.x), __builtin_fmaf(s, a.y, b.y),
+          __builtin_fmaf(s, a.z, b.z)};
+}
 
 // Adjoint of one distance impulse.  Inputs: predicted segment vector d (before the impulse),
 // coefficients ci, cil, inverse masses, and the adjoints gl, gh of the two end velocities after
@@ -34,9 +38,9 @@ __device__ __forceinline__ V3 impulse_adjoint(V3 d, float ci, float cil, float w
                                               V3 gh) {
   const float il = rsqrtf(fmaxf(dot(d, d), 1e-30f));
   const float s = ci - cil * il;
-  const V3 Db = wl * gl - wh * gh;          // Delta = s d; v_hi -= w_hi Delta; v_lo += w_lo Delta
+  const V3 Db = fnma3(wh, gh, wl * gl);     // Delta = s d; v_hi -= w_hi Delta; v_lo += w_lo Delta
   const float sb = dot(Db, d);
-  return s * Db + (sb * cil * il * il * il) * d;
+  return fma3(sb * cil * il * il * il, d, s * Db);
 }
 
 template <int W, int E>
@@ -152,7 +156,7 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         AXn[e] = AX[e];
-        AVc[e] = AV[e] + dt * AX[e];
+        AVc[e] = fma3(dt, AX[e], AV[e]);
         const Q4 q = Q0[e];
         const V3 o = L.Om[e];
         const float hdt = 0.5f * dt;
@@ -162,13 +166,13 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
                       q.z + hdt * (q.w * o.z + q.x * o.y - q.y * o.x)};
         const float ip = rsqrtf(q_dot(p, p));
         const Q4 qo = q_scale(ip, p);
-        Q4 pb = q_scale(ip, q_add(AQ[e], q_scale(-q_dot(qo, AQ[e]), qo)));
+        Q4 pb = q_scale(ip, qfma(-q_dot(qo, AQ[e]), qo, AQ[e]));
         if (clamp0 && e == 0) pb = {0.f, 0.f, 0.f, 0.f};   // q'_0 = q_c
         // dq: p_bar - dt/2 p_bar (x) (0, omega');  domega': dt/2 vec(conj(q) (x) p_bar)
         const Q4 po = qmul(pb, Q4{0.f, o.x, o.y, o.z});
         AQn[e] = {pb.w - hdt * po.w, pb.x - hdt * po.x, pb.y - hdt * po.y, pb.z - hdt * po.z};
         const Q4 cq = qmul(Q4{q.w, -q.x, -q.y, -q.z}, pb);
-        AWp[e] = AW[e] + hdt * V3{cq.x, cq.y, cq.z};
+        AWp[e] = fma3(hdt, V3{cq.x, cq.y, cq.z}, AW[e]);
         if (clamp0 && e == 0) AWp[e] = {0.f, 0.f, 0.f};      // omega'_0 = omega_c
       }
       V3 abxn, abvc;
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
         abvc = abv;
       } else {
         abxn = abx;
-        abvc = abv + dt * abx;
+        abvc = fma3(dt, abx, abv);
       }
 
       // ---- reverse C: half-sweeps in reverse order
@@ -216,13 +220,13 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
               // as left end of segment j+1
               const V3 db_l = impulse_adjoint(d, L.P[P_CI_NEXT][e], L.P[P_CIL_NEXT][e], w_me,
                                               WN[e], AVc[e], g_hi);
-              nv[e] = sel(is_hi, AVc[e] + dt * db_h, AVc[e] - dt * db_l);
+              nv[e] = sel(is_hi, fma3(dt, db_h, AVc[e]), fnma3(dt, db_l, AVc[e]));
               EB[e] = sel(is_hi, EB[e] + db_h, EB[e]);
               if (e == 0) dbase = db_h;
             }
 #pragma unroll
             for (int e = 0; e < E; ++e) AVc[e] = nv[e];
-            if (g == 0 && h == 0) abvc = abvc - dt * dbase;  // base point: left end of segment 0
+            if (g == 0 && h == 0) abvc = fnma3(dt, dbase, abvc);  // base point: left end of segment 0
           }
         }
       }
@@ -238,8 +242,8 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
         TB[e] = {i1 * a.x, i1 * a.y, i3 * a.z};
         const V3 o = Om0[e];
         const float ga = rd.damp_ang;
-        AW[e] = AWp[e] + V3{-ga * a.x + kg * o.z * a.y, -kg * o.z * a.x - ga * a.y,
-                            -kg * o.y * a.x + kg * o.x * a.y - ga * a.z};
+        AW[e] = {AWp[e].x - ga * a.x + kg * o.z * a.y, AWp[e].y - kg * o.z * a.x - ga * a.y,
+                 AWp[e].z - kg * o.y * a.x + kg * o.x * a.y - ga * a.z};
         if (clamp0 && e == 0) {
           TB[e] = {0.f, 0.f, 0.f};
           AW[e] = {0.f, 0.f, 0.f};
@@ -247,7 +251,7 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
       }
       V3 fb0 = {0.f, 0.f, 0.f};   // adjoint of the base point's force (free base only)
       if (rd.clamp) {
-        abxn = abxn - (1.0f / dt) * abvc;                     // v'_0 = (x_c - x_0) / dt
+        abxn = fnma3(1.0f / dt, abvc, abxn);                  // v'_0 = (x_c - x_0) / dt
         abv = {0.f, 0.f, 0.f};
       } else {
         fb0 = (dt * rd.winv0) * abvc;
@@ -289,14 +293,14 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
         const V3 fbar = sel(L.ok[e], FB[e] - ((e == 0) ? fb_lo : FB[e - 1]), V3{0.f, 0.f, 0.f});
         const V3 tpb = sel(L.ok[e], TB[e], V3{0.f, 0.f, 0.f});
         const float tf = dot(t, fbar);
-        const V3 d3b = (lkp * il) * (fbar - tf * t);
-        V3 tb = (-lkp * il) * (td3 * fbar + tf * d3) - (ksl * (len - L.P[P_LEN][e])) * fbar;
-        tb = tb + lkp * (tpb.y * d1 - tpb.x * d2);
+        const V3 d3b = (lkp * il) * fnma3(tf, t, fbar);
+        V3 tb = fnma3(ksl * (len - L.P[P_LEN][e]), fbar, (-lkp * il) * fma3(td3, fbar, tf * d3));
+        tb = fma3(lkp, fnma3(tpb.x, d2, tpb.y * d1), tb);
         const V3 d2b = (-lkp * tpb.x) * t;
         const V3 d1b = (lkp * tpb.y) * t;
         const float ilb = lkp * (dot(d3, fbar) - td3 * tf);
         const float lenb = -ksl * tf;
-        V3 db = il * (tb - dot(t, tb) * t) + (lenb - ilb * il * il) * t;
+        V3 db = fma3(lenb - ilb * il * il, t, il * fnma3(dot(t, tb), t, tb));
         db = sel(L.ok[e], db + EB[e], V3{0.f, 0.f, 0.f});     // + constraint use of e_j
         AXn[e] = AXn[e] + db;                                 // d = x_{j+1} - x_j
         if (e == 0) dneg_first = db;
@@ -316,20 +320,23 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
         const Q4 dq = {qb.w - q.w, qb.x - q.x, qb.y - q.y, qb.z - q.z};
         const float rw = q.w * qb.w + q.x * qb.x + q.y * qb.y + q.z * qb.z;
         const V3 va = {q.x, q.y, q.z}, vb = {qb.x, qb.y, qb.z}, dv = {dq.x, dq.y, dq.z};
-        const V3 rv = q.w * dv - dq.w * va - cross(va, dv);
+        const V3 rv = {q.w * dv.x - dq.w * va.x - (va.y * dv.z - va.z * dv.y),
+                       q.w * dv.y - dq.w * va.y - (va.z * dv.x - va.x * dv.z),
+                       q.w * dv.z - dq.w * va.z - (va.x * dv.y - va.y * dv.x)};
         const float C1 = L.P[P_C1][e], C3 = L.P[P_C3][e];
         const V3 m = {C1 * rv.x - L.P[P_D0][e], C1 * rv.y - L.P[P_D1][e], C3 * rv.z - L.P[P_D2][e]};
         const V3 tjb = tpb;                                   // tj goes to frame j
         const V3 tnb = sel(L.ok[e], (e == E - 1) ? tb_hi : TB[e + 1], V3{0.f, 0.f, 0.f});
         const float rwb = dot(m, tjb - tnb);
         const V3 cb = tjb + tnb;
-        const V3 mb_ = rw * (tjb - tnb) + cross(cb, rv);
-        const V3 rvb = cross(m, cb) + V3{C1 * mb_.x, C1 * mb_.y, C3 * mb_.z};
+        const V3 mb_ = fma3(rw, tjb - tnb, cross(cb, rv));
+        const V3 rvb = {m.y * cb.z - m.z * cb.y + C1 * mb_.x, m.z * cb.x - m.x * cb.z + C1 * mb_.y,
+                        m.x * cb.y - m.y * cb.x + C3 * mb_.z};
         gb += mb_.x * (C1b[e] * rv.x - D0b[e]) + mb_.y * (C1b[e] * rv.y - D1b[e]);
         gt += mb_.z * (C3b[e] * rv.z - D2b[e]);
         // rw = qa . qb ; rv = qa_w qb_v - qb_w qa_v - qa_v x qb_v
-        const V3 qav = (-qb.w) * rvb - cross(vb, rvb);
-        const V3 qbv = q.w * rvb - cross(rvb, va);
+        const V3 qav = fnma3(qb.w, rvb, cross(rvb, vb));
+        const V3 qbv = fma3(q.w, rvb, cross(va, rvb));
         const Q4 qa_b = {rwb * qb.w + dot(rvb, vb), rwb * qb.x + qav.x, rwb * qb.y + qav.y,
                          rwb * qb.z + qav.z};
         const Q4 qb_b = {rwb * q.w - dot(rvb, va), rwb * q.x + qbv.x, rwb * q.y + qbv.y,

@@ -82,6 +82,14 @@ struct Q4 {
 __device__ __forceinline__ V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
 __device__ __forceinline__ V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ __forceinline__ V3 operator*(float s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+// s a + b and b - s a with one rounding per component (explicit, so that the fused forms do
+// not depend on what the compiler sees around an inlined call)
+__device__ __forceinline__ V3 fma3(float s, V3 a, V3 b) {
+  return {__builtin_fmaf(s, a.x, b.x), __builtin_fmaf(s, a.y, b.y), __builtin_fmaf(s, a.z, b.z)};
+}
+__device__ __forceinline__ V3 fnma3(float s, V3 a, V3 b) {
+  return {__builtin_fmaf(-s, a.x, b.x), __builtin_fmaf(-s, a.y, b.y), __builtin_fmaf(-s, a.z, b.z)};
+}
 __device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 __device__ __forceinline__ V3 cross(V3 a, V3 b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
@@ -360,21 +368,23 @@ struct RodLane {
       const V3 d3 = {2.f * (xz + wy), 2.f * (yz - wx), ww - xx - yy + zz};
       const float lkp = P[P_LKP][e];
       const float td3 = dot(t, d3);
-      V3 f = (lkp * il) * (d3 - td3 * t);                        // penalty, eq. (8)
+      V3 f = (lkp * il) * fnma3(td3, t, d3);                     // penalty, eq. (8)
       const float len = len2 * il;
-      f = f - (P[P_KS_L][e] * (len - P[P_LEN][e])) * t;          // stretch, eq. (2)
+      f = fnma3(P[P_KS_L][e] * (len - P[P_LEN][e]), t, f);       // stretch, eq. (2)
       f = sel(ok[e], f, V3{0.f, 0.f, 0.f});                      // force on point j+1
       const V3 tpen = {-lkp * dot(d2, t), lkp * dot(d1, t), 0.f};  // l K_p e_3 x R^T t
       const Q4 qb = (e == E - 1) ? qn : Qf[e + 1];
       const Q4 dq = {qb.w - q.w, qb.x - q.x, qb.y - q.y, qb.z - q.z};
       const float rw = q.w * qb.w + q.x * qb.x + q.y * qb.y + q.z * qb.z;
       const V3 va = {q.x, q.y, q.z}, dv = {dq.x, dq.y, dq.z};
-      const V3 rv = q.w * dv - dq.w * va - cross(va, dv);        // vec(conj(q_j) (x) q_{j+1})
+      const V3 rv = {q.w * dv.x - dq.w * va.x - (va.y * dv.z - va.z * dv.y),
+                     q.w * dv.y - dq.w * va.y - (va.z * dv.x - va.x * dv.z),
+                     q.w * dv.z - dq.w * va.z - (va.x * dv.y - va.y * dv.x)};  // vec(conj(q_j) (x) q_{j+1})
       const V3 m = {P[P_C1][e] * rv.x - P[P_D0][e], P[P_C1][e] * rv.y - P[P_D1][e],
                     P[P_C3][e] * rv.z - P[P_D2][e]};             // K (u - uhat)
       const V3 rxm = cross(rv, m);
-      const V3 tj = sel(ok[e], rw * m + rxm, V3{0.f, 0.f, 0.f});  // on frame j
-      const V3 tn = sel(ok[e], rxm - rw * m, V3{0.f, 0.f, 0.f});  // on frame j+1
+      const V3 tj = sel(ok[e], fma3(rw, m, rxm), V3{0.f, 0.f, 0.f});   // on frame j
+      const V3 tn = sel(ok[e], fnma3(rw, m, rxm), V3{0.f, 0.f, 0.f});  // on frame j+1
       F[e] = f;
       if (e == 0) fs0 = f;
       else F[e - 1] = F[e - 1] - f;                              // reaction on point j
@@ -406,14 +416,14 @@ struct RodLane {
         Fe = Fe + V3{pf[0], pf[1], pf[2]};
         tau = tau + V3{pt[0], pt[1], pt[2]};
       }
-      const V3 a = P[P_WINV][e] * Fe + grav - rd.damp_lin * Vv[e];
-      Vv[e] = Vv[e] + dt * a;
+      const V3 a = fma3(P[P_WINV][e], Fe, fnma3(rd.damp_lin, Vv[e], grav));
+      Vv[e] = fma3(dt, a, Vv[e]);
       const V3 o = Om[e];
       const float i1 = P[P_IINV1][e], i3 = P[P_IINV3][e], kg = P[P_GYRO][e];
       const V3 al = {i1 * tau.x - kg * o.y * o.z - rd.damp_ang * o.x,
                      i1 * tau.y + kg * o.x * o.z - rd.damp_ang * o.y,
                      i3 * tau.z - rd.damp_ang * o.z};
-      Om[e] = o + dt * al;
+      Om[e] = fma3(dt, al, o);
     }
     if (g == 0) {
       if (ghost) {
@@ -427,7 +437,7 @@ struct RodLane {
           const float* pf = fext + 3 * rd.pt_off;
           Fb = Fb + V3{pf[0], pf[1], pf[2]};
         }
-        bv = bv + dt * (rd.winv0 * Fb + grav - rd.damp_lin * bv);
+        bv = fma3(dt, fma3(rd.winv0, Fb, fnma3(rd.damp_lin, bv, grav)), bv);
       }
     }
   }
@@ -459,11 +469,11 @@ struct RodLane {
       const V3 v_lo = (e == 0) ? vlo : Vv[e - 1];
       const V3 v_hi = (e == E - 1) ? vhi : Vv[e + 1];
       const V3 e_next = (e == E - 1) ? enext : Ev[e + 1];
-      const V3 d_hi = Ev[e] + dt * (Vv[e] - v_lo);
-      const V3 d_lo = e_next + dt * (v_hi - Vv[e]);
+      const V3 d_hi = fma3(dt, Vv[e] - v_lo, Ev[e]);
+      const V3 d_lo = fma3(dt, v_hi - Vv[e], e_next);
       const V3 im_hi = impulse_d(d_hi, P[P_CI][e], P[P_CIL][e]);
       const V3 im_lo = impulse_d(d_lo, P[P_CI_NEXT][e], P[P_CIL_NEXT][e]);
-      nv[e] = sel(is_hi, Vv[e] - w_me * im_hi, Vv[e] + w_me * im_lo);
+      nv[e] = sel(is_hi, fnma3(w_me, im_hi, Vv[e]), fma3(w_me, im_lo, Vv[e]));
       if (dsnap) dsnap[e] = sel(is_hi, d_hi, d_lo);
       if (e == 0) dvb = P[P_WINV_PREV][e] * im_hi;   // base point: left end of segment 0
     }
@@ -476,7 +486,7 @@ struct RodLane {
   __device__ __forceinline__ void integrate_velocities(const RodDev& rd, V3 xc, Q4 qc) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      X[e] = X[e] + dt * Vv[e];
+      X[e] = fma3(dt, Vv[e], X[e]);
       Qf[e] = advance_quat(Qf[e], Om[e], dt);
     }
     if (g == 0 && !ghost) {
@@ -484,7 +494,7 @@ struct RodLane {
         bx = xc;
         Qf[0] = qc;
       } else {
-        bx = bx + dt * bv;
+        bx = fma3(dt, bv, bx);
       }
     }
   }
