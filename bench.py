@@ -193,7 +193,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=20000)
     ap.add_argument("--shape", default="", help="W,E kernel shape (default: autotune)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched (4096 rods) and long-rod measurements")
+                    help="skip the batched (4096 rods), long-rod and adjoint measurements")
+    ap.add_argument("--extras", default="batch,long_rod,adjoint",
+                    help="comma-separated subset of batch,long_rod,adjoint to measure")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the rods of this workload are independent and a "
@@ -279,8 +281,8 @@ def main():
                      "frac_of_measured_copy": achieved / copy["GB/s"]},
     }
     if not args.no_extras:
-        out["extras"] = {"batch": batch_extras(R, W), "long_rod": long_rod_extras(R, W),
-                         "adjoint": adjoint_extras(R, W)}
+        fns = {"batch": batch_extras, "long_rod": long_rod_extras, "adjoint": adjoint_extras}
+        out["extras"] = {k: fns[k](R, W) for k in args.extras.split(",") if k}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -199,7 +199,7 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
               float mh[3] = {AVc[E - 1].x, AVc[E - 1].y, AVc[E - 1].z};
               float ml[3] = {AVc[0].x, AVc[0].y, AVc[0].z};
               float lo[3], hi[3];
-              exchange<W, 3, 3>(mh, lo, ml, hi, mb, par);
+              exchange<W, E, 3, 3>(mh, lo, ml, hi, mb, par);
               glo = {lo[0], lo[1], lo[2]};
               ghi = {hi[0], hi[1], hi[2]};
               if (g == 0) glo = abvc;
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
         float mh[3] = {FB[E - 1].x, FB[E - 1].y, FB[E - 1].z};
         float ml[3] = {TB[0].x, TB[0].y, TB[0].z};
         float lo[3], hi[3];
-        exchange<W, 3, 3>(mh, lo, ml, hi, mb, par);
+        exchange<W, E, 3, 3>(mh, lo, ml, hi, mb, par);
         fb_lo = {lo[0], lo[1], lo[2]};
         tb_hi = {hi[0], hi[1], hi[2]};
         if (g == 0) fb_lo = fb0;
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
         float mh[4] = {qb_last.w, qb_last.x, qb_last.y, qb_last.z};
         float ml[3] = {dneg_first.x, dneg_first.y, dneg_first.z};
         float lo[4], hi[3];
-        exchange<W, 4, 3>(mh, lo, ml, hi, mb, par);
+        exchange<W, E, 4, 3>(mh, lo, ml, hi, mb, par);
         // joint j-1's adjoint for frame j (from below); segment j+1's -d for point j+1 (above)
         const Q4 qfrom = {lo[0], lo[1], lo[2], lo[3]};
         const V3 dfrom = {hi[0], hi[1], hi[2]};

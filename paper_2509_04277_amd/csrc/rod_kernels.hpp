@@ -101,23 +101,24 @@ __device__ __forceinline__ Q4 sel4(bool c, Q4 a, Q4 b) {
   return {c ? a.w : b.w, c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
 }
 
-// DPP whole-wavefront shifts; the lane without a source receives 0.
+// DPP whole-wavefront shifts; the lane without a source receives 0 (bound_ctrl).
 __device__ __forceinline__ float from_lower_lane(float v) {  // lane i <- lane i-1
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float from_upper_lane(float v) {  // lane i <- lane i+1
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
 // Neighbour exchange across the rod's lanes.  `lo` receives the KL values `mine_hi` of the
 // lane below (its last slot), `hi` receives the KH values `mine_lo` of the lane above (its
-// first slot).  Global lane 0 and the last lane receive 0 (the caller substitutes).
+// first slot).  Global lane 0 and the last lane receive 0 (the caller substitutes).  E (the
+// elements per lane) only sets how much register room the reads may use.
 template <int W>
 struct Mailbox {
   float buf[2][W][2][8];
 };
 
-template <int W, int KL, int KH>
+template <int W, int E, int KL, int KH>
 __device__ __forceinline__ void exchange(const float (&mine_hi)[KL], float (&lo)[KL],
                                          const float (&mine_lo)[KH], float (&hi)[KH],
                                          Mailbox<W>& mb, int& parity) {
@@ -137,20 +138,42 @@ __device__ __forceinline__ void exchange(const float (&mine_hi)[KL], float (&lo)
       for (int k = 0; k < KH; ++k) mb.buf[parity][wave][0][k] = mine_lo[k];
     }
     __syncthreads();
-    // every lane reads the same (broadcast) word; only the wave's edge lanes keep it
+    // every lane reads the same (broadcast) words and only the wave's edge lanes keep them.
+    // Where registers allow, an empty asm consumes the loaded values so the loads stay
+    // unconditional (a load moved under the lane test becomes an exec-mask branch per word);
+    // 8 waves x 4 elements (256 registers) and 16 waves (128) would spill with all words live.
+    constexpr bool kPinLoads = (W <= 4) || (W <= 8 && E <= 2);
     const int wl = wave > 0 ? wave - 1 : 0;
     const int wh = wave < W - 1 ? wave + 1 : W - 1;
     const bool take_lo = (lane == 0) && (wave > 0);
     const bool take_hi = (lane == 63) && (wave < W - 1);
+    if constexpr (kPinLoads) {
+      float tl[KL], th[KH];
 #pragma unroll
-    for (int k = 0; k < KL; ++k) {
-      const float t = mb.buf[parity][wl][1][k];
-      lo[k] = take_lo ? t : lo[k];
-    }
+      for (int k = 0; k < KL; ++k) tl[k] = mb.buf[parity][wl][1][k];
 #pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      const float t = mb.buf[parity][wh][0][k];
-      hi[k] = take_hi ? t : hi[k];
+      for (int k = 0; k < KH; ++k) th[k] = mb.buf[parity][wh][0][k];
+#pragma unroll
+      for (int k = 0; k < KL; ++k) {
+        asm volatile("" : "+v"(tl[k]));
+        lo[k] = take_lo ? tl[k] : lo[k];
+      }
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        asm volatile("" : "+v"(th[k]));
+        hi[k] = take_hi ? th[k] : hi[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < KL; ++k) {
+        const float t = mb.buf[parity][wl][1][k];
+        lo[k] = take_lo ? t : lo[k];
+      }
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const float t = mb.buf[parity][wh][0][k];
+        hi[k] = take_hi ? t : hi[k];
+      }
     }
     parity ^= 1;
   }
@@ -336,7 +359,7 @@ struct RodLane {
     float mh[3] = {X[E - 1].x, X[E - 1].y, X[E - 1].z};
     float ml[4] = {Qf[0].w, Qf[0].x, Qf[0].y, Qf[0].z};
     float lo[3], hi[4];
-    exchange<W, 3, 4>(mh, lo, ml, hi, mb, par);
+    exchange<W, E, 3, 4>(mh, lo, ml, hi, mb, par);
     xl = {lo[0], lo[1], lo[2]};
     if (g == 0) xl = bx;
     qn = {hi[0], hi[1], hi[2], hi[3]};
@@ -394,7 +417,7 @@ struct RodLane {
     float mh[3] = {tn_prev.x, tn_prev.y, tn_prev.z};
     float ml[6] = {fs0.x, fs0.y, fs0.z, Ev[0].x, Ev[0].y, Ev[0].z};
     float lo[3], hi[6];
-    exchange<W, 3, 6>(mh, lo, ml, hi, mb, par);
+    exchange<W, E, 3, 6>(mh, lo, ml, hi, mb, par);
     T[0] = T[0] + V3{lo[0], lo[1], lo[2]};
     F[E - 1] = F[E - 1] - V3{hi[0], hi[1], hi[2]};
     enext = {hi[3], hi[4], hi[5]};
@@ -452,7 +475,7 @@ struct RodLane {
       float mh[3] = {Vv[E - 1].x, Vv[E - 1].y, Vv[E - 1].z};
       float ml[3] = {Vv[0].x, Vv[0].y, Vv[0].z};
       float lo[3], hi[3];
-      exchange<W, 3, 3>(mh, lo, ml, hi, mb, par);
+      exchange<W, E, 3, 3>(mh, lo, ml, hi, mb, par);
       vlo = {lo[0], lo[1], lo[2]};
       vhi = {hi[0], hi[1], hi[2]};
       if (g == 0) vlo = bv;
