@@ -20,6 +20,7 @@
 namespace corde {
 
 constexpr int kAdjointMaxIter = 10;   // constraint iterations the adjoint kernel holds
+constexpr int kAdjointMaxLanes = 512;  // lanes per rod of the widest adjoint kernel (8 waves)
 constexpr int P_WINV_NEXT = P_NROWS;  // extra coefficient row: inverse mass of point j+2
 
 __device__ __forceinline__ Q4 q_add(Q4 a, Q4 b) { return {a.w + b.w, a.x + b.x, a.y + b.y, a.z + b.z}; }
@@ -49,10 +50,9 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
     int prm_stride, const float* __restrict__ traj, long long traj_stride, int n_pts, int n_frames,
     int n_seg, long long tstep0, int tip0, const float* __restrict__ dtips, int tip_steps,
     float* __restrict__ ax, float* __restrict__ av, float* __restrict__ aq, float* __restrict__ aw,
-    float* __restrict__ gstep, const float* __restrict__ fext, const float* __restrict__ text,
+    double* __restrict__ gacc, const float* __restrict__ fext, const float* __restrict__ text,
     int* __restrict__ status) {
   __shared__ Mailbox<W> mb;
-  __shared__ float red[2][W];
   const int rod = rod_ids[blockIdx.x];
   const RodDev rd = rods[rod];
   RodLane<W, E> L;
@@ -104,19 +104,48 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
   }
   const int tip_lane = (rd.n - 1) / E, tip_e = (rd.n - 1) % E;
   const bool clamp0 = rd.clamp && g == 0;   // this lane holds the kinematic frame 0 / point 0
+  // this lane's multiplier gradients, accumulated in FP64 over all steps newest first (the
+  // same sequence of additions for every checkpoint interval) and kept between launches
+  double* acc = gacc + ((long long)rod * kAdjointMaxLanes + threadIdx.x) * 2;
+  double gb_acc = acc[0], gt_acc = acc[1];
+
+  // S_n and dL/dtip(n) of the next step to reverse are loaded one step ahead
+  RodLane<W, E> S;
+  S.off = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) S.ok[e] = L.ok[e];
+  S.g = g;
+  S.j0 = j0;
+  auto fetch = [&](int i, V3& dtip) {
+    const float* base = traj + (long long)i * traj_stride;
+    S.load_state(rd, base, base + 3 * n_pts, base + 6 * n_pts, base + 6 * n_pts + 4 * n_frames);
+    dtip = {0.f, 0.f, 0.f};
+    if (dtips && g == tip_lane) {
+      const float* pt = dtips + ((long long)rod * tip_steps + tip0 + i) * 3;
+      dtip = {pt[0], pt[1], pt[2]};
+    }
+  };
+  V3 dtip_next;
+  fetch(n_seg - 1, dtip_next);
 
   for (int i = n_seg - 1; i >= 0; --i) {
     float gb = 0.f, gt = 0.f;
     // ---- S_n, loss gradient of the tip after this step, clamp pose
-    {
-      const float* base = traj + (long long)i * traj_stride;
-      L.load_state(rd, base, base + 3 * n_pts, base + 6 * n_pts, base + 6 * n_pts + 4 * n_frames);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      L.X[e] = S.X[e];
+      L.Vv[e] = S.Vv[e];
+      L.Qf[e] = S.Qf[e];
+      L.Om[e] = S.Om[e];
     }
+    L.bx = S.bx;
+    L.bv = S.bv;
+    const V3 dtip = dtip_next;
+    if (i > 0) fetch(i - 1, dtip_next);
     if (dtips && g == tip_lane) {
-      const float* pt = dtips + ((long long)rod * tip_steps + tip0 + i) * 3;
 #pragma unroll
       for (int e = 0; e < E; ++e)
-        if (e == tip_e) AX[e] = AX[e] + V3{pt[0], pt[1], pt[2]};
+        if (e == tip_e) AX[e] = AX[e] + dtip;
     }
     V3 xc = {rd.cx0[0], rd.cx0[1], rd.cx0[2]}, wc = {0.f, 0.f, 0.f};
     Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
@@ -366,34 +395,14 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
       }
       abx = abxn;
     }
-    // this step's multiplier gradients: one value per rod and step (summed later in a fixed
-    // order, so the result does not depend on the checkpoint segmentation)
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      gb += __shfl_xor(gb, off);
-      gt += __shfl_xor(gt, off);
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-      red[0][wave] = gb;
-      red[1][wave] = gt;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      float sb = 0.f, st = 0.f;
-      for (int w = 0; w < W; ++w) {
-        sb += red[0][w];
-        st += red[1][w];
-      }
-      float* pg = gstep + ((long long)rod * tip_steps + tip0 + i) * 2;
-      pg[0] = sb;
-      pg[1] = st;
-      if (!__builtin_isfinite(sb + st)) atomicOr(status, 2);
-    }
-    __syncthreads();
+    gb_acc += (double)gb;
+    gt_acc += (double)gt;
   }
 
-  // ---- write lambda, reduce the stiffness-multiplier gradients over the workgroup
+  // ---- write lambda and this lane's multiplier-gradient accumulators
+  acc[0] = gb_acc;
+  acc[1] = gt_acc;
+  if (!__builtin_isfinite(gb_acc + gt_acc)) atomicOr(status, 2);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int j = j0 + e;
@@ -415,6 +424,22 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
     p[0] = abv.x; p[1] = abv.y; p[2] = abv.z;
   }
   if (g == 0 && !__builtin_isfinite(abx.x + abx.y + abx.z + abv.x + abv.y + abv.z)) atomicOr(status, 2);
+}
+
+// Per-rod stiffness-multiplier gradients: the lanes' FP64 accumulators summed in lane order
+// (one thread per rod; unused lanes hold 0).
+__global__ void sum_multiplier_grads(const double* __restrict__ gacc, int n_rods,
+                                     float* __restrict__ dbend, float* __restrict__ dtwist) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rods) return;
+  double sb = 0.0, st = 0.0;
+  const double* g = gacc + (long long)r * kAdjointMaxLanes * 2;
+  for (int l = 0; l < kAdjointMaxLanes; ++l) {
+    sb += g[2 * l];
+    st += g[2 * l + 1];
+  }
+  dbend[r] = (float)sb;
+  dtwist[r] = (float)st;
 }
 
 }  // namespace corde

@@ -552,9 +552,11 @@ __device__ __forceinline__ void clamp_for_step(const RodDev& rd, float (*cbuf)[1
 }
 
 // Forward kernel: steps one rod per workgroup n_steps times with the state in registers.
-// traj (nullable): the whole-handle state at the start of every step s is written to
-// traj + s * traj_stride, laid out as [x (3 n_pts) | v (3 n_pts) | q (4 n_frames) | w (3 n_frames)].
+// traj (nullable): the whole-handle state at the start of step s < traj_steps is written to
+// traj + s * traj_stride, laid out as [x (3 n_pts) | v (3 n_pts) | q (4 n_frames) | w (3 n_frames)]
+// (traj_steps = 1 writes a checkpoint of the launch's initial state).
 // tips (nullable): x_N after step s goes to tips[(rod * tip_steps + steps_done - tip_base + s) * 3].
+// store_final = 0 leaves gx..gw untouched (a recomputation that only needs traj).
 template <int W, int E>
 __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
     const RodDev* __restrict__ rods, const int* __restrict__ rod_ids, const float* __restrict__ prm,
@@ -562,7 +564,7 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
     float* __restrict__ gw, const float* __restrict__ fext, const float* __restrict__ text,
     int n_steps, long long steps_done, int* __restrict__ status, float* __restrict__ traj,
     long long traj_stride, int n_pts, int n_frames, float* __restrict__ tips, int tip_steps,
-    long long tip_base) {
+    long long tip_base, int traj_steps, int store_final) {
   __shared__ Mailbox<W> mb;
   __shared__ float cbuf[kClampChunk][10];
   const int rod = rod_ids[blockIdx.x];
@@ -576,7 +578,7 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
   const int tip_lane = (rd.n - 1) / E, tip_e = (rd.n - 1) % E;
 
   for (int s = 0; s < n_steps; ++s) {
-    if (traj) {
+    if (traj && s < traj_steps) {
       float* base = traj + (long long)s * traj_stride;
       L.store_state(rd, base, base + 3 * n_pts, base + 6 * n_pts, base + 6 * n_pts + 4 * n_frames);
     }
@@ -601,8 +603,10 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
         }
     }
   }
-  const float chk = L.store_state(rd, gx, gv, gq, gw);
-  if (!__builtin_isfinite(chk)) atomicOr(status, 1);
+  if (store_final) {
+    const float chk = L.store_state(rd, gx, gv, gq, gw);
+    if (!__builtin_isfinite(chk)) atomicOr(status, 1);
+  }
 }
 
 // ---------------------------------------------------------------------------------------

@@ -26,7 +26,7 @@ constexpr double kPi = 3.14159265358979323846;
 
 using KernelFn = void (*)(const RodDev*, const int*, const float*, int, float*, float*, float*,
                           float*, const float*, const float*, int, long long, int*, float*,
-                          long long, int, int, float*, int, long long);
+                          long long, int, int, float*, int, long long, int, int);
 using GridFn = void (*)(const RodDev*, const corde::GridChunk*, const int*, const float*, int,
                         float*, float*, float*, float*, const float*, const float*, int, long long,
                         int*, float*, int, int, int*, int);
@@ -37,7 +37,7 @@ constexpr int kLongMax = 1 << 17;    // longest rod accepted (its chunks must be
 
 using AdjointFn = void (*)(const RodDev*, const int*, const float*, int, const float*, long long,
                            int, int, int, long long, int, const float*, int, float*, float*,
-                           float*, float*, float*, const float*, const float*, int*);
+                           float*, float*, double*, const float*, const float*, int*);
 
 struct AdjointEntry {
   int waves, elems;
@@ -124,11 +124,14 @@ struct rod_ctx {
   long long adj_step0 = 0;
   float* d_ckpt = nullptr;   // adj_nckpt whole-handle states (checkpoints)
   float* d_traj = nullptr;   // states at the start of each step of a segment (or of all steps)
+  size_t cap_ckpt = 0, cap_traj = 0, cap_tips = 0, cap_dtips = 0, cap_state = 0;
   float* d_tips = nullptr;   // n_rods x adj_steps x 3
   float* d_dtips = nullptr;
   float* d_adj = nullptr;    // adjoint state, whole-handle state layout
-  float* d_work = nullptr;   // recompute state
-  float* d_gmult = nullptr;  // n_rods x adj_steps x 2: per-step multiplier gradients
+  double* d_gacc = nullptr;  // n_rods x 512 lanes x 2: FP64 multiplier-gradient accumulators
+  // the backward pass recomputes segment k-1 on a second stream while segment k is reversed
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_start = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
   float last_ms = 0.f;
   int last_launches = 0;
   bool timed = false;
@@ -465,7 +468,7 @@ rod_status launch_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long long
   hipLaunchKernelGGL(k->fn, dim3(b.count), dim3(64 * k->waves), 0, c->stream, c->d_rods,
                      c->d_rod_ids + b.first, c->d_prm, c->prm_stride, c->d_x, c->d_v, c->d_q,
                      c->d_w, c->d_fext, c->d_text, ks, done, c->d_status, nullptr, 0LL,
-                     c->total_pts, c->total_frames, nullptr, 0, 0LL);
+                     c->total_pts, c->total_frames, nullptr, 0, 0LL, 0, 1);
   HIP_TRY(c, hipGetLastError());
   return ROD_OK;
 }
@@ -509,25 +512,64 @@ const AdjointEntry* adjoint_shape(int max_n, int waves = 0, int elems = 0) {
 size_t state_floats(const rod_ctx* c) { return (size_t)6 * c->total_pts + (size_t)7 * c->total_frames; }
 
 void free_adjoint(rod_ctx* c) {
-  for (float** p : {&c->d_ckpt, &c->d_traj, &c->d_tips, &c->d_dtips, &c->d_adj, &c->d_work,
-                    &c->d_gmult}) {
+  for (float** p : {&c->d_ckpt, &c->d_traj, &c->d_tips, &c->d_dtips, &c->d_adj}) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
   }
+  if (c->d_gacc) (void)hipFree(c->d_gacc);
+  c->d_gacc = nullptr;
+  c->cap_ckpt = c->cap_traj = c->cap_tips = c->cap_dtips = c->cap_state = 0;
   c->adj_ready = false;
+}
+
+// Grows the adjoint buffers to hold a rollout of n_steps with checkpoints every ck steps
+// (allocations are kept between rollouts; a larger rollout reallocates).
+bool ensure_adjoint(rod_ctx* c, int n_steps, int ck) {
+  const size_t S = state_floats(c);
+  const int nck = (n_steps + ck - 1) / ck;
+  const size_t need_ckpt = ck == 1 ? 1 : (size_t)nck * S;
+  const size_t need_traj = (ck == 1 ? (size_t)n_steps : 2 * (size_t)ck) * S;   // 2: ping-pong
+  const size_t need_tips = (size_t)3 * c->n_rods * n_steps;
+  auto grow = [&](float** p, size_t* cap, size_t n) {
+    if (*p && *cap >= n) return true;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    if (hipMalloc((void**)p, sizeof(float) * std::max<size_t>(n, 1)) != hipSuccess) {
+      *p = nullptr;
+      return false;
+    }
+    *cap = n;
+    return true;
+  };
+  if (!c->aux) {
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
+      c->aux = nullptr;
+      return false;
+    }
+    for (hipEvent_t* e : {&c->ev_start, &c->ev_rec[0], &c->ev_rec[1], &c->ev_rev[0], &c->ev_rev[1]})
+      if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return false;
+  }
+  return grow(&c->d_ckpt, &c->cap_ckpt, need_ckpt) && grow(&c->d_traj, &c->cap_traj, need_traj) &&
+         grow(&c->d_tips, &c->cap_tips, need_tips) && grow(&c->d_dtips, &c->cap_dtips, need_tips) &&
+         grow(&c->d_adj, &c->cap_state, S) &&
+         (c->d_gacc || hipMalloc((void**)&c->d_gacc, sizeof(double) * 2 * corde::kAdjointMaxLanes *
+                                                         (size_t)c->n_rods) == hipSuccess);
 }
 
 // Launches the forward kernel of every bucket on the given state arrays.
 rod_status launch_forward_on(rod_ctx* c, float* x, float* v, float* q, float* w, int ks,
-                             long long step, float* traj, float* tips, long long tip_base) {
+                             long long step, float* traj, float* tips, long long tip_base,
+                             int traj_steps, int store_final, hipStream_t stream = nullptr) {
+  if (!stream) stream = c->stream;
   const long long S = (long long)state_floats(c);
   for (const auto& b : c->buckets) {
     const KernelEntry* k = find_kernel(b.waves, b.elems);
     if (!k) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
-    hipLaunchKernelGGL(k->fn, dim3(b.count), dim3(64 * k->waves), 0, c->stream, c->d_rods,
+    hipLaunchKernelGGL(k->fn, dim3(b.count), dim3(64 * k->waves), 0, stream, c->d_rods,
                        c->d_rod_ids + b.first, c->d_prm, c->prm_stride, x, v, q, w, c->d_fext,
                        c->d_text, ks, step, c->d_status, traj, S, c->total_pts, c->total_frames,
-                       tips, c->adj_steps, tip_base);
+                       tips, c->adj_steps, tip_base, traj_steps, store_final);
     HIP_TRY(c, hipGetLastError());
   }
   return ROD_OK;
@@ -680,12 +722,18 @@ rod_status rod_destroy(rod_ctx* c) {
   for (void* p : {(void*)c->d_rods, (void*)c->d_prm, (void*)c->d_x, (void*)c->d_v,
                   (void*)c->d_q, (void*)c->d_w, (void*)c->d_fext, (void*)c->d_text,
                   (void*)c->d_status, (void*)c->d_rod_ids, (void*)c->d_ckpt, (void*)c->d_traj,
-                  (void*)c->d_tips, (void*)c->d_dtips, (void*)c->d_adj, (void*)c->d_work,
-                  (void*)c->d_gmult, (void*)c->d_chunks, (void*)c->d_block_chunk, (void*)c->d_pub,
+                  (void*)c->d_tips, (void*)c->d_dtips, (void*)c->d_adj,
+                  (void*)c->d_gacc, (void*)c->d_chunks, (void*)c->d_block_chunk, (void*)c->d_pub,
                   (void*)c->d_flags})
     if (p) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->aux) {
+    (void)hipStreamSynchronize(c->aux);
+    (void)hipStreamDestroy(c->aux);
+  }
+  for (hipEvent_t e : {c->ev_start, c->ev_rec[0], c->ev_rec[1], c->ev_rev[0], c->ev_rev[1]})
+    if (e) (void)hipEventDestroy(e);
   delete c;
   return ROD_OK;
 }
@@ -972,16 +1020,11 @@ rod_status rod_adjoint_forward(rod_ctx* c, int32_t n_steps, int32_t ckpt_every, 
   for (const auto& b : c->buckets)
     if (!adjoint_shape(b.max_n)) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
   if (c->n_chunks) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
-  free_adjoint(c);
+  c->adj_ready = false;
   const size_t S = state_floats(c);
   const int ck = std::min(ckpt_every, n_steps);
   const int nck = (n_steps + ck - 1) / ck;
-  const size_t traj_states = ck == 1 ? (size_t)n_steps : (size_t)ck;
-  auto dm = [&](float** p, size_t n) { return hipMalloc((void**)p, sizeof(float) * std::max<size_t>(n, 1)) == hipSuccess; };
-  if (!dm(&c->d_ckpt, ck == 1 ? 1 : nck * S) || !dm(&c->d_traj, traj_states * S) ||
-      !dm(&c->d_tips, (size_t)3 * c->n_rods * n_steps) || !dm(&c->d_dtips, (size_t)3 * c->n_rods * n_steps) ||
-      !dm(&c->d_adj, S) || !dm(&c->d_work, S) ||
-      !dm(&c->d_gmult, 2 * (size_t)c->n_rods * n_steps)) {
+  if (!ensure_adjoint(c, n_steps, ck)) {
     free_adjoint(c);
     return fail(c, ROD_E_NOMEM, "adjoint buffers do not fit");
   }
@@ -989,22 +1032,12 @@ rod_status rod_adjoint_forward(rod_ctx* c, int32_t n_steps, int32_t ckpt_every, 
   c->adj_ckpt = ck;
   c->adj_nckpt = nck;
   c->adj_step0 = c->steps_done;
-  const size_t P3 = (size_t)3 * c->total_pts, F4 = (size_t)4 * c->total_frames;
   for (int seg = 0; seg < nck; ++seg) {
     const int len = std::min(ck, n_steps - seg * ck);
-    float* traj = nullptr;
-    if (ck == 1) {
-      traj = c->d_traj + (size_t)seg * S;
-    } else {
-      float* dst = c->d_ckpt + (size_t)seg * S;
-      HIP_TRY(c, hipMemcpyAsync(dst, c->d_x, sizeof(float) * P3, hipMemcpyDeviceToDevice, c->stream));
-      HIP_TRY(c, hipMemcpyAsync(dst + P3, c->d_v, sizeof(float) * P3, hipMemcpyDeviceToDevice, c->stream));
-      HIP_TRY(c, hipMemcpyAsync(dst + 2 * P3, c->d_q, sizeof(float) * F4, hipMemcpyDeviceToDevice, c->stream));
-      HIP_TRY(c, hipMemcpyAsync(dst + 2 * P3 + F4, c->d_w, sizeof(float) * 3 * c->total_frames,
-                                hipMemcpyDeviceToDevice, c->stream));
-    }
+    // the launch writes its initial state: the checkpoint (or, with ck = 1, the stored step)
+    float* traj = (ck == 1 ? c->d_traj : c->d_ckpt) + (size_t)seg * S;
     rod_status st = launch_forward_on(c, c->d_x, c->d_v, c->d_q, c->d_w, len, c->steps_done, traj,
-                                      c->d_tips, c->adj_step0);
+                                      c->d_tips, c->adj_step0, 1, 1);
     if (st != ROD_OK) return st;
     c->steps_done += len;
   }
@@ -1029,31 +1062,60 @@ rod_status rod_adjoint_backward(rod_ctx* c, const float* dl_dtips, float* dl_dbe
   const hipMemcpyKind kin = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   HIP_TRY(c, hipMemcpyAsync(c->d_dtips, dl_dtips, sizeof(float) * 3 * c->n_rods * c->adj_steps, kin, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d_adj, 0, sizeof(float) * S, c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->d_gmult, 0, sizeof(float) * 2 * c->n_rods * c->adj_steps, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_gacc, 0, sizeof(double) * 2 * corde::kAdjointMaxLanes * c->n_rods,
+                            c->stream));
   const long long Sl = (long long)S;
-  for (int seg = c->adj_nckpt - 1; seg >= 0; --seg) {
-    const int len = std::min(c->adj_ckpt, c->adj_steps - seg * c->adj_ckpt);
-    const long long tstep0 = c->adj_step0 + (long long)seg * c->adj_ckpt;
-    const float* traj;
-    if (c->adj_ckpt == 1) {
-      traj = c->d_traj + (size_t)seg * S;
-    } else {
-      // recompute the segment from its checkpoint, storing the state at every step start
-      HIP_TRY(c, hipMemcpyAsync(c->d_work, c->d_ckpt + (size_t)seg * S, sizeof(float) * S,
-                                hipMemcpyDeviceToDevice, c->stream));
-      rod_status st = launch_forward_on(c, c->d_work, c->d_work + P3, c->d_work + 2 * P3,
-                                        c->d_work + 2 * P3 + F4, len, tstep0, c->d_traj, nullptr, 0);
-      if (st != ROD_OK) return st;
-      traj = c->d_traj;
-    }
+  const int nck = c->adj_nckpt, ck = c->adj_ckpt;
+  auto reverse = [&](int seg, const float* traj) -> rod_status {
+    const int len = std::min(ck, c->adj_steps - seg * ck);
+    const long long tstep0 = c->adj_step0 + (long long)seg * ck;
     for (const auto& b : c->buckets) {
       const AdjointEntry* a = adjoint_shape(b.max_n, b.waves, b.elems);
+      if (!a || 64 * a->waves > corde::kAdjointMaxLanes)
+        return fail(c, ROD_E_UNSUPPORTED, "no adjoint kernel for this bucket");
       hipLaunchKernelGGL(a->fn, dim3(b.count), dim3(64 * a->waves), 0, c->stream, c->d_rods,
                          c->d_rod_ids + b.first, c->d_prm, c->prm_stride, traj, Sl, c->total_pts,
-                         c->total_frames, len, tstep0, seg * c->adj_ckpt, c->d_dtips, c->adj_steps,
+                         c->total_frames, len, tstep0, seg * ck, c->d_dtips, c->adj_steps,
                          c->d_adj, c->d_adj + P3, c->d_adj + 2 * P3, c->d_adj + 2 * P3 + F4,
-                         c->d_gmult, c->d_fext, c->d_text, c->d_status);
+                         c->d_gacc, c->d_fext, c->d_text, c->d_status);
       HIP_TRY(c, hipGetLastError());
+    }
+    return ROD_OK;
+  };
+  if (ck == 1) {
+    for (int seg = nck - 1; seg >= 0; --seg) {
+      rod_status st = reverse(seg, c->d_traj + (size_t)seg * S);
+      if (st != ROD_OK) return st;
+    }
+  } else {
+    // segment k - 1 is recomputed from its checkpoint (every step start stored in one of two
+    // buffers) on the second stream while segment k is reversed on the handle's stream
+    float* tb[2] = {c->d_traj, c->d_traj + (size_t)ck * S};
+    auto recompute = [&](int seg) -> rod_status {
+      const int len = std::min(ck, c->adj_steps - seg * ck);
+      const long long tstep0 = c->adj_step0 + (long long)seg * ck;
+      float* cp = c->d_ckpt + (size_t)seg * S;
+      rod_status st = launch_forward_on(c, cp, cp + P3, cp + 2 * P3, cp + 2 * P3 + F4, len, tstep0,
+                                        tb[seg & 1], nullptr, 0, len, 0, c->aux);
+      if (st != ROD_OK) return st;
+      HIP_TRY(c, hipEventRecord(c->ev_rec[seg & 1], c->aux));
+      return ROD_OK;
+    };
+    HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
+    HIP_TRY(c, hipStreamWaitEvent(c->aux, c->ev_start, 0));
+    rod_status st = recompute(nck - 1);
+    if (st != ROD_OK) return st;
+    for (int seg = nck - 1; seg >= 0; --seg) {
+      HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_rec[seg & 1], 0));
+      st = reverse(seg, tb[seg & 1]);
+      if (st != ROD_OK) return st;
+      HIP_TRY(c, hipEventRecord(c->ev_rev[seg & 1], c->stream));
+      if (seg > 0) {
+        // buffer (seg - 1) & 1 was last read by the reverse pass of segment seg + 1
+        if (seg + 1 < nck) HIP_TRY(c, hipStreamWaitEvent(c->aux, c->ev_rev[(seg + 1) & 1], 0));
+        st = recompute(seg - 1);
+        if (st != ROD_OK) return st;
+      }
     }
   }
   const hipMemcpyKind kout = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -1061,23 +1123,20 @@ rod_status rod_adjoint_backward(rod_ctx* c, const float* dl_dtips, float* dl_dbe
   if (dl_dv) HIP_TRY(c, hipMemcpyAsync(dl_dv, c->d_adj + P3, sizeof(float) * P3, kout, c->stream));
   if (dl_dq) HIP_TRY(c, hipMemcpyAsync(dl_dq, c->d_adj + 2 * P3, sizeof(float) * F4, kout, c->stream));
   if (dl_dw) HIP_TRY(c, hipMemcpyAsync(dl_dw, c->d_adj + 2 * P3 + F4, sizeof(float) * 3 * c->total_frames, kout, c->stream));
-  std::vector<float> gm(2 * (size_t)c->n_rods * c->adj_steps);
-  HIP_TRY(c, hipMemcpyAsync(gm.data(), c->d_gmult, sizeof(float) * gm.size(), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  std::vector<float> gb(c->n_rods), gt(c->n_rods);
-  for (int r = 0; r < c->n_rods; ++r) {   // fixed summation order over the steps, in FP64
-    double sb = 0.0, st = 0.0;
-    for (int s = 0; s < c->adj_steps; ++s) {
-      sb += gm[((size_t)r * c->adj_steps + s) * 2];
-      st += gm[((size_t)r * c->adj_steps + s) * 2 + 1];
-    }
-    gb[r] = (float)sb;
-    gt[r] = (float)st;
+  if (dl_dbend || dl_dtwist) {
+    // fixed-order FP64 sums over the steps, into the first 2 n_rods floats of d_dtips (the
+    // loss gradient is no longer needed) and from there to the caller
+    float* gb = c->d_dtips;
+    float* gt = c->d_dtips + c->n_rods;
+    hipLaunchKernelGGL(corde::sum_multiplier_grads, dim3((c->n_rods + 63) / 64), dim3(64), 0,
+                       c->stream, c->d_gacc, c->n_rods, gb, gt);
+    HIP_TRY(c, hipGetLastError());
+    if (dl_dbend) HIP_TRY(c, hipMemcpyAsync(dl_dbend, gb, sizeof(float) * c->n_rods, kout, c->stream));
+    if (dl_dtwist) HIP_TRY(c, hipMemcpyAsync(dl_dtwist, gt, sizeof(float) * c->n_rods, kout, c->stream));
   }
-  if (dl_dbend) HIP_TRY(c, hipMemcpy(dl_dbend, gb.data(), sizeof(float) * c->n_rods, on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
-  if (dl_dtwist) HIP_TRY(c, hipMemcpy(dl_dtwist, gt.data(), sizeof(float) * c->n_rods, on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
   int stt = 0;
-  HIP_TRY(c, hipMemcpy(&stt, c->d_status, sizeof(int), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpyAsync(&stt, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (stt) return fail(c, ROD_E_UNSTABLE, "non-finite value in the adjoint");
   return ROD_OK;
 }
