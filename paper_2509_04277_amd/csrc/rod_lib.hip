@@ -132,6 +132,10 @@ struct rod_ctx {
   // the backward pass recomputes segment k-1 on a second stream while segment k is reversed
   hipStream_t aux = nullptr;
   hipEvent_t ev_start = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
+  // one stream per bucket (and one for the chunked long rods): buckets step concurrently
+  std::vector<hipStream_t> bstreams;
+  std::vector<hipEvent_t> bevents;
+  hipEvent_t ev_fork = nullptr;
   float last_ms = 0.f;
   int last_launches = 0;
   bool timed = false;
@@ -333,7 +337,10 @@ rod_status make_buckets(rod_ctx* c, ShapeFn shape) {
     if (c->n[r] > c->chunk_above) continue;   // long rods run chunked
     int w, e;
     shape(r, &w, &e);
-    key.push_back({((long long)(w * 16 + e) << 32) | (long long)(0x7fffffff - c->n[r]), r});
+    // within a bucket, most work first (a constraint iteration costs about a quarter of the
+    // rest of a step), so the last workgroups dispatched are the cheap ones
+    const long long cost = (long long)c->n[r] * (4 + c->rods[r].n_iter);
+    key.push_back({((long long)(w * 16 + e) << 32) | (0x7fffffffLL - cost), r});
   }
   std::sort(key.begin(), key.end());
   c->buckets.clear();
@@ -435,7 +442,8 @@ rod_status setup_long_rods(rod_ctx* c) {
 }
 
 // Chunked long rods: one cooperative launch of ks steps.
-rod_status launch_long(rod_ctx* c, float* x, float* v, float* q, float* w, int ks, long long done) {
+rod_status launch_long(rod_ctx* c, float* x, float* v, float* q, float* w, int ks, long long done,
+                       hipStream_t stream) {
   if (!c->n_chunks) return ROD_OK;
   int spin = 1 << 22;
   const RodDev* rods = c->d_rods;
@@ -452,7 +460,7 @@ rod_status launch_long(rod_ctx* c, float* x, float* v, float* q, float* w, int k
   void* args[] = {&rods, &chunks, &bc, &prm, &stride, &x, &v, &q, &w, &fe, &te, &ks, &done,
                   &st, &pub, &ps, &nc, &fl, &spin};
   HIP_TRY(c, hipLaunchCooperativeKernel((const void*)grid_kernel(), dim3(c->n_chunks),
-                                        dim3(64 * kGridWaves), args, 0, c->stream));
+                                        dim3(64 * kGridWaves), args, 0, stream));
   return ROD_OK;
 }
 
@@ -462,10 +470,11 @@ rod_status reset_flags(rod_ctx* c) {
   return ROD_OK;
 }
 
-rod_status launch_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long long done) {
+rod_status launch_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long long done,
+                         hipStream_t stream) {
   const KernelEntry* k = find_kernel(b.waves, b.elems);
   if (!k) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
-  hipLaunchKernelGGL(k->fn, dim3(b.count), dim3(64 * k->waves), 0, c->stream, c->d_rods,
+  hipLaunchKernelGGL(k->fn, dim3(b.count), dim3(64 * k->waves), 0, stream, c->d_rods,
                      c->d_rod_ids + b.first, c->d_prm, c->prm_stride, c->d_x, c->d_v, c->d_q,
                      c->d_w, c->d_fext, c->d_text, ks, done, c->d_status, nullptr, 0LL,
                      c->total_pts, c->total_frames, nullptr, 0, 0LL, 0, 1);
@@ -477,17 +486,48 @@ rod_status launch_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long long
 rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it, int bucket = -1) {
   if (time_it) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
   int launches = 0;
-  for (int done = 0; done < n_steps; done += spl) {
-    const int ks = std::min(spl, n_steps - done);
-    for (int b = 0; b < (int)c->buckets.size(); ++b) {
-      if (bucket >= 0 && b != bucket) continue;
-      rod_status st = launch_bucket(c, c->buckets[b], ks, c->steps_done + done);
-      if (st != ROD_OK) return st;
+  // the buckets are independent: with several, each steps on its own stream (forked from and
+  // joined back to the handle's stream)
+  const int nb = bucket >= 0 ? 1 : (int)c->buckets.size();
+  const bool fork = nb > 1;
+  if (fork) {
+    while ((int)c->bstreams.size() < nb) {
+      hipStream_t st = nullptr;
+      hipEvent_t ev = nullptr;
+      HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      c->bstreams.push_back(st);
+      HIP_TRY(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      c->bevents.push_back(ev);
+    }
+    if (!c->ev_fork) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
+  }
+  for (int gi = 0; gi < nb; ++gi) {
+    hipStream_t st = c->stream;
+    if (fork) {
+      st = c->bstreams[gi];
+      HIP_TRY(c, hipStreamWaitEvent(st, c->ev_fork, 0));
+    }
+    for (int done = 0; done < n_steps; done += spl) {
+      const int ks = std::min(spl, n_steps - done);
+      rod_status rs = launch_bucket(c, c->buckets[bucket >= 0 ? bucket : gi], ks,
+                                    c->steps_done + done, st);
+      if (rs != ROD_OK) return rs;
       ++launches;
     }
-    if (bucket < 0 && c->n_chunks) {
-      rod_status st = launch_long(c, c->d_x, c->d_v, c->d_q, c->d_w, ks, c->steps_done + done);
-      if (st != ROD_OK) return st;
+    if (fork) {
+      HIP_TRY(c, hipEventRecord(c->bevents[gi], st));
+      HIP_TRY(c, hipStreamWaitEvent(c->stream, c->bevents[gi], 0));
+    }
+  }
+  // chunked long rods on the handle's stream, after the buckets: their cooperative launch
+  // must find every chunk's workgroup resident together
+  if (bucket < 0 && c->n_chunks) {
+    for (int done = 0; done < n_steps; done += spl) {
+      const int ks = std::min(spl, n_steps - done);
+      rod_status rs = launch_long(c, c->d_x, c->d_v, c->d_q, c->d_w, ks, c->steps_done + done,
+                                  c->stream);
+      if (rs != ROD_OK) return rs;
       ++launches;
     }
   }
@@ -732,6 +772,12 @@ rod_status rod_destroy(rod_ctx* c) {
     (void)hipStreamSynchronize(c->aux);
     (void)hipStreamDestroy(c->aux);
   }
+  for (hipStream_t st : c->bstreams) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  for (hipEvent_t e : c->bevents) (void)hipEventDestroy(e);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   for (hipEvent_t e : {c->ev_start, c->ev_rec[0], c->ev_rec[1], c->ev_rev[0], c->ev_rev[1]})
     if (e) (void)hipEventDestroy(e);
   delete c;
