@@ -629,6 +629,15 @@ struct GridChunk {
 
 constexpr int kPubSlotFloats = 13;   // x, v (point j+1), q, w (frame j)
 
+// Mailbox words are read and written as device-scope relaxed atomics (coherent across the
+// XCDs' L2 caches without writing back or invalidating them); the step flags order them.
+__device__ __forceinline__ void put_coherent(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float get_coherent(const float* p) {
+  return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int W, int E>
 __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
     const RodDev* __restrict__ rods, const GridChunk* __restrict__ chunks,
@@ -675,30 +684,30 @@ __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int o = L.j0 + e - own_lo;   // owned index
+      // (with several chunks c >= 2 H + 2, so no slot is in both parts)
       const bool p0 = L.ok[e] && o >= 0 && o < H && ck.left >= 0;
       const bool p1 = L.ok[e] && o >= ck.c - H - 1 && o < ck.c && ck.right >= 0;
       if (p0 || p1) {
         float* d = mine + (p0 ? o : pub_slots + o - (ck.c - H - 1)) * kPubSlotFloats;
-        d[0] = L.X[e].x; d[1] = L.X[e].y; d[2] = L.X[e].z;
-        d[3] = L.Vv[e].x; d[4] = L.Vv[e].y; d[5] = L.Vv[e].z;
-        d[6] = L.Qf[e].w; d[7] = L.Qf[e].x; d[8] = L.Qf[e].y; d[9] = L.Qf[e].z;
-        d[10] = L.Om[e].x; d[11] = L.Om[e].y; d[12] = L.Om[e].z;
-        if (p0 && p1) {   // a slot in both parts (c < 2 H + 1)
-          float* d1 = mine + (pub_slots + o - (ck.c - H - 1)) * kPubSlotFloats;
-          for (int k = 0; k < kPubSlotFloats; ++k) d1[k] = d[k];
-        }
+        const float v[kPubSlotFloats] = {L.X[e].x, L.X[e].y, L.X[e].z, L.Vv[e].x, L.Vv[e].y,
+                                         L.Vv[e].z, L.Qf[e].w, L.Qf[e].x, L.Qf[e].y, L.Qf[e].z,
+                                         L.Om[e].x, L.Om[e].y, L.Om[e].z};
+#pragma unroll
+        for (int k = 0; k < kPubSlotFloats; ++k) put_coherent(d + k, v[k]);
       }
     }
-    __threadfence();
+    // this thread's mailbox stores are complete (device-visible) before the barrier, and the
+    // flag is raised after it
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
-      __hip_atomic_store(&flags[ci], (int)(gs + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&flags[ci], (int)(gs + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       // wait for both neighbours to have published this step (bounded spin)
       int spins = 0;
       for (int side = 0; side < 2; ++side) {
         const int nb = side == 0 ? ck.left : ck.right;
         if (nb < 0) continue;
-        while (__hip_atomic_load(&flags[nb], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (int)(gs + 1)) {
+        while (__hip_atomic_load(&flags[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (int)(gs + 1)) {
           __builtin_amdgcn_s_sleep(1);
           if (++spins > spin_limit) {
             abort_flag = 1;
@@ -707,8 +716,7 @@ __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
         }
       }
     }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();   // the neighbours' words are read (device-coherent) only after this
     if (abort_flag) {
       if (threadIdx.x == 0) atomicOr(status, 4);
       break;
@@ -727,15 +735,18 @@ __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
       if (L.ok[e] && o < 0 && lp) src = lp + (o + H + 1) * kPubSlotFloats;   // slot s0 + o
       if (L.ok[e] && o >= ck.c && rp) src = rp + (o - ck.c) * kPubSlotFloats;
       if (src) {
-        L.X[e] = {src[0], src[1], src[2]};
-        L.Vv[e] = {src[3], src[4], src[5]};
-        L.Qf[e] = {src[6], src[7], src[8], src[9]};
-        L.Om[e] = {src[10], src[11], src[12]};
+        float v[kPubSlotFloats];
+#pragma unroll
+        for (int k = 0; k < kPubSlotFloats; ++k) v[k] = get_coherent(src + k);
+        L.X[e] = {v[0], v[1], v[2]};
+        L.Vv[e] = {v[3], v[4], v[5]};
+        L.Qf[e] = {v[6], v[7], v[8], v[9]};
+        L.Om[e] = {v[10], v[11], v[12]};
       }
     }
     if (L.g == 0 && L.ghost && lp) {   // halo-edge point: point win0 = point of slot win0 - 1
-      L.bx = {lp[0], lp[1], lp[2]};
-      L.bv = {lp[3], lp[4], lp[5]};
+      L.bx = {get_coherent(lp), get_coherent(lp + 1), get_coherent(lp + 2)};
+      L.bv = {get_coherent(lp + 3), get_coherent(lp + 4), get_coherent(lp + 5)};
     }
   }
   const float chk = L.store_state(rd, gx, gv, gq, gw, own_lo, own_hi);

@@ -81,18 +81,19 @@ def test_chunked_is_bitwise_single_workgroup(case):
             assert np.array_equal(u, v)
 
 
-@pytest.mark.parametrize("inext", [True, False])
-def test_chunked_matches_wider_single_workgroup(oracle, inext):
-    """A 2000-element rod in 5 chunks against the same rod in one 8-wave x 4-element
-    workgroup: multiply-adds are fused only within a source expression, so the grouping of
-    elements into lanes does not change any element's arithmetic."""
+@pytest.mark.parametrize("inext,chunk", [(True, 0), (False, 0), (True, 60), (False, 60)])
+def test_chunked_matches_wider_single_workgroup(oracle, inext, chunk):
+    """A 2000-element rod in 5 chunks (or 34 of about 60 elements, most neighbours on other
+    XCDs) against the same rod in one 8-wave x 4-element workgroup: multiply-adds are fused
+    only within a source expression, so the grouping of elements into lanes does not change
+    any element's arithmetic, and the halo exchange must deliver every neighbour value."""
     wl = W.config2(2000, inext)
     L = float(np.sum(wl.rods[0][0].seg_len))
     n_steps = 300
     one, info1 = _run(wl.rods, n_steps, 10)
-    many, info2 = _run(wl.rods, n_steps, 10, chunk_above=1024)
-    _say("1x2000 %s, %d steps; buckets single %s, chunked %s"
-         % ("inext" if inext else "ext", n_steps, info1, info2))
+    many, info2 = _run(wl.rods, n_steps, 10, chunk_above=1024, chunk=chunk)
+    _say("1x2000 %s, %d steps, chunk %d; buckets single %s, chunked %s"
+         % ("inext" if inext else "ext", n_steps, chunk, info1, info2))
     assert info2 == [(4, 2, 1, 0.0)]
     (x1, v1, q1, w1), (x2, v2, q2, w2) = one[0], many[0]
     dx, dq = np.abs(x1 - x2).max(), np.abs(q1 - q2).max()
