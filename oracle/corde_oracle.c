@@ -362,12 +362,22 @@ static void project_segment(const oracle_rod* rod, int j, const double* x, doubl
     }
 }
 
-void oracle_step(const oracle_rod* rod, double t, double* x, double* v, double* q, double* w) {
+/* The phases of one step (Sec. 2.1; Fig. 5 without collisions): forces and their integration
+ * with the clamp velocities (first), the distance constraints of one iteration (middle), and the
+ * velocity integration with the clamp pose (last). */
+typedef struct {
+    double* winv;
+    double xc[3], qc[4], wc[3];
+} step_scratch;
+
+static void step_first(const oracle_rod* rod, double t, const double* x, double* v, const double* q,
+                       double* w, step_scratch* sc) {
     const int n = rod->n;
     const double dt = rod->dt;
     double* F = (double*)malloc(sizeof(double) * 3 * (n + 1));
     double* tau = (double*)malloc(sizeof(double) * 3 * n);
-    double* winv = (double*)malloc(sizeof(double) * (n + 1));
+    sc->winv = (double*)malloc(sizeof(double) * (n + 1));
+    double* winv = sc->winv;
 
     /* forces and torques from the start-of-step configuration */
     oracle_forces(rod, x, q, F, tau);
@@ -399,20 +409,27 @@ void oracle_step(const oracle_rod* rod, double t, double* x, double* v, double* 
         }
         for (int a = 0; a < 3; ++a) wj[a] += dt * (tq[a] / I[a] - rod->damp_ang * wj[a]);
     }
-    double xc[3], qc[4], wc[3];
     if (rod->clamp) {
-        oracle_clamp_pose(rod, t + dt, xc, qc, wc);
+        oracle_clamp_pose(rod, t + dt, sc->xc, sc->qc, sc->wc);
         for (int c = 0; c < 3; ++c) {
-            v[c] = (xc[c] - x[c]) / dt;
-            w[c] = wc[c];
+            v[c] = (sc->xc[c] - x[c]) / dt;
+            w[c] = sc->wc[c];
         }
     }
-    /* inextensible variant: red-black Gauss-Seidel over the distance constraints */
-    if (rod->inextensible) {
-        for (int it = 0; it < rod->n_iter; ++it)
-            for (int parity = 0; parity < 2; ++parity)
-                for (int j = parity; j < n; j += 2) project_segment(rod, j, x, v, winv);
-    }
+    free(F);
+    free(tau);
+}
+
+/* one constraint iteration of the inextensible variant: red-black Gauss-Seidel sweeps */
+static void step_sweeps(const oracle_rod* rod, const double* x, double* v, const step_scratch* sc) {
+    for (int parity = 0; parity < 2; ++parity)
+        for (int j = parity; j < rod->n; j += 2) project_segment(rod, j, x, v, sc->winv);
+}
+
+static void step_last(const oracle_rod* rod, double* x, const double* v, double* q, const double* w,
+                      step_scratch* sc) {
+    const int n = rod->n;
+    const double dt = rod->dt;
     /* integrate velocities */
     for (int i = 0; i <= n; ++i)
         for (int c = 0; c < 3; ++c) x[3 * i + c] += dt * v[3 * i + c];
@@ -430,12 +447,67 @@ void oracle_step(const oracle_rod* rod, double t, double* x, double* v, double* 
         for (int a = 0; a < 4; ++a) qj[a] /= nq;
     }
     if (rod->clamp) {
-        for (int c = 0; c < 3; ++c) x[c] = xc[c];
-        for (int a = 0; a < 4; ++a) q[a] = qc[a];
+        for (int c = 0; c < 3; ++c) x[c] = sc->xc[c];
+        for (int a = 0; a < 4; ++a) q[a] = sc->qc[a];
     }
-    free(F);
-    free(tau);
-    free(winv);
+    free(sc->winv);
+    sc->winv = NULL;
+}
+
+void oracle_step(const oracle_rod* rod, double t, double* x, double* v, double* q, double* w) {
+    step_scratch sc;
+    step_first(rod, t, x, v, q, w, &sc);
+    if (rod->inextensible)
+        for (int it = 0; it < rod->n_iter; ++it) step_sweeps(rod, x, v, &sc);
+    step_last(rod, x, v, q, w, &sc);
+}
+
+/* ------------------------------------------------------------------------ binding -- */
+
+/* One binding constraint (Sec. 2.1 "Constraints": a distance constraint whose rest length is
+ * zero, solved as a velocity impulse like the distance constraints) between point a (position
+ * xa, velocity va, inverse mass wa) and point b.  two-way: both points respond by their inverse
+ * masses; one-way: point b belongs to the master instrument and does not move. */
+void oracle_bind_impulse(const double* xa, double* va, double wa, const double* xb, double* vb,
+                         double wb, double dt, int32_t one_way) {
+    double d[3];
+    for (int c = 0; c < 3; ++c) d[c] = (xa[c] + dt * va[c]) - (xb[c] + dt * vb[c]);
+    const double len = norm3(d);
+    const double wsum = one_way ? wa : wa + wb;
+    if (!(wsum > 0.0) || !(len > 0.0)) return;
+    const double lambda = (len - 0.0) / (dt * wsum);   /* C = |d| - 0 */
+    for (int c = 0; c < 3; ++c) {
+        const double nc = d[c] / len;
+        va[c] -= wa * lambda * nc;
+        if (!one_way) vb[c] += wb * lambda * nc;
+    }
+}
+
+void oracle_step_pair(const oracle_rod* a, const oracle_rod* b, const oracle_binding* bind,
+                      double t, double* xa, double* va, double* qa, double* wa, double* xb,
+                      double* vb, double* qb, double* wb) {
+    step_scratch sa, sb;
+    step_first(a, t, xa, va, qa, wa, &sa);
+    step_first(b, t, xb, vb, qb, wb, &sb);
+    /* per iteration: distance constraints of both rods, then the binding impulses (Fig. 5) */
+    for (int it = 0; it < a->n_iter; ++it) {
+        if (a->inextensible) step_sweeps(a, xa, va, &sa);
+        if (b->inextensible) step_sweeps(b, xb, vb, &sb);
+        for (int k = 0; k < bind->n_pairs; ++k) {
+            const int i = bind->point_a[k], j = bind->point_b[k];
+            oracle_bind_impulse(xa + 3 * i, va + 3 * i, sa.winv[i], xb + 3 * j, vb + 3 * j,
+                                sb.winv[j], a->dt, bind->one_way);
+        }
+    }
+    step_last(a, xa, va, qa, wa, &sa);
+    step_last(b, xb, vb, qb, wb, &sb);
+}
+
+void oracle_rollout_pair(const oracle_rod* a, const oracle_rod* b, const oracle_binding* bind,
+                         double t0, int32_t n_steps, double* xa, double* va, double* qa, double* wa,
+                         double* xb, double* vb, double* qb, double* wb) {
+    for (int s = 0; s < n_steps; ++s)
+        oracle_step_pair(a, b, bind, t0 + s * a->dt, xa, va, qa, wa, xb, vb, qb, wb);
 }
 
 void oracle_rollout(const oracle_rod* rod, double t0, int32_t n_steps, double* x, double* v,

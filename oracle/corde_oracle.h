@@ -124,6 +124,35 @@ void oracle_rotmat(const double* q, double* out9);
 /* Hamilton product r = a (x) b of (w, x, y, z) quaternions. */
 void oracle_qmul(const double* a, const double* b, double* r);
 
+/* ---- Binding constraints between two rods (Sec. 2.1 "Constraints"; Sec. 3.4 variants) ----
+ * Distance constraints of rest length zero between point point_a[k] of rod a and point
+ * point_b[k] of rod b, solved as velocity impulses after the distance constraints in every
+ * constraint iteration (Fig. 5).  one_way = 1: rod b is the master instrument and is not moved
+ * by the bindings (variant 1); 0: both rods respond by their inverse masses (variant 2). */
+typedef struct {
+    int32_t n_pairs;
+    const int32_t* point_a;   /* point indices 0..n of rod a */
+    const int32_t* point_b;   /* point indices 0..n of rod b */
+    int32_t one_way;
+} oracle_binding;
+
+/* One binding impulse between point a (position xa, velocity va, inverse mass wa) and point b:
+ * d = (xa + dt va) - (xb + dt vb), lambda = |d| / (dt (wa + wb)) (wa alone if one_way), and
+ * va -= wa lambda d/|d|, vb += wb lambda d/|d| (vb unchanged if one_way). */
+void oracle_bind_impulse(const double* xa, double* va, double wa, const double* xb, double* vb,
+                         double wb, double dt, int32_t one_way);
+
+/* One step of two bound rods from time t, in place.  Both rods step with a's dt and a's number
+ * of constraint iterations (the caller gives them equal dt and n_iter). */
+void oracle_step_pair(const oracle_rod* a, const oracle_rod* b, const oracle_binding* bind,
+                      double t, double* xa, double* va, double* qa, double* wa, double* xb,
+                      double* vb, double* qb, double* wb);
+
+/* n_steps of oracle_step_pair starting at time t0, in place. */
+void oracle_rollout_pair(const oracle_rod* a, const oracle_rod* b, const oracle_binding* bind,
+                         double t0, int32_t n_steps, double* xa, double* va, double* qa, double* wa,
+                         double* xb, double* vb, double* qb, double* wb);
+
 #ifdef __cplusplus
 }
 #endif

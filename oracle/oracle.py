@@ -84,8 +84,19 @@ def lib():
         L.oracle_bmat.argtypes = [C.c_int32, _DP]
         L.oracle_qmul.restype = None
         L.oracle_qmul.argtypes = [_DP, _DP, _DP]
+        L.oracle_bind_impulse.restype = None
+        L.oracle_bind_impulse.argtypes = [_DP, _DP, C.c_double, _DP, _DP, C.c_double, C.c_double,
+                                          C.c_int32]
+        L.oracle_rollout_pair.restype = None
+        L.oracle_rollout_pair.argtypes = [C.POINTER(_Rod), C.POINTER(_Rod), C.POINTER(_Binding),
+                                          C.c_double, C.c_int32] + [_DP] * 8
         _lib = L
     return _lib
+
+
+class _Binding(C.Structure):
+    _fields_ = [("n_pairs", C.c_int32), ("point_a", C.POINTER(C.c_int32)),
+                ("point_b", C.POINTER(C.c_int32)), ("one_way", C.c_int32)]
 
 
 def _p(a):
@@ -218,6 +229,38 @@ def qmul(a, b):
     r = np.zeros(4)
     lib().oracle_qmul(_p(a), _p(b), _p(r))
     return r
+
+
+def bind_impulse(xa, va, wa, xb, vb, wb, dt, one_way):
+    """One binding impulse (zero-length distance constraint); returns the new (va, vb)."""
+    xa, xb = _f64(xa, (3,)), _f64(xb, (3,))
+    va, vb = _f64(va, (3,)).copy(), _f64(vb, (3,)).copy()
+    lib().oracle_bind_impulse(_p(xa), _p(va), float(wa), _p(xb), _p(vb), float(wb), float(dt),
+                              int(bool(one_way)))
+    return va, vb
+
+
+def rollout_pair(spec_a, spec_b, state_a, state_b, point_a, point_b, one_way, n_steps, t0=0.0):
+    """Two rods bound point_a[k] <-> point_b[k] (rod b the master if one_way), n_steps steps;
+    returns the new (state_a, state_b); the inputs are not modified."""
+    ra, rb = Rod(spec_a), Rod(spec_b)
+    ia = np.ascontiguousarray(np.asarray(point_a, dtype=np.int32))
+    ib = np.ascontiguousarray(np.asarray(point_b, dtype=np.int32))
+    if ia.shape != ib.shape:
+        raise ValueError("point_a and point_b differ in length")
+    bd = _Binding(len(ia), ia.ctypes.data_as(C.POINTER(C.c_int32)),
+                  ib.ctypes.data_as(C.POINTER(C.c_int32)), int(bool(one_way)))
+    out = []
+    arrs = []
+    for r, st in ((ra, state_a), (rb, state_b)):
+        o = st.copy()
+        o.x, o.v = _f64(st.x, (r.n + 1, 3)).copy(), _f64(st.v, (r.n + 1, 3)).copy()
+        o.q, o.w = _f64(st.q, (r.n, 4)).copy(), _f64(st.w, (r.n, 3)).copy()
+        out.append(o)
+        arrs += [o.x, o.v, o.q, o.w]
+    lib().oracle_rollout_pair(C.byref(ra.c), C.byref(rb.c), C.byref(bd), float(t0), int(n_steps),
+                              *[_p(a) for a in arrs])
+    return out[0], out[1]
 
 
 def rollout_many(specs_states, n_steps, t0=0.0, tip=False):

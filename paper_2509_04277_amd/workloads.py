@@ -302,6 +302,32 @@ def config1(dt: Optional[float] = None, n: int = 512, static_clamp: bool = False
                     n_steps=n_steps, steps_per_launch=10)
 
 
+def config5(one_way: bool, n: int = 512, shift: int = 128,
+            n_steps: int = 20000) -> Tuple[Workload, np.ndarray]:
+    """Catheter / guidewire pair bound together (Sec. 3.4 variants 1 and 2).
+
+    The two rods of the 2 x 512 workload: rod 0 (catheter) keeps its driven clamp; rod 1
+    (guidewire) is moved onto the catheter's axis with its static clamp `shift` elements behind
+    the catheter's base, so its points shift + k coincide with the catheter's points k.  Returns
+    the workload and the binding pairs (k, 4): (dependent rod, point, master rod, point) with the
+    guidewire dependent, i.e. (1, k + shift, 0, k) for k = 1 .. n - shift.
+    """
+    wl = config1(n=n, n_steps=n_steps)
+    (sa, sta), (sb, stb) = wl.rods
+    l = float(sa.seg_len[0])
+    base = sta.x[0] - np.array([shift * l, 0.0, 0.0])   # the catheter's base at t = 0
+    x = base[None, :] + np.outer(np.arange(n + 1) * l, [1.0, 0.0, 0.0])
+    q = np.tile(np.asarray(Q_ALONG_X, dtype=np.float64), (n, 1))
+    sb = sb.replace(clamp_x0=tuple(base), clamp_q0=tuple(Q_ALONG_X), clamp_amp=(0.0, 0.0, 0.0),
+                    clamp_twist_amp=0.0)
+    k = np.arange(1, n - shift + 1)
+    pairs = np.stack([np.ones_like(k), k + shift, np.zeros_like(k), k], axis=1).astype(np.int32)
+    kind = "one-way" if one_way else "two-way"
+    return (Workload("c5: catheter/guidewire 2x%d, %d %s bindings" % (n, len(k), kind),
+                     [(sa, sta), (sb, _zero_state(x, q))], n_steps=n_steps, steps_per_launch=10),
+            pairs)
+
+
 def config2(n: int, inextensible: bool, dt: Optional[float] = None) -> Workload:
     """Single long rod with seeded initial curvature; element length 1/64 m."""
     rng = np.random.default_rng((2, n))

@@ -292,3 +292,29 @@ def test_batch_buckets_and_autotune_vs_oracle(oracle):
     ref = run_oracle(oracle, rods, 150)
     compare(got, ref, [s for s, _ in rods], "batch")
     compare(got2, ref, [s for s, _ in rods], "batch-tuned")
+
+
+def test_c3_full_size_sampled(oracle):
+    """The full 4096-rod batch in the benchmark's launch configuration (autotuned shapes, 1000
+    steps in one launch per bucket) against the oracle on sampled rods: every 256th rod, the
+    costliest (longest inextensible) and the shortest."""
+    wl = W.config3()
+    rods = [(s.replace(dt=R.stable_dt(s)), st) for s, st in wl.rods]
+    b = R.RodBatch([s for s, _ in rods])
+    b.set_state_rods([st for _, st in rods])
+    t = b.autotune(probe_steps=50, steps_per_launch=wl.n_steps)
+    _say("c3 full: 4096 rods, %d steps in one launch per bucket; tuned %s, buckets %s"
+         % (wl.n_steps, t, b.buckets()))
+    b.set_state_rods([st for _, st in rods])
+    b.step(wl.n_steps, wl.n_steps)
+    got = b.get_state_rods()
+    b.close()
+    ns = np.array([s.n for s, _ in rods])
+    cost = ns * np.array([4 + s.n_iter for s, _ in rods])
+    pick = sorted(set(range(0, len(rods), 256)) | {int(np.argmax(cost)), int(np.argmin(ns))})
+    sample = [rods[i] for i in pick]
+    ref = run_oracle(oracle, sample, wl.n_steps)
+    compare([got[i] for i in pick], ref, [s for s, _ in sample], "c3-sampled")
+    for i, (x, v, q, w) in enumerate(got):   # every rod: finite, unit quaternions
+        assert np.isfinite(x).all() and np.isfinite(v).all()
+        assert np.abs(np.linalg.norm(q.astype(np.float64), axis=1) - 1).max() <= 1e-6, i
