@@ -166,6 +166,31 @@ def adjoint_extras(R, W):
             "adjoint_over_forward": (afwd_ms + bwd_ms) / fwd_ms}
 
 
+def binding_extras(R, W):
+    """Catheter / guidewire pair (2 x 512, 384 bound points): us/step unbound (variant 0),
+    one-way (1) and two-way (2) bindings, 10 steps per launch."""
+    out = {}
+    for name, one_way in (("v0", None), ("v1", True), ("v2", False)):
+        wl, pairs = W.config5(bool(one_way))
+        b = R.RodBatch([s for s, _ in wl.rods])
+        if one_way is not None:
+            b.set_bindings(pairs, one_way)
+        b.set_state_rods([st for _, st in wl.rods])
+        b.step(500, 10)
+        b.step(5000, 10)
+        b.sync()
+        ms, launches = b.last_step_time()
+        b.close()
+        out[name] = {"us_per_step": 1e3 * ms / 5000,
+                     "kernel": ("rod_resident_kernel<4,2>, one workgroup per rod" if one_way is None
+                                else "rod_pair_kernel<4,2>, both rods in one workgroup")}
+    for v in ("v1", "v2"):
+        out[v]["overhead_vs_v0"] = out[v]["us_per_step"] / out["v0"]["us_per_step"] - 1.0
+    out["workload"] = ("catheter/guidewire 2x512 inextensible, guidewire coaxial and bound at 384 "
+                       "points, 5000 steps at 10 per launch")
+    return out
+
+
 def long_rod_extras(R, W):
     """c2: us/step vs rod length and steps per launch.  Rods up to 2048 elements run in one
     workgroup ("single") and, for comparison, split over several ("chunked"); longer rods are
@@ -206,8 +231,8 @@ def main():
     ap.add_argument("--shape", default="", help="W,E kernel shape (default: autotune)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (4096 rods), long-rod and adjoint measurements")
-    ap.add_argument("--extras", default="batch,long_rod,adjoint",
-                    help="comma-separated subset of batch,long_rod,adjoint to measure")
+    ap.add_argument("--extras", default="batch,long_rod,adjoint,binding",
+                    help="comma-separated subset of batch,long_rod,adjoint,binding to measure")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the rods of this workload are independent and a "
@@ -293,7 +318,8 @@ def main():
                      "frac_of_measured_copy": achieved / copy["GB/s"]},
     }
     if not args.no_extras:
-        fns = {"batch": batch_extras, "long_rod": long_rod_extras, "adjoint": adjoint_extras}
+        fns = {"batch": batch_extras, "long_rod": long_rod_extras, "adjoint": adjoint_extras,
+               "binding": binding_extras}
         out["extras"] = {k: fns[k](R, W) for k in args.extras.split(",") if k}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)

@@ -146,7 +146,8 @@ rod_status rod_set_tuning(rod_ctx* ctx, const rod_tuning* t);
 rod_status rod_get_tuning(const rod_ctx* ctx, rod_tuning* t);
 
 /* Shape, measured time (0 if not measured) and rod count of bucket `bucket` (0-based; the
- * long-rod bucket, if any, is last); ROD_E_INVALID past the end. */
+ * bound-pair buckets follow the single-rod ones, and the long-rod bucket, if any, is last;
+ * a pair bucket's shape is per rod); ROD_E_INVALID past the end. */
 rod_status rod_bucket_info(const rod_ctx* ctx, int32_t bucket, rod_tuning* t, int32_t* n_rods);
 
 /* Step every rod longer than min_elements (1..2048; default 2048) with the chunked long-rod
@@ -159,6 +160,19 @@ rod_status rod_bucket_info(const rod_ctx* ctx, int32_t bucket, rod_tuning* t, in
  * chunked.  Errors: INVALID, UNSUPPORTED (too many constraint iterations to split a rod, or
  * more chunks than the device holds at once; the default split is then restored), DEVICE. */
 rod_status rod_set_chunking(rod_ctx* ctx, int32_t min_elements, int32_t chunk_elements);
+
+/* ---- Binding constraints (Sec. 2.1 "Constraints"; Sec. 3.4 variants 1 and 2) ----------
+ * Bind point pairs of two rods with distance constraints of rest length zero, solved as
+ * velocity impulses after the distance constraints of every constraint iteration (Fig. 5).
+ * pairs: n_pairs x 4 int32 (rod_a, point_a, rod_b, point_b), points 1..n (the base point 0 is
+ * not bindable); every point at most once; a rod may be bound to one other rod only.
+ * mode 1 = one-way (rod_b is the master and is not moved; all pairs of two rods must name the
+ * same master), 2 = two-way (both rods respond by their inverse masses).  n_pairs = 0 removes
+ * all bindings.  Bound rods must be inextensible with equal n_constraint_iters and dt and at
+ * most 1024 elements; each bound pair is stepped by one workgroup (the two rods exchange
+ * their points through LDS).  Replaces earlier bindings; takes effect at the next rod_step.
+ * The adjoint refuses handles with bound rods.  Errors: INVALID, UNSUPPORTED, NOMEM, DEVICE. */
+rod_status rod_set_bindings(rod_ctx* ctx, int32_t n_pairs, const int32_t* pairs, int32_t mode);
 
 /* Per bucket, time every built shape that holds its longest rod on probe_steps steps (the
  * state is saved and restored, the step counter unchanged) and keep the fastest; sets the

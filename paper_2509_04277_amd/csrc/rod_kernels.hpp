@@ -128,7 +128,8 @@ __device__ __forceinline__ void exchange(const float (&mine_hi)[KL], float (&lo)
 #pragma unroll
   for (int k = 0; k < KH; ++k) hi[k] = from_upper_lane(mine_lo[k]);
   if constexpr (W > 1) {
-    const int wave = threadIdx.x >> 6;
+    static_assert((W & (W - 1)) == 0, "W must be a power of two");
+    const int wave = (threadIdx.x >> 6) & (W - 1);   // wavefront within the rod's W
     if (lane == 63) {
 #pragma unroll
       for (int k = 0; k < KL; ++k) mb.buf[parity][wave][1][k] = mine_hi[k];
@@ -256,7 +257,7 @@ struct RodLane {
   // Both only perturb slots within one step's dependency radius of the window edges.
   __device__ __forceinline__ void load_params(const RodDev& rd, const float* __restrict__ prm,
                                               int prm_stride, int win_off = 0, int win_n = -1) {
-    g = threadIdx.x;
+    g = threadIdx.x & (64 * W - 1);   // lane within the rod's 64 W (a workgroup may hold two)
     n = rd.n;
     off = win_off;
     nloc = win_n < 0 ? rd.n : win_n;
@@ -524,17 +525,19 @@ struct RodLane {
 };
 
 // Prescribed clamp pose of step s (global step index steps_done + s), evaluated kClampChunk
-// steps at a time, one step per lane, into LDS.  Must be reached by every thread.
+// steps at a time, one step per lane (g: the lane within the rod), into LDS.  Must be reached
+// by every thread; any_driven (uniform over the workgroup) says whether any rod in the
+// workgroup has a driven clamp, i.e. whether the chunk barriers are taken.
 template <int W>
 __device__ __forceinline__ void clamp_for_step(const RodDev& rd, float (*cbuf)[10], int s,
                                                int n_steps, long long steps_done, V3& xc, Q4& qc,
-                                               V3& wc) {
-  if (!(rd.driven && rd.clamp)) return;
+                                               V3& wc, bool any_driven, int g) {
+  if (!any_driven) return;
+  const bool mine = rd.driven && rd.clamp;
   const int cs = s % kClampChunk;
   if (cs == 0) {
     __syncthreads();
-    const int g = threadIdx.x;
-    if (g < kClampChunk && s + g < n_steps) {
+    if (mine && g < kClampChunk && s + g < n_steps) {
       V3 pxc, pwc;
       Q4 pqc;
       clamp_pose(rd, rd.t0 + (double)(steps_done + s + g + 1) * rd.dt_d, pxc, pqc, pwc);
@@ -545,6 +548,7 @@ __device__ __forceinline__ void clamp_for_step(const RodDev& rd, float (*cbuf)[1
     }
     __syncthreads();
   }
+  if (!mine) return;
   const float* c = cbuf[cs];
   xc = {c[0], c[1], c[2]};
   qc = {c[3], c[4], c[5], c[6]};
@@ -587,7 +591,7 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
     L.exchange_a(mb, par, xl, qn);
     V3 F[E], T[E], Ev[E], fs0, enext;
     L.forces(mb, par, xl, qn, F, T, Ev, fs0, enext);
-    clamp_for_step<W>(rd, cbuf, s, n_steps, steps_done, xc, qc, wc);
+    clamp_for_step<W>(rd, cbuf, s, n_steps, steps_done, xc, qc, wc, rd.driven && rd.clamp, L.g);
     L.integrate_forces(rd, F, T, fs0, xc, wc, fext, text);
     for (int it = 0; it < rd.n_iter; ++it) {
       L.half_sweep(rd, mb, par, 0, Ev, enext, nullptr);
@@ -607,6 +611,84 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
     const float chk = L.store_state(rd, gx, gv, gq, gw);
     if (!__builtin_isfinite(chk)) atomicOr(status, 1);
   }
+}
+
+// ---------------------------------------------------------------------------------------
+// Two bound rods per workgroup (binding constraints of Sec. 2.1 "Constraints": distance
+// constraints of rest length zero between points of the two rods; Sec. 3.4 variants 1 and 2).
+// Threads [0, 64 W) step the first rod of the pair and [64 W, 128 W) the second, each exactly
+// as rod_resident_kernel steps one rod (both rods have the same number of constraint
+// iterations, so the halves take the same barriers).  After the distance sweeps of every
+// constraint iteration each point writes its predicted position x + dt v and inverse mass to
+// LDS, and each bound point applies the zero-length distance impulse against its partner:
+// v -= w d / (dt (w + w_partner)) with d = p - p_partner (two-way), or v -= d / dt for the
+// first rod only (one-way: the second rod is the master and is not moved).
+// partner[slot]: slot of the bound point in the other rod (point = slot + 1), -1 if unbound.
+// pair_mode[block]: 1 one-way, 2 two-way.
+template <int W, int E>
+__global__ __launch_bounds__(128 * W) void rod_pair_kernel(
+    const RodDev* __restrict__ rods, const int* __restrict__ pair_rods,
+    const int* __restrict__ pair_mode, const int* __restrict__ partner,
+    const float* __restrict__ prm, int prm_stride, float* __restrict__ gx, float* __restrict__ gv,
+    float* __restrict__ gq, float* __restrict__ gw, const float* __restrict__ fext,
+    const float* __restrict__ text, int n_steps, long long steps_done, int* __restrict__ status) {
+  __shared__ Mailbox<W> mb[2];
+  __shared__ float cbuf[2][kClampChunk][10];
+  __shared__ float4 bp[2][64 * W * E];
+  const int sub = threadIdx.x >= 64 * W ? 1 : 0;
+  const RodDev rd = rods[pair_rods[2 * blockIdx.x + sub]];
+  const RodDev& ro = rods[pair_rods[2 * blockIdx.x + 1 - sub]];
+  const bool any_driven = (rd.driven && rd.clamp) || (ro.driven && ro.clamp);
+  const int mode = pair_mode[blockIdx.x];
+  const bool moved = !(mode == 1 && sub == 1);
+  RodLane<W, E> L;
+  L.load_params(rd, prm, prm_stride);
+  L.load_state(rd, gx, gv, gq, gw);
+  int part[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) part[e] = L.ok[e] ? partner[rd.slot_off + L.j0 + e] : -1;
+  int par = 0;
+  V3 xc = {rd.cx0[0], rd.cx0[1], rd.cx0[2]}, wc = {0.f, 0.f, 0.f};
+  Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
+  const float dt = rd.dt;
+
+  for (int s = 0; s < n_steps; ++s) {
+    V3 xl;
+    Q4 qn;
+    L.exchange_a(mb[sub], par, xl, qn);
+    V3 F[E], T[E], Ev[E], fs0, enext;
+    L.forces(mb[sub], par, xl, qn, F, T, Ev, fs0, enext);
+    clamp_for_step<W>(rd, cbuf[sub], s, n_steps, steps_done, xc, qc, wc, any_driven, L.g);
+    L.integrate_forces(rd, F, T, fs0, xc, wc, fext, text);
+    for (int it = 0; it < rd.n_iter; ++it) {
+      L.half_sweep(rd, mb[sub], par, 0, Ev, enext, nullptr);
+      L.half_sweep(rd, mb[sub], par, 1, Ev, enext, nullptr);
+      // binding impulses against the other rod's predicted positions
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (L.ok[e]) {
+          const V3 p = fma3(dt, L.Vv[e], L.X[e]);
+          bp[sub][L.j0 + e] = make_float4(p.x, p.y, p.z, L.P[P_WINV][e]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (part[e] >= 0 && moved) {
+          const float4 o = bp[1 - sub][part[e]];
+          const V3 p = fma3(dt, L.Vv[e], L.X[e]);
+          const V3 d = {p.x - o.x, p.y - o.y, p.z - o.z};
+          const float wm = L.P[P_WINV][e];
+          const float ws = mode == 2 ? wm + o.w : wm;
+          if (ws > 0.f) L.Vv[e] = fnma3(wm / (dt * ws), d, L.Vv[e]);
+        }
+      }
+      __syncthreads();
+    }
+    L.integrate_velocities(rd, xc, qc);
+  }
+  const float chk = L.store_state(rd, gx, gv, gq, gw);
+  if (!__builtin_isfinite(chk)) atomicOr(status, 1);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -670,7 +752,8 @@ __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
     L.exchange_a(mb, par, xl, qn);
     V3 F[E], T[E], Ev[E], fs0, enext;
     L.forces(mb, par, xl, qn, F, T, Ev, fs0, enext);
-    if (ck.win0 == 0) clamp_for_step<W>(rd, cbuf, s, n_steps, steps_done, xc, qc, wc);
+    if (ck.win0 == 0)
+      clamp_for_step<W>(rd, cbuf, s, n_steps, steps_done, xc, qc, wc, rd.driven && rd.clamp, L.g);
     L.integrate_forces(rd, F, T, fs0, xc, wc, fext, text);
     for (int it = 0; it < rd.n_iter; ++it) {
       L.half_sweep(rd, mb, par, 0, Ev, enext, nullptr);

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -78,6 +79,21 @@ const KernelEntry* find_kernel(int w, int e) {
 
 GridFn grid_kernel() { return corde::rod_grid_kernel<kGridWaves, kGridElems>; }
 
+using PairFn = void (*)(const RodDev*, const int*, const int*, const int*, const float*, int,
+                        float*, float*, float*, float*, const float*, const float*, int, long long,
+                        int*);
+struct PairEntry {
+  int waves, elems;
+  PairFn fn;
+};
+// Shapes of the two-rod (bound pair) kernel, per rod; a workgroup holds 2 x 64 waves threads
+// (at most 8 wavefronts: with 16 the register budget halves and the kernel spills).
+const PairEntry kPairs[] = {
+    {2, 2, corde::rod_pair_kernel<2, 2>}, {4, 2, corde::rod_pair_kernel<4, 2>},
+    {2, 4, corde::rod_pair_kernel<2, 4>}, {2, 8, corde::rod_pair_kernel<2, 8>},
+};
+constexpr int kPairMax = 1024;   // longest rod a bound pair may hold
+
 thread_local std::string g_last_error;
 
 }  // namespace
@@ -115,6 +131,13 @@ struct rod_ctx {
   float* d_pub = nullptr;
   int* d_flags = nullptr;
   std::vector<Bucket> buckets;
+  // bound pairs (binding constraints): two rods per workgroup, grouped by kernel shape
+  std::vector<char> bound;              // per rod: stepped by the pair kernel
+  std::vector<int> pair_rods, pair_mode;  // 2 rods and the mode per pair, bucket by bucket
+  std::vector<Bucket> pair_buckets;     // first/count index pairs
+  int* d_pair_rods = nullptr;
+  int* d_pair_mode = nullptr;
+  int* d_partner = nullptr;             // per slot: slot of the bound point in the other rod
   std::vector<int> rod_ids;
   int* d_rod_ids = nullptr;
   int steps_per_launch = 10;
@@ -335,6 +358,7 @@ rod_status make_buckets(rod_ctx* c, ShapeFn shape) {
   std::vector<std::pair<long long, int>> key;
   for (int r = 0; r < c->n_rods; ++r) {
     if (c->n[r] > c->chunk_above) continue;   // long rods run chunked
+    if (!c->bound.empty() && c->bound[r]) continue;   // bound pairs have their own kernel
     int w, e;
     shape(r, &w, &e);
     // within a bucket, most work first (a constraint iteration costs about a quarter of the
@@ -482,16 +506,32 @@ rod_status launch_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long long
   return ROD_OK;
 }
 
+rod_status launch_pair_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long long done,
+                              hipStream_t stream) {
+  const PairEntry* k = nullptr;
+  for (const auto& e : kPairs)
+    if (e.waves == b.waves && e.elems == b.elems) k = &e;
+  if (!k) return fail(c, ROD_E_UNSUPPORTED, "pair kernel shape not built");
+  hipLaunchKernelGGL(k->fn, dim3(b.count), dim3(128 * k->waves), 0, stream, c->d_rods,
+                     c->d_pair_rods + 2 * b.first, c->d_pair_mode + b.first, c->d_partner, c->d_prm,
+                     c->prm_stride, c->d_x, c->d_v, c->d_q, c->d_w, c->d_fext, c->d_text, ks, done,
+                     c->d_status);
+  HIP_TRY(c, hipGetLastError());
+  return ROD_OK;
+}
+
 // n_steps steps of every rod, spl steps per launch; bucket < 0: all buckets, else that one.
 rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it, int bucket = -1) {
   if (time_it) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
   int launches = 0;
-  // the buckets are independent: with several, each steps on its own stream (forked from and
-  // joined back to the handle's stream)
+  // the buckets (and the bound-pair buckets) are independent: with several, each steps on its
+  // own stream (forked from and joined back to the handle's stream)
   const int nb = bucket >= 0 ? 1 : (int)c->buckets.size();
-  const bool fork = nb > 1;
+  const int np = bucket >= 0 ? 0 : (int)c->pair_buckets.size();
+  const int ng = nb + np;
+  const bool fork = ng > 1;
   if (fork) {
-    while ((int)c->bstreams.size() < nb) {
+    while ((int)c->bstreams.size() < ng) {
       hipStream_t st = nullptr;
       hipEvent_t ev = nullptr;
       HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -502,7 +542,7 @@ rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it, int buck
     if (!c->ev_fork) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
   }
-  for (int gi = 0; gi < nb; ++gi) {
+  for (int gi = 0; gi < ng; ++gi) {
     hipStream_t st = c->stream;
     if (fork) {
       st = c->bstreams[gi];
@@ -510,8 +550,9 @@ rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it, int buck
     }
     for (int done = 0; done < n_steps; done += spl) {
       const int ks = std::min(spl, n_steps - done);
-      rod_status rs = launch_bucket(c, c->buckets[bucket >= 0 ? bucket : gi], ks,
-                                    c->steps_done + done, st);
+      rod_status rs =
+          gi < nb ? launch_bucket(c, c->buckets[bucket >= 0 ? bucket : gi], ks, c->steps_done + done, st)
+                  : launch_pair_bucket(c, c->pair_buckets[gi - nb], ks, c->steps_done + done, st);
       if (rs != ROD_OK) return rs;
       ++launches;
     }
@@ -763,7 +804,8 @@ rod_status rod_destroy(rod_ctx* c) {
                   (void*)c->d_q, (void*)c->d_w, (void*)c->d_fext, (void*)c->d_text,
                   (void*)c->d_status, (void*)c->d_rod_ids, (void*)c->d_ckpt, (void*)c->d_traj,
                   (void*)c->d_tips, (void*)c->d_dtips, (void*)c->d_adj,
-                  (void*)c->d_gacc, (void*)c->d_chunks, (void*)c->d_block_chunk, (void*)c->d_pub,
+                  (void*)c->d_gacc, (void*)c->d_pair_rods, (void*)c->d_pair_mode,
+                  (void*)c->d_partner, (void*)c->d_chunks, (void*)c->d_block_chunk, (void*)c->d_pub,
                   (void*)c->d_flags})
     if (p) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -893,7 +935,17 @@ rod_status rod_get_tuning(const rod_ctx* c, rod_tuning* t) {
 
 rod_status rod_bucket_info(const rod_ctx* c, int32_t bucket, rod_tuning* t, int32_t* n_rods) {
   if (!c || !t || !n_rods) return fail(nullptr, ROD_E_INVALID, "null argument");
-  const int nb = (int)c->buckets.size();
+  const int nb0 = (int)c->buckets.size();
+  if (bucket >= nb0 && bucket < nb0 + (int)c->pair_buckets.size()) {
+    const auto& b = c->pair_buckets[bucket - nb0];
+    t->waves = b.waves;
+    t->elems_per_lane = b.elems;
+    t->steps_per_launch = c->steps_per_launch;
+    t->us_per_step = 0.f;
+    *n_rods = 2 * b.count;
+    return ROD_OK;
+  }
+  const int nb = nb0 + (int)c->pair_buckets.size();
   if (bucket == nb && c->n_chunks) {
     t->waves = kGridWaves;
     t->elems_per_lane = kGridElems;
@@ -902,7 +954,7 @@ rod_status rod_bucket_info(const rod_ctx* c, int32_t bucket, rod_tuning* t, int3
     *n_rods = (int)c->long_rods.size();
     return ROD_OK;
   }
-  if (bucket < 0 || bucket >= nb)
+  if (bucket < 0 || bucket >= nb0)
     return fail(const_cast<rod_ctx*>(c), ROD_E_INVALID, "bucket index out of range");
   const auto& b = c->buckets[bucket];
   t->waves = b.waves;
@@ -918,6 +970,9 @@ rod_status rod_set_chunking(rod_ctx* c, int32_t min_elements, int32_t chunk_elem
   if (min_elements < 1 || min_elements > kResidentMax)
     return fail(c, ROD_E_INVALID, "min_elements must be in [1, 2048]");
   if (chunk_elements < 0) return fail(c, ROD_E_INVALID, "chunk_elements must be >= 0");
+  for (int r = 0; r < c->n_rods; ++r)
+    if (!c->bound.empty() && c->bound[r] && c->n[r] > min_elements)
+      return fail(c, ROD_E_UNSUPPORTED, "a bound rod cannot be chunked");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (void** p : {(void**)&c->d_chunks, (void**)&c->d_block_chunk, (void**)&c->d_pub,
                    (void**)&c->d_flags}) {
@@ -948,6 +1003,98 @@ rod_status rod_set_chunking(rod_ctx* c, int32_t min_elements, int32_t chunk_elem
   }
   if (c->n_chunks) c->adj_ready = false;   // the adjoint does not step chunked rods
   return ROD_OK;
+}
+
+rod_status rod_set_bindings(rod_ctx* c, int32_t n_pairs, const int32_t* pairs, int32_t mode) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (n_pairs < 0 || (n_pairs > 0 && !pairs)) return fail(c, ROD_E_INVALID, "bad pair list");
+  if (n_pairs > 0 && mode != 1 && mode != 2)
+    return fail(c, ROD_E_INVALID, "mode must be 1 (one-way) or 2 (two-way)");
+  std::vector<int> partner((size_t)std::max(c->total_frames, 1), -1);
+  std::vector<int> group_of(c->n_rods, -1);
+  std::vector<std::array<int, 2>> groups;   // (first, second); second = master if one-way
+  for (int k = 0; k < n_pairs; ++k) {
+    const int ra = pairs[4 * k], pa = pairs[4 * k + 1], rb = pairs[4 * k + 2], pb = pairs[4 * k + 3];
+    if (ra < 0 || ra >= c->n_rods || rb < 0 || rb >= c->n_rods || ra == rb)
+      return fail(c, ROD_E_INVALID, "pair " + std::to_string(k) + ": bad rod index");
+    if (pa < 1 || pa > c->n[ra] || pb < 1 || pb > c->n[rb])
+      return fail(c, ROD_E_INVALID, "pair " + std::to_string(k) + ": point index outside 1..n");
+    int g = group_of[ra];
+    if (g < 0 && group_of[rb] < 0) {
+      g = (int)groups.size();
+      groups.push_back({ra, rb});
+      group_of[ra] = group_of[rb] = g;
+    } else if (g < 0 || group_of[rb] != g) {
+      return fail(c, ROD_E_INVALID, "pair " + std::to_string(k) + ": a rod is bound to two others");
+    } else if (mode == 1 && groups[g][1] != rb) {
+      return fail(c, ROD_E_INVALID, "pair " + std::to_string(k) + ": one-way pairs must name the same master");
+    }
+    const int sa = c->rods[ra].slot_off + pa - 1, sb = c->rods[rb].slot_off + pb - 1;
+    if (partner[sa] >= 0 || partner[sb] >= 0)
+      return fail(c, ROD_E_INVALID, "pair " + std::to_string(k) + ": a point is bound twice");
+    partner[sa] = pb - 1;
+    partner[sb] = pa - 1;
+  }
+  for (const auto& g : groups) {
+    const RodDev &a = c->rods[g[0]], &b = c->rods[g[1]];
+    if (a.n_iter < 1 || a.n_iter != b.n_iter)
+      return fail(c, ROD_E_UNSUPPORTED, "bound rods must be inextensible with equal constraint iterations");
+    if (a.dt_d != b.dt_d) return fail(c, ROD_E_UNSUPPORTED, "bound rods must have equal dt");
+    if (std::max(a.n, b.n) > std::min(kPairMax, c->chunk_above))
+      return fail(c, ROD_E_UNSUPPORTED, "bound rods are limited to 1024 elements and must not be chunked");
+  }
+  // pair buckets: the smallest shape that holds both rods, costliest pairs first
+  auto shape_of = [&](int n, int* w, int* e) {
+    *w = n <= 512 ? (n <= 256 ? 2 : 4) : 2;
+    *e = n <= 512 ? 2 : 8;
+  };
+  std::vector<std::pair<long long, int>> key;
+  for (int g = 0; g < (int)groups.size(); ++g) {
+    const int nmax = std::max(c->n[groups[g][0]], c->n[groups[g][1]]);
+    int w, e;
+    shape_of(nmax, &w, &e);
+    const long long cost = (long long)(c->n[groups[g][0]] + c->n[groups[g][1]]) *
+                           (4 + c->rods[groups[g][0]].n_iter);
+    key.push_back({((long long)(w * 16 + e) << 32) | (0x7fffffffLL - cost), g});
+  }
+  std::sort(key.begin(), key.end());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));   // no launch may still read the old tables
+  for (hipStream_t st : c->bstreams) HIP_TRY(c, hipStreamSynchronize(st));
+  c->pair_rods.clear();
+  c->pair_mode.clear();
+  c->pair_buckets.clear();
+  c->bound.assign(c->n_rods, 0);
+  for (int i = 0; i < (int)key.size(); ++i) {
+    const auto& g = groups[key[i].second];
+    int w, e;
+    shape_of(std::max(c->n[g[0]], c->n[g[1]]), &w, &e);
+    c->pair_rods.push_back(g[0]);
+    c->pair_rods.push_back(g[1]);
+    c->pair_mode.push_back(mode);
+    c->bound[g[0]] = c->bound[g[1]] = 1;
+    if (c->pair_buckets.empty() || c->pair_buckets.back().waves != w || c->pair_buckets.back().elems != e)
+      c->pair_buckets.push_back({w, e, i, 0, 0, 0.f});
+    c->pair_buckets.back().count++;
+    c->pair_buckets.back().max_n = std::max(c->pair_buckets.back().max_n, std::max(c->n[g[0]], c->n[g[1]]));
+  }
+  for (void** p : {(void**)&c->d_pair_rods, (void**)&c->d_pair_mode}) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+  if (!groups.empty()) {
+    if (!c->d_partner && hipMalloc((void**)&c->d_partner, sizeof(int) * partner.size()) != hipSuccess)
+      return fail(c, ROD_E_NOMEM, "binding tables");
+    if (hipMalloc((void**)&c->d_pair_rods, sizeof(int) * c->pair_rods.size()) != hipSuccess ||
+        hipMalloc((void**)&c->d_pair_mode, sizeof(int) * c->pair_mode.size()) != hipSuccess)
+      return fail(c, ROD_E_NOMEM, "binding tables");
+    HIP_TRY(c, hipMemcpy(c->d_partner, partner.data(), sizeof(int) * partner.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_pair_rods, c->pair_rods.data(), sizeof(int) * c->pair_rods.size(),
+                         hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_pair_mode, c->pair_mode.data(), sizeof(int) * c->pair_mode.size(),
+                         hipMemcpyHostToDevice));
+    c->adj_ready = false;   // the adjoint does not step bound pairs
+  }
+  return make_buckets(c, [&](int r, int* w, int* e) { default_shape(c->n[r], w, e); });
 }
 
 rod_status rod_last_step_time(rod_ctx* c, float* ms, int32_t* launches) {
@@ -1066,6 +1213,7 @@ rod_status rod_adjoint_forward(rod_ctx* c, int32_t n_steps, int32_t ckpt_every, 
   for (const auto& b : c->buckets)
     if (!adjoint_shape(b.max_n)) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
   if (c->n_chunks) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
+  if (!c->pair_rods.empty()) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not step bound rods");
   c->adj_ready = false;
   const size_t S = state_floats(c);
   const int ck = std::min(ckpt_every, n_steps);

@@ -68,6 +68,7 @@ _SIGS = {
     "rod_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(rod_tuning)]),
     "rod_bucket_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rod_tuning), C.POINTER(C.c_int32)]),
     "rod_set_chunking": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "rod_set_bindings": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32]),
     "rod_stable_dt": (C.c_int, [C.POINTER(rod_params), _DP]),
     "rod_last_step_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     "rod_set_stiffness_mult": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
@@ -319,6 +320,14 @@ class RodBatch:
                 return out
             out.append((t.waves, t.elems_per_lane, n.value, t.us_per_step))
             b += 1
+
+    def set_bindings(self, pairs, one_way: bool):
+        """Bind point pairs (k, 4) = (rod_a, point_a, rod_b, point_b) with zero-length distance
+        constraints; one_way: rod_b is the master.  An empty list removes the bindings."""
+        arr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 4))
+        _check(lib().rod_set_bindings(self.h, int(arr.shape[0]),
+                                      arr.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      1 if one_way else 2), self.h)
 
     def set_chunking(self, min_elements: int, chunk_elements: int = 0):
         """Step rods longer than min_elements with the chunked multi-workgroup kernel, about

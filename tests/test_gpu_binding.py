@@ -1,0 +1,146 @@
+"""GPU parity of the binding constraints (two rods bound by zero-length distance constraints,
+stepped by one workgroup per pair) against the FP64 oracle's pair step.  Tolerance from the
+method's target: every point within 1e-4 x rod length after the run."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_04277_amd import rod as R
+from paper_2509_04277_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    torch.cuda.init()
+    yield
+
+
+def _gpu(rods, pairs, one_way, n_steps, spl=10, shape=None):
+    b = R.RodBatch([s for s, _ in rods])
+    if shape is not None:
+        b.set_tuning(shape[0], shape[1], spl)
+    if pairs is not None:
+        b.set_bindings(pairs, one_way)
+    b.set_state_rods([st for _, st in rods])
+    b.step(n_steps, spl)
+    b.sync()
+    out = b.get_state_rods()
+    info = b.buckets()
+    b.close()
+    return out, info
+
+
+def _oracle(rods, pairs, one_way, n_steps):
+    (sa, sta), (sb, stb) = rods[pairs[0, 0]], rods[pairs[0, 2]]
+    A, B = O.rollout_pair(sa, sb, sta, stb, pairs[:, 1], pairs[:, 3], one_way, n_steps)
+    out = [None, None]
+    out[pairs[0, 0]], out[pairs[0, 2]] = A, B
+    return out
+
+
+@pytest.mark.parametrize("one_way", [True, False])
+def test_catheter_guidewire_vs_oracle(one_way):
+    wl, pairs = W.config5(one_way)
+    n_steps = 2000
+    _say("c5 %s: 2x512 bound by %d pairs, %d steps at 10 per launch"
+         % ("one-way" if one_way else "two-way", len(pairs), n_steps))
+    gpu, info = _gpu(wl.rods, pairs, one_way, n_steps)
+    _say("buckets %s" % info)
+    assert info == [(4, 2, 2, 0.0)]
+    ref = _oracle(wl.rods, pairs, one_way, n_steps)
+    for (x, v, q, w), o, (s, _) in zip(gpu, ref, wl.rods):
+        L = float(np.sum(s.seg_len))
+        ex = float(np.abs(x - o.x).max())
+        tip = float(np.linalg.norm(x[-1] - o.x[-1]))
+        _say("  N=%d: max|dx| %.2e tip %.2e (tol %.1e), |q|-1 %.1e" % (
+            s.n, ex, tip, 1e-4 * L, np.abs(np.linalg.norm(q.astype(np.float64), axis=1) - 1).max()))
+        assert np.isfinite(x).all() and np.isfinite(v).all()
+        assert ex <= 1e-4 * L and tip <= 1e-4 * L
+    # bound points coincide at the end of every step (binding is the last constraint)
+    gap = np.abs(gpu[1][0][pairs[:, 1]] - gpu[0][0][pairs[:, 3]]).max()
+    _say("  bound-point gap %.2e m" % gap)
+    assert gap <= 1e-6
+    # and they actually moved the rods: against the unbound run
+    free, _ = _gpu(wl.rods, None, one_way, n_steps)
+    moved = max(np.abs(gpu[r][0] - free[r][0]).max() for r in (0, 1))
+    _say("  largest displacement from the unbound run %.2e m" % moved)
+    assert moved > 1e-6
+
+
+def test_one_way_master_is_bitwise_alone():
+    """Variant 1: the master rod in the pair kernel evolves exactly as in the single-rod kernel
+    (its arithmetic does not depend on the kernel shape or on the bound partner)."""
+    wl, pairs = W.config5(True)
+    gpu, _ = _gpu(wl.rods, pairs, True, 300)
+    alone, _ = _gpu([wl.rods[0]], None, True, 300, shape=(4, 2))
+    for u, v in zip(gpu[0], alone[0]):
+        assert np.array_equal(u, v)
+    assert np.abs(gpu[1][0] - _gpu([wl.rods[1]], None, True, 300)[0][0][0]).max() > 0
+
+
+def test_cleared_bindings_step_independently():
+    wl, pairs = W.config5(False)
+    b = R.RodBatch([s for s, _ in wl.rods])
+    b.set_bindings(pairs, False)
+    assert b.buckets() == [(4, 2, 2, 0.0)]
+    b.set_bindings([], False)
+    assert b.buckets() == [(4, 2, 2, 0.0)] or len(b.buckets()) == 1
+    b.set_state_rods([st for _, st in wl.rods])
+    b.step(200, 10)
+    got = b.get_state_rods()
+    b.close()
+    ref, _ = _gpu(wl.rods, None, False, 200)
+    for a, c in zip(got, ref):
+        for u, v in zip(a, c):
+            assert np.array_equal(u, v)
+
+
+def test_bound_pair_beside_other_rods():
+    """A handle with a bound pair and unbound rods: the pair and the buckets step together."""
+    wl, pairs = W.config5(False)
+    extra = W.config0().rods + W.config2(700, True).rods
+    rods = wl.rods + extra
+    gpu, info = _gpu(rods, pairs, False, 500)
+    _say("mixed handle buckets %s" % info)
+    assert (4, 2, 2, 0.0) in info
+    ref = _oracle(wl.rods, pairs, False, 500)
+    for (x, _, _, _), o in zip(gpu[:2], ref):
+        assert np.abs(x - o.x).max() <= 1e-4
+    for (x, _, _, _), (s, st) in zip(gpu[2:], extra):
+        o, _ = O.Rod(s).rollout(st, 500)
+        assert np.abs(x - o.x).max() <= 1e-4 * float(np.sum(s.seg_len))
+
+
+def test_binding_arguments():
+    wl, pairs = W.config5(True)
+    rods = wl.rods + W.config0().rods
+    b = R.RodBatch([s for s, _ in rods])
+    bad = [
+        [[0, 0, 1, 5]],               # base point
+        [[0, 513, 1, 5]],             # past the end
+        [[0, 5, 0, 6]],               # same rod
+        [[0, 5, 1, 5], [0, 5, 1, 6]],  # a point twice
+        [[0, 5, 1, 5], [0, 6, 2, 6]],  # a rod bound to two others
+        [[2, 5, 1, 5]],               # extensible rod
+    ]
+    for p in bad:
+        with pytest.raises(R.RodError):
+            b.set_bindings(p, False)
+    with pytest.raises(R.RodError):   # one-way pairs naming both rods as master
+        b.set_bindings([[0, 5, 1, 5], [1, 6, 0, 6]], True)
+    b.set_bindings(pairs, True)
+    b.set_state_rods([st for _, st in rods])
+    with pytest.raises(R.RodError):
+        b.adjoint_forward(10, 5)
+    b.close()
