@@ -634,7 +634,9 @@ __global__ __launch_bounds__(128 * W) void rod_pair_kernel(
     const float* __restrict__ text, int n_steps, long long steps_done, int* __restrict__ status) {
   __shared__ Mailbox<W> mb[2];
   __shared__ float cbuf[2][kClampChunk][10];
-  __shared__ float4 bp[2][64 * W * E];
+  // predicted positions and inverse masses, double-buffered by iteration parity: the reads of
+  // iteration i and the writes of iteration i + 2 are separated by iteration i + 1's barrier
+  __shared__ float4 bp[2][2][64 * W * E];
   const int sub = threadIdx.x >= 64 * W ? 1 : 0;
   const RodDev rd = rods[pair_rods[2 * blockIdx.x + sub]];
   const RodDev& ro = rods[pair_rods[2 * blockIdx.x + 1 - sub]];
@@ -651,6 +653,7 @@ __global__ __launch_bounds__(128 * W) void rod_pair_kernel(
   V3 xc = {rd.cx0[0], rd.cx0[1], rd.cx0[2]}, wc = {0.f, 0.f, 0.f};
   Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
   const float dt = rd.dt;
+  int bpar = 0;
 
   for (int s = 0; s < n_steps; ++s) {
     V3 xl;
@@ -668,14 +671,14 @@ __global__ __launch_bounds__(128 * W) void rod_pair_kernel(
       for (int e = 0; e < E; ++e) {
         if (L.ok[e]) {
           const V3 p = fma3(dt, L.Vv[e], L.X[e]);
-          bp[sub][L.j0 + e] = make_float4(p.x, p.y, p.z, L.P[P_WINV][e]);
+          bp[bpar][sub][L.j0 + e] = make_float4(p.x, p.y, p.z, L.P[P_WINV][e]);
         }
       }
       __syncthreads();
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         if (part[e] >= 0 && moved) {
-          const float4 o = bp[1 - sub][part[e]];
+          const float4 o = bp[bpar][1 - sub][part[e]];
           const V3 p = fma3(dt, L.Vv[e], L.X[e]);
           const V3 d = {p.x - o.x, p.y - o.y, p.z - o.z};
           const float wm = L.P[P_WINV][e];
@@ -683,7 +686,7 @@ __global__ __launch_bounds__(128 * W) void rod_pair_kernel(
           if (ws > 0.f) L.Vv[e] = fnma3(wm / (dt * ws), d, L.Vv[e]);
         }
       }
-      __syncthreads();
+      bpar ^= 1;
     }
     L.integrate_velocities(rd, xc, qc);
   }
