@@ -503,6 +503,155 @@ void oracle_step_pair(const oracle_rod* a, const oracle_rod* b, const oracle_bin
     step_last(b, xb, vb, qb, wb, &sb);
 }
 
+/* ------------------------------------------------------------------------ contact -- */
+
+/* Sphere radius of point i: the radius of its element, the mean of both at interior points. */
+static double point_radius(const oracle_rod* rod, int i) {
+    if (i == 0) return rod->radius[0];
+    if (i == rod->n) return rod->radius[rod->n - 1];
+    return 0.5 * (rod->radius[i - 1] + rod->radius[i]);
+}
+
+int32_t oracle_self_skip(const oracle_rod* rod) {
+    double rmax = 0.0, lmin = INFINITY;
+    for (int j = 0; j < rod->n; ++j) {
+        if (rod->radius[j] > rmax) rmax = rod->radius[j];
+        if (rod->seg_len[j] < lmin) lmin = rod->seg_len[j];
+    }
+    int32_t s = (int32_t)ceil(2.0 * rmax / lmin);
+    return s < 1 ? 1 : s;
+}
+
+/* contacts of point i of rod ra: (rod, point) pairs with overlapping spheres at positions x */
+typedef struct {
+    int rod, pt;
+    double n[3], D;
+} contact_t;
+
+static int find_contacts(const oracle_rod* const* rods, int n_rods, double* const* x, int ra,
+                         int i, contact_t* out, int cap) {
+    int k = 0;
+    const double ri = point_radius(rods[ra], i);
+    for (int rb = 0; rb < n_rods; ++rb) {
+        const int skip = oracle_self_skip(rods[rb]);
+        for (int j = 1; j <= rods[rb]->n; ++j) {
+            if (rb == ra && abs(j - i) <= skip) continue;
+            double d[3];
+            for (int c = 0; c < 3; ++c) d[c] = x[ra][3 * i + c] - x[rb][3 * j + c];
+            const double len = norm3(d);
+            const double D = ri + point_radius(rods[rb], j);
+            if (!(len < D) || !(len > 0.0)) continue;
+            if (k < cap) {
+                out[k].rod = rb;
+                out[k].pt = j;
+                for (int c = 0; c < 3; ++c) out[k].n[c] = d[c] / len;
+                out[k].D = D;
+            }
+            ++k;
+        }
+    }
+    return k;
+}
+
+void oracle_step_group(const oracle_rod* const* rods, int32_t n_rods, const oracle_binding* bind,
+                       const oracle_contact* contact, double t, double* const* x, double* const* v,
+                       double* const* q, double* const* w, int32_t* max_contacts) {
+    step_scratch sc[2];
+    const oracle_rod* a = rods[0];
+    const double dt = a->dt;
+    for (int r = 0; r < n_rods; ++r) step_first(rods[r], t, x[r], v[r], q[r], w[r], &sc[r]);
+    /* contacts from the start-of-step positions (Fig. 5: detection first), points 1..n */
+    contact_t* cl[2] = {NULL, NULL};
+    int* cn[2] = {NULL, NULL};
+    int cap = 0, most = 0;
+    if (contact) {
+        for (int r = 0; r < n_rods; ++r) cap += rods[r]->n;
+        for (int r = 0; r < n_rods; ++r) {
+            cl[r] = (contact_t*)malloc(sizeof(contact_t) * (size_t)(rods[r]->n + 1) * cap);
+            cn[r] = (int*)calloc((size_t)rods[r]->n + 1, sizeof(int));
+            for (int i = 1; i <= rods[r]->n; ++i) {
+                cn[r][i] = find_contacts(rods, n_rods, x, r, i, cl[r] + (size_t)i * cap, cap);
+                if (cn[r][i] > most) most = cn[r][i];
+            }
+        }
+    }
+    if (max_contacts) *max_contacts = most;
+    double* dv[2] = {NULL, NULL};
+    if (contact)
+        for (int r = 0; r < n_rods; ++r) dv[r] = (double*)malloc(sizeof(double) * 3 * (rods[r]->n + 1));
+    /* per iteration: distance constraints, bindings, then the contact impulses (Fig. 5) */
+    for (int it = 0; it < a->n_iter; ++it) {
+        for (int r = 0; r < n_rods; ++r)
+            if (rods[r]->inextensible) step_sweeps(rods[r], x[r], v[r], &sc[r]);
+        if (bind && n_rods == 2)
+            for (int k = 0; k < bind->n_pairs; ++k) {
+                const int i = bind->point_a[k], j = bind->point_b[k];
+                oracle_bind_impulse(x[0] + 3 * i, v[0] + 3 * i, sc[0].winv[i], x[1] + 3 * j,
+                                    v[1] + 3 * j, sc[1].winv[j], dt, bind->one_way);
+            }
+        if (!contact) continue;
+        /* Jacobi: every point's contacts from the same velocities; a point applies the mean of
+         * its active contacts' impulses */
+        for (int r = 0; r < n_rods; ++r)
+            for (int i = 0; i <= rods[r]->n; ++i) {
+                double acc[3] = {0.0, 0.0, 0.0};
+                int active = 0;
+                for (int k = 0; i > 0 && k < cn[r][i]; ++k) {
+                    const contact_t* ct = cl[r] + (size_t)i * cap + k;
+                    const double* xi = x[r] + 3 * i;
+                    const double* vi = v[r] + 3 * i;
+                    const double* xj = x[ct->rod] + 3 * ct->pt;
+                    const double* vj = v[ct->rod] + 3 * ct->pt;
+                    const double wi = sc[r].winv[i], wj = sc[ct->rod].winv[ct->pt];
+                    if (!(wi + wj > 0.0)) continue;
+                    double sep = -ct->D;   /* predicted separation along the contact normal */
+                    for (int c = 0; c < 3; ++c) sep += ((xi[c] + dt * vi[c]) - (xj[c] + dt * vj[c])) * ct->n[c];
+                    if (!(sep < 0.0)) continue;
+                    const double lam = -sep / (dt * (wi + wj));       /* normal impulse */
+                    double vr[3], vrn = 0.0;
+                    for (int c = 0; c < 3; ++c) {
+                        vr[c] = vi[c] - vj[c];
+                        vrn += vr[c] * ct->n[c];
+                    }
+                    double vt[3];
+                    for (int c = 0; c < 3; ++c) vt[c] = vr[c] - vrn * ct->n[c];
+                    const double vtl = norm3(vt);
+                    double lt = 0.0;                                   /* Coulomb friction */
+                    if (vtl > 0.0) {
+                        lt = vtl / (wi + wj);
+                        if (lt > contact->mu * lam) lt = contact->mu * lam;
+                    }
+                    for (int c = 0; c < 3; ++c)
+                        acc[c] += wi * lam * ct->n[c] - (vtl > 0.0 ? wi * lt * vt[c] / vtl : 0.0);
+                    ++active;
+                }
+                for (int c = 0; c < 3; ++c) dv[r][3 * i + c] = active ? acc[c] / active : 0.0;
+            }
+        for (int r = 0; r < n_rods; ++r)
+            for (int i = 0; i <= rods[r]->n; ++i)
+                for (int c = 0; c < 3; ++c) v[r][3 * i + c] += dv[r][3 * i + c];
+    }
+    for (int r = 0; r < n_rods; ++r) {
+        step_last(rods[r], x[r], v[r], q[r], w[r], &sc[r]);
+        free(cl[r]);
+        free(cn[r]);
+        free(dv[r]);
+    }
+}
+
+void oracle_rollout_group(const oracle_rod* const* rods, int32_t n_rods,
+                          const oracle_binding* bind, const oracle_contact* contact, double t0,
+                          int32_t n_steps, double* const* x, double* const* v, double* const* q,
+                          double* const* w, int32_t* max_contacts) {
+    int32_t most = 0;
+    for (int s = 0; s < n_steps; ++s) {
+        int32_t m = 0;
+        oracle_step_group(rods, n_rods, bind, contact, t0 + s * rods[0]->dt, x, v, q, w, &m);
+        if (m > most) most = m;
+    }
+    if (max_contacts) *max_contacts = most;
+}
+
 void oracle_rollout_pair(const oracle_rod* a, const oracle_rod* b, const oracle_binding* bind,
                          double t0, int32_t n_steps, double* xa, double* va, double* qa, double* wa,
                          double* xb, double* vb, double* qb, double* wb) {

@@ -148,6 +148,39 @@ void oracle_step_pair(const oracle_rod* a, const oracle_rod* b, const oracle_bin
                       double t, double* xa, double* va, double* qa, double* wa, double* xb,
                       double* vb, double* qb, double* wb);
 
+/* ---- Contact (Sec. 2.2 "Collisions and self-collisions"; Sec. 2.1 "Constraints") -------
+ * Every point 1..n carries a sphere of its element's radius (the mean of its two elements'
+ * at interior points).  Two points are in contact when their spheres overlap at the start of
+ * the step (points of one rod only if they are more than oracle_self_skip() apart along it,
+ * so resting neighbours never count); the contact keeps that normal n (from the other point
+ * towards this one) and target distance D = sum of the radii for the step.  In every
+ * constraint iteration, after the distance constraints and bindings, every point computes the
+ * impulse of each of its contacts from the same velocities: a normal impulse removing the
+ * predicted penetration, lambda = -s / (dt (w_i + w_j)) with s = (p_i - p_j) . n - D < 0,
+ * p = x + dt v, and a Coulomb friction impulse opposing the relative tangential velocity,
+ * at most mu lambda; the point applies the mean of its active contacts' impulses. */
+typedef struct {
+    double mu;   /* friction coefficient */
+} oracle_contact;
+
+/* Index distance along one rod within which points never collide: ceil(2 r_max / l_min), at
+ * least 1. */
+int32_t oracle_self_skip(const oracle_rod* rod);
+
+/* One step of a group of 1 or 2 rods (bindings need 2; either may be NULL), from time t, in
+ * place; x[r], v[r], q[r], w[r] are rod r's arrays.  All rods step with rods[0]'s dt and
+ * number of constraint iterations.  max_contacts (nullable) receives the largest number of
+ * contacts of one point. */
+void oracle_step_group(const oracle_rod* const* rods, int32_t n_rods, const oracle_binding* bind,
+                       const oracle_contact* contact, double t, double* const* x, double* const* v,
+                       double* const* q, double* const* w, int32_t* max_contacts);
+
+/* n_steps of oracle_step_group from time t0; max_contacts over all steps. */
+void oracle_rollout_group(const oracle_rod* const* rods, int32_t n_rods,
+                          const oracle_binding* bind, const oracle_contact* contact, double t0,
+                          int32_t n_steps, double* const* x, double* const* v, double* const* q,
+                          double* const* w, int32_t* max_contacts);
+
 /* n_steps of oracle_step_pair starting at time t0, in place. */
 void oracle_rollout_pair(const oracle_rod* a, const oracle_rod* b, const oracle_binding* bind,
                          double t0, int32_t n_steps, double* xa, double* va, double* qa, double* wa,

@@ -87,6 +87,12 @@ def lib():
         L.oracle_bind_impulse.restype = None
         L.oracle_bind_impulse.argtypes = [_DP, _DP, C.c_double, _DP, _DP, C.c_double, C.c_double,
                                           C.c_int32]
+        L.oracle_rollout_group.restype = None
+        L.oracle_rollout_group.argtypes = [C.POINTER(C.POINTER(_Rod)), C.c_int32,
+                                           C.POINTER(_Binding), C.POINTER(_Contact), C.c_double,
+                                           C.c_int32] + [C.POINTER(_DP)] * 4 + [C.POINTER(C.c_int32)]
+        L.oracle_self_skip.restype = C.c_int32
+        L.oracle_self_skip.argtypes = [C.POINTER(_Rod)]
         L.oracle_rollout_pair.restype = None
         L.oracle_rollout_pair.argtypes = [C.POINTER(_Rod), C.POINTER(_Rod), C.POINTER(_Binding),
                                           C.c_double, C.c_int32] + [_DP] * 8
@@ -97,6 +103,10 @@ def lib():
 class _Binding(C.Structure):
     _fields_ = [("n_pairs", C.c_int32), ("point_a", C.POINTER(C.c_int32)),
                 ("point_b", C.POINTER(C.c_int32)), ("one_way", C.c_int32)]
+
+
+class _Contact(C.Structure):
+    _fields_ = [("mu", C.c_double)]
 
 
 def _p(a):
@@ -261,6 +271,38 @@ def rollout_pair(spec_a, spec_b, state_a, state_b, point_a, point_b, one_way, n_
     lib().oracle_rollout_pair(C.byref(ra.c), C.byref(rb.c), C.byref(bd), float(t0), int(n_steps),
                               *[_p(a) for a in arrs])
     return out[0], out[1]
+
+
+def self_skip(spec):
+    return int(lib().oracle_self_skip(C.byref(Rod(spec).c)))
+
+
+def rollout_group(specs, states, n_steps, mu=None, pairs=None, one_way=False, t0=0.0):
+    """One or two rods stepped together: optional bindings (pairs: (k, 2) point indices of
+    rod 0 and rod 1, rod 1 the master if one_way) and optional contact with friction
+    coefficient mu.  Returns (new states, largest number of contacts of one point)."""
+    rods = [Rod(s) for s in specs]
+    outs, keep = [], []
+    for r, st in zip(rods, states):
+        o = st.copy()
+        o.x, o.v = _f64(st.x, (r.n + 1, 3)).copy(), _f64(st.v, (r.n + 1, 3)).copy()
+        o.q, o.w = _f64(st.q, (r.n, 4)).copy(), _f64(st.w, (r.n, 3)).copy()
+        outs.append(o)
+    rp = (C.POINTER(_Rod) * len(rods))(*[C.pointer(r.c) for r in rods])
+    arr = lambda k: (_DP * len(outs))(*[_p(getattr(o, k)) for o in outs])
+    bd = None
+    if pairs is not None:
+        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        ia, ib = np.ascontiguousarray(pr[:, 0]), np.ascontiguousarray(pr[:, 1])
+        keep += [ia, ib]
+        bd = _Binding(len(pr), ia.ctypes.data_as(C.POINTER(C.c_int32)),
+                      ib.ctypes.data_as(C.POINTER(C.c_int32)), int(bool(one_way)))
+    ct = _Contact(float(mu)) if mu is not None else None
+    most = C.c_int32(0)
+    lib().oracle_rollout_group(rp, len(rods), C.byref(bd) if bd is not None else None,
+                               C.byref(ct) if ct is not None else None, float(t0), int(n_steps),
+                               arr("x"), arr("v"), arr("q"), arr("w"), C.byref(most))
+    return outs, int(most.value)
 
 
 def rollout_many(specs_states, n_steps, t0=0.0, tip=False):
