@@ -203,11 +203,35 @@ def binding_extras(R, W):
         b.close()
         out[name] = {"us_per_step": 1e3 * ms / 5000,
                      "kernel": ("rod_resident_kernel<4,2>, one workgroup per rod" if one_way is None
-                                else "rod_pair_kernel<4,2>, both rods in one workgroup")}
+                                else "rod_group_kernel<4,2>, both rods in one workgroup")}
     for v in ("v1", "v2"):
         out[v]["overhead_vs_v0"] = out[v]["us_per_step"] / out["v0"]["us_per_step"] - 1.0
     out["workload"] = ("catheter/guidewire 2x512 inextensible, guidewire coaxial and bound at 384 "
                        "points, 5000 steps at 10 per launch")
+    return out
+
+
+def contact_extras(R, W):
+    """Crossing rods (2 x 128, falling onto each other): us/step without and with sphere
+    contact (friction 0.3), 10 steps per launch."""
+    wl = W.config6()
+    dt = min(R.stable_dt(s) for s, _ in wl.rods)
+    rods = [(s.replace(dt=dt), st) for s, st in wl.rods]
+    out = {}
+    for name, sets in (("no_contact", None), ("contact", [[0, 1]])):
+        b = R.RodBatch([s for s, _ in rods])
+        if sets is not None:
+            b.set_contact(sets, 0.3)
+        b.set_state_rods([st for _, st in rods])
+        b.step(200, 10)
+        b.step(2000, 10)
+        b.sync()
+        ms, _ = b.last_step_time()
+        b.close()
+        out[name] = {"us_per_step": 1e3 * ms / 2000}
+    out["overhead"] = out["contact"]["us_per_step"] / out["no_contact"]["us_per_step"] - 1.0
+    out["workload"] = ("2 x 128-element inextensible rods crossing, one falling onto the other; "
+                       "contact: both rods in one workgroup, sphere broad phase every step")
     return out
 
 
@@ -251,8 +275,8 @@ def main():
     ap.add_argument("--shape", default="", help="W,E kernel shape (default: autotune)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (4096 rods), long-rod and adjoint measurements")
-    ap.add_argument("--extras", default="batch,long_rod,adjoint,binding",
-                    help="comma-separated subset of batch,long_rod,adjoint,binding to measure")
+    ap.add_argument("--extras", default="batch,long_rod,adjoint,binding,contact",
+                    help="comma-separated subset of batch,long_rod,adjoint,binding,contact")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the rods of this workload are independent and a "
@@ -339,7 +363,7 @@ def main():
     }
     if not args.no_extras:
         fns = {"batch": batch_extras, "long_rod": long_rod_extras, "adjoint": adjoint_extras,
-               "binding": binding_extras}
+               "binding": binding_extras, "contact": contact_extras}
         out["extras"] = {k: fns[k](R, W) for k in args.extras.split(",") if k}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)

@@ -128,7 +128,10 @@ rod_status rod_step(rod_ctx* ctx, int32_t n_steps, int32_t steps_per_launch);
  * next step.  x0[3], q0[4] as in rod_params; the sinusoidal amplitudes are kept. */
 rod_status rod_set_clamp(rod_ctx* ctx, int32_t rod, const double* x0, const double* q0);
 
-/* Wait for the handle's stream; returns ROD_E_UNSTABLE if a non-finite state was seen. */
+/* Wait for the handle's stream; returns ROD_E_UNSTABLE if a non-finite state was seen,
+ * ROD_E_TIMEOUT if chunked long-rod workgroups lost step synchronisation, ROD_E_UNSUPPORTED
+ * if a point had more contacts than the kernel holds (the conditions stay latched until the
+ * next rod_set_state). */
 rod_status rod_sync(rod_ctx* ctx);
 
 /* Simulation time [s] and number of steps taken since rod_set_state(). */
@@ -173,6 +176,21 @@ rod_status rod_set_chunking(rod_ctx* ctx, int32_t min_elements, int32_t chunk_el
  * their points through LDS).  Replaces earlier bindings; takes effect at the next rod_step.
  * The adjoint refuses handles with bound rods.  Errors: INVALID, UNSUPPORTED, NOMEM, DEVICE. */
 rod_status rod_set_bindings(rod_ctx* ctx, int32_t n_pairs, const int32_t* pairs, int32_t mode);
+
+/* ---- Contact (Sec. 2.2 "Collisions and self-collisions"; Sec. 2.1 contact constraints) ---
+ * sets: n_sets x 2 int32 (rod_a, rod_b), rod_b = -1 for a rod alone: the points of the set's
+ * rods touch each other and themselves.  Every point 1..n carries a sphere of its element's
+ * radius (the mean of its two elements' radii inside the rod); at the start of each step,
+ * points whose spheres overlap are in contact (points of one rod only if more than
+ * ceil(2 r_max / l_min) apart along it) with the step-start normal and the sum of the radii as
+ * target distance; every constraint iteration, after the distance constraints and bindings,
+ * each point applies the mean of its active contacts' impulses: one removing the predicted
+ * penetration and a Coulomb friction impulse (coefficient mu) opposing the relative tangential
+ * velocity.  A set's rods share one workgroup (with a bound pair: the same two rods); they
+ * must be inextensible with equal dt and n_constraint_iters, at most 512 elements each, and
+ * a point may have at most 8 contacts (more: rod_sync reports ROD_E_UNSUPPORTED).  n_sets = 0
+ * removes all contact sets.  Errors: INVALID, UNSUPPORTED, NOMEM, DEVICE. */
+rod_status rod_set_contact(rod_ctx* ctx, int32_t n_sets, const int32_t* sets, double mu);
 
 /* Per bucket, time every built shape that holds its longest rod on probe_steps steps (the
  * state is saved and restored, the step counter unchanged) and keep the fastest; sets the

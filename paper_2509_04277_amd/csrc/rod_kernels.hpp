@@ -60,6 +60,7 @@ struct RodDev {
   int32_t fr_off;     // first frame in q, w
   int32_t n_iter;     // constraint iterations (0: extensible)
   int32_t clamp;      // 1: base point and frame 0 kinematic
+  int32_t self_skip;  // points of this rod closer than this along it never touch
   int32_t driven;     // 1: clamp trajectory has non-zero amplitudes
   int32_t has_ext;    // 1: read f_ext / tau_ext
   float dt, damp_lin, damp_ang, winv0;
@@ -614,48 +615,166 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
 }
 
 // ---------------------------------------------------------------------------------------
-// Two bound rods per workgroup (binding constraints of Sec. 2.1 "Constraints": distance
-// constraints of rest length zero between points of the two rods; Sec. 3.4 variants 1 and 2).
-// Threads [0, 64 W) step the first rod of the pair and [64 W, 128 W) the second, each exactly
-// as rod_resident_kernel steps one rod (both rods have the same number of constraint
-// iterations, so the halves take the same barriers).  After the distance sweeps of every
-// constraint iteration each point writes its predicted position x + dt v and inverse mass to
-// LDS, and each bound point applies the zero-length distance impulse against its partner:
-// v -= w d / (dt (w + w_partner)) with d = p - p_partner (two-way), or v -= d / dt for the
-// first rod only (one-way: the second rod is the master and is not moved).
-// partner[slot]: slot of the bound point in the other rod (point = slot + 1), -1 if unbound.
-// pair_mode[block]: 1 one-way, 2 two-way.
+// Groups of one or two rods per workgroup, for the constraints that couple points across rods
+// or far apart along one rod: bindings (Sec. 2.1 "Constraints": distance constraints of rest
+// length zero between points of two rods; Sec. 3.4 variants 1 and 2) and sphere contact with
+// Coulomb friction (Sec. 2.2 "Collisions and self-collisions").  Threads [0, 64 W) step the
+// group's first rod and [64 W, 128 W) the second, each exactly as rod_resident_kernel steps
+// one rod; a single rod leaves the second half idle (a rod of no elements taking the same
+// barriers).  Both rods have the same number of constraint iterations.
+//   Step start: every point writes its position and sphere radius to LDS; with contact, one
+//   thread per group of 8 consecutive points builds a bounding sphere, one thread per sphere
+//   marks the spheres overlapping it, and every point lists (in (rod, point) order, at most
+//   kMaxContacts) the points of overlapping spheres whose spheres overlap its own, leaving out
+//   points of its own rod within self_skip of it.
+//   Every constraint iteration, after the distance sweeps: points publish velocity and inverse
+//   mass; bound points apply the zero-length distance impulse (two-way, or one-way with the
+//   second rod the master); then, with contact, points publish again and every point applies
+//   the mean of its active contacts' impulses, computed from the published values: a normal
+//   impulse removing the predicted penetration along the step-start normal and a friction
+//   impulse opposing the relative tangential velocity, at most mu times the normal one.
+constexpr int kMaxContacts = 8;    // contacts per point (more sets status bit 8)
+constexpr int kSphereSize = 8;     // points per bounding sphere
+
+struct GroupDev {
+  int32_t rod[2];      // rod[1] = -1: a single rod
+  int32_t bind_mode;   // 0 none, 1 one-way (rod[1] is the master), 2 two-way
+  int32_t contact;     // 1: sphere contact between and within the group's rods
+  float mu;            // friction coefficient
+};
+
 template <int W, int E>
-__global__ __launch_bounds__(128 * W) void rod_pair_kernel(
-    const RodDev* __restrict__ rods, const int* __restrict__ pair_rods,
-    const int* __restrict__ pair_mode, const int* __restrict__ partner,
+__global__ __launch_bounds__(128 * W) void rod_group_kernel(
+    const RodDev* __restrict__ rods, const GroupDev* __restrict__ groups,
+    const int* __restrict__ partner, const float* __restrict__ rho_slot,
     const float* __restrict__ prm, int prm_stride, float* __restrict__ gx, float* __restrict__ gv,
     float* __restrict__ gq, float* __restrict__ gw, const float* __restrict__ fext,
     const float* __restrict__ text, int n_steps, long long steps_done, int* __restrict__ status) {
+  constexpr int CAP = 64 * W * E;                                   // slots per rod
+  constexpr int SMAX = 2 * ((CAP + kSphereSize - 1) / kSphereSize);  // spheres per group
   __shared__ Mailbox<W> mb[2];
   __shared__ float cbuf[2][kClampChunk][10];
-  // predicted positions and inverse masses, double-buffered by iteration parity: the reads of
-  // iteration i and the writes of iteration i + 2 are separated by iteration i + 1's barrier
-  __shared__ float4 bp[2][2][64 * W * E];
+  __shared__ float4 xs[2][CAP];      // step-start position and sphere radius
+  // velocity and inverse mass, double-buffered by publication parity: the reads after one
+  // publication and the writes two publications later are separated by a barrier
+  __shared__ float4 vw[2][2][CAP];
+  __shared__ float4 sph[SMAX];                           // bounding spheres: centre, radius
+  __shared__ uint32_t sov[SMAX][(SMAX + 31) / 32];       // sphere-overlap bitmask
+  __shared__ uint16_t lst[2][CAP][kMaxContacts];         // contacts: sub * CAP + slot
+  const GroupDev gp = groups[blockIdx.x];
   const int sub = threadIdx.x >= 64 * W ? 1 : 0;
-  const RodDev rd = rods[pair_rods[2 * blockIdx.x + sub]];
-  const RodDev& ro = rods[pair_rods[2 * blockIdx.x + 1 - sub]];
-  const bool any_driven = (rd.driven && rd.clamp) || (ro.driven && ro.clamp);
-  const int mode = pair_mode[blockIdx.x];
-  const bool moved = !(mode == 1 && sub == 1);
+  const bool active = gp.rod[sub] >= 0;
+  RodDev rd = rods[active ? gp.rod[sub] : gp.rod[0]];
+  if (!active) rd.n = 0;   // idle half: no slots, same barriers
+  const RodDev& r0 = rods[gp.rod[0]];
+  bool any_driven = r0.driven && r0.clamp;
+  int nrod[2] = {r0.n, 0};
+  if (gp.rod[1] >= 0) {
+    const RodDev& r1 = rods[gp.rod[1]];
+    any_driven = any_driven || (r1.driven && r1.clamp);
+    nrod[1] = r1.n;
+  }
+  const bool moved = !(gp.bind_mode == 1 && sub == 1);
+  const bool contact = gp.contact != 0;
   RodLane<W, E> L;
   L.load_params(rd, prm, prm_stride);
   L.load_state(rd, gx, gv, gq, gw);
-  int part[E];
+  int part[E], cnt[E];
+  float rho[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) part[e] = L.ok[e] ? partner[rd.slot_off + L.j0 + e] : -1;
+  for (int e = 0; e < E; ++e) {
+    part[e] = (L.ok[e] && gp.bind_mode) ? partner[rd.slot_off + L.j0 + e] : -1;
+    rho[e] = L.ok[e] ? rho_slot[rd.slot_off + L.j0 + e] : 0.f;
+    cnt[e] = 0;
+  }
+  const int skip = rd.self_skip;
   int par = 0;
   V3 xc = {rd.cx0[0], rd.cx0[1], rd.cx0[2]}, wc = {0.f, 0.f, 0.f};
   Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
   const float dt = rd.dt;
   int bpar = 0;
+  bool overflow = false;
+  auto publish = [&]() {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (L.ok[e]) vw[bpar][sub][L.j0 + e] = make_float4(L.Vv[e].x, L.Vv[e].y, L.Vv[e].z, L.P[P_WINV][e]);
+    __syncthreads();
+  };
 
   for (int s = 0; s < n_steps; ++s) {
+    // ---- step start: positions and radii; contact lists
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (L.ok[e]) xs[sub][L.j0 + e] = make_float4(L.X[e].x, L.X[e].y, L.X[e].z, rho[e]);
+    __syncthreads();
+    if (contact) {
+      const int s0 = (nrod[0] + kSphereSize - 1) / kSphereSize;
+      const int ns = s0 + (nrod[1] + kSphereSize - 1) / kSphereSize;
+      const int t = threadIdx.x;
+      if (t < ns) {
+        const int r = t < s0 ? 0 : 1, k = t < s0 ? t : t - s0;
+        const int a = k * kSphereSize, b = min(a + kSphereSize, nrod[r]);
+        float cx = 0.f, cy = 0.f, cz = 0.f, rm = 0.f;
+        for (int j = a; j < b; ++j) {
+          const float4 p = xs[r][j];
+          cx += p.x; cy += p.y; cz += p.z;
+          rm = fmaxf(rm, p.w);
+        }
+        const float inv = 1.0f / (float)(b - a);
+        cx *= inv; cy *= inv; cz *= inv;
+        float d2 = 0.f;
+        for (int j = a; j < b; ++j) {
+          const float4 p = xs[r][j];
+          d2 = fmaxf(d2, (p.x - cx) * (p.x - cx) + (p.y - cy) * (p.y - cy) + (p.z - cz) * (p.z - cz));
+        }
+        sph[t] = make_float4(cx, cy, cz, sqrtf(d2) + rm);
+      }
+      __syncthreads();
+      if (t < ns) {
+        const float4 me = sph[t];
+        for (int wd = 0; wd < (ns + 31) / 32; ++wd) {
+          uint32_t bits = 0;
+          for (int bb = 0; bb < 32; ++bb) {
+            const int k = wd * 32 + bb;
+            if (k < ns) {
+              const float4 o = sph[k];
+              const float dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z, rr = me.w + o.w;
+              if (dx * dx + dy * dy + dz * dz < rr * rr) bits |= 1u << bb;
+            }
+          }
+          sov[t][wd] = bits;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        cnt[e] = 0;
+        if (!L.ok[e]) continue;
+        const int i = L.j0 + e;
+        const int own = sub * s0 + i / kSphereSize;
+        const V3 xi = L.X[e];
+        for (int wd = 0; wd < (ns + 31) / 32; ++wd) {
+          uint32_t bits = sov[own][wd];
+          while (bits) {
+            const int k = wd * 32 + __builtin_ctz(bits);
+            bits &= bits - 1;
+            const int r = k < s0 ? 0 : 1, kk = k < s0 ? k : k - s0;
+            const int a = kk * kSphereSize, b = min(a + kSphereSize, nrod[r]);
+            for (int j = a; j < b; ++j) {
+              if (r == sub && abs(j - i) <= skip) continue;
+              const float4 p = xs[r][j];
+              const float dx = xi.x - p.x, dy = xi.y - p.y, dz = xi.z - p.z, D = rho[e] + p.w;
+              const float d2 = dx * dx + dy * dy + dz * dz;
+              if (!(d2 < D * D) || !(d2 > 0.f)) continue;
+              if (cnt[e] < kMaxContacts) lst[sub][i][cnt[e]++] = (uint16_t)(r * CAP + j);
+              else overflow = true;
+            }
+          }
+        }
+      }
+    }
+
+    // ---- the step
     V3 xl;
     Q4 qn;
     L.exchange_a(mb[sub], par, xl, qn);
@@ -666,32 +785,68 @@ __global__ __launch_bounds__(128 * W) void rod_pair_kernel(
     for (int it = 0; it < rd.n_iter; ++it) {
       L.half_sweep(rd, mb[sub], par, 0, Ev, enext, nullptr);
       L.half_sweep(rd, mb[sub], par, 1, Ev, enext, nullptr);
-      // binding impulses against the other rod's predicted positions
+      if (gp.bind_mode) {
+        publish();
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        if (L.ok[e]) {
-          const V3 p = fma3(dt, L.Vv[e], L.X[e]);
-          bp[bpar][sub][L.j0 + e] = make_float4(p.x, p.y, p.z, L.P[P_WINV][e]);
+        for (int e = 0; e < E; ++e) {
+          if (part[e] >= 0 && moved) {
+            const float4 ox = xs[1 - sub][part[e]];
+            const float4 ov = vw[bpar][1 - sub][part[e]];
+            const V3 p = fma3(dt, L.Vv[e], L.X[e]);
+            const V3 po = fma3(dt, V3{ov.x, ov.y, ov.z}, V3{ox.x, ox.y, ox.z});
+            const V3 d = p - po;
+            const float wm = L.P[P_WINV][e];
+            const float ws = gp.bind_mode == 2 ? wm + ov.w : wm;
+            if (ws > 0.f) L.Vv[e] = fnma3(wm / (dt * ws), d, L.Vv[e]);
+          }
         }
+        bpar ^= 1;
       }
-      __syncthreads();
+      if (contact) {
+        publish();
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        if (part[e] >= 0 && moved) {
-          const float4 o = bp[bpar][1 - sub][part[e]];
-          const V3 p = fma3(dt, L.Vv[e], L.X[e]);
-          const V3 d = {p.x - o.x, p.y - o.y, p.z - o.z};
-          const float wm = L.P[P_WINV][e];
-          const float ws = mode == 2 ? wm + o.w : wm;
-          if (ws > 0.f) L.Vv[e] = fnma3(wm / (dt * ws), d, L.Vv[e]);
+        for (int e = 0; e < E; ++e) {
+          if (!cnt[e]) continue;
+          const int i = L.j0 + e;
+          const V3 xi = L.X[e], vi = L.Vv[e];
+          const V3 pi = fma3(dt, vi, xi);
+          const float wi = L.P[P_WINV][e];
+          V3 acc = {0.f, 0.f, 0.f};
+          int act = 0;
+          for (int c = 0; c < cnt[e]; ++c) {
+            const int gidx = lst[sub][i][c];
+            const int r = gidx >= CAP ? 1 : 0, j = gidx - r * CAP;
+            const float4 ox = xs[r][j];
+            const float4 ov = vw[bpar][r][j];
+            const V3 xj = {ox.x, ox.y, ox.z}, vj = {ov.x, ov.y, ov.z};
+            const float wsum = wi + ov.w;
+            if (!(wsum > 0.f)) continue;
+            const V3 d0 = xi - xj;
+            const V3 nrm = rsqrtf(dot(d0, d0)) * d0;        // step-start normal, towards i
+            const V3 pj = fma3(dt, vj, xj);
+            const float sep = dot(pi - pj, nrm) - (rho[e] + ox.w);
+            if (!(sep < 0.f)) continue;
+            const float lam = -sep / (dt * wsum);
+            const V3 vr = vi - vj;
+            const V3 vt = fnma3(dot(vr, nrm), nrm, vr);
+            const float vtl = sqrtf(dot(vt, vt));
+            V3 imp = (wi * lam) * nrm;
+            if (vtl > 0.f) imp = fnma3(wi * fminf(vtl / wsum, gp.mu * lam) / vtl, vt, imp);
+            acc = acc + imp;
+            ++act;
+          }
+          if (act) L.Vv[e] = fma3(1.0f / (float)act, acc, L.Vv[e]);
         }
+        bpar ^= 1;
       }
-      bpar ^= 1;
     }
     L.integrate_velocities(rd, xc, qc);
   }
-  const float chk = L.store_state(rd, gx, gv, gq, gw);
-  if (!__builtin_isfinite(chk)) atomicOr(status, 1);
+  if (active) {
+    const float chk = L.store_state(rd, gx, gv, gq, gw);
+    if (!__builtin_isfinite(chk)) atomicOr(status, 1);
+  }
+  if (overflow) atomicOr(status, 8);
 }
 
 // ---------------------------------------------------------------------------------------

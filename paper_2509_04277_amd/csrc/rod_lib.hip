@@ -79,20 +79,21 @@ const KernelEntry* find_kernel(int w, int e) {
 
 GridFn grid_kernel() { return corde::rod_grid_kernel<kGridWaves, kGridElems>; }
 
-using PairFn = void (*)(const RodDev*, const int*, const int*, const int*, const float*, int,
-                        float*, float*, float*, float*, const float*, const float*, int, long long,
-                        int*);
-struct PairEntry {
+using GroupFn = void (*)(const RodDev*, const corde::GroupDev*, const int*, const float*,
+                         const float*, int, float*, float*, float*, float*, const float*,
+                         const float*, int, long long, int*);
+struct GroupEntry {
   int waves, elems;
-  PairFn fn;
+  GroupFn fn;
 };
-// Shapes of the two-rod (bound pair) kernel, per rod; a workgroup holds 2 x 64 waves threads
-// (at most 8 wavefronts: with 16 the register budget halves and the kernel spills).
-const PairEntry kPairs[] = {
-    {2, 2, corde::rod_pair_kernel<2, 2>}, {4, 2, corde::rod_pair_kernel<4, 2>},
-    {2, 4, corde::rod_pair_kernel<2, 4>}, {2, 8, corde::rod_pair_kernel<2, 8>},
+// Shapes of the rod-group kernel (bindings, contact), per rod; a workgroup holds 2 x 64 waves
+// threads (at most 8 wavefronts: with 16 the register budget halves and the kernel spills).
+const GroupEntry kGroups[] = {
+    {2, 2, corde::rod_group_kernel<2, 2>}, {4, 2, corde::rod_group_kernel<4, 2>},
+    {2, 4, corde::rod_group_kernel<2, 4>}, {2, 8, corde::rod_group_kernel<2, 8>},
 };
-constexpr int kPairMax = 1024;   // longest rod a bound pair may hold
+constexpr int kGroupMax = 1024;     // longest rod a group may hold
+constexpr int kContactMax = 512;    // longest rod of a group with contact
 
 thread_local std::string g_last_error;
 
@@ -131,13 +132,18 @@ struct rod_ctx {
   float* d_pub = nullptr;
   int* d_flags = nullptr;
   std::vector<Bucket> buckets;
-  // bound pairs (binding constraints): two rods per workgroup, grouped by kernel shape
-  std::vector<char> bound;              // per rod: stepped by the pair kernel
-  std::vector<int> pair_rods, pair_mode;  // 2 rods and the mode per pair, bucket by bucket
-  std::vector<Bucket> pair_buckets;     // first/count index pairs
-  int* d_pair_rods = nullptr;
-  int* d_pair_mode = nullptr;
-  int* d_partner = nullptr;             // per slot: slot of the bound point in the other rod
+  // rod groups (bindings, contact): one or two rods per workgroup, grouped by kernel shape
+  std::vector<std::array<int, 2>> bind_pairs;   // as set: bound rod pairs (second = master)
+  int bind_mode = 0;
+  std::vector<int> partner;                     // per slot: slot of the bound point, or -1
+  std::vector<std::array<int, 2>> contact_sets; // as set: rods in contact (second -1: alone)
+  float contact_mu = 0.f;
+  std::vector<char> bound;                      // per rod: stepped by the group kernel
+  std::vector<corde::GroupDev> groups;          // bucket by bucket
+  std::vector<Bucket> pair_buckets;             // shapes of the group buckets
+  corde::GroupDev* d_groups = nullptr;
+  int* d_partner = nullptr;
+  float* d_rho = nullptr;                       // per slot: sphere radius of point slot + 1
   std::vector<int> rod_ids;
   int* d_rod_ids = nullptr;
   int steps_per_launch = 10;
@@ -307,6 +313,14 @@ RodDev make_dev(const rod_params& p, int slot_off, int pt_off, int fr_off, doubl
   d.fr_off = fr_off;
   d.n_iter = p.inextensible ? p.n_constraint_iters : 0;
   d.clamp = p.clamp_end0;
+  {  // contact: points closer than 2 r_max along the rod (in elements of l_min) never touch
+    double rmax = 0.0, lmin = INFINITY;
+    for (int j = 0; j < p.n_elements; ++j) {
+      rmax = std::max(rmax, p.radius[j]);
+      lmin = std::min(lmin, p.seg_len[j]);
+    }
+    d.self_skip = std::max(1, (int)std::ceil(2.0 * rmax / lmin));
+  }
   d.has_ext = (p.f_ext || p.tau_ext) ? 1 : 0;
   d.dt = (float)p.dt;
   d.dt_d = p.dt;
@@ -508,16 +522,103 @@ rod_status launch_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long long
 
 rod_status launch_pair_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long long done,
                               hipStream_t stream) {
-  const PairEntry* k = nullptr;
-  for (const auto& e : kPairs)
+  const GroupEntry* k = nullptr;
+  for (const auto& e : kGroups)
     if (e.waves == b.waves && e.elems == b.elems) k = &e;
-  if (!k) return fail(c, ROD_E_UNSUPPORTED, "pair kernel shape not built");
+  if (!k) return fail(c, ROD_E_UNSUPPORTED, "group kernel shape not built");
   hipLaunchKernelGGL(k->fn, dim3(b.count), dim3(128 * k->waves), 0, stream, c->d_rods,
-                     c->d_pair_rods + 2 * b.first, c->d_pair_mode + b.first, c->d_partner, c->d_prm,
-                     c->prm_stride, c->d_x, c->d_v, c->d_q, c->d_w, c->d_fext, c->d_text, ks, done,
-                     c->d_status);
+                     c->d_groups + b.first, c->d_partner, c->d_rho, c->d_prm, c->prm_stride,
+                     c->d_x, c->d_v, c->d_q, c->d_w, c->d_fext, c->d_text, ks, done, c->d_status);
   HIP_TRY(c, hipGetLastError());
   return ROD_OK;
+}
+
+// Merges the bindings and contact sets into workgroup groups (a rod in one group at most),
+// checks them, and rebuilds the group and single-rod buckets.
+rod_status rebuild_groups(rod_ctx* c) {
+  std::vector<corde::GroupDev> gs;
+  std::vector<int> group_of(c->n_rods, -1);
+  for (const auto& p : c->bind_pairs) {
+    group_of[p[0]] = group_of[p[1]] = (int)gs.size();
+    gs.push_back({{p[0], p[1]}, c->bind_mode, 0, 0.f});
+  }
+  for (const auto& cs : c->contact_sets) {
+    const int a = cs[0], b = cs[1];
+    int g = group_of[a];
+    if (g >= 0) {
+      if (b >= 0 && !(gs[g].rod[0] == b || gs[g].rod[1] == b))
+        return fail(c, ROD_E_INVALID, "contact set of rods in different groups");
+    } else if (b >= 0 && group_of[b] >= 0) {
+      return fail(c, ROD_E_INVALID, "contact set of rods in different groups");
+    } else {
+      g = (int)gs.size();
+      gs.push_back({{a, b}, 0, 0, 0.f});
+      group_of[a] = g;
+      if (b >= 0) group_of[b] = g;
+    }
+    gs[g].contact = 1;
+    gs[g].mu = c->contact_mu;
+  }
+  for (const auto& g : gs) {
+    const RodDev& a = c->rods[g.rod[0]];
+    const int n = std::max(a.n, g.rod[1] >= 0 ? c->rods[g.rod[1]].n : 0);
+    if (a.n_iter < 1) return fail(c, ROD_E_UNSUPPORTED, "grouped rods must be inextensible");
+    if (g.rod[1] >= 0) {
+      const RodDev& b = c->rods[g.rod[1]];
+      if (b.n_iter != a.n_iter) return fail(c, ROD_E_UNSUPPORTED, "grouped rods need equal constraint iterations");
+      if (b.dt_d != a.dt_d) return fail(c, ROD_E_UNSUPPORTED, "grouped rods need equal dt");
+    }
+    if (n > std::min(g.contact ? kContactMax : kGroupMax, c->chunk_above))
+      return fail(c, ROD_E_UNSUPPORTED, "grouped rods are limited to 1024 elements (512 with contact) "
+                                        "and must not be chunked");
+  }
+  auto shape_of = [&](int n, int* w, int* e) {
+    *w = n <= 512 ? (n <= 256 ? 2 : 4) : 2;
+    *e = n <= 512 ? 2 : 8;
+  };
+  auto nmax = [&](const corde::GroupDev& g) {
+    return std::max(c->n[g.rod[0]], g.rod[1] >= 0 ? c->n[g.rod[1]] : 0);
+  };
+  std::vector<std::pair<long long, int>> key;
+  for (int g = 0; g < (int)gs.size(); ++g) {
+    int w, e;
+    shape_of(nmax(gs[g]), &w, &e);
+    const long long cost = (long long)(c->n[gs[g].rod[0]] + (gs[g].rod[1] >= 0 ? c->n[gs[g].rod[1]] : 0)) *
+                           (4 + c->rods[gs[g].rod[0]].n_iter);
+    key.push_back({((long long)(w * 16 + e) << 32) | (0x7fffffffLL - cost), g});
+  }
+  std::sort(key.begin(), key.end());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));   // no launch may still read the old tables
+  for (hipStream_t st : c->bstreams) HIP_TRY(c, hipStreamSynchronize(st));
+  c->groups.clear();
+  c->pair_buckets.clear();
+  c->bound.assign(c->n_rods, 0);
+  for (int i = 0; i < (int)key.size(); ++i) {
+    const auto& g = gs[key[i].second];
+    int w, e;
+    shape_of(nmax(g), &w, &e);
+    c->groups.push_back(g);
+    c->bound[g.rod[0]] = 1;
+    if (g.rod[1] >= 0) c->bound[g.rod[1]] = 1;
+    if (c->pair_buckets.empty() || c->pair_buckets.back().waves != w || c->pair_buckets.back().elems != e)
+      c->pair_buckets.push_back({w, e, i, 0, 0, 0.f});
+    c->pair_buckets.back().count++;
+    c->pair_buckets.back().max_n = std::max(c->pair_buckets.back().max_n, nmax(g));
+  }
+  if (c->d_groups) (void)hipFree(c->d_groups);
+  c->d_groups = nullptr;
+  if (!c->groups.empty()) {
+    if (hipMalloc((void**)&c->d_groups, sizeof(corde::GroupDev) * c->groups.size()) != hipSuccess)
+      return fail(c, ROD_E_NOMEM, "group tables");
+    HIP_TRY(c, hipMemcpy(c->d_groups, c->groups.data(), sizeof(corde::GroupDev) * c->groups.size(),
+                         hipMemcpyHostToDevice));
+    if (!c->d_partner && hipMalloc((void**)&c->d_partner, sizeof(int) * c->partner.size()) != hipSuccess)
+      return fail(c, ROD_E_NOMEM, "group tables");
+    HIP_TRY(c, hipMemcpy(c->d_partner, c->partner.data(), sizeof(int) * c->partner.size(),
+                         hipMemcpyHostToDevice));
+    c->adj_ready = false;   // the adjoint does not step grouped rods
+  }
+  return make_buckets(c, [&](int r, int* w, int* e) { default_shape(c->n[r], w, e); });
 }
 
 // n_steps steps of every rod, spl steps per launch; bucket < 0: all buckets, else that one.
@@ -736,6 +837,7 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
   c->prm_stride = (int)frames;
   std::vector<float> rows((size_t)(corde::P_NROWS + 1) * c->prm_stride, 0.f);
   std::vector<float> fext, text;
+  std::vector<float> rho((size_t)std::max<long long>(frames, 1), 0.f);   // sphere radius per slot
   bool any_ext = false;
   for (int r = 0; r < n_rods; ++r) any_ext = any_ext || params[r].f_ext || params[r].tau_ext;
   if (any_ext) {
@@ -747,6 +849,9 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
     const rod_params& p = params[r];
     double winv0 = 0;
     fill_rows(p, rows, c->prm_stride, slot, &winv0);
+    for (int j = 0; j < p.n_elements; ++j)   // point j + 1: its element's radius, the mean inside
+      rho[(size_t)slot + j] = (float)(j + 1 == p.n_elements ? p.radius[j]
+                                                             : 0.5 * (p.radius[j] + p.radius[j + 1]));
     c->rods.push_back(make_dev(p, slot, pt, fr, winv0));
     c->n.push_back(p.n_elements);
     if (p.f_ext)
@@ -767,13 +872,15 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
       !dmalloc((void**)&c->d_q, sizeof(float) * 4 * frames) ||
       !dmalloc((void**)&c->d_w, sizeof(float) * 3 * frames) ||
       !dmalloc((void**)&c->d_status, sizeof(int)) ||
-      !dmalloc((void**)&c->d_rod_ids, sizeof(int) * n_rods))
+      !dmalloc((void**)&c->d_rod_ids, sizeof(int) * n_rods) ||
+      !dmalloc((void**)&c->d_rho, sizeof(float) * rho.size()))
     return cleanup(fail(nullptr, ROD_E_NOMEM, "device allocation failed"));
   if (any_ext && (!dmalloc((void**)&c->d_fext, sizeof(float) * fext.size()) ||
                   !dmalloc((void**)&c->d_text, sizeof(float) * text.size())))
     return cleanup(fail(nullptr, ROD_E_NOMEM, "device allocation failed"));
   e = hipMemcpy(c->d_rods, c->rods.data(), sizeof(RodDev) * n_rods, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_prm, rows.data(), sizeof(float) * rows.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_rho, rho.data(), sizeof(float) * rho.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && any_ext) {
     e = hipMemcpy(c->d_fext, fext.data(), sizeof(float) * fext.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_text, text.data(), sizeof(float) * text.size(), hipMemcpyHostToDevice);
@@ -804,8 +911,8 @@ rod_status rod_destroy(rod_ctx* c) {
                   (void*)c->d_q, (void*)c->d_w, (void*)c->d_fext, (void*)c->d_text,
                   (void*)c->d_status, (void*)c->d_rod_ids, (void*)c->d_ckpt, (void*)c->d_traj,
                   (void*)c->d_tips, (void*)c->d_dtips, (void*)c->d_adj,
-                  (void*)c->d_gacc, (void*)c->d_pair_rods, (void*)c->d_pair_mode,
-                  (void*)c->d_partner, (void*)c->d_chunks, (void*)c->d_block_chunk, (void*)c->d_pub,
+                  (void*)c->d_gacc, (void*)c->d_groups, (void*)c->d_partner, (void*)c->d_rho,
+                  (void*)c->d_chunks, (void*)c->d_block_chunk, (void*)c->d_pub,
                   (void*)c->d_flags})
     if (p) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -896,6 +1003,7 @@ rod_status rod_sync(rod_ctx* c) {
   int st = 0;
   HIP_TRY(c, hipMemcpy(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost));
   if (st & 4) return fail(c, ROD_E_TIMEOUT, "a long-rod chunk waited too long for a neighbour");
+  if (st & 8) return fail(c, ROD_E_UNSUPPORTED, "a point had more than 8 contacts in one step");
   if (st) return fail(c, ROD_E_UNSTABLE, "non-finite state detected by the step kernel");
   return ROD_OK;
 }
@@ -942,7 +1050,9 @@ rod_status rod_bucket_info(const rod_ctx* c, int32_t bucket, rod_tuning* t, int3
     t->elems_per_lane = b.elems;
     t->steps_per_launch = c->steps_per_launch;
     t->us_per_step = 0.f;
-    *n_rods = 2 * b.count;
+    int nr = 0;
+    for (int i = 0; i < b.count; ++i) nr += c->groups[b.first + i].rod[1] >= 0 ? 2 : 1;
+    *n_rods = nr;
     return ROD_OK;
   }
   const int nb = nb0 + (int)c->pair_buckets.size();
@@ -1035,66 +1145,54 @@ rod_status rod_set_bindings(rod_ctx* c, int32_t n_pairs, const int32_t* pairs, i
     partner[sa] = pb - 1;
     partner[sb] = pa - 1;
   }
-  for (const auto& g : groups) {
-    const RodDev &a = c->rods[g[0]], &b = c->rods[g[1]];
-    if (a.n_iter < 1 || a.n_iter != b.n_iter)
-      return fail(c, ROD_E_UNSUPPORTED, "bound rods must be inextensible with equal constraint iterations");
-    if (a.dt_d != b.dt_d) return fail(c, ROD_E_UNSUPPORTED, "bound rods must have equal dt");
-    if (std::max(a.n, b.n) > std::min(kPairMax, c->chunk_above))
-      return fail(c, ROD_E_UNSUPPORTED, "bound rods are limited to 1024 elements and must not be chunked");
+  const auto old_pairs = c->bind_pairs;
+  const auto old_partner = c->partner;
+  const int old_mode = c->bind_mode;
+  c->bind_pairs = groups;
+  c->partner = partner;
+  c->bind_mode = groups.empty() ? 0 : mode;
+  rod_status st = rebuild_groups(c);
+  if (st != ROD_OK) {   // keep the previous configuration
+    const std::string err = c->err;
+    c->bind_pairs = old_pairs;
+    c->partner = old_partner;
+    c->bind_mode = old_mode;
+    (void)rebuild_groups(c);
+    return fail(c, st, err);
   }
-  // pair buckets: the smallest shape that holds both rods, costliest pairs first
-  auto shape_of = [&](int n, int* w, int* e) {
-    *w = n <= 512 ? (n <= 256 ? 2 : 4) : 2;
-    *e = n <= 512 ? 2 : 8;
-  };
-  std::vector<std::pair<long long, int>> key;
-  for (int g = 0; g < (int)groups.size(); ++g) {
-    const int nmax = std::max(c->n[groups[g][0]], c->n[groups[g][1]]);
-    int w, e;
-    shape_of(nmax, &w, &e);
-    const long long cost = (long long)(c->n[groups[g][0]] + c->n[groups[g][1]]) *
-                           (4 + c->rods[groups[g][0]].n_iter);
-    key.push_back({((long long)(w * 16 + e) << 32) | (0x7fffffffLL - cost), g});
+  return ROD_OK;
+}
+
+rod_status rod_set_contact(rod_ctx* c, int32_t n_sets, const int32_t* sets, double mu) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (n_sets < 0 || (n_sets > 0 && !sets)) return fail(c, ROD_E_INVALID, "bad contact list");
+  if (!(std::isfinite(mu) && mu >= 0.0)) return fail(c, ROD_E_INVALID, "mu must be finite and >= 0");
+  std::vector<std::array<int, 2>> cs;
+  std::vector<char> seen(c->n_rods, 0);
+  for (int k = 0; k < n_sets; ++k) {
+    const int a = sets[2 * k], b = sets[2 * k + 1];
+    if (a < 0 || a >= c->n_rods || b < -1 || b >= c->n_rods || a == b)
+      return fail(c, ROD_E_INVALID, "contact set " + std::to_string(k) + ": bad rod index");
+    if (seen[a] || (b >= 0 && seen[b]))
+      return fail(c, ROD_E_INVALID, "contact set " + std::to_string(k) + ": a rod is in two sets");
+    seen[a] = 1;
+    if (b >= 0) seen[b] = 1;
+    cs.push_back({a, b});
   }
-  std::sort(key.begin(), key.end());
-  HIP_TRY(c, hipStreamSynchronize(c->stream));   // no launch may still read the old tables
-  for (hipStream_t st : c->bstreams) HIP_TRY(c, hipStreamSynchronize(st));
-  c->pair_rods.clear();
-  c->pair_mode.clear();
-  c->pair_buckets.clear();
-  c->bound.assign(c->n_rods, 0);
-  for (int i = 0; i < (int)key.size(); ++i) {
-    const auto& g = groups[key[i].second];
-    int w, e;
-    shape_of(std::max(c->n[g[0]], c->n[g[1]]), &w, &e);
-    c->pair_rods.push_back(g[0]);
-    c->pair_rods.push_back(g[1]);
-    c->pair_mode.push_back(mode);
-    c->bound[g[0]] = c->bound[g[1]] = 1;
-    if (c->pair_buckets.empty() || c->pair_buckets.back().waves != w || c->pair_buckets.back().elems != e)
-      c->pair_buckets.push_back({w, e, i, 0, 0, 0.f});
-    c->pair_buckets.back().count++;
-    c->pair_buckets.back().max_n = std::max(c->pair_buckets.back().max_n, std::max(c->n[g[0]], c->n[g[1]]));
+  const auto old = c->contact_sets;
+  const float old_mu = c->contact_mu;
+  c->contact_sets = cs;
+  c->contact_mu = (float)mu;
+  if (c->partner.empty()) c->partner.assign((size_t)std::max(c->total_frames, 1), -1);
+  rod_status st = rebuild_groups(c);
+  if (st != ROD_OK) {
+    const std::string err = c->err;
+    c->contact_sets = old;
+    c->contact_mu = old_mu;
+    (void)rebuild_groups(c);
+    return fail(c, st, err);
   }
-  for (void** p : {(void**)&c->d_pair_rods, (void**)&c->d_pair_mode}) {
-    if (*p) (void)hipFree(*p);
-    *p = nullptr;
-  }
-  if (!groups.empty()) {
-    if (!c->d_partner && hipMalloc((void**)&c->d_partner, sizeof(int) * partner.size()) != hipSuccess)
-      return fail(c, ROD_E_NOMEM, "binding tables");
-    if (hipMalloc((void**)&c->d_pair_rods, sizeof(int) * c->pair_rods.size()) != hipSuccess ||
-        hipMalloc((void**)&c->d_pair_mode, sizeof(int) * c->pair_mode.size()) != hipSuccess)
-      return fail(c, ROD_E_NOMEM, "binding tables");
-    HIP_TRY(c, hipMemcpy(c->d_partner, partner.data(), sizeof(int) * partner.size(), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->d_pair_rods, c->pair_rods.data(), sizeof(int) * c->pair_rods.size(),
-                         hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->d_pair_mode, c->pair_mode.data(), sizeof(int) * c->pair_mode.size(),
-                         hipMemcpyHostToDevice));
-    c->adj_ready = false;   // the adjoint does not step bound pairs
-  }
-  return make_buckets(c, [&](int r, int* w, int* e) { default_shape(c->n[r], w, e); });
+  return ROD_OK;
 }
 
 rod_status rod_last_step_time(rod_ctx* c, float* ms, int32_t* launches) {
@@ -1213,7 +1311,7 @@ rod_status rod_adjoint_forward(rod_ctx* c, int32_t n_steps, int32_t ckpt_every, 
   for (const auto& b : c->buckets)
     if (!adjoint_shape(b.max_n)) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
   if (c->n_chunks) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
-  if (!c->pair_rods.empty()) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not step bound rods");
+  if (!c->groups.empty()) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not step grouped rods");
   c->adj_ready = false;
   const size_t S = state_floats(c);
   const int ck = std::min(ckpt_every, n_steps);

@@ -69,6 +69,7 @@ _SIGS = {
     "rod_bucket_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rod_tuning), C.POINTER(C.c_int32)]),
     "rod_set_chunking": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "rod_set_bindings": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32]),
+    "rod_set_contact": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_double]),
     "rod_stable_dt": (C.c_int, [C.POINTER(rod_params), _DP]),
     "rod_last_step_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     "rod_set_stiffness_mult": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
@@ -328,6 +329,13 @@ class RodBatch:
         _check(lib().rod_set_bindings(self.h, int(arr.shape[0]),
                                       arr.ctypes.data_as(C.POINTER(C.c_int32)),
                                       1 if one_way else 2), self.h)
+
+    def set_contact(self, sets, mu: float):
+        """Contact sets (k, 2) = (rod_a, rod_b or -1) with friction coefficient mu; an empty list
+        removes them."""
+        arr = np.ascontiguousarray(np.asarray(sets, dtype=np.int32).reshape(-1, 2))
+        _check(lib().rod_set_contact(self.h, int(arr.shape[0]),
+                                     arr.ctypes.data_as(C.POINTER(C.c_int32)), float(mu)), self.h)
 
     def set_chunking(self, min_elements: int, chunk_elements: int = 0):
         """Step rods longer than min_elements with the chunked multi-workgroup kernel, about

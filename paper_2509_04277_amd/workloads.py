@@ -328,6 +328,30 @@ def config5(one_way: bool, n: int = 512, shift: int = 128,
             pairs)
 
 
+def config6(n: int = 128, gap: float = 1e-3, dt: float = 0.0) -> Workload:
+    """Two crossing rods for sphere contact: a stiff bar along x without gravity and a soft rod
+    along y, `gap` above it where they cross (at their middles), that falls onto it.  Both 1 m,
+    radius 1 cm, inextensible, static clamps.  dt = 0: set by the caller from the stability
+    rule (the stricter of the two, shared by both)."""
+    l = 1.0 / n
+    r = 0.01
+    rods = []
+    q_y = (math.cos(math.pi / 4), -math.sin(math.pi / 4), 0.0, 0.0)   # third axis along +y
+    for base, d3, q0, young, grav in (((0.0, 0.0, 0.0), (1.0, 0.0, 0.0), Q_ALONG_X, 1e7,
+                                       (0.0, 0.0, 0.0)),
+                                      ((0.5, -0.5, 2 * r + gap), (0.0, 1.0, 0.0), q_y, 1e6,
+                                       (0.0, 0.0, -9.81))):
+        x = np.asarray(base)[None, :] + np.outer(np.arange(n + 1) * l, d3)
+        q = np.tile(np.asarray(q0, dtype=np.float64), (n, 1))
+        spec = RodSpec(n=n, inextensible=True, n_iter=10, clamp=True, dt=float(dt),
+                       gravity=grav, damp_lin=0.5, damp_ang=0.5, poisson=0.5, density=1000.0,
+                       seg_len=np.full(n, l), radius=np.full(n, r), young=np.full(n, young),
+                       clamp_x0=tuple(base), clamp_q0=tuple(q0))
+        rods.append((spec, _zero_state(x, q)))
+    return Workload("c6: 2x%d crossing rods in sphere contact" % n, rods, n_steps=2000,
+                    steps_per_launch=10)
+
+
 def config2(n: int, inextensible: bool, dt: Optional[float] = None) -> Workload:
     """Single long rod with seeded initial curvature; element length 1/64 m."""
     rng = np.random.default_rng((2, n))
