@@ -342,7 +342,7 @@ void oracle_clamp_pose(const oracle_rod* rod, double t, double* xc, double* qc, 
 /* --------------------------------------------------------------------------- step -- */
 
 static void project_segment(const oracle_rod* rod, int j, const double* x, double* v,
-                            const double* winv) {
+                            const double* winv, double* imp0) {
     const double dt = rod->dt;
     double p0[3], p1[3], d[3];
     for (int c = 0; c < 3; ++c) {
@@ -359,6 +359,7 @@ static void project_segment(const oracle_rod* rod, int j, const double* x, doubl
         double nc = d[c] / len;
         v[3 * j + c] += winv[j] * lambda * nc;
         v[3 * (j + 1) + c] -= winv[j + 1] * lambda * nc;
+        if (j == 0 && imp0) imp0[c] += lambda * nc;   /* impulse of segment 0 on point 0 */
     }
 }
 
@@ -368,6 +369,7 @@ static void project_segment(const oracle_rod* rod, int j, const double* x, doubl
 typedef struct {
     double* winv;
     double xc[3], qc[4], wc[3];
+    double fb[3];   /* force on the base point: internal force, then + impulses / dt */
 } step_scratch;
 
 static void step_first(const oracle_rod* rod, double t, const double* x, double* v, const double* q,
@@ -381,6 +383,11 @@ static void step_first(const oracle_rod* rod, double t, const double* x, double*
 
     /* forces and torques from the start-of-step configuration */
     oracle_forces(rod, x, q, F, tau);
+    {   /* internal force on point 0: without its weight and external load */
+        const double M0 = point_mass(rod, 0);
+        for (int c = 0; c < 3; ++c)
+            sc->fb[c] = F[c] - M0 * rod->gravity[c] - (rod->f_ext ? rod->f_ext[c] : 0.0);
+    }
 
     /* integrate forces: points as particles */
     for (int i = 0; i <= n; ++i) {
@@ -421,9 +428,11 @@ static void step_first(const oracle_rod* rod, double t, const double* x, double*
 }
 
 /* one constraint iteration of the inextensible variant: red-black Gauss-Seidel sweeps */
-static void step_sweeps(const oracle_rod* rod, const double* x, double* v, const step_scratch* sc) {
+static void step_sweeps(const oracle_rod* rod, const double* x, double* v, step_scratch* sc) {
+    double imp0[3] = {0.0, 0.0, 0.0};
     for (int parity = 0; parity < 2; ++parity)
-        for (int j = parity; j < rod->n; j += 2) project_segment(rod, j, x, v, sc->winv);
+        for (int j = parity; j < rod->n; j += 2) project_segment(rod, j, x, v, sc->winv, imp0);
+    for (int c = 0; c < 3; ++c) sc->fb[c] += imp0[c] / rod->dt;
 }
 
 static void step_last(const oracle_rod* rod, double* x, const double* v, double* q, const double* w,
@@ -455,11 +464,24 @@ static void step_last(const oracle_rod* rod, double* x, const double* v, double*
 }
 
 void oracle_step(const oracle_rod* rod, double t, double* x, double* v, double* q, double* w) {
+    oracle_step_fb(rod, t, x, v, q, w, NULL);
+}
+
+void oracle_step_fb(const oracle_rod* rod, double t, double* x, double* v, double* q, double* w,
+                    double* fbase) {
     step_scratch sc;
     step_first(rod, t, x, v, q, w, &sc);
     if (rod->inextensible)
         for (int it = 0; it < rod->n_iter; ++it) step_sweeps(rod, x, v, &sc);
+    if (fbase)
+        for (int c = 0; c < 3; ++c) fbase[c] = sc.fb[c];
     step_last(rod, x, v, q, w, &sc);
+}
+
+void oracle_rollout_fb(const oracle_rod* rod, double t0, int32_t n_steps, double* x, double* v,
+                       double* q, double* w, double* fbase) {
+    for (int s = 0; s < n_steps; ++s)
+        oracle_step_fb(rod, t0 + s * rod->dt, x, v, q, w, fbase ? fbase + 3 * s : NULL);
 }
 
 /* ------------------------------------------------------------------------ binding -- */

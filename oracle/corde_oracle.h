@@ -93,6 +93,18 @@ void oracle_clamp_pose(const oracle_rod* rod, double t, double* xc, double* qc, 
 /* One step from time t to t + dt, in place. */
 void oracle_step(const oracle_rod* rod, double t, double* x, double* v, double* q, double* w);
 
+/* One step like oracle_step that also returns the force the rod exerts on its base point 0
+ * during the step (the force feedback of a haptic clamp, Sec. 2.2): the internal elastic
+ * force on point 0 (element 0's stretch and penalty forces, eqs. (2), (8)) plus the impulses
+ * of segment 0's distance constraints on point 0 summed over the iterations, divided by dt.
+ * Gravity and the external load on point 0 itself are not part of it. */
+void oracle_step_fb(const oracle_rod* rod, double t, double* x, double* v, double* q, double* w,
+                    double* fbase);
+
+/* n_steps of oracle_step_fb; fbase (n_steps x 3, nullable) receives every step's force. */
+void oracle_rollout_fb(const oracle_rod* rod, double t0, int32_t n_steps, double* x, double* v,
+                       double* q, double* w, double* fbase);
+
 /* n_steps steps starting at time t0, in place.  If tip != NULL it receives x_N after every
  * step (n_steps x 3). */
 void oracle_rollout(const oracle_rod* rod, double t0, int32_t n_steps,

@@ -87,6 +87,9 @@ def lib():
         L.oracle_bind_impulse.restype = None
         L.oracle_bind_impulse.argtypes = [_DP, _DP, C.c_double, _DP, _DP, C.c_double, C.c_double,
                                           C.c_int32]
+        L.oracle_rollout_fb.restype = None
+        L.oracle_rollout_fb.argtypes = [C.POINTER(_Rod), C.c_double, C.c_int32, _DP, _DP, _DP, _DP,
+                                        _DP]
         L.oracle_rollout_group.restype = None
         L.oracle_rollout_group.argtypes = [C.POINTER(C.POINTER(_Rod)), C.c_int32,
                                            C.POINTER(_Binding), C.POINTER(_Contact), C.c_double,
@@ -213,6 +216,17 @@ class Rod:
                              _p(w), _p(tr))
         st.x, st.v, st.q, st.w = x, v, q, w
         return st, tr
+
+    def rollout_fb(self, state, n_steps, t0=0.0):
+        """Returns (new_state, force on the base point for every step (n_steps, 3))."""
+        st = state.copy()
+        x, v = _f64(st.x, (self.n + 1, 3)).copy(), _f64(st.v, (self.n + 1, 3)).copy()
+        q, w = _f64(st.q, (self.n, 4)).copy(), _f64(st.w, (self.n, 3)).copy()
+        fb = np.zeros((int(n_steps), 3))
+        lib().oracle_rollout_fb(C.byref(self.c), float(t0), int(n_steps), _p(x), _p(v), _p(q),
+                                _p(w), _p(fb))
+        st.x, st.v, st.q, st.w = x, v, q, w
+        return st, fb
 
     def stable(self, state, n_steps, t0=0.0, energy_factor=1.01):
         x, v = _f64(state.x, (self.n + 1, 3)), _f64(state.v, (self.n + 1, 3))
