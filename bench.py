@@ -235,6 +235,81 @@ def contact_extras(R, W):
     return out
 
 
+def haptic_extras(R, W):
+    """Haptic mailbox on the two-instrument workload with static clamps (2 x 512): us/step
+    without and with both rods' mailboxes attached (a record every step, or every 20 steps; 10
+    steps per launch), and, with a record every step, during one long
+    launch, the latency from a pose written by a 1 kHz haptic thread to the first force record
+    that names it, plus how often a new force record appears."""
+    import threading
+    import numpy as np
+    wl = W.config1(static_clamp=True)
+    specs = [s for s, _ in wl.rods]
+    out = {}
+    for name, every in (("no_mailbox", 0), ("mailbox", 1), ("mailbox_window_20", 20)):
+        b = R.RodBatch(specs)
+        if every:
+            b.haptic_attach(0, every)
+            b.haptic_attach(1, every)
+        b.set_state_rods([st for _, st in wl.rods])
+        b.step(500, 10)
+        b.step(5000, 10)
+        b.sync()
+        ms, _ = b.last_step_time()
+        b.close()
+        out[name] = {"us_per_step": 1e3 * ms / 5000}
+    for name in ("mailbox", "mailbox_window_20"):
+        out[name]["overhead"] = out[name]["us_per_step"] / out["no_mailbox"]["us_per_step"] - 1.0
+    b = R.RodBatch(specs)
+    b.haptic_attach(0)
+    b.haptic_attach(1)
+    b.set_state_rods([st for _, st in wl.rods])
+    b.step(10, 10)
+    b.sync()
+    n_long = int(0.5e6 / max(out["mailbox"]["us_per_step"], 1e-3))   # about half a second
+    lat, gaps = [], []
+    stop = threading.Event()
+    base = np.asarray(specs[0].clamp_x0)
+
+    def haptic():
+        k = 0
+        last_step, last_t = None, None
+        while not stop.is_set():
+            k += 1
+            t0 = time.perf_counter()
+            b.haptic_set_pose(0, base + np.array([0.0, 1e-7 * k, 0.0]), specs[0].clamp_q0)
+            seen = False
+            while time.perf_counter() - t0 < 1e-3:
+                _, s, p = b.haptic_get_force(0)
+                now = time.perf_counter()
+                if last_step is not None and s != last_step:
+                    gaps.append((now - last_t) / max(s - last_step, 1))
+                if s != last_step:
+                    last_step, last_t = s, now
+                if not seen and p >= k:
+                    lat.append(now - t0)
+                    seen = True
+            if stop.is_set():
+                break
+
+    th = threading.Thread(target=haptic)
+    th.start()
+    b.step(n_long, n_long)
+    b.sync()
+    stop.set()
+    th.join()
+    b.close()
+    lat_us = 1e6 * np.asarray(lat[1:-1]) if len(lat) > 2 else np.zeros(1)
+    out["pose_to_force_latency_us"] = {"median": float(np.median(lat_us)),
+                                       "p99": float(np.percentile(lat_us, 99)),
+                                       "poses": int(len(lat_us))}
+    out["host_seen_us_per_step"] = float(1e6 * np.median(gaps)) if gaps else None
+    out["workload"] = ("two-instrument 2 x 512 inextensible rods, static clamps, mailboxes on both; "
+                       "latency: one launch of %d steps, pose of rod 0 written at 1 kHz from a "
+                       "host thread, polled until a force record names it" % n_long)
+    return out
+
+
 def long_rod_extras(R, W):
     """c2: us/step vs rod length and steps per launch.  Rods up to 2048 elements run in one
     workgroup ("single") and, for comparison, split over several ("chunked"); longer rods are
@@ -275,7 +350,7 @@ def main():
     ap.add_argument("--shape", default="", help="W,E kernel shape (default: autotune)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (4096 rods), long-rod and adjoint measurements")
-    ap.add_argument("--extras", default="batch,long_rod,adjoint,binding,contact",
+    ap.add_argument("--extras", default="batch,long_rod,adjoint,binding,contact,haptic",
                     help="comma-separated subset of batch,long_rod,adjoint,binding,contact")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -363,7 +438,7 @@ def main():
     }
     if not args.no_extras:
         fns = {"batch": batch_extras, "long_rod": long_rod_extras, "adjoint": adjoint_extras,
-               "binding": binding_extras, "contact": contact_extras}
+               "binding": binding_extras, "contact": contact_extras, "haptic": haptic_extras}
         out["extras"] = {k: fns[k](R, W) for k in args.extras.split(",") if k}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)

@@ -192,6 +192,51 @@ rod_status rod_set_bindings(rod_ctx* ctx, int32_t n_pairs, const int32_t* pairs,
  * removes all contact sets.  Errors: INVALID, UNSUPPORTED, NOMEM, DEVICE. */
 rod_status rod_set_contact(rod_ctx* ctx, int32_t n_sets, const int32_t* sets, double mu);
 
+/* ---- Haptic mailbox (Sec. 2.2: the haptic thread hands a new device position to the
+ * running simulation and reads its force-feedback vector at any time, at 0.5-1 kHz) ---------
+ * rod_haptic_attach() gives rod `rod` a mailbox in pinned host memory that its kernel reads
+ * and writes while it runs, so the pose and force calls below never wait for a launch and make
+ * no GPU call.  The kernel works in windows of steps_per_record (>= 1) steps, counted from the
+ * first step of each launch (a launch's last window may be shorter): at the clamp of a window's
+ * first step it takes the newest whole pose; after its last step it writes one force record,
+ * the mean over the window.  The rod must be clamped with a static clamp (clamp_amp and
+ * clamp_twist_amp 0 or clamp_freq 0) and stepped by the one-rod-per-workgroup kernel: not
+ * bound, in a contact set or chunked (those calls then return ROD_E_UNSUPPORTED, and so does
+ * the adjoint).  Rods with a mailbox step in buckets of their own, with a kernel variant that
+ * holds the mailbox code (shapes (1,1), (1,2), (2,2), (4,2), (4,4), (4,8), (8,4); a tuned shape
+ * without it falls back to the default shape).  Attaching again only changes steps_per_record.
+ * Errors: INVALID (rod index, unclamped rod, steps_per_record), UNSUPPORTED, NOMEM, DEVICE.
+ * rod_haptic_detach() waits for the handle's kernels and frees the mailbox (no-op without). */
+rod_status rod_haptic_attach(rod_ctx* ctx, int32_t rod, int32_t steps_per_record);
+rod_status rod_haptic_detach(rod_ctx* ctx, int32_t rod);
+
+/* New clamp pose of rod `rod`: x0[3] [m], q0[4] (w, x, y, z; must have unit norm within 1e-6,
+ * normalised here).  Taken at the start of the next window (of a running launch, or of the
+ * next launch); a read that overlaps this write keeps the previous pose for one more window.
+ * Every launch re-applies the newest pose at its first step.  Once a pose is set, it replaces
+ * the pose of rod_set_clamp().  Poses are numbered 1, 2, ... per rod.  rod_step() returns
+ * before its launches end: a pose set afterwards may be taken by them.  May be called from
+ * another thread while the handle's owner steps it; one caller per rod.
+ * Errors: INVALID, ORDER (no mailbox). */
+rod_status rod_haptic_set_pose(rod_ctx* ctx, int32_t rod, const double* x0, const double* q0);
+
+typedef struct {
+  double f[3];        /* [N] mean force of the rod on its clamped base point over the window */
+  uint32_t step;      /* steps taken when the window ended (low 32 bits of the step count;
+                         0 with f = 0 before the first window after attaching) */
+  uint32_t pose;      /* number of the pose in use in the window (0: the rod_set_clamp pose) */
+  uint32_t n_steps;   /* steps in the window */
+} rod_haptic_force;
+
+/* Newest force record of rod `rod`.  The force on the base over one step is the internal
+ * (stretch and penalty) force of element 0 on point 0 plus the impulses of the distance
+ * constraint of element 0 on point 0, summed over the constraint iterations, divided by dt;
+ * gravity and the external load of point 0 are not included.  The record holds its mean over
+ * the window (the momentum passed to the base divided by the window's duration).  Thread rules
+ * as for rod_haptic_set_pose().  Errors: INVALID, ORDER (no mailbox), TIMEOUT (no whole record
+ * read in 2^20 attempts). */
+rod_status rod_haptic_get_force(rod_ctx* ctx, int32_t rod, rod_haptic_force* out);
+
 /* Per bucket, time every built shape that holds its longest rod on probe_steps steps (the
  * state is saved and restored, the step counter unchanged) and keep the fastest; sets the
  * handle's steps_per_launch.  out (nullable) receives rod_get_tuning(). */

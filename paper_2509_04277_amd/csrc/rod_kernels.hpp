@@ -53,6 +53,28 @@ enum PrmRow : int {
 // Clamp poses are evaluated for up to kClampChunk steps at a time, one step per lane, into LDS.
 constexpr int kClampChunk = 64;
 
+// Haptic mailbox of one clamped rod, in pinned host memory mapped for the device (Sec. 2.2:
+// the haptic thread writes the device position and reads the force feedback at any time,
+// while the kernel runs).  Every word is a 64-bit value (tag << 32 | bits of a float), read
+// and written whole; a record is taken only when all its words carry the same tag, so a read
+// that overlaps a write is never taken and no ordering between words is needed.
+//   pose: x, y, z, qw, qx, qy, qz               tag = the host's pose number (1, 2, ...)
+//   fb:   fx, fy, fz, pose number, window steps  tag = steps completed (low 32 bits)
+struct HapticBox {
+  uint64_t pose[8];
+  uint64_t fb[8];
+};
+
+// Mailbox words are accessed through global-address-space pointers: a flat access would also
+// count against the LDS wait counter, so every LDS exchange would wait for the PCIe round trip.
+using GlobalWord = __attribute__((address_space(1))) uint64_t;
+__device__ __forceinline__ uint64_t mailbox_load(const uint64_t* p) {
+  return __hip_atomic_load((GlobalWord*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void mailbox_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store((GlobalWord*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 struct RodDev {
   int32_t n;          // elements
   int32_t slot_off;   // first slot in the coefficient rows
@@ -71,6 +93,9 @@ struct RodDev {
   float mult_bend;    // learnable multipliers of the bend (K_1 = K_2) and twist (K_3) stiffness
   float mult_twist;
   double dt_d, t0, omega, ph_x, ph_t;
+  HapticBox* hbox;    // haptic mailbox (device address of pinned host memory), or null
+  int32_t hstride;    // steps per force record (>= 1 with a mailbox)
+  int32_t pad_h;
 };
 
 struct V3 {
@@ -250,6 +275,7 @@ struct RodLane {
   int g, j0, n;
   int off, nloc;   // window of the rod held by this workgroup: slots [off, off + nloc)
   bool ghost;      // off > 0: lane 0's "base point" is point `off`, held fixed (a halo edge)
+  V3 imp0;         // lane 0: momentum passed to point 0 (forces x dt + impulses)
   float dt;
 
   // Loads the coefficients of slots [off, off + nloc) (the whole rod by default).  A window
@@ -501,6 +527,7 @@ struct RodLane {
       nv[e] = sel(is_hi, fnma3(w_me, im_hi, Vv[e]), fma3(w_me, im_lo, Vv[e]));
       if (dsnap) dsnap[e] = sel(is_hi, d_hi, d_lo);
       if (e == 0) dvb = P[P_WINV_PREV][e] * im_hi;   // base point: left end of segment 0
+      if (e == 0 && h == 0) imp0 = imp0 + im_hi;
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) Vv[e] = nv[e];
@@ -562,7 +589,7 @@ __device__ __forceinline__ void clamp_for_step(const RodDev& rd, float (*cbuf)[1
 // (traj_steps = 1 writes a checkpoint of the launch's initial state).
 // tips (nullable): x_N after step s goes to tips[(rod * tip_steps + steps_done - tip_base + s) * 3].
 // store_final = 0 leaves gx..gw untouched (a recomputation that only needs traj).
-template <int W, int E>
+template <int W, int E, bool H = false>
 __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
     const RodDev* __restrict__ rods, const int* __restrict__ rod_ids, const float* __restrict__ prm,
     int prm_stride, float* __restrict__ gx, float* __restrict__ gv, float* __restrict__ gq,
@@ -581,6 +608,16 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
   V3 xc = {rd.cx0[0], rd.cx0[1], rd.cx0[2]}, wc = {0.f, 0.f, 0.f};
   Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
   const int tip_lane = (rd.n - 1) / E, tip_e = (rd.n - 1) % E;
+  // haptic mailbox: records cover windows of hstride steps (the last one of a launch may be
+  // shorter); the pose is taken at the clamp of each window's first step.  Lanes 0..6 of wave 0
+  // hold one pose word each, loaded a whole window before it is needed.
+  HapticBox* const hb = H ? rd.hbox : nullptr;   // H: the variant built with the mailbox code
+  const int hk = rd.hstride;
+  uint32_t htag = 0;   // pose number in use (0: the rod's own clamp pose)
+  int hn = 0;          // steps in the current window
+  uint64_t pw = 0;
+  if (hb && L.g < 7)
+    pw = mailbox_load(&hb->pose[L.g]);
 
   for (int s = 0; s < n_steps; ++s) {
     if (traj && s < traj_steps) {
@@ -593,12 +630,45 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
     V3 F[E], T[E], Ev[E], fs0, enext;
     L.forces(mb, par, xl, qn, F, T, Ev, fs0, enext);
     clamp_for_step<W>(rd, cbuf, s, n_steps, steps_done, xc, qc, wc, rd.driven && rd.clamp, L.g);
+    const bool hfirst = hb && hn == 0;
+    if (hfirst && L.g < 64) {   // wave 0, all lanes: take the pose if whole and new
+      const uint32_t tag = (uint32_t)(pw >> 32);
+      const int word = (int)(uint32_t)pw;
+      const uint32_t tag0 = __builtin_amdgcn_readfirstlane(tag);
+      const bool whole = (__ballot(L.g < 7 && tag == tag0) & 0x7full) == 0x7full;
+      if (whole && tag0 != htag) {
+        htag = tag0;
+        auto lane = [&](int k) { return __int_as_float(__builtin_amdgcn_readlane(word, k)); };
+        xc = {lane(0), lane(1), lane(2)};
+        qc = {lane(3), lane(4), lane(5), lane(6)};
+      }
+      if (L.g < 7 && s + hk < n_steps)   // the next window's pose
+        pw = mailbox_load(&hb->pose[L.g]);
+    }
     L.integrate_forces(rd, F, T, fs0, xc, wc, fext, text);
+    // momentum the base point receives over the window: internal force x dt, plus segment 0's
+    // constraint impulses (accumulated by the sweeps)
+    L.imp0 = fnma3(rd.dt, fs0, hn == 0 ? V3{0.f, 0.f, 0.f} : L.imp0);
     for (int it = 0; it < rd.n_iter; ++it) {
       L.half_sweep(rd, mb, par, 0, Ev, enext, nullptr);
       L.half_sweep(rd, mb, par, 1, Ev, enext, nullptr);
     }
     L.integrate_velocities(rd, xc, qc);
+    if (hb) {
+      ++hn;
+      if (hn == hk || s + 1 == n_steps) {   // window done: mean force of the rod on its base
+        if (L.g == 0) {
+          const V3 f = (1.0f / ((float)hn * rd.dt)) * L.imp0;
+          const uint64_t tag = (uint64_t)(uint32_t)(steps_done + s + 1) << 32;
+          const uint32_t rec[5] = {__float_as_uint(f.x), __float_as_uint(f.y), __float_as_uint(f.z),
+                                   htag, (uint32_t)hn};
+#pragma unroll
+          for (int k = 0; k < 5; ++k)
+            mailbox_store(&hb->fb[k], tag | rec[k]);
+        }
+        hn = 0;
+      }
+    }
     if (tips && (int)threadIdx.x == tip_lane) {
 #pragma unroll
       for (int e = 0; e < E; ++e)

@@ -57,19 +57,20 @@ const AdjointEntry kAdjoints[] = {
 struct KernelEntry {
   int waves, elems;
   KernelFn fn;
+  KernelFn hfn;   // the variant with the haptic mailbox code (the default shapes only)
 };
 
 // Built kernel shapes: (waves per rod, elements per lane).  Capacity = 64 * waves * elems.
+#define ROD_SHAPE(w, e) {w, e, corde::rod_resident_kernel<w, e>, nullptr}
+#define ROD_SHAPE_H(w, e) {w, e, corde::rod_resident_kernel<w, e>, corde::rod_resident_kernel<w, e, true>}
 const KernelEntry kKernels[] = {
-    {1, 1, corde::rod_resident_kernel<1, 1>},   {1, 2, corde::rod_resident_kernel<1, 2>},
-    {1, 4, corde::rod_resident_kernel<1, 4>},   {1, 8, corde::rod_resident_kernel<1, 8>},
-    {2, 1, corde::rod_resident_kernel<2, 1>},   {2, 2, corde::rod_resident_kernel<2, 2>},
-    {2, 4, corde::rod_resident_kernel<2, 4>},   {4, 1, corde::rod_resident_kernel<4, 1>},
-    {4, 2, corde::rod_resident_kernel<4, 2>},   {4, 4, corde::rod_resident_kernel<4, 4>},
-    {4, 8, corde::rod_resident_kernel<4, 8>},   {8, 1, corde::rod_resident_kernel<8, 1>},
-    {8, 2, corde::rod_resident_kernel<8, 2>},   {8, 4, corde::rod_resident_kernel<8, 4>},
-    {16, 1, corde::rod_resident_kernel<16, 1>},
+    ROD_SHAPE_H(1, 1), ROD_SHAPE_H(1, 2), ROD_SHAPE(1, 4),    ROD_SHAPE(1, 8),
+    ROD_SHAPE(2, 1),   ROD_SHAPE_H(2, 2), ROD_SHAPE(2, 4),    ROD_SHAPE(4, 1),
+    ROD_SHAPE_H(4, 2), ROD_SHAPE_H(4, 4), ROD_SHAPE_H(4, 8),  ROD_SHAPE(8, 1),
+    ROD_SHAPE(8, 2),   ROD_SHAPE_H(8, 4), ROD_SHAPE(16, 1),
 };
+#undef ROD_SHAPE
+#undef ROD_SHAPE_H
 
 const KernelEntry* find_kernel(int w, int e) {
   for (const auto& k : kKernels)
@@ -121,6 +122,7 @@ struct rod_ctx {
   struct Bucket {
     int waves, elems, first, count, max_n;
     float us_per_step;
+    bool haptic = false;   // its rods have haptic mailboxes (the kernel variant with that code)
   };
   // long rods (more than chunk_above elements): chunked, one workgroup per chunk
   int chunk_above = kResidentMax;
@@ -147,6 +149,14 @@ struct rod_ctx {
   std::vector<int> rod_ids;
   int* d_rod_ids = nullptr;
   int steps_per_launch = 10;
+  // haptic mailboxes (pinned host memory mapped for the device), per rod; seq: last pose number
+  struct Haptic {
+    corde::HapticBox* host = nullptr;
+    corde::HapticBox* dev = nullptr;
+    uint32_t seq = 0;
+  };
+  std::vector<Haptic> haptic;
+  int n_haptic = 0;
   // adjoint rollout (rod_adjoint_forward / rod_adjoint_backward)
   bool adj_ready = false;
   int adj_steps = 0, adj_ckpt = 0, adj_nckpt = 0;
@@ -370,26 +380,35 @@ void default_shape(int n, int* w, int* e) {
 template <class ShapeFn>
 rod_status make_buckets(rod_ctx* c, ShapeFn shape) {
   std::vector<std::pair<long long, int>> key;
+  std::vector<int> wr(c->n_rods), er(c->n_rods);
+  std::vector<char> hr(c->n_rods);
   for (int r = 0; r < c->n_rods; ++r) {
     if (c->n[r] > c->chunk_above) continue;   // long rods run chunked
     if (!c->bound.empty() && c->bound[r]) continue;   // bound pairs have their own kernel
     int w, e;
     shape(r, &w, &e);
+    const bool h = c->haptic[r].host != nullptr;
+    if (h) {   // rods with a mailbox need a shape built with the mailbox code
+      const KernelEntry* k = find_kernel(w, e);
+      if (!k || !k->hfn) default_shape(c->n[r], &w, &e);
+    }
+    wr[r] = w, er[r] = e, hr[r] = h;
     // within a bucket, most work first (a constraint iteration costs about a quarter of the
     // rest of a step), so the last workgroups dispatched are the cheap ones
     const long long cost = (long long)c->n[r] * (4 + c->rods[r].n_iter);
-    key.push_back({((long long)(w * 16 + e) << 32) | (0x7fffffffLL - cost), r});
+    key.push_back({((long long)((w * 16 + e) * 2 + h) << 32) | (0x7fffffffLL - cost), r});
   }
   std::sort(key.begin(), key.end());
   c->buckets.clear();
   c->rod_ids.assign(std::max(c->n_rods, 1), 0);
   for (int i = 0; i < (int)key.size(); ++i) {
     const int r = key[i].second;
-    int w, e;
-    shape(r, &w, &e);
+    const int w = wr[r], e = er[r];
+    const bool h = hr[r];
     c->rod_ids[i] = r;
-    if (c->buckets.empty() || c->buckets.back().waves != w || c->buckets.back().elems != e)
-      c->buckets.push_back({w, e, i, 0, 0, 0.f});
+    if (c->buckets.empty() || c->buckets.back().waves != w || c->buckets.back().elems != e ||
+        c->buckets.back().haptic != h)
+      c->buckets.push_back({w, e, i, 0, 0, 0.f, h});
     c->buckets.back().count++;
     c->buckets.back().max_n = std::max(c->buckets.back().max_n, c->n[r]);
   }
@@ -397,6 +416,21 @@ rod_status make_buckets(rod_ctx* c, ShapeFn shape) {
                             hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return ROD_OK;
+}
+
+// Rebuilds the buckets with every rod keeping its current shape (after a mailbox change).
+rod_status rebucket(rod_ctx* c) {
+  std::vector<int> shape_of(c->n_rods, 0);
+  for (const auto& b : c->buckets)
+    for (int i = 0; i < b.count; ++i) shape_of[c->rod_ids[b.first + i]] = b.waves * 16 + b.elems;
+  return make_buckets(c, [&](int r, int* w, int* e) {
+    if (shape_of[r]) {
+      *w = shape_of[r] / 16;
+      *e = shape_of[r] % 16;
+    } else {
+      default_shape(c->n[r], w, e);
+    }
+  });
 }
 
 // Splits every rod longer than chunk_above into chunks owning c slots (even, at least 2 H + 2
@@ -511,8 +545,9 @@ rod_status reset_flags(rod_ctx* c) {
 rod_status launch_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long long done,
                          hipStream_t stream) {
   const KernelEntry* k = find_kernel(b.waves, b.elems);
-  if (!k) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
-  hipLaunchKernelGGL(k->fn, dim3(b.count), dim3(64 * k->waves), 0, stream, c->d_rods,
+  const KernelFn fn = k ? (b.haptic ? k->hfn : k->fn) : nullptr;
+  if (!fn) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
+  hipLaunchKernelGGL(fn, dim3(b.count), dim3(64 * k->waves), 0, stream, c->d_rods,
                      c->d_rod_ids + b.first, c->d_prm, c->prm_stride, c->d_x, c->d_v, c->d_q,
                      c->d_w, c->d_fext, c->d_text, ks, done, c->d_status, nullptr, 0LL,
                      c->total_pts, c->total_frames, nullptr, 0, 0LL, 0, 1);
@@ -560,6 +595,8 @@ rod_status rebuild_groups(rod_ctx* c) {
     gs[g].mu = c->contact_mu;
   }
   for (const auto& g : gs) {
+    if (c->haptic[g.rod[0]].host || (g.rod[1] >= 0 && c->haptic[g.rod[1]].host))
+      return fail(c, ROD_E_UNSUPPORTED, "a rod with a haptic mailbox cannot be grouped");
     const RodDev& a = c->rods[g.rod[0]];
     const int n = std::max(a.n, g.rod[1] >= 0 ? c->rods[g.rod[1]].n : 0);
     if (a.n_iter < 1) return fail(c, ROD_E_UNSUPPORTED, "grouped rods must be inextensible");
@@ -853,6 +890,7 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
       rho[(size_t)slot + j] = (float)(j + 1 == p.n_elements ? p.radius[j]
                                                              : 0.5 * (p.radius[j] + p.radius[j + 1]));
     c->rods.push_back(make_dev(p, slot, pt, fr, winv0));
+    c->haptic.push_back({});
     c->n.push_back(p.n_elements);
     if (p.f_ext)
       for (int i = 0; i < 3 * (p.n_elements + 1); ++i) fext[(size_t)3 * pt + i] = (float)p.f_ext[i];
@@ -929,6 +967,8 @@ rod_status rod_destroy(rod_ctx* c) {
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   for (hipEvent_t e : {c->ev_start, c->ev_rec[0], c->ev_rec[1], c->ev_rev[0], c->ev_rev[1]})
     if (e) (void)hipEventDestroy(e);
+  for (auto& h : c->haptic)
+    if (h.host) (void)hipHostFree(h.host);
   delete c;
   return ROD_OK;
 }
@@ -1080,9 +1120,12 @@ rod_status rod_set_chunking(rod_ctx* c, int32_t min_elements, int32_t chunk_elem
   if (min_elements < 1 || min_elements > kResidentMax)
     return fail(c, ROD_E_INVALID, "min_elements must be in [1, 2048]");
   if (chunk_elements < 0) return fail(c, ROD_E_INVALID, "chunk_elements must be >= 0");
-  for (int r = 0; r < c->n_rods; ++r)
+  for (int r = 0; r < c->n_rods; ++r) {
     if (!c->bound.empty() && c->bound[r] && c->n[r] > min_elements)
       return fail(c, ROD_E_UNSUPPORTED, "a bound rod cannot be chunked");
+    if (c->haptic[r].host && c->n[r] > min_elements)
+      return fail(c, ROD_E_UNSUPPORTED, "a rod with a haptic mailbox cannot be chunked");
+  }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (void** p : {(void**)&c->d_chunks, (void**)&c->d_block_chunk, (void**)&c->d_pub,
                    (void**)&c->d_flags}) {
@@ -1205,6 +1248,117 @@ rod_status rod_last_step_time(rod_ctx* c, float* ms, int32_t* launches) {
   return ROD_OK;
 }
 
+rod_status rod_haptic_attach(rod_ctx* c, int32_t rod, int32_t steps_per_record) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (rod < 0 || rod >= c->n_rods) return fail(c, ROD_E_INVALID, "rod index out of range");
+  if (steps_per_record < 1) return fail(c, ROD_E_INVALID, "steps_per_record must be >= 1");
+  RodDev& d = c->rods[rod];
+  if (!d.clamp) return fail(c, ROD_E_INVALID, "a haptic mailbox drives a clamped base");
+  if (d.driven) return fail(c, ROD_E_UNSUPPORTED, "the rod's clamp is driven by its sinusoid");
+  if (!c->bound.empty() && c->bound[rod])
+    return fail(c, ROD_E_UNSUPPORTED, "a rod with a haptic mailbox cannot be grouped");
+  if (c->n[rod] > c->chunk_above)
+    return fail(c, ROD_E_UNSUPPORTED, "a rod with a haptic mailbox cannot be chunked");
+  auto& hh = c->haptic[rod];
+  const bool fresh = hh.host == nullptr;
+  corde::HapticBox* h = hh.host;
+  corde::HapticBox* hd = hh.dev;
+  if (fresh) {
+    if (hipHostMalloc((void**)&h, sizeof(corde::HapticBox), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess || !h)
+      return fail(c, ROD_E_NOMEM, "haptic mailbox");
+    std::memset((void*)h, 0, sizeof(corde::HapticBox));
+    hipError_t e = hipHostGetDevicePointer((void**)&hd, h, 0);
+    if (e != hipSuccess) {
+      (void)hipHostFree(h);
+      return hip_fail(c, e, "hipHostGetDevicePointer");
+    }
+  }
+  const RodDev before = d;
+  d.hbox = hd;
+  d.hstride = steps_per_record;
+  hipError_t e = hipMemcpyAsync(c->d_rods + rod, &d, sizeof(RodDev), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    d = before;
+    if (fresh) (void)hipHostFree(h);
+    return hip_fail(c, e, "rod_haptic_attach");
+  }
+  if (!fresh) return ROD_OK;
+  hh = {h, hd, 0};
+  c->n_haptic++;
+  c->adj_ready = false;
+  return rebucket(c);   // the rod moves to a bucket of the kernel variant with the mailbox code
+}
+
+rod_status rod_haptic_detach(rod_ctx* c, int32_t rod) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (rod < 0 || rod >= c->n_rods) return fail(c, ROD_E_INVALID, "rod index out of range");
+  auto& h = c->haptic[rod];
+  if (!h.host) return ROD_OK;
+  RodDev& d = c->rods[rod];
+  d.hbox = nullptr;
+  d.hstride = 0;
+  HIP_TRY(c, hipMemcpyAsync(c->d_rods + rod, &d, sizeof(RodDev), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));   // no kernel still uses the mailbox
+  for (hipStream_t st : c->bstreams) HIP_TRY(c, hipStreamSynchronize(st));
+  (void)hipHostFree(h.host);
+  h = {};
+  c->n_haptic--;
+  return rebucket(c);
+}
+
+rod_status rod_haptic_set_pose(rod_ctx* c, int32_t rod, const double* x0, const double* q0) {
+  // called from the haptic thread: no GPU call, no write to the handle other than the mailbox
+  if (!c || rod < 0 || rod >= c->n_rods || !x0 || !q0)
+    return fail(nullptr, ROD_E_INVALID, "bad handle, rod index or pose");
+  auto& h = c->haptic[rod];
+  if (!h.host) return fail(nullptr, ROD_E_ORDER, "rod has no haptic mailbox");
+  double qn = 0;
+  for (int k = 0; k < 4; ++k) qn += q0[k] * q0[k];
+  if (!(std::fabs(qn - 1.0) < 1e-6)) return fail(nullptr, ROD_E_INVALID, "q0 must be a unit quaternion");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(x0[k])) return fail(nullptr, ROD_E_INVALID, "x0 must be finite");
+  if (++h.seq == 0) h.seq = 1;   // pose number 0 means "no pose"
+  const uint64_t tag = (uint64_t)h.seq << 32;
+  const double inv = 1.0 / std::sqrt(qn);
+  const float w[7] = {(float)x0[0], (float)x0[1], (float)x0[2], (float)(q0[0] * inv),
+                      (float)(q0[1] * inv), (float)(q0[2] * inv), (float)(q0[3] * inv)};
+  for (int k = 0; k < 7; ++k) {
+    uint32_t bits;
+    std::memcpy(&bits, &w[k], 4);
+    __atomic_store_n(&h.host->pose[k], tag | bits, __ATOMIC_RELAXED);
+  }
+  return ROD_OK;
+}
+
+rod_status rod_haptic_get_force(rod_ctx* c, int32_t rod, rod_haptic_force* out) {
+  // called from the haptic thread: no GPU call, no write to the handle
+  if (!c || rod < 0 || rod >= c->n_rods || !out)
+    return fail(nullptr, ROD_E_INVALID, "bad handle, rod index or output");
+  const auto& h = c->haptic[rod];
+  if (!h.host) return fail(nullptr, ROD_E_ORDER, "rod has no haptic mailbox");
+  for (int attempt = 0; attempt < (1 << 20); ++attempt) {
+    uint64_t w[5];
+    for (int k = 0; k < 5; ++k) w[k] = __atomic_load_n(&h.host->fb[k], __ATOMIC_RELAXED);
+    const uint32_t tag = (uint32_t)(w[0] >> 32);
+    bool whole = true;
+    for (int k = 1; k < 5; ++k) whole = whole && (uint32_t)(w[k] >> 32) == tag;
+    if (!whole) continue;   // a record being written: read again
+    for (int k = 0; k < 3; ++k) {
+      const uint32_t bits = (uint32_t)w[k];
+      float v;
+      std::memcpy(&v, &bits, 4);
+      out->f[k] = v;
+    }
+    out->step = tag;
+    out->pose = (uint32_t)w[3];
+    out->n_steps = (uint32_t)w[4];
+    return ROD_OK;
+  }
+  return fail(nullptr, ROD_E_TIMEOUT, "no whole force record could be read");
+}
+
 rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launch, rod_tuning* out) {
   if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
   if (!c->have_state) return fail(c, ROD_E_ORDER, "rod_autotune before rod_set_state");
@@ -1236,6 +1390,7 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
     for (const auto& k : kKernels) {
       const int cap = 64 * k.waves * k.elems;
       if (cap < best.max_n || cap >= 4 * std::max(best.max_n, 64)) continue;
+      if (best.haptic && !k.hfn) continue;
       c->buckets[bi].waves = k.waves;
       c->buckets[bi].elems = k.elems;
       float ms_best = INFINITY;
@@ -1262,12 +1417,13 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
       for (int i = 0; i < chosen[bi].count; ++i)
         shape_of[c->rod_ids[chosen[bi].first + i]] = chosen[bi].waves * 16 + chosen[bi].elems;
     std::vector<std::pair<int, float>> us_of;
-    for (const auto& b : chosen) us_of.push_back({b.waves * 16 + b.elems, b.us_per_step});
+    for (const auto& b : chosen)
+      us_of.push_back({(b.waves * 16 + b.elems) * 2 + b.haptic, b.us_per_step});
     st = make_buckets(c, [&](int r, int* w, int* e) { *w = shape_of[r] / 16; *e = shape_of[r] % 16; });
     for (auto& b : c->buckets) {
       b.us_per_step = 0.f;
       for (const auto& u : us_of)
-        if (u.first == b.waves * 16 + b.elems) b.us_per_step += u.second;
+        if (u.first == (b.waves * 16 + b.elems) * 2 + b.haptic) b.us_per_step += u.second;
     }
   }
   c->steps_per_launch = steps_per_launch;
@@ -1312,6 +1468,7 @@ rod_status rod_adjoint_forward(rod_ctx* c, int32_t n_steps, int32_t ckpt_every, 
     if (!adjoint_shape(b.max_n)) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
   if (c->n_chunks) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
   if (!c->groups.empty()) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not step grouped rods");
+  if (c->n_haptic) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not step rods with a haptic mailbox");
   c->adj_ready = false;
   const size_t S = state_floats(c);
   const int ck = std::min(ckpt_every, n_steps);

@@ -53,6 +53,11 @@ class rod_tuning(C.Structure):
                 ("steps_per_launch", C.c_int32), ("us_per_step", C.c_float)]
 
 
+class rod_haptic_force(C.Structure):
+    _fields_ = [("f", C.c_double * 3), ("step", C.c_uint32), ("pose", C.c_uint32),
+                ("n_steps", C.c_uint32)]
+
+
 # Exported entry points and their argument types (same names as include/rod.h).
 _SIGS = {
     "rod_create": (C.c_int, [C.POINTER(rod_params), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -70,6 +75,10 @@ _SIGS = {
     "rod_set_chunking": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "rod_set_bindings": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32]),
     "rod_set_contact": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_double]),
+    "rod_haptic_attach": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "rod_haptic_detach": (C.c_int, [C.c_void_p, C.c_int32]),
+    "rod_haptic_set_pose": (C.c_int, [C.c_void_p, C.c_int32, _DP, _DP]),
+    "rod_haptic_get_force": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rod_haptic_force)]),
     "rod_stable_dt": (C.c_int, [C.POINTER(rod_params), _DP]),
     "rod_last_step_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     "rod_set_stiffness_mult": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
@@ -336,6 +345,26 @@ class RodBatch:
         arr = np.ascontiguousarray(np.asarray(sets, dtype=np.int32).reshape(-1, 2))
         _check(lib().rod_set_contact(self.h, int(arr.shape[0]),
                                      arr.ctypes.data_as(C.POINTER(C.c_int32)), float(mu)), self.h)
+
+    def haptic_attach(self, rod: int, steps_per_record: int = 1):
+        _check(lib().rod_haptic_attach(self.h, rod, steps_per_record), self.h)
+
+    def haptic_detach(self, rod: int):
+        _check(lib().rod_haptic_detach(self.h, rod), self.h)
+
+    def haptic_set_pose(self, rod: int, x0, q0):
+        """Thread-safe against the stepping thread (no GPU call); errors name no handle."""
+        x = (C.c_double * 3)(*[float(v) for v in x0])
+        q = (C.c_double * 4)(*[float(v) for v in q0])
+        _check(lib().rod_haptic_set_pose(self.h, rod, x, q))
+
+    def haptic_get_force(self, rod: int, window: bool = False):
+        """(mean force (3,) [N] on the clamped base over the newest record's window, steps taken
+        at its end, pose number in use[, steps in the window if window])."""
+        r = rod_haptic_force()
+        _check(lib().rod_haptic_get_force(self.h, rod, C.byref(r)))
+        out = (np.array(r.f[:]), int(r.step), int(r.pose))
+        return out + (int(r.n_steps),) if window else out
 
     def set_chunking(self, min_elements: int, chunk_elements: int = 0):
         """Step rods longer than min_elements with the chunked multi-workgroup kernel, about

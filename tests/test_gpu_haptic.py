@@ -1,0 +1,324 @@
+"""GPU tests of the haptic mailbox (Sec. 2.2: the haptic thread gives the running simulation a
+new device position and reads back its force-feedback vector at any time): the force the kernel
+reports against the FP64 oracle's clamp force, poses taken between and during launches, and the
+calls' argument checks."""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_04277_amd import rod as R
+from paper_2509_04277_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    torch.cuda.init()
+    yield
+
+
+def _swinging(n, inext, seed=3):
+    """A clamped horizontal rod released under gravity, slightly perturbed."""
+    spec, st = W.straight_rod(n, inextensible=inext, dt=1e-5, damp=0.3)
+    spec = spec.replace(dt=R.stable_dt(spec))
+    rng = np.random.default_rng(seed)
+    st = st.copy()
+    st.x = st.x + rng.normal(0, 1e-4, st.x.shape) * np.r_[0.0, np.ones(n)][:, None]
+    return spec, st
+
+
+def _gpu_forces(spec, st, n_steps):
+    """Steps one launch per step, reading the mailbox after each."""
+    b = R.RodBatch([spec])
+    b.haptic_attach(0)
+    f0, s0, p0 = b.haptic_get_force(0)
+    assert s0 == 0 and p0 == 0 and not f0.any()
+    b.set_state_rods([st])
+    out = np.empty((n_steps, 3))
+    for k in range(n_steps):
+        b.step(1, 1)
+        b.sync()
+        f, s, p = b.haptic_get_force(0)
+        assert s == k + 1 and p == 0
+        out[k] = f
+    state = b.get_state_rods()[0]
+    b.close()
+    return out, state
+
+
+EPS32 = 2.0 ** -24
+
+
+def _masses(spec):
+    r = O.Rod(spec)
+    m = np.empty(spec.n + 1)
+    for i in range(spec.n + 1):
+        v = np.zeros((spec.n + 1, 3))
+        v[i, 0] = 1.0
+        m[i] = 2.0 * r.kinetic(v, np.zeros((spec.n, 3)))
+    return m
+
+
+def _fp32_storage_error(spec, st, n_steps, ref, win):
+    """How far the oracle's feedback moves when its state is rounded to FP32 after every step
+    (FP64 arithmetic otherwise).  Returns (largest single-step change, largest change of a
+    window mean)."""
+    rod = O.Rod(spec)
+    r = st.copy()
+    out = np.empty((n_steps, 3))
+    for k in range(n_steps):
+        for a in "xvqw":
+            setattr(r, a, getattr(r, a).astype(np.float32).astype(np.float64))
+        r, f = rod.rollout_fb(r, 1, t0=k * spec.dt)
+        out[k] = f[0]
+    d = np.abs(out - ref).max()
+    dw = np.abs(out.reshape(-1, win, 3).mean(axis=1) - ref.reshape(-1, win, 3).mean(axis=1)).max()
+    return d, dw
+
+
+def _fp32_arith_bounds(spec, xmax, win):
+    """FP32 arithmetic on predicted positions of size xmax rounds an element length by up to
+    d = 2 eps xmax.  A constraint impulse answers that with d / (dt (w_0 + w_1)) on the base
+    (w_0 = 0), so over n_iter iterations one step's force moves by up to n_iter d / (dt^2 w_1).
+    Over a window of T = win dt the impulses sum to the momentum the rod gives its base, and the
+    rod's own momentum at the window ends carries velocity noise of at most d / dt per point:
+    the window mean moves by up to 2 M d / (dt T)."""
+    d = 2 * EPS32 * xmax
+    m = _masses(spec)
+    step = max(spec.n_iter, 1) * d / (spec.dt ** 2 / m[1])
+    window = 2 * m[1:].sum() * (d / spec.dt) / (win * spec.dt)
+    return step, window
+
+
+@pytest.mark.parametrize("inext", [False, True])
+def test_force_matches_oracle(inext):
+    """Every step's force against the oracle's, and means over windows of 50 steps.  Extensible
+    rods (a smooth function of the state): within 3x what FP32 storage of the state alone moves
+    the oracle's force.  Inextensible rods (constraint impulses that answer the rounding of
+    predicted element lengths): within the FP32 arithmetic bounds above."""
+    spec, st = _swinging(64, inext)
+    n_steps, win = 300, 50
+    gpu, _ = _gpu_forces(spec, st, n_steps)
+    _, ref = O.Rod(spec).rollout_fb(st, n_steps)
+    err = np.abs(gpu - ref).max()
+    werr = np.abs(gpu.reshape(-1, win, 3).mean(axis=1) - ref.reshape(-1, win, 3).mean(axis=1)).max()
+    if inext:
+        tol, wtol = _fp32_arith_bounds(spec, 1.0, win)
+    else:
+        d32, dw32 = _fp32_storage_error(spec, st, n_steps, ref, win)
+        tol, wtol = 3 * d32, 3 * dw32
+    _say("%s 64: step error %.2e (tol %.2e), window-mean error %.2e (tol %.2e), max |f| %.2e"
+         % ("inextensible" if inext else "extensible", err, tol, werr, wtol, np.abs(ref).max()))
+    assert np.isfinite(gpu).all()
+    assert err <= tol
+    assert werr <= wtol
+
+
+def test_windowed_records_vs_oracle():
+    """Records over windows of 10 steps hold the mean force of the window; windows restart at
+    each launch, whose last one may be shorter."""
+    spec, st = _swinging(64, True)
+    k = 10
+    b = R.RodBatch([spec])
+    b.haptic_attach(0, k)
+    b.set_state_rods([st])
+    recs = []
+    done = 0
+    for n in (50, 25, 40, 35):
+        b.step(n, n)
+        b.sync()
+        done += n
+        f, s, p, m = b.haptic_get_force(0, window=True)
+        assert s == done and p == 0 and m == (n % k or k)
+        recs.append((done, m, f))
+    b.close()
+    _, ref = O.Rod(spec).rollout_fb(st, done)
+    _, wtol = _fp32_arith_bounds(spec, 1.0, k)
+    for end, m, f in recs:
+        want = ref[end - m:end].mean(axis=0)
+        _say("window of %d steps ending at %d: error %.2e (tol %.2e)" % (m, end, np.abs(f - want).max(), wtol))
+        assert np.abs(f - want).max() <= wtol
+
+
+def test_hanging_rod_reports_its_weight():
+    """At rest the rod passes its weight (all points but the clamped one) to its base; the mean
+    of the last 50 steps' forces is compared with it within the FP32 window bound."""
+    n, win = 32, 50
+    spec, st = W.straight_rod(n, inextensible=True, dt=1e-4, n_iter=200, damp=1.0,
+                              q0=(0.0, 1.0, 0.0, 0.0))
+    b = R.RodBatch([spec])
+    b.haptic_attach(0)
+    b.set_state_rods([st])
+    b.step(100, 10)
+    fs = []
+    for _ in range(win):
+        b.step(1, 1)
+        b.sync()
+        fs.append(b.haptic_get_force(0)[0])
+    b.close()
+    weight = _masses(spec)[1:].sum() * np.asarray(spec.gravity)
+    got = np.mean(fs, axis=0)
+    _, wtol = _fp32_arith_bounds(spec, 1.0, win)
+    _say("hanging 32: mean feedback %s, weight %s (tol %.2e)" % (got, weight, wtol))
+    assert np.abs(got - weight).max() <= wtol
+
+
+def test_pose_between_launches_vs_oracle():
+    """A pose set while no launch runs is the clamp pose from the next step on: the rollout equals
+    the oracle's with the clamp moved at that step.  (step() returns before its launches end, and
+    they would take a pose set meanwhile: hence the sync.)"""
+    spec, st = _swinging(64, True)
+    k1, k2 = 200, 300
+    x1 = np.asarray(spec.clamp_x0) + np.array([0.0, 2e-3, -1e-3])
+    a = 0.05
+    q1 = np.array([np.cos(a / 2), 0.0, 0.0, np.sin(a / 2)])   # turn about z ...
+    q1 = W._qprod(q1, np.asarray(spec.clamp_q0))               # ... of the start frame
+    b = R.RodBatch([spec])
+    b.haptic_attach(0)
+    b.set_state_rods([st])
+    b.step(k1, 10)
+    b.sync()
+    b.haptic_set_pose(0, x1 + 1.0, q1)     # superseded before the next launch
+    b.haptic_set_pose(0, x1, q1)
+    b.step(k2, 10)
+    b.sync()
+    x, v, q, w = b.get_state_rods()[0]
+    f, s, p = b.haptic_get_force(0)
+    b.close()
+    assert s == k1 + k2 and p == 2
+    mid, _ = O.Rod(spec).rollout(st, k1)
+    ref, _ = O.Rod(spec.replace(clamp_x0=tuple(x1), clamp_q0=tuple(q1))).rollout(mid, k2, t0=k1 * spec.dt)
+    ex = np.abs(x - ref.x).max()
+    _say("pose change: max|dx| %.2e (tol 1e-4), base %s" % (ex, x[0]))
+    assert np.array_equal(x[0], x1.astype(np.float32))
+    assert np.abs(q[0] - q1).max() <= 1e-6
+    assert ex <= 1e-4
+
+
+def test_mailbox_leaves_the_rollout_unchanged():
+    """Attached but never given a pose, a rod steps bitwise as without a mailbox (in a bucket of
+    its own, with the kernel variant that holds the mailbox code); so does a rod beside it."""
+    rods = [_swinging(64, True), _swinging(64, True, seed=4)]
+    out = []
+    for attach in (False, True):
+        b = R.RodBatch([s for s, _ in rods])
+        if attach:
+            b.haptic_attach(0, 7)
+            assert len(b.buckets()) == 2
+            b.haptic_detach(0)
+            assert len(b.buckets()) == 1
+            b.haptic_attach(0, 3)
+        b.set_state_rods([st for _, st in rods])
+        b.step(100, 10)
+        out.append(b.get_state_rods())
+        b.close()
+    for r in range(2):
+        for u, v in zip(out[0][r], out[1][r]):
+            assert np.array_equal(u, v)
+
+
+def test_poses_and_forces_during_one_launch():
+    """A haptic thread moves the clamp and reads the force while one long launch runs: forces of
+    successive steps arrive before the launch ends, poses set during it are taken in order, and
+    the base ends on the pose the last force record names."""
+    wl = W.config1(static_clamp=True)
+    spec, st = wl.rods[0]
+    n_steps = 40000
+    b = R.RodBatch([spec])
+    b.haptic_attach(0)
+    b.set_state_rods([st])
+    b.step(10, 10)   # first launch (code load) outside the timed part
+    b.sync()
+    base = np.asarray(spec.clamp_x0)
+    poses = {}
+    seen = []
+    bad = []
+    stop = threading.Event()
+
+    def haptic():
+        k = 0
+        while not stop.is_set():
+            k += 1
+            x = base + np.array([0.0, 1e-6 * k, 0.0])
+            poses[k] = x
+            b.haptic_set_pose(0, x, spec.clamp_q0)
+            t_end = time.perf_counter() + 1e-3
+            while time.perf_counter() < t_end:
+                f, s, p = b.haptic_get_force(0)
+                seen.append((s, p))
+                if not np.isfinite(f).all():
+                    bad.append((s, f))
+                time.sleep(1e-4)
+
+    th = threading.Thread(target=haptic)
+    th.start()
+    b.step(n_steps, n_steps)
+    b.sync()
+    stop.set()
+    th.join()
+    f, s, p = b.haptic_get_force(0)
+    x = b.get_state_rods()[0][0]
+    b.close()
+    steps = np.array([a for a, _ in seen])
+    pn = np.array([c for _, c in seen])
+    during = steps[(steps > 10) & (steps < 10 + n_steps)]
+    _say("one launch of %d steps: %d force reads, %d distinct steps seen during it, poses set %d, "
+         "last pose taken %d" % (n_steps, len(seen), len(np.unique(during)), len(poses), p))
+    assert s == 10 + n_steps and not bad
+    assert np.all(np.diff(steps) >= 0) and np.all(np.diff(pn) >= 0)
+    assert len(np.unique(during)) >= 10
+    assert len(np.unique(pn[(steps > 10) & (steps < 10 + n_steps)])) >= 3
+    assert p >= 1 and np.array_equal(x[0], poses[p].astype(np.float32))
+
+
+def test_haptic_arguments():
+    a, sta = W.straight_rod(512, inextensible=True, dt=1e-5)
+    c, stc = W.straight_rod(512, inextensible=True, dt=1e-5)
+    drv, std = W.config1().rods[0]
+    free = a.replace(clamp=False)
+    pairs = [[1, 5, 0, 5]]
+    b = R.RodBatch([a, c, drv, free])
+    with pytest.raises(R.RodError):
+        b.haptic_attach(4)
+    with pytest.raises(R.RodError):
+        b.haptic_attach(2)          # driven clamp
+    with pytest.raises(R.RodError):
+        b.haptic_attach(3)          # no clamp
+    with pytest.raises(R.RodError):
+        b.haptic_set_pose(0, [0, 0, 0], [1, 0, 0, 0])   # no mailbox
+    b.haptic_attach(0)
+    b.haptic_attach(0)
+    with pytest.raises(R.RodError):
+        b.haptic_set_pose(0, [0, 0, 0], [1, 1, 0, 0])   # not a unit quaternion
+    with pytest.raises(R.RodError):
+        b.haptic_set_pose(0, [0, np.nan, 0], [1, 0, 0, 0])
+    with pytest.raises(R.RodError):
+        b.set_bindings(pairs, True)
+    with pytest.raises(R.RodError):
+        b.set_contact([[0, -1]], 0.1)
+    with pytest.raises(R.RodError):
+        b.set_chunking(256)
+    b.set_state_rods([sta, stc, std, sta])
+    with pytest.raises(R.RodError):
+        b.adjoint_forward(10, 5)
+    b.set_contact([[1, -1]], 0.1)   # other rods may still be grouped
+    b.set_contact([], 0.1)
+    b.haptic_detach(0)
+    with pytest.raises(R.RodError):
+        b.haptic_get_force(0)
+    b.set_bindings(pairs, True)     # detached: may be bound now
+    with pytest.raises(R.RodError):
+        b.haptic_attach(0)
+    b.close()
