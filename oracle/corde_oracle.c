@@ -674,6 +674,169 @@ void oracle_rollout_group(const oracle_rod* const* rods, int32_t n_rods,
     if (max_contacts) *max_contacts = most;
 }
 
+/* -------------------------------------------------------------- environment -- */
+
+static void segment_closest(const double* p, const double* a, const double* b, double* out) {
+    double ab[3], ap[3];
+    for (int c = 0; c < 3; ++c) {
+        ab[c] = b[c] - a[c];
+        ap[c] = p[c] - a[c];
+    }
+    const double L2 = dot3(ab, ab);
+    double t = L2 > 0.0 ? dot3(ap, ab) / L2 : 0.0;
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    for (int c = 0; c < 3; ++c) out[c] = a[c] + t * ab[c];
+}
+
+void oracle_closest_point_triangle(const double* p, const double* tri, double* out) {
+    const double* A = tri;
+    const double* B = tri + 3;
+    const double* Cv = tri + 6;
+    double ab[3], ac[3], N[3];
+    for (int c = 0; c < 3; ++c) {
+        ab[c] = B[c] - A[c];
+        ac[c] = Cv[c] - A[c];
+    }
+    cross3(ab, ac, N);
+    const double nn = dot3(N, N);
+    if (nn > 0.0) {
+        /* projection onto the plane; inside if it lies on the inner side of all three edges */
+        double ap[3];
+        for (int c = 0; c < 3; ++c) ap[c] = p[c] - A[c];
+        const double h = dot3(ap, N) / nn;
+        double pp[3];
+        for (int c = 0; c < 3; ++c) pp[c] = p[c] - h * N[c];
+        const double* V[3] = {A, B, Cv};
+        int inside = 1;
+        for (int k = 0; k < 3; ++k) {
+            const double* P0 = V[k];
+            const double* P1 = V[(k + 1) % 3];
+            double e[3], d[3], cr[3];
+            for (int c = 0; c < 3; ++c) {
+                e[c] = P1[c] - P0[c];
+                d[c] = pp[c] - P0[c];
+            }
+            cross3(e, d, cr);
+            if (dot3(cr, N) < 0.0) inside = 0;
+        }
+        if (inside) {
+            for (int c = 0; c < 3; ++c) out[c] = pp[c];
+            return;
+        }
+    }
+    /* otherwise the nearest point of the three edges */
+    double best = INFINITY;
+    const double* E[3][2] = {{A, B}, {B, Cv}, {Cv, A}};
+    for (int k = 0; k < 3; ++k) {
+        double q[3], d[3];
+        segment_closest(p, E[k][0], E[k][1], q);
+        for (int c = 0; c < 3; ++c) d[c] = p[c] - q[c];
+        const double dd = dot3(d, d);
+        if (dd < best) {
+            best = dd;
+            for (int c = 0; c < 3; ++c) out[c] = q[c];
+        }
+    }
+}
+
+void oracle_env_response(const oracle_env* env, const double* c, double r, double* n,
+                         double* depth, int32_t* hits) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    double dmax = 0.0;
+    int k = 0;
+    for (int t = 0; t < env->n_tris; ++t) {
+        const double* tri = env->tris + 9 * t;
+        double q[3], d[3], ab[3], ac[3], N[3];
+        oracle_closest_point_triangle(c, tri, q);
+        for (int a = 0; a < 3; ++a) {
+            d[a] = c[a] - q[a];
+            ab[a] = tri[3 + a] - tri[a];
+            ac[a] = tri[6 + a] - tri[a];
+        }
+        const double dist = norm3(d);
+        if (!(dist < r)) continue;
+        cross3(ab, ac, N);
+        const double nl = norm3(N);
+        if (!(nl > 0.0)) continue;
+        for (int a = 0; a < 3; ++a) N[a] /= nl;
+        double cp[3];
+        for (int a = 0; a < 3; ++a) cp[a] = c[a] - tri[a];
+        /* penetration depth: the sphere reaches r - dist past the face, or, with its centre
+         * behind the face, r + dist */
+        const double dep = dot3(cp, N) >= 0.0 ? r - dist : r + dist;
+        for (int a = 0; a < 3; ++a) acc[a] += dep * N[a];
+        if (dep > dmax) dmax = dep;
+        ++k;
+    }
+    const double al = norm3(acc);
+    if (k > 0 && al > 0.0) {
+        for (int a = 0; a < 3; ++a) n[a] = acc[a] / al;
+        *depth = dmax;
+    } else {
+        for (int a = 0; a < 3; ++a) n[a] = 0.0;
+        *depth = 0.0;
+    }
+    if (hits) *hits = k;
+}
+
+void oracle_env_impulse(const double* n, double depth, double winv, double dt, double mu,
+                        double* v) {
+    if (!(depth > 0.0) || !(winv > 0.0)) return;
+    const double sep = dt * dot3(v, n) - depth;   /* predicted motion along n minus the depth */
+    if (!(sep < 0.0)) return;
+    const double lam = -sep / (dt * winv);       /* normal impulse (the wall does not move) */
+    const double vn = dot3(v, n);
+    double vt[3];
+    for (int c = 0; c < 3; ++c) vt[c] = v[c] - vn * n[c];
+    const double vtl = norm3(vt);
+    double lt = 0.0;                              /* Coulomb friction */
+    if (vtl > 0.0) {
+        lt = vtl / winv;
+        if (lt > mu * lam) lt = mu * lam;
+    }
+    for (int c = 0; c < 3; ++c)
+        v[c] += winv * lam * n[c] - (vtl > 0.0 ? winv * lt * vt[c] / vtl : 0.0);
+}
+
+void oracle_step_env(const oracle_rod* rod, const oracle_env* env, double t, double* x, double* v,
+                     double* q, double* w, int32_t* colliding) {
+    step_scratch sc;
+    step_first(rod, t, x, v, q, w, &sc);
+    /* detection from the start-of-step positions (Fig. 5: detection first), points 1..n */
+    const int n = rod->n;
+    double* nrm = (double*)calloc((size_t)3 * (n + 1), sizeof(double));
+    double* dep = (double*)calloc((size_t)n + 1, sizeof(double));
+    int count = 0;
+    for (int i = 1; i <= n; ++i) {
+        oracle_env_response(env, x + 3 * i, point_radius(rod, i), nrm + 3 * i, dep + i, NULL);
+        if (dep[i] > 0.0) ++count;
+    }
+    if (colliding) *colliding = count;
+    /* per iteration: distance constraints, then the collision response (Fig. 5); a rod
+     * without constraint iterations takes the response once */
+    const int iters = (rod->inextensible && rod->n_iter > 0) ? rod->n_iter : 1;
+    for (int it = 0; it < iters; ++it) {
+        if (rod->inextensible) step_sweeps(rod, x, v, &sc);
+        for (int i = 1; i <= n; ++i)
+            oracle_env_impulse(nrm + 3 * i, dep[i], sc.winv[i], rod->dt, env->mu, v + 3 * i);
+    }
+    free(nrm);
+    free(dep);
+    step_last(rod, x, v, q, w, &sc);
+}
+
+void oracle_rollout_env(const oracle_rod* rod, const oracle_env* env, double t0, int32_t n_steps,
+                        double* x, double* v, double* q, double* w, int32_t* most) {
+    int32_t m = 0;
+    for (int s = 0; s < n_steps; ++s) {
+        int32_t c = 0;
+        oracle_step_env(rod, env, t0 + s * rod->dt, x, v, q, w, &c);
+        if (c > m) m = c;
+    }
+    if (most) *most = m;
+}
+
 void oracle_rollout_pair(const oracle_rod* a, const oracle_rod* b, const oracle_binding* bind,
                          double t0, int32_t n_steps, double* xa, double* va, double* qa, double* wa,
                          double* xb, double* vb, double* qb, double* wb) {

@@ -193,6 +193,45 @@ void oracle_rollout_group(const oracle_rod* const* rods, int32_t n_rods,
                           int32_t n_steps, double* const* x, double* const* v, double* const* q,
                           double* const* w, int32_t* max_contacts);
 
+/* ---- Environment collision (Sec. 2.2 "Collisions") ------------------------------------
+ * A static triangle mesh; each triangle's face normal (b - a) x (c - a), normalised, points to
+ * the side the rods are on.  At the start of a step every point 1..n (sphere of its element's
+ * radius r, as for contact) collides with every triangle whose nearest point lies closer than
+ * r; per colliding triangle the penetration depth is r - dist (centre in front of the face) or
+ * r + dist (centre behind it).  The point's response is n = normalise(sum_k depth_k N_k), the
+ * depth-weighted mean of the colliding triangles' normals, with depth = max_k depth_k.  In
+ * every constraint iteration, after the distance constraints, a colliding point whose
+ * predicted motion along n falls short of the depth, s = dt v . n - depth < 0, takes the
+ * impulse lambda = -s / (dt w) along n (the mesh does not move) and a Coulomb friction impulse
+ * against its tangential velocity, at most mu lambda.  A rod without constraint iterations
+ * (the extensible variant) takes the response once per step. */
+typedef struct {
+    int32_t n_tris;
+    const double* tris;   /* n_tris x 9: vertices a, b, c */
+    double mu;            /* friction coefficient */
+} oracle_env;
+
+/* Nearest point of triangle tri (9 values: a, b, c) to p. */
+void oracle_closest_point_triangle(const double* p, const double* tri, double* out);
+
+/* Response of a sphere (centre c, radius r) against the mesh: unit n, depth (0 with n = 0 if
+ * it touches nothing or the normals cancel), hits = colliding triangles (nullable). */
+void oracle_env_response(const oracle_env* env, const double* c, double r, double* n,
+                         double* depth, int32_t* hits);
+
+/* The collision impulse of one point (inverse mass winv) on its velocity v, in place. */
+void oracle_env_impulse(const double* n, double depth, double winv, double dt, double mu,
+                        double* v);
+
+/* One step of one rod against the mesh, from time t, in place; colliding (nullable) receives
+ * the number of colliding points. */
+void oracle_step_env(const oracle_rod* rod, const oracle_env* env, double t, double* x, double* v,
+                     double* q, double* w, int32_t* colliding);
+
+/* n_steps of oracle_step_env from time t0; most = the largest number of colliding points. */
+void oracle_rollout_env(const oracle_rod* rod, const oracle_env* env, double t0, int32_t n_steps,
+                        double* x, double* v, double* q, double* w, int32_t* most);
+
 /* n_steps of oracle_step_pair starting at time t0, in place. */
 void oracle_rollout_pair(const oracle_rod* a, const oracle_rod* b, const oracle_binding* bind,
                          double t0, int32_t n_steps, double* xa, double* va, double* qa, double* wa,

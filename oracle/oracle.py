@@ -99,6 +99,16 @@ def lib():
         L.oracle_rollout_pair.restype = None
         L.oracle_rollout_pair.argtypes = [C.POINTER(_Rod), C.POINTER(_Rod), C.POINTER(_Binding),
                                           C.c_double, C.c_int32] + [_DP] * 8
+        L.oracle_closest_point_triangle.restype = None
+        L.oracle_closest_point_triangle.argtypes = [_DP, _DP, _DP]
+        L.oracle_env_response.restype = None
+        L.oracle_env_response.argtypes = [C.POINTER(_Env), _DP, C.c_double, _DP, _DP,
+                                          C.POINTER(C.c_int32)]
+        L.oracle_env_impulse.restype = None
+        L.oracle_env_impulse.argtypes = [_DP, C.c_double, C.c_double, C.c_double, C.c_double, _DP]
+        L.oracle_rollout_env.restype = None
+        L.oracle_rollout_env.argtypes = [C.POINTER(_Rod), C.POINTER(_Env), C.c_double, C.c_int32,
+                                         _DP, _DP, _DP, _DP, C.POINTER(C.c_int32)]
         _lib = L
     return _lib
 
@@ -110,6 +120,50 @@ class _Binding(C.Structure):
 
 class _Contact(C.Structure):
     _fields_ = [("mu", C.c_double)]
+
+
+class _Env(C.Structure):
+    _fields_ = [("n_tris", C.c_int32), ("tris", _DP), ("mu", C.c_double)]
+
+
+class Env:
+    """A static triangle mesh (tris: (k, 3, 3) vertices, face normal (b - a) x (c - a) towards
+    the rods) with friction coefficient mu, for the oracle's environment collision."""
+
+    def __init__(self, tris, mu=0.0):
+        self.tris = np.ascontiguousarray(np.asarray(tris, dtype=np.float64).reshape(-1, 9))
+        self.c = _Env(len(self.tris), self.tris.ctypes.data_as(_DP), float(mu))
+
+    def response(self, c, r):
+        """(n (3,), depth, colliding triangles) of a sphere of centre c and radius r."""
+        c = _f64(c, (3,))
+        n, d, k = np.zeros(3), C.c_double(0.0), C.c_int32(0)
+        lib().oracle_env_response(C.byref(self.c), _p(c), float(r), _p(n), C.byref(d), C.byref(k))
+        return n, float(d.value), int(k.value)
+
+
+def closest_point_triangle(p, tri):
+    p, t, out = _f64(p, (3,)), _f64(tri, (9,)), np.zeros(3)
+    lib().oracle_closest_point_triangle(_p(p), _p(t), _p(out))
+    return out
+
+
+def env_impulse(n, depth, winv, dt, mu, v):
+    n, out = _f64(n, (3,)), _f64(v, (3,)).copy()
+    lib().oracle_env_impulse(_p(n), float(depth), float(winv), float(dt), float(mu), _p(out))
+    return out
+
+
+def rollout_env(spec, state, n_steps, env, t0=0.0):
+    """One rod against the mesh of ``env``; returns (new state, most colliding points)."""
+    r = Rod(spec)
+    o = state.copy()
+    o.x, o.v = _f64(state.x, (r.n + 1, 3)).copy(), _f64(state.v, (r.n + 1, 3)).copy()
+    o.q, o.w = _f64(state.q, (r.n, 4)).copy(), _f64(state.w, (r.n, 3)).copy()
+    most = C.c_int32(0)
+    lib().oracle_rollout_env(C.byref(r.c), C.byref(env.c), float(t0), int(n_steps), _p(o.x),
+                             _p(o.v), _p(o.q), _p(o.w), C.byref(most))
+    return o, int(most.value)
 
 
 def _p(a):

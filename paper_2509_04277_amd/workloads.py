@@ -406,6 +406,91 @@ def config4(n_rods: int = 256, n: int = 256, dt: float = 0.0) -> Workload:
                     n_steps=400, steps_per_launch=20)
 
 
+def tube_centreline(straight1: float = 0.3, bend_radius: float = 0.3,
+                    bend_angle: float = 0.5 * math.pi, straight2: float = 0.5,
+                    ds: float = 0.01) -> np.ndarray:
+    """Centreline of a bent vessel in the horizontal plane: straight along x, an arc turning
+    towards +y, straight again; points about ds apart."""
+    pts = [np.array([s_, 0.0, 0.0]) for s_ in np.arange(0.0, straight1, ds)]
+    c = np.array([straight1, bend_radius, 0.0])
+    n_arc = max(2, int(math.ceil(bend_radius * bend_angle / ds)))
+    for k in range(n_arc):
+        a = bend_angle * k / n_arc
+        pts.append(c + bend_radius * np.array([math.sin(a), -math.cos(a), 0.0]))
+    end = c + bend_radius * np.array([math.sin(bend_angle), -math.cos(bend_angle), 0.0])
+    tdir = np.array([math.cos(bend_angle), math.sin(bend_angle), 0.0])
+    n_st = max(1, int(math.ceil(straight2 / ds)))
+    for k in range(n_st + 1):
+        pts.append(end + tdir * straight2 * k / n_st)
+    return np.asarray(pts)
+
+
+def tube_mesh(centre: np.ndarray, radius: float, n_around: int) -> np.ndarray:
+    """Triangles (k, 3, 3) of a tube of the given radius around a centreline polyline: rings of
+    n_around vertices (frames carried along by parallel transport), two triangles per quad,
+    wound so that each face normal (b - a) x (c - a) points into the tube."""
+    m = len(centre)
+    t = np.gradient(centre, axis=0)
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    u = np.zeros_like(centre)
+    u0 = np.cross(t[0], [0.0, 0.0, 1.0])
+    if np.linalg.norm(u0) < 1e-6:
+        u0 = np.cross(t[0], [0.0, 1.0, 0.0])
+    u[0] = u0 / np.linalg.norm(u0)
+    for k in range(1, m):
+        uk = u[k - 1] - np.dot(u[k - 1], t[k]) * t[k]
+        u[k] = uk / np.linalg.norm(uk)
+    w = np.cross(t, u)
+    th = 2.0 * math.pi * np.arange(n_around) / n_around
+    ring = centre[:, None, :] + radius * (np.cos(th)[None, :, None] * u[:, None, :]
+                                          + np.sin(th)[None, :, None] * w[:, None, :])
+    tris = []
+    for k in range(m - 1):
+        axis_mid = 0.5 * (centre[k] + centre[k + 1])
+        for j in range(n_around):
+            a, b = ring[k, j], ring[k, (j + 1) % n_around]
+            c, d = ring[k + 1, (j + 1) % n_around], ring[k + 1, j]
+            for tri in ((a, b, c), (a, c, d)):
+                tri = np.array(tri)
+                nrm = np.cross(tri[1] - tri[0], tri[2] - tri[0])
+                if np.dot(nrm, axis_mid - tri.mean(axis=0)) < 0:
+                    tri = tri[[0, 2, 1]]
+                tris.append(tri)
+    return np.asarray(tris)
+
+
+def _along(poly: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """Points at arc lengths s along a polyline."""
+    seg = np.linalg.norm(np.diff(poly, axis=0), axis=1)
+    cum = np.r_[0.0, np.cumsum(seg)]
+    out = np.empty((len(s), 3))
+    for i, si in enumerate(s):
+        k = min(np.searchsorted(cum, si, side="right") - 1, len(seg) - 1)
+        f = (si - cum[k]) / seg[k]
+        out[i] = poly[k] + f * (poly[k + 1] - poly[k])
+    return out
+
+
+def config7(n: int = 64, L: float = 1.0, rod_radius: float = 2e-3, young: float = 1e7,
+            tube_radius: float = 1e-2, n_around: int = 12, dt: float = 0.0):
+    """A straight-at-rest rod laid along the centreline of a bent vessel (procedural tube mesh)
+    and clamped at its entrance: gravity and its own stiffness press it onto the wall.
+    Returns (Workload, triangles (k, 3, 3))."""
+    centre = tube_centreline()
+    tris = tube_mesh(centre, tube_radius, n_around)
+    x = _along(centre, np.linspace(0.0, L, n + 1))
+    q = frames_from_polyline(x)
+    seg = np.linalg.norm(np.diff(x, axis=0), axis=1)
+    spec = RodSpec(n=n, inextensible=True, n_iter=10, clamp=True, dt=1.0, gravity=(0.0, 0.0, -9.81),
+                   damp_lin=0.5, damp_ang=0.5, poisson=0.5, density=1000.0, seg_len=seg,
+                   radius=np.full(n, rod_radius), young=np.full(n, young),
+                   clamp_x0=tuple(x[0]), clamp_q0=tuple(q[0]))
+    if dt > 0:
+        spec = spec.replace(dt=dt)
+    return Workload("c7: %d-element rod in a bent tube (%d triangles)" % (n, len(tris)),
+                    [(spec, _zero_state(x, q))], n_steps=400, steps_per_launch=10), tris
+
+
 def straight_rod(n: int, L: float = 1.0, radius: float = 0.01, young: float = 1e6,
                  inextensible: bool = False, dt: float = 1e-5, gravity=(0.0, 0.0, -9.81),
                  damp: float = 0.0, n_iter: int = 10, clamp: bool = True,
