@@ -192,6 +192,29 @@ rod_status rod_set_bindings(rod_ctx* ctx, int32_t n_pairs, const int32_t* pairs,
  * removes all contact sets.  Errors: INVALID, UNSUPPORTED, NOMEM, DEVICE. */
 rod_status rod_set_contact(rod_ctx* ctx, int32_t n_sets, const int32_t* sets, double mu);
 
+/* ---- Environment collision (Sec. 2.2 "Collisions"; Sec. 2.1 contact constraints) --------
+ * A static triangle mesh that every rod of the handle collides with.  tris: n_tris x 9
+ * doubles, the vertices a, b, c of each triangle; the face normal (b - a) x (c - a) points to
+ * the side the rods are on (into the lumen of a vessel).  Degenerate triangles are dropped.
+ * The library builds an AABB tree over them by volume partitioning (leaves of at most 2
+ * triangles) and copies it to the device.  At the start of every step each point 1..n (a
+ * sphere of its element's radius, as for contact) finds the triangles whose nearest point is
+ * closer than its radius; each has a depth, radius - distance (centre in front of the face) or
+ * radius + distance (behind it); the point's response is the depth-weighted mean of their face
+ * normals, normalised, with the largest depth.  In every constraint iteration, after the
+ * distance constraints, a colliding point whose predicted motion along that normal falls
+ * short of the depth is pushed out by a velocity impulse, with Coulomb friction (coefficient
+ * mu) against its tangential velocity; rods without constraint iterations take the response
+ * once per step.  n_tris = 0 removes the mesh.  Rods collide in kernel variants of their own
+ * (default shapes only, as for the haptic mailbox).  Grouped (bound, contact) and chunked rods
+ * do not collide: with any, this returns ROD_E_UNSUPPORTED, and so do rod_set_bindings,
+ * rod_set_contact, rod_set_chunking and the adjoint while a mesh is set.
+ * Errors: INVALID, UNSUPPORTED, NOMEM, DEVICE. */
+rod_status rod_set_environment(rod_ctx* ctx, int32_t n_tris, const double* tris, double mu);
+
+/* Size of the environment's tree: nodes and (non-degenerate) triangles, 0 without a mesh. */
+rod_status rod_environment_info(const rod_ctx* ctx, int32_t* n_nodes, int32_t* n_tris);
+
 /* ---- Haptic mailbox (Sec. 2.2: the haptic thread hands a new device position to the
  * running simulation and reads its force-feedback vector at any time, at 0.5-1 kHz) ---------
  * rod_haptic_attach() gives rod `rod` a mailbox in pinned host memory that its kernel reads

@@ -817,7 +817,7 @@ void oracle_step_env(const oracle_rod* rod, const oracle_env* env, double t, dou
      * without constraint iterations takes the response once */
     const int iters = (rod->inextensible && rod->n_iter > 0) ? rod->n_iter : 1;
     for (int it = 0; it < iters; ++it) {
-        if (rod->inextensible) step_sweeps(rod, x, v, &sc);
+        if (rod->inextensible && it < rod->n_iter) step_sweeps(rod, x, v, &sc);
         for (int i = 1; i <= n; ++i)
             oracle_env_impulse(nrm + 3 * i, dep[i], sc.winv[i], rod->dt, env->mu, v + 3 * i);
     }

@@ -75,6 +75,20 @@ __device__ __forceinline__ void mailbox_store(uint64_t* p, uint64_t v) {
   __hip_atomic_store((GlobalWord*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// Static triangle mesh of the environment (Sec. 2.2 "Collisions"): an AABB tree by volume
+// partitioning, its nodes in depth-first order so that a query walks it without a stack: at a
+// node whose box the sphere reaches, go to the next node (its first child), or test a leaf's
+// triangles and go to `skip`; elsewhere jump to `skip`, the node after its subtree.
+struct alignas(16) EnvNode {
+  float lo[3];
+  int32_t skip;   // index of the first node after this subtree
+  float hi[3];
+  int32_t leaf;   // -1: interior node; else (first triangle << 3) | triangle count
+};
+struct alignas(16) EnvTri {
+  float a[3], e1[3], e2[3], n[3];   // vertex a, b - a, c - a, unit face normal
+};
+
 struct RodDev {
   int32_t n;          // elements
   int32_t slot_off;   // first slot in the coefficient rows
@@ -95,8 +109,17 @@ struct RodDev {
   double dt_d, t0, omega, ph_x, ph_t;
   HapticBox* hbox;    // haptic mailbox (device address of pinned host memory), or null
   int32_t hstride;    // steps per force record (>= 1 with a mailbox)
-  int32_t pad_h;
+  int32_t env_n_nodes;   // environment tree (0: none)
+  const EnvNode* env_nodes;
+  const EnvTri* env_tris;
+  const float* rho;   // per slot: sphere radius of point slot + 1
+  float env_mu;       // friction coefficient against the environment
+  int32_t pad_e;
 };
+
+// Kernel feature bits of rod_resident_kernel's variants.
+constexpr int kFeatHaptic = 1;
+constexpr int kFeatEnv = 2;
 
 struct V3 {
   float x, y, z;
@@ -262,6 +285,77 @@ __device__ __forceinline__ void clamp_pose(const RodDev& rd, double t, V3& xc, Q
 }
 
 
+// Nearest point of triangle t to p, by the Voronoi region of p (vertex, edge or face) found
+// from the signs of dot products with the edges (Ericson, Real-Time Collision Detection, 5.1.5).
+__device__ __forceinline__ V3 tri_closest(const EnvTri& t, V3 p) {
+  const V3 a = {t.a[0], t.a[1], t.a[2]};
+  const V3 ab = {t.e1[0], t.e1[1], t.e1[2]};
+  const V3 ac = {t.e2[0], t.e2[1], t.e2[2]};
+  const V3 ap = p - a;
+  const float d1 = dot(ab, ap), d2 = dot(ac, ap);
+  if (d1 <= 0.f && d2 <= 0.f) return a;
+  const V3 bp = ap - ab;
+  const float d3 = dot(ab, bp), d4 = dot(ac, bp);
+  if (d3 >= 0.f && d4 <= d3) return a + ab;
+  const float vc = d1 * d4 - d3 * d2;
+  if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) return fma3(d1 / (d1 - d3), ab, a);
+  const V3 cp = ap - ac;
+  const float d5 = dot(ab, cp), d6 = dot(ac, cp);
+  if (d6 >= 0.f && d5 <= d6) return a + ac;
+  const float vb = d5 * d2 - d1 * d6;
+  if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) return fma3(d2 / (d2 - d6), ac, a);
+  const float va = d3 * d6 - d5 * d4;
+  if (va <= 0.f && d4 - d3 >= 0.f && d5 - d6 >= 0.f) {
+    const float u = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+    return fma3(u, ac - ab, a + ab);
+  }
+  const float den = 1.0f / (va + vb + vc);
+  return fma3(vc * den, ac, fma3(vb * den, ab, a));
+}
+
+// Collision response of a sphere (centre c, radius r) against the environment: the
+// depth-weighted mean n of the colliding triangles' normals and the largest depth (0: none).
+// A triangle collides when its nearest point is closer than r; its depth is r - dist with the
+// centre in front of the face, r + dist behind it.
+__device__ __forceinline__ void env_query(const RodDev& rd, V3 c, float r, V3& n, float& depth) {
+  V3 acc = {0.f, 0.f, 0.f};
+  float dmax = 0.f;
+  const float r2 = r * r;
+  int i = 0;
+  while (i < rd.env_n_nodes) {
+    const EnvNode nd = rd.env_nodes[i];
+    const float bx = fmaxf(fmaxf(nd.lo[0] - c.x, c.x - nd.hi[0]), 0.f);
+    const float by = fmaxf(fmaxf(nd.lo[1] - c.y, c.y - nd.hi[1]), 0.f);
+    const float bz = fmaxf(fmaxf(nd.lo[2] - c.z, c.z - nd.hi[2]), 0.f);
+    const bool reach = bx * bx + by * by + bz * bz < r2;
+    if (reach && nd.leaf >= 0) {
+      const int first = nd.leaf >> 3, cnt = nd.leaf & 7;
+      for (int k = 0; k < cnt; ++k) {
+        const EnvTri t = rd.env_tris[first + k];
+        const V3 q = tri_closest(t, c);
+        const V3 d = c - q;
+        const float dist = sqrtf(dot(d, d));
+        if (dist < r) {
+          const V3 nf = {t.n[0], t.n[1], t.n[2]};
+          const V3 ca = {c.x - t.a[0], c.y - t.a[1], c.z - t.a[2]};
+          const float dep = dot(ca, nf) >= 0.f ? r - dist : r + dist;
+          acc = fma3(dep, nf, acc);
+          dmax = fmaxf(dmax, dep);
+        }
+      }
+    }
+    i = (reach && nd.leaf < 0) ? i + 1 : nd.skip;
+  }
+  const float al2 = dot(acc, acc);
+  if (dmax > 0.f && al2 > 0.f) {
+    n = rsqrtf(al2) * acc;
+    depth = dmax;
+  } else {
+    n = {0.f, 0.f, 0.f};
+    depth = 0.f;
+  }
+}
+
 // Registers of one lane of a rod's workgroup: E slots (frame j, point j+1) plus, in lane 0,
 // the base point.  The member functions are the phases of one time step; the forward kernel
 // and the adjoint kernel call the same functions, so a recomputed step is bit-identical.
@@ -276,6 +370,8 @@ struct RodLane {
   int off, nloc;   // window of the rod held by this workgroup: slots [off, off + nloc)
   bool ghost;      // off > 0: lane 0's "base point" is point `off`, held fixed (a halo edge)
   V3 imp0;         // lane 0: momentum passed to point 0 (forces x dt + impulses)
+  V3 en[E];        // environment collision of each slot's point this step: normal, depth
+  float ed[E];
   float dt;
 
   // Loads the coefficients of slots [off, off + nloc) (the whole rod by default).  A window
@@ -534,6 +630,42 @@ struct RodLane {
     if (g == 0 && h == 0 && !rd.clamp && !ghost) bv = bv + dvb;
   }
 
+  // Environment collision detection from the step-start positions (points 1..n).
+  __device__ __forceinline__ void env_detect(const RodDev& rd) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      en[e] = {0.f, 0.f, 0.f};
+      ed[e] = 0.f;
+      if (ok[e]) env_query(rd, X[e], rd.rho[rd.slot_off + off + j0 + e], en[e], ed[e]);
+    }
+  }
+
+  // Collision response impulses (after a constraint iteration's distance sweeps): a point whose
+  // predicted motion along n falls short of its depth is pushed out, with Coulomb friction
+  // against its tangential velocity, at most mu times the normal impulse.
+  __device__ __forceinline__ void env_impulses(const RodDev& rd) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const V3 n = en[e];
+      const V3 v = Vv[e];
+      const float vn = dot(v, n);
+      const float sep = fmaf(dt, vn, -ed[e]);
+      const float w = P[P_WINV][e];
+      if (ed[e] > 0.f && sep < 0.f && w > 0.f) {
+        const float dvn = -sep / dt;                   // w lambda: the normal velocity change
+        const V3 vt = fnma3(vn, n, v);
+        const float vtl2 = dot(vt, vt);
+        V3 nv = fma3(dvn, n, v);
+        if (vtl2 > 0.f) {
+          const float il = rsqrtf(vtl2);
+          const float dvt = fminf(vtl2 * il, rd.env_mu * dvn);   // w times the friction impulse
+          nv = fnma3(dvt * il, vt, nv);
+        }
+        Vv[e] = nv;
+      }
+    }
+  }
+
   // X: integrate velocities (semi-implicit Euler), renormalise, impose the clamp pose.
   __device__ __forceinline__ void integrate_velocities(const RodDev& rd, V3 xc, Q4 qc) {
 #pragma unroll
@@ -589,7 +721,7 @@ __device__ __forceinline__ void clamp_for_step(const RodDev& rd, float (*cbuf)[1
 // (traj_steps = 1 writes a checkpoint of the launch's initial state).
 // tips (nullable): x_N after step s goes to tips[(rod * tip_steps + steps_done - tip_base + s) * 3].
 // store_final = 0 leaves gx..gw untouched (a recomputation that only needs traj).
-template <int W, int E, bool H = false>
+template <int W, int E, int F = 0>
 __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
     const RodDev* __restrict__ rods, const int* __restrict__ rod_ids, const float* __restrict__ prm,
     int prm_stride, float* __restrict__ gx, float* __restrict__ gv, float* __restrict__ gq,
@@ -611,7 +743,7 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
   // haptic mailbox: records cover windows of hstride steps (the last one of a launch may be
   // shorter); the pose is taken at the clamp of each window's first step.  Lanes 0..6 of wave 0
   // hold one pose word each, loaded a whole window before it is needed.
-  HapticBox* const hb = H ? rd.hbox : nullptr;   // H: the variant built with the mailbox code
+  HapticBox* const hb = (F & kFeatHaptic) ? rd.hbox : nullptr;   // the mailbox variant only
   const int hk = rd.hstride;
   uint32_t htag = 0;   // pose number in use (0: the rod's own clamp pose)
   int hn = 0;          // steps in the current window
@@ -624,11 +756,12 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
       float* base = traj + (long long)s * traj_stride;
       L.store_state(rd, base, base + 3 * n_pts, base + 6 * n_pts, base + 6 * n_pts + 4 * n_frames);
     }
+    if (F & kFeatEnv) L.env_detect(rd);   // environment collisions (Fig. 5: detection first)
     V3 xl;
     Q4 qn;
     L.exchange_a(mb, par, xl, qn);
-    V3 F[E], T[E], Ev[E], fs0, enext;
-    L.forces(mb, par, xl, qn, F, T, Ev, fs0, enext);
+    V3 Fo[E], T[E], Ev[E], fs0, enext;
+    L.forces(mb, par, xl, qn, Fo, T, Ev, fs0, enext);
     clamp_for_step<W>(rd, cbuf, s, n_steps, steps_done, xc, qc, wc, rd.driven && rd.clamp, L.g);
     const bool hfirst = hb && hn == 0;
     if (hfirst && L.g < 64) {   // wave 0, all lanes: take the pose if whole and new
@@ -645,14 +778,16 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
       if (L.g < 7 && s + hk < n_steps)   // the next window's pose
         pw = mailbox_load(&hb->pose[L.g]);
     }
-    L.integrate_forces(rd, F, T, fs0, xc, wc, fext, text);
+    L.integrate_forces(rd, Fo, T, fs0, xc, wc, fext, text);
     // momentum the base point receives over the window: internal force x dt, plus segment 0's
     // constraint impulses (accumulated by the sweeps)
     L.imp0 = fnma3(rd.dt, fs0, hn == 0 ? V3{0.f, 0.f, 0.f} : L.imp0);
     for (int it = 0; it < rd.n_iter; ++it) {
       L.half_sweep(rd, mb, par, 0, Ev, enext, nullptr);
       L.half_sweep(rd, mb, par, 1, Ev, enext, nullptr);
+      if (F & kFeatEnv) L.env_impulses(rd);   // then the collision response (Fig. 5)
     }
+    if ((F & kFeatEnv) && rd.n_iter == 0) L.env_impulses(rd);   // without iterations: once
     L.integrate_velocities(rd, xc, qc);
     if (hb) {
       ++hn;

@@ -56,21 +56,23 @@ const AdjointEntry kAdjoints[] = {
 
 struct KernelEntry {
   int waves, elems;
-  KernelFn fn;
-  KernelFn hfn;   // the variant with the haptic mailbox code (the default shapes only)
+  KernelFn fn[4];   // by feature bits (kFeatHaptic, kFeatEnv); the variants exist for the
+                    // default shapes only
 };
 
 // Built kernel shapes: (waves per rod, elements per lane).  Capacity = 64 * waves * elems.
-#define ROD_SHAPE(w, e) {w, e, corde::rod_resident_kernel<w, e>, nullptr}
-#define ROD_SHAPE_H(w, e) {w, e, corde::rod_resident_kernel<w, e>, corde::rod_resident_kernel<w, e, true>}
+#define ROD_SHAPE(w, e) {w, e, {corde::rod_resident_kernel<w, e, 0>, nullptr, nullptr, nullptr}}
+#define ROD_SHAPE_F(w, e)                                                                   \
+  {w, e, {corde::rod_resident_kernel<w, e, 0>, corde::rod_resident_kernel<w, e, 1>,       \
+          corde::rod_resident_kernel<w, e, 2>, corde::rod_resident_kernel<w, e, 3>}}
 const KernelEntry kKernels[] = {
-    ROD_SHAPE_H(1, 1), ROD_SHAPE_H(1, 2), ROD_SHAPE(1, 4),    ROD_SHAPE(1, 8),
-    ROD_SHAPE(2, 1),   ROD_SHAPE_H(2, 2), ROD_SHAPE(2, 4),    ROD_SHAPE(4, 1),
-    ROD_SHAPE_H(4, 2), ROD_SHAPE_H(4, 4), ROD_SHAPE_H(4, 8),  ROD_SHAPE(8, 1),
-    ROD_SHAPE(8, 2),   ROD_SHAPE_H(8, 4), ROD_SHAPE(16, 1),
+    ROD_SHAPE_F(1, 1), ROD_SHAPE_F(1, 2), ROD_SHAPE(1, 4),    ROD_SHAPE(1, 8),
+    ROD_SHAPE(2, 1),   ROD_SHAPE_F(2, 2), ROD_SHAPE(2, 4),    ROD_SHAPE(4, 1),
+    ROD_SHAPE_F(4, 2), ROD_SHAPE_F(4, 4), ROD_SHAPE_F(4, 8),  ROD_SHAPE(8, 1),
+    ROD_SHAPE(8, 2),   ROD_SHAPE_F(8, 4), ROD_SHAPE(16, 1),
 };
 #undef ROD_SHAPE
-#undef ROD_SHAPE_H
+#undef ROD_SHAPE_F
 
 const KernelEntry* find_kernel(int w, int e) {
   for (const auto& k : kKernels)
@@ -122,7 +124,7 @@ struct rod_ctx {
   struct Bucket {
     int waves, elems, first, count, max_n;
     float us_per_step;
-    bool haptic = false;   // its rods have haptic mailboxes (the kernel variant with that code)
+    int feat = 0;   // kernel feature bits of its rods (mailbox, environment)
   };
   // long rods (more than chunk_above elements): chunked, one workgroup per chunk
   int chunk_above = kResidentMax;
@@ -157,6 +159,10 @@ struct rod_ctx {
   };
   std::vector<Haptic> haptic;
   int n_haptic = 0;
+  // environment mesh (rod_set_environment): AABB tree and triangles on the device
+  corde::EnvNode* d_env_nodes = nullptr;
+  corde::EnvTri* d_env_tris = nullptr;
+  int env_nodes = 0, env_tris = 0;
   // adjoint rollout (rod_adjoint_forward / rod_adjoint_backward)
   bool adj_ready = false;
   int adj_steps = 0, adj_ckpt = 0, adj_nckpt = 0;
@@ -200,6 +206,11 @@ rod_status hip_fail(rod_ctx* c, hipError_t e, const char* what) {
   } while (0)
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Kernel feature bits rod r needs (a mailbox, the environment).
+int rod_features(const rod_ctx* c, int r) {
+  return (c->haptic[r].host ? corde::kFeatHaptic : 0) | (c->env_nodes ? corde::kFeatEnv : 0);
+}
 
 // Validates one rod description; returns "" or a message.
 std::string check_params(const rod_params& p, int idx) {
@@ -381,22 +392,22 @@ template <class ShapeFn>
 rod_status make_buckets(rod_ctx* c, ShapeFn shape) {
   std::vector<std::pair<long long, int>> key;
   std::vector<int> wr(c->n_rods), er(c->n_rods);
-  std::vector<char> hr(c->n_rods);
+  std::vector<int> hr(c->n_rods);
   for (int r = 0; r < c->n_rods; ++r) {
     if (c->n[r] > c->chunk_above) continue;   // long rods run chunked
     if (!c->bound.empty() && c->bound[r]) continue;   // bound pairs have their own kernel
     int w, e;
     shape(r, &w, &e);
-    const bool h = c->haptic[r].host != nullptr;
-    if (h) {   // rods with a mailbox need a shape built with the mailbox code
+    const int h = rod_features(c, r);
+    if (h) {   // a shape built with the feature code
       const KernelEntry* k = find_kernel(w, e);
-      if (!k || !k->hfn) default_shape(c->n[r], &w, &e);
+      if (!k || !k->fn[h]) default_shape(c->n[r], &w, &e);
     }
     wr[r] = w, er[r] = e, hr[r] = h;
     // within a bucket, most work first (a constraint iteration costs about a quarter of the
     // rest of a step), so the last workgroups dispatched are the cheap ones
     const long long cost = (long long)c->n[r] * (4 + c->rods[r].n_iter);
-    key.push_back({((long long)((w * 16 + e) * 2 + h) << 32) | (0x7fffffffLL - cost), r});
+    key.push_back({((long long)((w * 16 + e) * 4 + h) << 32) | (0x7fffffffLL - cost), r});
   }
   std::sort(key.begin(), key.end());
   c->buckets.clear();
@@ -404,10 +415,10 @@ rod_status make_buckets(rod_ctx* c, ShapeFn shape) {
   for (int i = 0; i < (int)key.size(); ++i) {
     const int r = key[i].second;
     const int w = wr[r], e = er[r];
-    const bool h = hr[r];
+    const int h = hr[r];
     c->rod_ids[i] = r;
     if (c->buckets.empty() || c->buckets.back().waves != w || c->buckets.back().elems != e ||
-        c->buckets.back().haptic != h)
+        c->buckets.back().feat != h)
       c->buckets.push_back({w, e, i, 0, 0, 0.f, h});
     c->buckets.back().count++;
     c->buckets.back().max_n = std::max(c->buckets.back().max_n, c->n[r]);
@@ -416,6 +427,75 @@ rod_status make_buckets(rod_ctx* c, ShapeFn shape) {
                             hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return ROD_OK;
+}
+
+// AABB tree of a triangle mesh by volume partitioning: the triangles of a node are split at
+// the median of their centroids along the longest axis of the centroids' bounds, down to leaves
+// of at most kLeafTris triangles; nodes are emitted depth-first (see corde::EnvNode), leaf
+// triangles in leaf order.  Boxes are padded by pad so that the FP32 box test never rejects a
+// triangle the FP32 narrow phase would accept.
+constexpr int kLeafTris = 2;
+struct BuildTri {
+  double v[3][3];
+  double cen[3];
+};
+
+void build_env_node(std::vector<BuildTri>& t, int b, int e, float pad,
+                    std::vector<corde::EnvNode>& nodes, std::vector<corde::EnvTri>& out) {
+  const int me = (int)nodes.size();
+  nodes.push_back({});
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int i = b; i < e; ++i)
+    for (int a = 0; a < 3; ++a) {
+      for (int k = 0; k < 3; ++k) {
+        lo[a] = std::min(lo[a], (float)t[i].v[k][a]);
+        hi[a] = std::max(hi[a], (float)t[i].v[k][a]);
+      }
+      clo[a] = std::min(clo[a], t[i].cen[a]);
+      chi[a] = std::max(chi[a], t[i].cen[a]);
+    }
+  corde::EnvNode nd;
+  for (int a = 0; a < 3; ++a) {
+    nd.lo[a] = lo[a] - pad;
+    nd.hi[a] = hi[a] + pad;
+  }
+  if (e - b <= kLeafTris) {
+    nd.leaf = ((int)out.size() << 3) | (e - b);
+    for (int i = b; i < e; ++i) {
+      corde::EnvTri tr;
+      double e1[3], e2[3], n[3];
+      for (int a = 0; a < 3; ++a) {
+        e1[a] = t[i].v[1][a] - t[i].v[0][a];
+        e2[a] = t[i].v[2][a] - t[i].v[0][a];
+      }
+      n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+      n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+      n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+      const double nl = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      for (int a = 0; a < 3; ++a) {
+        tr.a[a] = (float)t[i].v[0][a];
+        tr.e1[a] = (float)e1[a];
+        tr.e2[a] = (float)e2[a];
+        tr.n[a] = (float)(n[a] / nl);
+      }
+      out.push_back(tr);
+    }
+    nd.skip = me + 1;
+    nodes[me] = nd;
+    return;
+  }
+  int axis = 0;
+  for (int a = 1; a < 3; ++a)
+    if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+  const int mid = (b + e) / 2;
+  std::nth_element(t.begin() + b, t.begin() + mid, t.begin() + e,
+                   [axis](const BuildTri& x, const BuildTri& y) { return x.cen[axis] < y.cen[axis]; });
+  build_env_node(t, b, mid, pad, nodes, out);
+  build_env_node(t, mid, e, pad, nodes, out);
+  nd.leaf = -1;
+  nd.skip = (int)nodes.size();
+  nodes[me] = nd;
 }
 
 // Rebuilds the buckets with every rod keeping its current shape (after a mailbox change).
@@ -545,7 +625,7 @@ rod_status reset_flags(rod_ctx* c) {
 rod_status launch_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long long done,
                          hipStream_t stream) {
   const KernelEntry* k = find_kernel(b.waves, b.elems);
-  const KernelFn fn = k ? (b.haptic ? k->hfn : k->fn) : nullptr;
+  const KernelFn fn = k ? k->fn[b.feat] : nullptr;
   if (!fn) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
   hipLaunchKernelGGL(fn, dim3(b.count), dim3(64 * k->waves), 0, stream, c->d_rods,
                      c->d_rod_ids + b.first, c->d_prm, c->prm_stride, c->d_x, c->d_v, c->d_q,
@@ -594,6 +674,8 @@ rod_status rebuild_groups(rod_ctx* c) {
     gs[g].contact = 1;
     gs[g].mu = c->contact_mu;
   }
+  if (!gs.empty() && c->env_nodes)
+    return fail(c, ROD_E_UNSUPPORTED, "rods in groups do not collide with the environment");
   for (const auto& g : gs) {
     if (c->haptic[g.rod[0]].host || (g.rod[1] >= 0 && c->haptic[g.rod[1]].host))
       return fail(c, ROD_E_UNSUPPORTED, "a rod with a haptic mailbox cannot be grouped");
@@ -785,7 +867,8 @@ rod_status launch_forward_on(rod_ctx* c, float* x, float* v, float* q, float* w,
   for (const auto& b : c->buckets) {
     const KernelEntry* k = find_kernel(b.waves, b.elems);
     if (!k) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
-    hipLaunchKernelGGL(k->fn, dim3(b.count), dim3(64 * k->waves), 0, stream, c->d_rods,
+    if (b.feat) return fail(c, ROD_E_UNSUPPORTED, "the adjoint steps plain rods only");
+    hipLaunchKernelGGL(k->fn[0], dim3(b.count), dim3(64 * k->waves), 0, stream, c->d_rods,
                        c->d_rod_ids + b.first, c->d_prm, c->prm_stride, x, v, q, w, c->d_fext,
                        c->d_text, ks, step, c->d_status, traj, S, c->total_pts, c->total_frames,
                        tips, c->adj_steps, tip_base, traj_steps, store_final);
@@ -916,6 +999,7 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
   if (any_ext && (!dmalloc((void**)&c->d_fext, sizeof(float) * fext.size()) ||
                   !dmalloc((void**)&c->d_text, sizeof(float) * text.size())))
     return cleanup(fail(nullptr, ROD_E_NOMEM, "device allocation failed"));
+  for (auto& d : c->rods) d.rho = c->d_rho;
   e = hipMemcpy(c->d_rods, c->rods.data(), sizeof(RodDev) * n_rods, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_prm, rows.data(), sizeof(float) * rows.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_rho, rho.data(), sizeof(float) * rho.size(), hipMemcpyHostToDevice);
@@ -951,7 +1035,7 @@ rod_status rod_destroy(rod_ctx* c) {
                   (void*)c->d_tips, (void*)c->d_dtips, (void*)c->d_adj,
                   (void*)c->d_gacc, (void*)c->d_groups, (void*)c->d_partner, (void*)c->d_rho,
                   (void*)c->d_chunks, (void*)c->d_block_chunk, (void*)c->d_pub,
-                  (void*)c->d_flags})
+                  (void*)c->d_flags, (void*)c->d_env_nodes, (void*)c->d_env_tris})
     if (p) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -1125,6 +1209,8 @@ rod_status rod_set_chunking(rod_ctx* c, int32_t min_elements, int32_t chunk_elem
       return fail(c, ROD_E_UNSUPPORTED, "a bound rod cannot be chunked");
     if (c->haptic[r].host && c->n[r] > min_elements)
       return fail(c, ROD_E_UNSUPPORTED, "a rod with a haptic mailbox cannot be chunked");
+    if (c->env_nodes && c->n[r] > min_elements)
+      return fail(c, ROD_E_UNSUPPORTED, "chunked rods do not collide with the environment");
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (void** p : {(void**)&c->d_chunks, (void**)&c->d_block_chunk, (void**)&c->d_pub,
@@ -1359,6 +1445,85 @@ rod_status rod_haptic_get_force(rod_ctx* c, int32_t rod, rod_haptic_force* out) 
   return fail(nullptr, ROD_E_TIMEOUT, "no whole force record could be read");
 }
 
+rod_status rod_set_environment(rod_ctx* c, int32_t n_tris, const double* tris, double mu) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (n_tris < 0 || n_tris > (1 << 26) || (n_tris > 0 && !tris))
+    return fail(c, ROD_E_INVALID, "bad triangle list");
+  if (!(std::isfinite(mu) && mu >= 0.0)) return fail(c, ROD_E_INVALID, "mu must be finite and >= 0");
+  std::vector<BuildTri> bt;
+  double cmax = 0.0;
+  for (int i = 0; i < n_tris; ++i) {
+    BuildTri t;
+    bool fin = true;
+    for (int k = 0; k < 3; ++k)
+      for (int a = 0; a < 3; ++a) {
+        t.v[k][a] = tris[9 * i + 3 * k + a];
+        fin = fin && std::isfinite(t.v[k][a]);
+        cmax = std::max(cmax, std::fabs(t.v[k][a]));
+      }
+    if (!fin) return fail(c, ROD_E_INVALID, "triangle coordinates must be finite");
+    double e1[3], e2[3];
+    for (int a = 0; a < 3; ++a) {
+      e1[a] = t.v[1][a] - t.v[0][a];
+      e2[a] = t.v[2][a] - t.v[0][a];
+      t.cen[a] = (t.v[0][a] + t.v[1][a] + t.v[2][a]) / 3.0;
+    }
+    const double nx = e1[1] * e2[2] - e1[2] * e2[1], ny = e1[2] * e2[0] - e1[0] * e2[2],
+                 nz = e1[0] * e2[1] - e1[1] * e2[0];
+    if (nx * nx + ny * ny + nz * nz > 0.0) bt.push_back(t);   // degenerate triangles have no face
+  }
+  if (!bt.empty()) {
+    if (!c->groups.empty())
+      return fail(c, ROD_E_UNSUPPORTED, "rods in groups do not collide with the environment");
+    if (c->n_chunks) return fail(c, ROD_E_UNSUPPORTED, "chunked rods do not collide with the environment");
+  }
+  std::vector<corde::EnvNode> nodes;
+  std::vector<corde::EnvTri> out;
+  if (!bt.empty()) build_env_node(bt, 0, (int)bt.size(), (float)(1e-6 * (1.0 + cmax)), nodes, out);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));   // no launch still reads the old mesh
+  for (hipStream_t st : c->bstreams) HIP_TRY(c, hipStreamSynchronize(st));
+  for (void** p : {(void**)&c->d_env_nodes, (void**)&c->d_env_tris}) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+  c->env_nodes = c->env_tris = 0;
+  if (!nodes.empty()) {
+    if (hipMalloc((void**)&c->d_env_nodes, sizeof(corde::EnvNode) * nodes.size()) != hipSuccess ||
+        hipMalloc((void**)&c->d_env_tris, sizeof(corde::EnvTri) * out.size()) != hipSuccess) {
+      for (void** p : {(void**)&c->d_env_nodes, (void**)&c->d_env_tris}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+      }
+      for (auto& d : c->rods) d.env_n_nodes = 0;
+      (void)hipMemcpy(c->d_rods, c->rods.data(), sizeof(RodDev) * c->n_rods, hipMemcpyHostToDevice);
+      (void)rebucket(c);
+      return fail(c, ROD_E_NOMEM, "environment tables");
+    }
+    HIP_TRY(c, hipMemcpy(c->d_env_nodes, nodes.data(), sizeof(corde::EnvNode) * nodes.size(),
+                         hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_env_tris, out.data(), sizeof(corde::EnvTri) * out.size(),
+                         hipMemcpyHostToDevice));
+    c->env_nodes = (int)nodes.size();
+    c->env_tris = (int)out.size();
+  }
+  for (auto& d : c->rods) {
+    d.env_n_nodes = c->env_nodes;
+    d.env_nodes = c->d_env_nodes;
+    d.env_tris = c->d_env_tris;
+    d.env_mu = (float)mu;
+  }
+  HIP_TRY(c, hipMemcpy(c->d_rods, c->rods.data(), sizeof(RodDev) * c->n_rods, hipMemcpyHostToDevice));
+  if (c->env_nodes) c->adj_ready = false;
+  return rebucket(c);   // the rods move to the kernel variant with the collision code
+}
+
+rod_status rod_environment_info(const rod_ctx* c, int32_t* n_nodes, int32_t* n_tris) {
+  if (!c || !n_nodes || !n_tris) return fail(nullptr, ROD_E_INVALID, "null argument");
+  *n_nodes = c->env_nodes;
+  *n_tris = c->env_tris;
+  return ROD_OK;
+}
+
 rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launch, rod_tuning* out) {
   if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
   if (!c->have_state) return fail(c, ROD_E_ORDER, "rod_autotune before rod_set_state");
@@ -1390,7 +1555,7 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
     for (const auto& k : kKernels) {
       const int cap = 64 * k.waves * k.elems;
       if (cap < best.max_n || cap >= 4 * std::max(best.max_n, 64)) continue;
-      if (best.haptic && !k.hfn) continue;
+      if (!k.fn[best.feat]) continue;
       c->buckets[bi].waves = k.waves;
       c->buckets[bi].elems = k.elems;
       float ms_best = INFINITY;
@@ -1418,12 +1583,12 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
         shape_of[c->rod_ids[chosen[bi].first + i]] = chosen[bi].waves * 16 + chosen[bi].elems;
     std::vector<std::pair<int, float>> us_of;
     for (const auto& b : chosen)
-      us_of.push_back({(b.waves * 16 + b.elems) * 2 + b.haptic, b.us_per_step});
+      us_of.push_back({(b.waves * 16 + b.elems) * 4 + b.feat, b.us_per_step});
     st = make_buckets(c, [&](int r, int* w, int* e) { *w = shape_of[r] / 16; *e = shape_of[r] % 16; });
     for (auto& b : c->buckets) {
       b.us_per_step = 0.f;
       for (const auto& u : us_of)
-        if (u.first == (b.waves * 16 + b.elems) * 2 + b.haptic) b.us_per_step += u.second;
+        if (u.first == (b.waves * 16 + b.elems) * 4 + b.feat) b.us_per_step += u.second;
     }
   }
   c->steps_per_launch = steps_per_launch;
@@ -1469,6 +1634,7 @@ rod_status rod_adjoint_forward(rod_ctx* c, int32_t n_steps, int32_t ckpt_every, 
   if (c->n_chunks) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
   if (!c->groups.empty()) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not step grouped rods");
   if (c->n_haptic) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not step rods with a haptic mailbox");
+  if (c->env_nodes) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not step rods against an environment");
   c->adj_ready = false;
   const size_t S = state_floats(c);
   const int ck = std::min(ckpt_every, n_steps);

@@ -79,6 +79,8 @@ _SIGS = {
     "rod_haptic_detach": (C.c_int, [C.c_void_p, C.c_int32]),
     "rod_haptic_set_pose": (C.c_int, [C.c_void_p, C.c_int32, _DP, _DP]),
     "rod_haptic_get_force": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rod_haptic_force)]),
+    "rod_set_environment": (C.c_int, [C.c_void_p, C.c_int32, _DP, C.c_double]),
+    "rod_environment_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "rod_stable_dt": (C.c_int, [C.POINTER(rod_params), _DP]),
     "rod_last_step_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     "rod_set_stiffness_mult": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
@@ -345,6 +347,18 @@ class RodBatch:
         arr = np.ascontiguousarray(np.asarray(sets, dtype=np.int32).reshape(-1, 2))
         _check(lib().rod_set_contact(self.h, int(arr.shape[0]),
                                      arr.ctypes.data_as(C.POINTER(C.c_int32)), float(mu)), self.h)
+
+    def set_environment(self, tris, mu: float):
+        """Static triangle mesh (k, 3, 3) the rods collide with; an empty list removes it."""
+        t = np.ascontiguousarray(np.asarray(tris, dtype=np.float64).reshape(-1, 9))
+        _check(lib().rod_set_environment(self.h, len(t), t.ctypes.data_as(_DP) if len(t) else None,
+                                         float(mu)), self.h)
+
+    def environment_info(self):
+        """(tree nodes, triangles) of the environment."""
+        a, b = C.c_int32(), C.c_int32()
+        _check(lib().rod_environment_info(self.h, C.byref(a), C.byref(b)), self.h)
+        return int(a.value), int(b.value)
 
     def haptic_attach(self, rod: int, steps_per_record: int = 1):
         _check(lib().rod_haptic_attach(self.h, rod, steps_per_record), self.h)

@@ -1,0 +1,175 @@
+"""GPU parity of environment collision (Sec. 2.2 "Collisions": AABB tree broad phase,
+sphere-triangle narrow phase, depth-weighted response normal; contact impulses with Coulomb
+friction) against the FP64 oracle, which checks every triangle by brute force.  Tolerance: the
+method's target, every point within 1e-4 x rod length after the run, or, for runs whose
+contacts (on/off, stick/slip) amplify rounding, 3x how far the oracle's own result moves when
+its state is rounded to FP32 after every step, whichever is larger."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_04277_amd import rod as R
+from paper_2509_04277_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    torch.cuda.init()
+    yield
+
+
+def _tube(n=64):
+    wl, tris = W.config7(n=n)
+    spec, st = wl.rods[0]
+    return spec.replace(dt=R.stable_dt(spec)), st, tris
+
+
+def _gpu(spec, st, n_steps, tris=None, mu=0.0, spl=10, haptic=False):
+    b = R.RodBatch([spec])
+    if tris is not None:
+        b.set_environment(tris, mu)
+    if haptic:
+        b.haptic_attach(0, 5)
+    b.set_state_rods([st])
+    b.step(n_steps, spl)
+    b.sync()
+    out = b.get_state_rods()[0]
+    info = b.environment_info()
+    b.close()
+    return out, info
+
+
+def _fp32_storage_dev(spec, st, n_steps, env):
+    """max |dx| between the oracle's run and the same run with the state rounded to FP32 after
+    every step (FP64 arithmetic otherwise)."""
+    ref, _ = O.rollout_env(spec, st, n_steps, env)
+    r = st.copy()
+    for k in range(n_steps):
+        for a in "xvqw":
+            setattr(r, a, getattr(r, a).astype(np.float32).astype(np.float64))
+        r, _ = O.rollout_env(spec, r, 1, env, t0=k * spec.dt)
+    return float(np.abs(r.x - ref.x).max())
+
+
+def _floor(z=0.0, size=2.0):
+    a, b, c, d = ([-size, -size, z], [size, -size, z], [size, size, z], [-size, size, z])
+    return np.array([[a, b, c], [a, c, d]])
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_rod_in_bent_tube_vs_oracle(mu):
+    spec, st, tris = _tube()
+    n_steps = 1200
+    _say("c7: 64-element rod in a bent tube of %d triangles, mu %.1f, %d steps" % (len(tris), mu, n_steps))
+    (x, v, q, w), info = _gpu(spec, st, n_steps, tris, mu)
+    _say("  tree: %d nodes, %d triangles" % info)
+    assert info[1] == len(tris) and info[0] >= len(tris) // 2
+    env = O.Env(tris, mu)
+    ref, most = O.rollout_env(spec, st, n_steps, env)
+    ex = float(np.abs(x - ref.x).max())
+    tol = max(1e-4, 3 * _fp32_storage_dev(spec, st, n_steps, env))
+    _say("  max|dx| %.2e (tol %.2e), colliding points (oracle, most) %d" % (ex, tol, most))
+    assert most >= 3 and np.isfinite(x).all()
+    assert ex <= tol
+    cen = W.tube_centreline(ds=0.002)
+    off_axis = np.linalg.norm(x[:, None, :] - cen[None, :, :], axis=2).min(axis=1).max()
+    _say("  largest distance from the tube's axis %.4f (tube radius 0.01)" % off_axis)
+    assert off_axis <= 0.01
+
+
+@pytest.mark.parametrize("inext", [True, False])
+def test_rod_falls_onto_a_floor_vs_oracle(inext):
+    """A clamped rod sags onto a floor just below it and slides on it with friction."""
+    spec, st = W.straight_rod(32, L=0.5, radius=0.01, inextensible=inext, dt=1e-5, damp=0.5)
+    spec = spec.replace(dt=R.stable_dt(spec))
+    tris = _floor(z=-0.02)
+    n_steps = 1500
+    (x, v, q, w), _ = _gpu(spec, st, n_steps, tris, 0.4)
+    env = O.Env(tris, 0.4)
+    ref, most = O.rollout_env(spec, st, n_steps, env)
+    ex = float(np.abs(x - ref.x).max())
+    tol = max(1e-4 * 0.5, 3 * _fp32_storage_dev(spec, st, n_steps, env))
+    _say("floor, %s: max|dx| %.2e (tol %.2e), lowest point %.5f (floor + radius %.5f), colliding %d"
+         % ("inextensible" if inext else "extensible", ex, tol, x[1:, 2].min(), -0.02 + 0.01, most))
+    assert most >= 5
+    assert ex <= tol
+    assert x[1:, 2].min() >= -0.02 + 0.01 - 2e-3   # resting on it, not through it
+
+
+def test_out_of_reach_mesh_is_the_plain_step():
+    """A mesh no point reaches: the collision variant steps bitwise as the plain kernel, and a
+    removed mesh gives the plain kernel back."""
+    spec, st, tris = _tube()
+    far = tris + np.array([0.0, 0.0, 50.0])
+    plain, _ = _gpu(spec, st, 200)
+    got, _ = _gpu(spec, st, 200, far, 0.3)
+    for u, v in zip(plain, got):
+        assert np.array_equal(u, v)
+    b = R.RodBatch([spec])
+    b.set_environment(tris, 0.3)
+    b.set_environment([], 0.3)
+    assert b.environment_info() == (0, 0)
+    b.set_state_rods([st])
+    b.step(200, 10)
+    again = b.get_state_rods()[0]
+    b.close()
+    for u, v in zip(plain, again):
+        assert np.array_equal(u, v)
+
+
+def test_mailbox_and_environment_together():
+    """The variant with both the mailbox and the collision code steps bitwise as the collision
+    variant, and its force records stay finite."""
+    spec, st, tris = _tube()
+    a, _ = _gpu(spec, st, 600, tris, 0.3)
+    b = R.RodBatch([spec])
+    b.set_environment(tris, 0.3)
+    b.haptic_attach(0, 5)
+    b.set_state_rods([st])
+    b.step(600, 10)
+    b.sync()
+    f, s, p = b.haptic_get_force(0)
+    got = b.get_state_rods()[0]
+    b.close()
+    assert s == 600 and np.isfinite(f).all()
+    for u, v in zip(a, got):
+        assert np.array_equal(u, v)
+
+
+def test_environment_arguments():
+    spec, st, tris = _tube()
+    other, ost = W.straight_rod(64, inextensible=True, dt=spec.dt)
+    b = R.RodBatch([spec, other])
+    for bad_t, bad_mu in ((tris, -1.0), (tris, float("nan")), (np.full((1, 3, 3), np.nan), 0.1)):
+        with pytest.raises(R.RodError):
+            b.set_environment(bad_t, bad_mu)
+    b.set_environment(tris, 0.2)
+    with pytest.raises(R.RodError):
+        b.set_contact([[1, -1]], 0.1)
+    with pytest.raises(R.RodError):
+        b.set_chunking(32)
+    b.set_state_rods([st, ost])
+    with pytest.raises(R.RodError):
+        b.adjoint_forward(10, 5)
+    b.set_environment([], 0.2)
+    b.set_contact([[1, -1]], 0.1)
+    with pytest.raises(R.RodError):
+        b.set_environment(tris, 0.2)   # grouped rods do not collide with the mesh
+    b.close()
+    # degenerate triangles are dropped
+    b = R.RodBatch([spec])
+    deg = np.concatenate([tris[:10], np.zeros((3, 3, 3))])
+    b.set_environment(deg, 0.0)
+    assert b.environment_info()[1] == 10
+    b.close()
