@@ -310,6 +310,33 @@ def haptic_extras(R, W):
     return out
 
 
+def environment_extras(R, W):
+    """Environment collision on the bent-tube workload with 512 elements (a guidewire in a
+    vessel): us/step without the mesh, with the mesh (3072 triangles) and with a mesh four times
+    finer around; collision detection runs for every point every step, 10 steps per launch."""
+    out = {}
+    for name, n_around in (("plain", 0), ("tube_3072", 12), ("tube_12288", 48)):
+        wl, tris = W.config7(n=512, n_around=max(n_around, 12))
+        spec, st = wl.rods[0]
+        spec = spec.replace(dt=R.stable_dt(spec))
+        b = R.RodBatch([spec])
+        if n_around:
+            b.set_environment(tris, 0.3)
+        b.set_state_rods([st])
+        b.step(500, 10)
+        b.step(5000, 10)
+        b.sync()
+        ms, _ = b.last_step_time()
+        nodes, nt = b.environment_info()
+        b.close()
+        out[name] = {"us_per_step": 1e3 * ms / 5000, "triangles": nt, "tree_nodes": nodes}
+    for name in ("tube_3072", "tube_12288"):
+        out[name]["overhead"] = out[name]["us_per_step"] / out["plain"]["us_per_step"] - 1.0
+    out["workload"] = ("512-element inextensible rod (1 m, r = 2 mm) laid along a bent tube of radius "
+                       "1 cm, clamped at its entrance, 5000 steps after 500 of settling")
+    return out
+
+
 def long_rod_extras(R, W):
     """c2: us/step vs rod length and steps per launch.  Rods up to 2048 elements run in one
     workgroup ("single") and, for comparison, split over several ("chunked"); longer rods are
@@ -350,7 +377,7 @@ def main():
     ap.add_argument("--shape", default="", help="W,E kernel shape (default: autotune)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (4096 rods), long-rod and adjoint measurements")
-    ap.add_argument("--extras", default="batch,long_rod,adjoint,binding,contact,haptic",
+    ap.add_argument("--extras", default="batch,long_rod,adjoint,binding,contact,haptic,environment",
                     help="comma-separated subset of batch,long_rod,adjoint,binding,contact")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -438,7 +465,8 @@ def main():
     }
     if not args.no_extras:
         fns = {"batch": batch_extras, "long_rod": long_rod_extras, "adjoint": adjoint_extras,
-               "binding": binding_extras, "contact": contact_extras, "haptic": haptic_extras}
+               "binding": binding_extras, "contact": contact_extras, "haptic": haptic_extras,
+               "environment": environment_extras}
         out["extras"] = {k: fns[k](R, W) for k in args.extras.split(",") if k}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)

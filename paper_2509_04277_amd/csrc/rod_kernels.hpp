@@ -112,6 +112,8 @@ struct RodDev {
   int32_t env_n_nodes;   // environment tree (0: none)
   const EnvNode* env_nodes;
   const EnvTri* env_tris;
+  float4* env_cache;  // per slot: where its candidate list was built, list length (int bits)
+  int32_t* env_cand;  // per slot: kEnvCand candidate triangles
   const float* rho;   // per slot: sphere radius of point slot + 1
   float env_mu;       // friction coefficient against the environment
   int32_t pad_e;
@@ -313,39 +315,46 @@ __device__ __forceinline__ V3 tri_closest(const EnvTri& t, V3 p) {
   return fma3(vc * den, ac, fma3(vb * den, ab, a));
 }
 
-// Collision response of a sphere (centre c, radius r) against the environment: the
-// depth-weighted mean n of the colliding triangles' normals and the largest depth (0: none).
-// A triangle collides when its nearest point is closer than r; its depth is r - dist with the
-// centre in front of the face, r + dist behind it.
-__device__ __forceinline__ void env_query(const RodDev& rd, V3 c, float r, V3& n, float& depth) {
-  V3 acc = {0.f, 0.f, 0.f};
-  float dmax = 0.f;
-  const float r2 = r * r;
+// Walks the environment's tree for a sphere of centre c and radius reach, calling leaf(k) for
+// every triangle k of every leaf whose box the sphere reaches, in tree order.
+template <class Leaf>
+__device__ __forceinline__ void env_walk(const RodDev& rd, V3 c, float reach, Leaf&& leaf) {
+  const float r2 = reach * reach;
   int i = 0;
   while (i < rd.env_n_nodes) {
     const EnvNode nd = rd.env_nodes[i];
     const float bx = fmaxf(fmaxf(nd.lo[0] - c.x, c.x - nd.hi[0]), 0.f);
     const float by = fmaxf(fmaxf(nd.lo[1] - c.y, c.y - nd.hi[1]), 0.f);
     const float bz = fmaxf(fmaxf(nd.lo[2] - c.z, c.z - nd.hi[2]), 0.f);
-    const bool reach = bx * bx + by * by + bz * bz < r2;
-    if (reach && nd.leaf >= 0) {
+    const bool in = bx * bx + by * by + bz * bz < r2;
+    if (in && nd.leaf >= 0) {
       const int first = nd.leaf >> 3, cnt = nd.leaf & 7;
-      for (int k = 0; k < cnt; ++k) {
-        const EnvTri t = rd.env_tris[first + k];
-        const V3 q = tri_closest(t, c);
-        const V3 d = c - q;
-        const float dist = sqrtf(dot(d, d));
-        if (dist < r) {
-          const V3 nf = {t.n[0], t.n[1], t.n[2]};
-          const V3 ca = {c.x - t.a[0], c.y - t.a[1], c.z - t.a[2]};
-          const float dep = dot(ca, nf) >= 0.f ? r - dist : r + dist;
-          acc = fma3(dep, nf, acc);
-          dmax = fmaxf(dmax, dep);
-        }
-      }
+      for (int k = 0; k < cnt; ++k) leaf(first + k);
     }
-    i = (reach && nd.leaf < 0) ? i + 1 : nd.skip;
+    i = (in && nd.leaf < 0) ? i + 1 : nd.skip;
   }
+}
+
+// Narrow phase of one triangle against a sphere (centre c, radius r): a triangle collides when
+// its nearest point is closer than r; its depth is r - dist with the centre in front of the
+// face, r + dist behind it; acc gathers depth x face normal, dmax the largest depth.  Returns
+// the distance.
+__device__ __forceinline__ float env_hit(const EnvTri& t, V3 c, float r, V3& acc, float& dmax) {
+  const V3 q = tri_closest(t, c);
+  const V3 d = c - q;
+  const float dist = sqrtf(dot(d, d));
+  if (dist < r) {
+    const V3 nf = {t.n[0], t.n[1], t.n[2]};
+    const V3 ca = {c.x - t.a[0], c.y - t.a[1], c.z - t.a[2]};
+    const float dep = dot(ca, nf) >= 0.f ? r - dist : r + dist;
+    acc = fma3(dep, nf, acc);
+    dmax = fmaxf(dmax, dep);
+  }
+  return dist;
+}
+
+// Collision response from the gathered hits: the depth-weighted mean normal, the largest depth.
+__device__ __forceinline__ void env_finish(V3 acc, float dmax, V3& n, float& depth) {
   const float al2 = dot(acc, acc);
   if (dmax > 0.f && al2 > 0.f) {
     n = rsqrtf(al2) * acc;
@@ -355,6 +364,15 @@ __device__ __forceinline__ void env_query(const RodDev& rd, V3 c, float r, V3& n
     depth = 0.f;
   }
 }
+
+// Candidate triangles cached per point: every triangle within (1 + m) r of the point where the
+// list was built, m = kEnvMargin.  While the point stays within m r of that place, the
+// triangles within r of it are all on the list, so the narrow phase runs over the list alone
+// (in tree order, as a walk would visit them); a point that moved farther rebuilds its list
+// with a walk.  A list that overflows makes the point walk the tree every step until its next
+// rebuild.
+constexpr int kEnvCand = 32;
+constexpr float kEnvMargin = 1.0f;
 
 // Registers of one lane of a rod's workgroup: E slots (frame j, point j+1) plus, in lane 0,
 // the base point.  The member functions are the phases of one time step; the forward kernel
@@ -630,13 +648,63 @@ struct RodLane {
     if (g == 0 && h == 0 && !rd.clamp && !ghost) bv = bv + dvb;
   }
 
-  // Environment collision detection from the step-start positions (points 1..n).
-  __device__ __forceinline__ void env_detect(const RodDev& rd) {
+  // Candidate lists of the slots (see kEnvCand): where each was built and its length, in HBM
+  // between launches and in LDS (lc, one float4 per slot) during one.
+  __device__ __forceinline__ void env_load(const RodDev& rd, float4* lc) const {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (ok[e]) lc[j0 + e] = rd.env_cache[rd.slot_off + off + j0 + e];
+  }
+  __device__ __forceinline__ void env_store(const RodDev& rd, const float4* lc) const {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (ok[e]) rd.env_cache[rd.slot_off + off + j0 + e] = lc[j0 + e];
+  }
+
+  // Environment collision detection from the step-start positions (points 1..n).  Each thread
+  // reads and writes only its own slots' entries of lc.
+  __device__ __forceinline__ void env_detect(const RodDev& rd, float4* lc) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       en[e] = {0.f, 0.f, 0.f};
       ed[e] = 0.f;
-      if (ok[e]) env_query(rd, X[e], rd.rho[rd.slot_off + off + j0 + e], en[e], ed[e]);
+      if (!ok[e]) continue;
+      const int slot = rd.slot_off + off + j0 + e;
+      const float r = rd.rho[slot];
+      const V3 c = X[e];
+      int* list = rd.env_cand + (size_t)slot * kEnvCand;
+      V3 acc = {0.f, 0.f, 0.f};
+      float dmax = 0.f;
+      const float4 cp = lc[j0 + e];
+      const int have = __float_as_int(cp.w);
+      const V3 moved = c - V3{cp.x, cp.y, cp.z};
+      if (dot(moved, moved) > (kEnvMargin * r) * (kEnvMargin * r)) {   // rebuild the list here
+        const float reach = (1.f + kEnvMargin) * r;
+        int cnt = 0;
+        env_walk(rd, c, reach, [&](int k) {
+          if (env_hit(rd.env_tris[k], c, r, acc, dmax) < reach) {
+            if (cnt < kEnvCand) list[cnt] = k;
+            ++cnt;
+          }
+        });
+        lc[j0 + e] = make_float4(c.x, c.y, c.z, __int_as_float(cnt));
+      } else if (have <= kEnvCand) {
+        // four candidates at a time: one load of their indices, then their triangles together
+        for (int k0 = 0; k0 < have; k0 += 4) {
+          const int4 ix = *reinterpret_cast<const int4*>(list + k0);
+          const int id[4] = {ix.x, ix.y, ix.z, ix.w};
+          EnvTri t[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (k0 + u < have) t[u] = rd.env_tris[id[u]];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (k0 + u < have) env_hit(t[u], c, r, acc, dmax);
+        }
+      } else {
+        env_walk(rd, c, r, [&](int k) { env_hit(rd.env_tris[k], c, r, acc, dmax); });
+      }
+      env_finish(acc, dmax, en[e], ed[e]);
     }
   }
 
@@ -736,6 +804,8 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
   RodLane<W, E> L;
   L.load_params(rd, prm, prm_stride);
   L.load_state(rd, gx, gv, gq, gw);
+  __shared__ float4 lcand[(F & kFeatEnv) ? 64 * W * E : 1];
+  if (F & kFeatEnv) L.env_load(rd, lcand);
   int par = 0;
   V3 xc = {rd.cx0[0], rd.cx0[1], rd.cx0[2]}, wc = {0.f, 0.f, 0.f};
   Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
@@ -756,7 +826,7 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
       float* base = traj + (long long)s * traj_stride;
       L.store_state(rd, base, base + 3 * n_pts, base + 6 * n_pts, base + 6 * n_pts + 4 * n_frames);
     }
-    if (F & kFeatEnv) L.env_detect(rd);   // environment collisions (Fig. 5: detection first)
+    if (F & kFeatEnv) L.env_detect(rd, lcand);   // environment collisions (Fig. 5: detection first)
     V3 xl;
     Q4 qn;
     L.exchange_a(mb, par, xl, qn);
@@ -813,6 +883,7 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
         }
     }
   }
+  if (F & kFeatEnv) L.env_store(rd, lcand);
   if (store_final) {
     const float chk = L.store_state(rd, gx, gv, gq, gw);
     if (!__builtin_isfinite(chk)) atomicOr(status, 1);

@@ -162,6 +162,8 @@ struct rod_ctx {
   // environment mesh (rod_set_environment): AABB tree and triangles on the device
   corde::EnvNode* d_env_nodes = nullptr;
   corde::EnvTri* d_env_tris = nullptr;
+  float4* d_env_cache = nullptr;   // per slot: candidate-list position and length
+  int32_t* d_env_cand = nullptr;   // per slot: candidate triangles
   int env_nodes = 0, env_tris = 0;
   // adjoint rollout (rod_adjoint_forward / rod_adjoint_backward)
   bool adj_ready = false;
@@ -1035,7 +1037,8 @@ rod_status rod_destroy(rod_ctx* c) {
                   (void*)c->d_tips, (void*)c->d_dtips, (void*)c->d_adj,
                   (void*)c->d_gacc, (void*)c->d_groups, (void*)c->d_partner, (void*)c->d_rho,
                   (void*)c->d_chunks, (void*)c->d_block_chunk, (void*)c->d_pub,
-                  (void*)c->d_flags, (void*)c->d_env_nodes, (void*)c->d_env_tris})
+                  (void*)c->d_flags, (void*)c->d_env_nodes, (void*)c->d_env_tris,
+                  (void*)c->d_env_cache, (void*)c->d_env_cand})
     if (p) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -1482,18 +1485,23 @@ rod_status rod_set_environment(rod_ctx* c, int32_t n_tris, const double* tris, d
   if (!bt.empty()) build_env_node(bt, 0, (int)bt.size(), (float)(1e-6 * (1.0 + cmax)), nodes, out);
   HIP_TRY(c, hipStreamSynchronize(c->stream));   // no launch still reads the old mesh
   for (hipStream_t st : c->bstreams) HIP_TRY(c, hipStreamSynchronize(st));
-  for (void** p : {(void**)&c->d_env_nodes, (void**)&c->d_env_tris}) {
-    if (*p) (void)hipFree(*p);
-    *p = nullptr;
-  }
+  auto free_env = [&]() {
+    for (void** p : {(void**)&c->d_env_nodes, (void**)&c->d_env_tris, (void**)&c->d_env_cache,
+                     (void**)&c->d_env_cand}) {
+      if (*p) (void)hipFree(*p);
+      *p = nullptr;
+    }
+  };
+  free_env();
   c->env_nodes = c->env_tris = 0;
+  size_t slots = 0;
+  for (int r = 0; r < c->n_rods; ++r) slots += (size_t)c->n[r];
   if (!nodes.empty()) {
     if (hipMalloc((void**)&c->d_env_nodes, sizeof(corde::EnvNode) * nodes.size()) != hipSuccess ||
-        hipMalloc((void**)&c->d_env_tris, sizeof(corde::EnvTri) * out.size()) != hipSuccess) {
-      for (void** p : {(void**)&c->d_env_nodes, (void**)&c->d_env_tris}) {
-        if (*p) (void)hipFree(*p);
-        *p = nullptr;
-      }
+        hipMalloc((void**)&c->d_env_tris, sizeof(corde::EnvTri) * out.size()) != hipSuccess ||
+        hipMalloc((void**)&c->d_env_cache, sizeof(float4) * slots) != hipSuccess ||
+        hipMalloc((void**)&c->d_env_cand, sizeof(int32_t) * slots * corde::kEnvCand) != hipSuccess) {
+      free_env();
       for (auto& d : c->rods) d.env_n_nodes = 0;
       (void)hipMemcpy(c->d_rods, c->rods.data(), sizeof(RodDev) * c->n_rods, hipMemcpyHostToDevice);
       (void)rebucket(c);
@@ -1503,6 +1511,9 @@ rod_status rod_set_environment(rod_ctx* c, int32_t n_tris, const double* tris, d
                          hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->d_env_tris, out.data(), sizeof(corde::EnvTri) * out.size(),
                          hipMemcpyHostToDevice));
+    // no candidate list yet: every point builds one at its first step
+    const std::vector<float4> far(slots, make_float4(1e30f, 1e30f, 1e30f, 0.f));
+    HIP_TRY(c, hipMemcpy(c->d_env_cache, far.data(), sizeof(float4) * slots, hipMemcpyHostToDevice));
     c->env_nodes = (int)nodes.size();
     c->env_tris = (int)out.size();
   }
@@ -1510,6 +1521,8 @@ rod_status rod_set_environment(rod_ctx* c, int32_t n_tris, const double* tris, d
     d.env_n_nodes = c->env_nodes;
     d.env_nodes = c->d_env_nodes;
     d.env_tris = c->d_env_tris;
+    d.env_cache = c->d_env_cache;
+    d.env_cand = c->d_env_cand;
     d.env_mu = (float)mu;
   }
   HIP_TRY(c, hipMemcpy(c->d_rods, c->rods.data(), sizeof(RodDev) * c->n_rods, hipMemcpyHostToDevice));
