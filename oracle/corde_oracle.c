@@ -314,6 +314,98 @@ void oracle_forces(const oracle_rod* rod, const double* x, const double* q, doub
     free(gq);
 }
 
+/* ---------------------------------------------------------------- internal friction -- */
+
+/* time derivative of the stretch s_j = |x_{j+1} - x_j| / l_j - 1 of element j */
+static double stretch_rate(const oracle_rod* rod, int j, const double* x, const double* v,
+                           double* t) {
+    double d[3], dv[3];
+    for (int c = 0; c < 3; ++c) {
+        d[c] = x[3 * (j + 1) + c] - x[3 * j + c];
+        dv[c] = v[3 * (j + 1) + c] - v[3 * j + c];
+    }
+    const double len = norm3(d);
+    for (int c = 0; c < 3; ++c) t[c] = d[c] / len;
+    return dot3(t, dv) / rod->seg_len[j];
+}
+
+/* d/dt of the Darboux vector of joint j, eq. (6): u_k = (2/lbar) (B_k q_j) . q_{j+1} with
+ * dq/dt = 1/2 q (x) (0, omega); also its coefficients a[k][b] = d udot_k / d omega_j,b and
+ * bb[k][b] = d udot_k / d omega_{j+1},b */
+static void darboux_rate(const oracle_rod* rod, const double* q, const double* w, int j,
+                         double* ud, double a[3][3], double bb[3][3]) {
+    joint_t jt;
+    joint(rod, j, &jt);
+    const double* qj = q + 4 * j;
+    const double* qn = q + 4 * (j + 1);
+    for (int k = 0; k < 3; ++k) {
+        double Bqj[4];
+        bmul(k, qj, Bqj);
+        ud[k] = 0.0;
+        for (int b = 0; b < 3; ++b) {
+            const double eb[4] = {0.0, b == 0, b == 1, b == 2};
+            double qe[4], Bqe[4], ne[4];
+            oracle_qmul(qj, eb, qe);          /* q_j (x) e_b */
+            bmul(k, qe, Bqe);
+            oracle_qmul(qn, eb, ne);          /* q_{j+1} (x) e_b */
+            a[k][b] = dot4(Bqe, qn) / jt.lbar;   /* (2/lbar) (B_k (1/2 q_j (x) e_b)) . q_{j+1} */
+            bb[k][b] = dot4(Bqj, ne) / jt.lbar;  /* (2/lbar) (B_k q_j) . (1/2 q_{j+1} (x) e_b) */
+            ud[k] += a[k][b] * w[3 * j + b] + bb[k][b] * w[3 * (j + 1) + b];
+        }
+    }
+}
+
+double oracle_dissipation(const oracle_rod* rod, const double* x, const double* q,
+                          const double* v, const double* w) {
+    const double td = rod->damp_int;
+    double D = 0.0;
+    for (int j = 0; j < rod->n; ++j) {
+        if (rod->inextensible) break;
+        elem_t e;
+        element(rod, j, &e);
+        double t[3];
+        const double sd = stretch_rate(rod, j, x, v, t);
+        D += 0.5 * td * e.Ks * e.l * sd * sd;                 /* eq. (2) at the strain rate */
+    }
+    for (int j = 0; j + 1 < rod->n; ++j) {
+        joint_t jt;
+        joint(rod, j, &jt);
+        double ud[3], a[3][3], bb[3][3];
+        darboux_rate(rod, q, w, j, ud, a, bb);
+        for (int k = 0; k < 3; ++k) D += 0.5 * td * jt.K[k] * ud[k] * ud[k] * jt.lbar;   /* eq. (3) */
+    }
+    return D;
+}
+
+void oracle_damping_forces(const oracle_rod* rod, const double* x, const double* q,
+                           const double* v, const double* w, double* F, double* tau) {
+    const double td = rod->damp_int;
+    if (!(td > 0.0)) return;
+    for (int j = 0; j < rod->n && !rod->inextensible; ++j) {
+        elem_t e;
+        element(rod, j, &e);
+        double t[3];
+        const double sd = stretch_rate(rod, j, x, v, t);
+        /* -dD/dv: D_j = 1/2 td Ks l sd^2, d sd / d v_{j+1} = t / l */
+        for (int c = 0; c < 3; ++c) {
+            F[3 * (j + 1) + c] -= td * e.Ks * sd * t[c];
+            F[3 * j + c] += td * e.Ks * sd * t[c];
+        }
+    }
+    for (int j = 0; j + 1 < rod->n; ++j) {
+        joint_t jt;
+        joint(rod, j, &jt);
+        double ud[3], a[3][3], bb[3][3];
+        darboux_rate(rod, q, w, j, ud, a, bb);
+        for (int b = 0; b < 3; ++b)
+            for (int k = 0; k < 3; ++k) {
+                const double g = td * jt.K[k] * ud[k] * jt.lbar;   /* dD / d udot_k */
+                tau[3 * j + b] -= g * a[k][b];
+                tau[3 * (j + 1) + b] -= g * bb[k][b];
+            }
+    }
+}
+
 /* -------------------------------------------------------------------------- clamp -- */
 
 void oracle_clamp_pose(const oracle_rod* rod, double t, double* xc, double* qc, double* wc) {
@@ -381,8 +473,10 @@ static void step_first(const oracle_rod* rod, double t, const double* x, double*
     sc->winv = (double*)malloc(sizeof(double) * (n + 1));
     double* winv = sc->winv;
 
-    /* forces and torques from the start-of-step configuration */
+    /* forces and torques from the start-of-step configuration, internal friction from the
+     * start-of-step velocities */
     oracle_forces(rod, x, q, F, tau);
+    oracle_damping_forces(rod, x, q, v, w, F, tau);
     {   /* internal force on point 0: without its weight and external load */
         const double M0 = point_mass(rod, 0);
         for (int c = 0; c < 3; ++c)
@@ -902,13 +996,26 @@ double oracle_dt_rule(const oracle_rod* rod) {
         int nm = 0;
         /* one-element mode frequencies of a uniform chain: 2 sqrt(k / m) for the
          * alternating translational modes, sqrt(k_rot / I) for the rotational ones */
-        if (!rod->inextensible) om[nm++] = 2.0 * sqrt(e.Ks / e.l / e.m);
+        int damped[5];
+        if (!rod->inextensible) {
+            damped[nm] = 1;
+            om[nm++] = 2.0 * sqrt(e.Ks / e.l / e.m);
+        }
+        damped[nm] = 0;
         om[nm++] = 2.0 * sqrt(e.Kp / e.l / e.m);
+        damped[nm] = 0;
         om[nm++] = sqrt(e.l * e.Kp / e.I1);
+        damped[nm] = 1;
         om[nm++] = sqrt(4.0 * e.K1 / (e.l * e.I1));
+        damped[nm] = 1;
         om[nm++] = sqrt(4.0 * e.K3 / (e.l * e.I3));
         for (int k = 0; k < nm; ++k) {
             double dt = 2.0 / om[k];
+            /* a Kelvin-Voigt damper on the mode decays at tau_d om^2: explicit in dt too */
+            if (damped[k] && rod->damp_int > 0.0) {
+                const double dd = 2.0 / (rod->damp_int * om[k] * om[k]);
+                if (dd < dt) dt = dd;
+            }
             if (dt < best) best = dt;
         }
     }

@@ -67,6 +67,10 @@ typedef struct oracle_rod {
     double clamp_freq;
     double clamp_phase_x;
     double clamp_phase_twist;
+    /* internal friction (Kelvin-Voigt): retardation time tau_d [s], 0 = none; the dissipation
+     * function is the elastic energy's quadratic form at the strain rates (see
+     * oracle_dissipation) */
+    double damp_int;
 } oracle_rod;
 
 /* 0 if the description is usable, else a negative code. */
@@ -83,6 +87,17 @@ double oracle_kinetic(const oracle_rod* rod, const double* v, const double* w);
  * torques tau_a = -1/2 (dV/dq) . (B_a q) on every frame (without tau_ext). */
 void oracle_forces(const oracle_rod* rod, const double* x, const double* q,
                    double* F, double* tau);
+
+/* Internal friction (the CoRdE dissipation terms, translational and angular), read as
+ * Kelvin-Voigt: the Rayleigh dissipation function is the elastic energy's quadratic form at the
+ * strain rates, D = sum_j 1/2 tau_d K_s l_j sdot_j^2 (extensible variant; s_j = |e_j|/l_j - 1)
+ * + sum_joints 1/2 tau_d lbar sum_k K_k udot_k^2, udot the time derivative of eq. (6) under
+ * dq/dt = 1/2 q (x) (0, omega).  oracle_damping_forces adds F = -dD/dv and body torques
+ * tau = -dD/domega to F and tau (nothing if damp_int = 0). */
+double oracle_dissipation(const oracle_rod* rod, const double* x, const double* q,
+                          const double* v, const double* w);
+void oracle_damping_forces(const oracle_rod* rod, const double* x, const double* q,
+                           const double* v, const double* w, double* F, double* tau);
 
 /* Discrete Darboux vector of joint j, eq. (6): u_k = (2 / lbar_j) (B_k q_j) . q_{j+1}. */
 void oracle_darboux(const oracle_rod* rod, const double* q, int32_t j, double* u);

@@ -43,6 +43,7 @@ class _Rod(C.Structure):
         ("clamp_amp", C.c_double * 3), ("clamp_twist_amp", C.c_double),
         ("clamp_twist_axis", C.c_double * 3), ("clamp_freq", C.c_double),
         ("clamp_phase_x", C.c_double), ("clamp_phase_twist", C.c_double),
+        ("damp_int", C.c_double),
     ]
 
 
@@ -99,6 +100,10 @@ def lib():
         L.oracle_rollout_pair.restype = None
         L.oracle_rollout_pair.argtypes = [C.POINTER(_Rod), C.POINTER(_Rod), C.POINTER(_Binding),
                                           C.c_double, C.c_int32] + [_DP] * 8
+        L.oracle_dissipation.restype = C.c_double
+        L.oracle_dissipation.argtypes = [C.POINTER(_Rod), _DP, _DP, _DP, _DP]
+        L.oracle_damping_forces.restype = None
+        L.oracle_damping_forces.argtypes = [C.POINTER(_Rod), _DP, _DP, _DP, _DP, _DP, _DP]
         L.oracle_closest_point_triangle.restype = None
         L.oracle_closest_point_triangle.argtypes = [_DP, _DP, _DP]
         L.oracle_env_response.restype = None
@@ -216,6 +221,7 @@ class Rod:
         r.clamp_freq = float(spec.clamp_freq)
         r.clamp_phase_x = float(spec.clamp_phase_x)
         r.clamp_phase_twist = float(spec.clamp_phase_twist)
+        r.damp_int = float(spec.damp_int)
         self.c = r
         rc = lib().oracle_check(C.byref(r))
         if rc != 0:
@@ -239,6 +245,19 @@ class Rod:
         F = np.zeros((self.n + 1, 3))
         tau = np.zeros((self.n, 3))
         lib().oracle_forces(C.byref(self.c), _p(x), _p(q), _p(F), _p(tau))
+        return F, tau
+
+    def dissipation(self, x, q, v, w):
+        x, q = _f64(x, (self.n + 1, 3)), _f64(q, (self.n, 4))
+        v, w = _f64(v, (self.n + 1, 3)), _f64(w, (self.n, 3))
+        return lib().oracle_dissipation(C.byref(self.c), _p(x), _p(q), _p(v), _p(w))
+
+    def damping_forces(self, x, q, v, w):
+        x, q = _f64(x, (self.n + 1, 3)), _f64(q, (self.n, 4))
+        v, w = _f64(v, (self.n + 1, 3)), _f64(w, (self.n, 3))
+        F = np.zeros((self.n + 1, 3))
+        tau = np.zeros((self.n, 3))
+        lib().oracle_damping_forces(C.byref(self.c), _p(x), _p(q), _p(v), _p(w), _p(F), _p(tau))
         return F, tau
 
     def darboux(self, q, j):

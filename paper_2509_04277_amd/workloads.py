@@ -68,6 +68,7 @@ class RodSpec:
     clamp_freq: float = 0.0
     clamp_phase_x: float = 0.0
     clamp_phase_twist: float = 0.0
+    damp_int: float = 0.0   # internal friction: Kelvin-Voigt retardation time [s]
 
     def replace(self, **kw) -> "RodSpec":
         return dataclasses.replace(self, **kw)
