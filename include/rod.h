@@ -86,6 +86,16 @@ typedef struct rod_params {
     double clamp_freq;
     double clamp_phase_x;
     double clamp_phase_twist;
+    /* Internal friction (Sec. 2.1: the CoRdE dissipation terms damping relative motion,
+     * translational and angular), Kelvin-Voigt: retardation time tau_d [s] >= 0.  Element j's
+     * stretch force uses (len - l) + tau_d d(len)/dt (extensible variant), joint k's bend/twist
+     * moment K (u - u_hat + tau_d du/dt); du/dt follows from the frames' angular velocities.
+     * 0 = none.  rod_stable_dt also keeps tau_d omega^2 dt <= 2 on the damped modes.  Rods
+     * with internal friction step in a variant of the one-rod-per-workgroup kernel only:
+     * rod_create refuses them above the chunking threshold, rod_set_bindings and
+     * rod_set_contact refuse to group them, rod_set_environment refuses handles holding them,
+     * and the adjoint refuses them (ROD_E_UNSUPPORTED). */
+    double damping_int;
 } rod_params;
 
 typedef struct rod_ctx rod_ctx;

@@ -116,12 +116,13 @@ struct RodDev {
   int32_t* env_cand;  // per slot: kEnvCand candidate triangles
   const float* rho;   // per slot: sphere radius of point slot + 1
   float env_mu;       // friction coefficient against the environment
-  int32_t pad_e;
+  float damp_int;     // internal friction: Kelvin-Voigt retardation time tau_d [s] (0: none)
 };
 
 // Kernel feature bits of rod_resident_kernel's variants.
 constexpr int kFeatHaptic = 1;
 constexpr int kFeatEnv = 2;
+constexpr int kFeatDamp = 4;   // internal friction
 
 struct V3 {
   float x, y, z;
@@ -497,23 +498,54 @@ struct RodLane {
 
   // A: x of each slot's left point (from the lane below; the base point for lane 0) and q of
   // the right frame (from the lane above).
+  // Exchange A: the left neighbour point's position and the next frame's quaternion; with
+  // internal friction (D) also that point's velocity vl and that frame's angular velocity wn.
+  template <bool D>
+  __device__ __forceinline__ void exchange_a(Mailbox<W>& mb, int& par, V3& xl, Q4& qn, V3& vl,
+                                             V3& wn) const {
+    if constexpr (D) {
+      float mh[6] = {X[E - 1].x, X[E - 1].y, X[E - 1].z, Vv[E - 1].x, Vv[E - 1].y, Vv[E - 1].z};
+      float ml[7] = {Qf[0].w, Qf[0].x, Qf[0].y, Qf[0].z, Om[0].x, Om[0].y, Om[0].z};
+      float lo[6], hi[7];
+      exchange<W, E, 6, 7>(mh, lo, ml, hi, mb, par);
+      xl = {lo[0], lo[1], lo[2]};
+      vl = {lo[3], lo[4], lo[5]};
+      if (g == 0) {
+        xl = bx;
+        vl = bv;
+      }
+      qn = {hi[0], hi[1], hi[2], hi[3]};
+      wn = {hi[4], hi[5], hi[6]};
+    } else {
+      float mh[3] = {X[E - 1].x, X[E - 1].y, X[E - 1].z};
+      float ml[4] = {Qf[0].w, Qf[0].x, Qf[0].y, Qf[0].z};
+      float lo[3], hi[4];
+      exchange<W, E, 3, 4>(mh, lo, ml, hi, mb, par);
+      xl = {lo[0], lo[1], lo[2]};
+      if (g == 0) xl = bx;
+      qn = {hi[0], hi[1], hi[2], hi[3]};
+      vl = {0.f, 0.f, 0.f};
+      wn = {0.f, 0.f, 0.f};
+    }
+  }
   __device__ __forceinline__ void exchange_a(Mailbox<W>& mb, int& par, V3& xl, Q4& qn) const {
-    float mh[3] = {X[E - 1].x, X[E - 1].y, X[E - 1].z};
-    float ml[4] = {Qf[0].w, Qf[0].x, Qf[0].y, Qf[0].z};
-    float lo[3], hi[4];
-    exchange<W, E, 3, 4>(mh, lo, ml, hi, mb, par);
-    xl = {lo[0], lo[1], lo[2]};
-    if (g == 0) xl = bx;
-    qn = {hi[0], hi[1], hi[2], hi[3]};
+    V3 vl, wn;
+    exchange_a<false>(mb, par, xl, qn, vl, wn);
   }
 
   // F: segment forces (stretch eq. (2), penalty eq. (8)) and joint torques (eq. (3) with the
   // discrete Darboux vector of eqs. (5)-(6)), accumulated per slot; then exchange B.
   // F[e]: force on point j+1; T[e]: body torque on frame j; Ev[e]: segment vector e_j;
   // fs0: force of the lane's first segment on its left point (negated); enext: e_{j+1} of the
-  // last slot.
+  // last slot.  With internal friction (D, Kelvin-Voigt, retardation time td), a segment's stretch uses
+  // (len - l) + td d(len)/dt and a joint's moment K (u - uhat + td du/dt), where
+  // du/dt = (rw (w_{j+1} - w_j) + rv x (w_{j+1} + w_j)) / lbar for the relative rotation
+  // r = conj(q_j) q_{j+1}; vl and wn are the exchanged neighbour velocities.
+  template <bool D = false>
   __device__ __forceinline__ void forces(Mailbox<W>& mb, int& par, V3 xl, Q4 qn, V3 (&F)[E],
-                                         V3 (&T)[E], V3 (&Ev)[E], V3& fs0, V3& enext) const {
+                                         V3 (&T)[E], V3 (&Ev)[E], V3& fs0, V3& enext,
+                                         float td = 0.f, V3 vl = {0.f, 0.f, 0.f},
+                                         V3 wn = {0.f, 0.f, 0.f}) const {
     V3 tn_prev = {0.f, 0.f, 0.f};
     fs0 = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -535,7 +567,9 @@ struct RodLane {
       const float td3 = dot(t, d3);
       V3 f = (lkp * il) * fnma3(td3, t, d3);                     // penalty, eq. (8)
       const float len = len2 * il;
-      f = fnma3(P[P_KS_L][e] * (len - P[P_LEN][e]), t, f);       // stretch, eq. (2)
+      float sd = len - P[P_LEN][e];
+      if constexpr (D) sd = fmaf(td, dot(t, Vv[e] - ((e == 0) ? vl : Vv[e - 1])), sd);
+      f = fnma3(P[P_KS_L][e] * sd, t, f);                         // stretch, eq. (2)
       f = sel(ok[e], f, V3{0.f, 0.f, 0.f});                      // force on point j+1
       const V3 tpen = {-lkp * dot(d2, t), lkp * dot(d1, t), 0.f};  // l K_p e_3 x R^T t
       const Q4 qb = (e == E - 1) ? qn : Qf[e + 1];
@@ -545,8 +579,16 @@ struct RodLane {
       const V3 rv = {q.w * dv.x - dq.w * va.x - (va.y * dv.z - va.z * dv.y),
                      q.w * dv.y - dq.w * va.y - (va.z * dv.x - va.x * dv.z),
                      q.w * dv.z - dq.w * va.z - (va.x * dv.y - va.y * dv.x)};  // vec(conj(q_j) (x) q_{j+1})
-      const V3 m = {P[P_C1][e] * rv.x - P[P_D0][e], P[P_C1][e] * rv.y - P[P_D1][e],
-                    P[P_C3][e] * rv.z - P[P_D2][e]};             // K (u - uhat)
+      V3 m = {P[P_C1][e] * rv.x - P[P_D0][e], P[P_C1][e] * rv.y - P[P_D1][e],
+              P[P_C3][e] * rv.z - P[P_D2][e]};                   // K (u - uhat)
+      if constexpr (D) {   // + td K du/dt (P_C = 2 K / lbar)
+        const V3 wj = Om[e];
+        const V3 wb = (e == E - 1) ? wn : Om[e + 1];
+        const V3 gs = fma3(rw, wb - wj, cross(rv, wb + wj));   // lbar du/dt
+        const float h = 0.5f * td;
+        m = {fmaf(h * P[P_C1][e], gs.x, m.x), fmaf(h * P[P_C1][e], gs.y, m.y),
+             fmaf(h * P[P_C3][e], gs.z, m.z)};
+      }
       const V3 rxm = cross(rv, m);
       const V3 tj = sel(ok[e], fma3(rw, m, rxm), V3{0.f, 0.f, 0.f});   // on frame j
       const V3 tn = sel(ok[e], fnma3(rw, m, rxm), V3{0.f, 0.f, 0.f});  // on frame j+1
@@ -827,11 +869,11 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
       L.store_state(rd, base, base + 3 * n_pts, base + 6 * n_pts, base + 6 * n_pts + 4 * n_frames);
     }
     if (F & kFeatEnv) L.env_detect(rd, lcand);   // environment collisions (Fig. 5: detection first)
-    V3 xl;
+    V3 xl, vl, wn;
     Q4 qn;
-    L.exchange_a(mb, par, xl, qn);
+    L.template exchange_a<(F & kFeatDamp) != 0>(mb, par, xl, qn, vl, wn);
     V3 Fo[E], T[E], Ev[E], fs0, enext;
-    L.forces(mb, par, xl, qn, Fo, T, Ev, fs0, enext);
+    L.template forces<(F & kFeatDamp) != 0>(mb, par, xl, qn, Fo, T, Ev, fs0, enext, rd.damp_int, vl, wn);
     clamp_for_step<W>(rd, cbuf, s, n_steps, steps_done, xc, qc, wc, rd.driven && rd.clamp, L.g);
     const bool hfirst = hb && hn == 0;
     if (hfirst && L.g < 64) {   // wave 0, all lanes: take the pose if whole and new

@@ -56,15 +56,16 @@ const AdjointEntry kAdjoints[] = {
 
 struct KernelEntry {
   int waves, elems;
-  KernelFn fn[4];   // by feature bits (kFeatHaptic, kFeatEnv); the variants exist for the
-                    // default shapes only
+  KernelFn fn[8];   // by feature bits (kFeatHaptic, kFeatEnv, kFeatDamp); the variants exist
+                    // for the default shapes only, without environment + internal friction
 };
 
 // Built kernel shapes: (waves per rod, elements per lane).  Capacity = 64 * waves * elems.
-#define ROD_SHAPE(w, e) {w, e, {corde::rod_resident_kernel<w, e, 0>, nullptr, nullptr, nullptr}}
+#define ROD_SHAPE(w, e) {w, e, {corde::rod_resident_kernel<w, e, 0>}}
 #define ROD_SHAPE_F(w, e)                                                                   \
   {w, e, {corde::rod_resident_kernel<w, e, 0>, corde::rod_resident_kernel<w, e, 1>,       \
-          corde::rod_resident_kernel<w, e, 2>, corde::rod_resident_kernel<w, e, 3>}}
+          corde::rod_resident_kernel<w, e, 2>, corde::rod_resident_kernel<w, e, 3>,       \
+          corde::rod_resident_kernel<w, e, 4>, corde::rod_resident_kernel<w, e, 5>}}
 const KernelEntry kKernels[] = {
     ROD_SHAPE_F(1, 1), ROD_SHAPE_F(1, 2), ROD_SHAPE(1, 4),    ROD_SHAPE(1, 8),
     ROD_SHAPE(2, 1),   ROD_SHAPE_F(2, 2), ROD_SHAPE(2, 4),    ROD_SHAPE(4, 1),
@@ -211,7 +212,8 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 // Kernel feature bits rod r needs (a mailbox, the environment).
 int rod_features(const rod_ctx* c, int r) {
-  return (c->haptic[r].host ? corde::kFeatHaptic : 0) | (c->env_nodes ? corde::kFeatEnv : 0);
+  return (c->haptic[r].host ? corde::kFeatHaptic : 0) | (c->env_nodes ? corde::kFeatEnv : 0) |
+         (c->rods[r].damp_int > 0.f ? corde::kFeatDamp : 0);
 }
 
 // Validates one rod description; returns "" or a message.
@@ -233,7 +235,7 @@ std::string check_params(const rod_params& p, int idx) {
       !(std::isfinite(p.twist_scale) && p.twist_scale >= 0))
     return bad("stiffness scales must be finite and >= 0");
   if (!(std::isfinite(p.damping_lin) && p.damping_lin >= 0 && std::isfinite(p.damping_ang) &&
-        p.damping_ang >= 0))
+        p.damping_ang >= 0 && std::isfinite(p.damping_int) && p.damping_int >= 0))
     return bad("damping must be finite and >= 0");
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(p.gravity[k])) return bad("gravity must be finite");
@@ -336,6 +338,7 @@ RodDev make_dev(const rod_params& p, int slot_off, int pt_off, int fr_off, doubl
   d.fr_off = fr_off;
   d.n_iter = p.inextensible ? p.n_constraint_iters : 0;
   d.clamp = p.clamp_end0;
+  d.damp_int = (float)p.damping_int;
   {  // contact: points closer than 2 r_max along the rod (in elements of l_min) never touch
     double rmax = 0.0, lmin = INFINITY;
     for (int j = 0; j < p.n_elements; ++j) {
@@ -409,7 +412,7 @@ rod_status make_buckets(rod_ctx* c, ShapeFn shape) {
     // within a bucket, most work first (a constraint iteration costs about a quarter of the
     // rest of a step), so the last workgroups dispatched are the cheap ones
     const long long cost = (long long)c->n[r] * (4 + c->rods[r].n_iter);
-    key.push_back({((long long)((w * 16 + e) * 4 + h) << 32) | (0x7fffffffLL - cost), r});
+    key.push_back({((long long)((w * 16 + e) * 8 + h) << 32) | (0x7fffffffLL - cost), r});
   }
   std::sort(key.begin(), key.end());
   c->buckets.clear();
@@ -526,6 +529,8 @@ rod_status setup_long_rods(rod_ctx* c) {
   for (int r = 0; r < c->n_rods; ++r) {
     const int n = c->n[r];
     if (n <= c->chunk_above) continue;
+    if (c->rods[r].damp_int > 0.f)
+      return fail(c, ROD_E_UNSUPPORTED, "rods with internal friction cannot be chunked");
     c->long_rods.push_back(r);
     int H = 2 * c->rods[r].n_iter + 4;
     H += H & 1;
@@ -678,6 +683,9 @@ rod_status rebuild_groups(rod_ctx* c) {
   }
   if (!gs.empty() && c->env_nodes)
     return fail(c, ROD_E_UNSUPPORTED, "rods in groups do not collide with the environment");
+  for (const auto& g : gs)
+    if (c->rods[g.rod[0]].damp_int > 0.f || (g.rod[1] >= 0 && c->rods[g.rod[1]].damp_int > 0.f))
+      return fail(c, ROD_E_UNSUPPORTED, "rods with internal friction cannot be grouped");
   for (const auto& g : gs) {
     if (c->haptic[g.rod[0]].host || (g.rod[1] >= 0 && c->haptic[g.rod[1]].host))
       return fail(c, ROD_E_UNSUPPORTED, "a rod with a haptic mailbox cannot be grouped");
@@ -912,15 +920,28 @@ rod_status rod_stable_dt(const rod_params* p, double* dt_out) {
     const Elem e = element(*p, j);
     // one-element modes: alternating translation 2 sqrt(k/m) with k = K/l, rotation
     // sqrt(k_rot / I) with k_rot = l K_p (penalty), 4 K_1 / l (bend), 4 K_3 / l (twist)
+    // (the stretch, bend and twist modes carry the internal-friction dashpot: its decay rate
+    // tau_d w^2 must stay below 2 / dt as well)
     double w[5];
+    bool dashpot[5];
     int nw = 0;
-    if (!p->inextensible) w[nw++] = 2.0 * std::sqrt(e.Ks / (e.l * e.m));
+    if (!p->inextensible) {
+      dashpot[nw] = true;
+      w[nw++] = 2.0 * std::sqrt(e.Ks / (e.l * e.m));
+    }
+    dashpot[nw] = false;
     w[nw++] = 2.0 * std::sqrt(e.Kp / (e.l * e.m));
+    dashpot[nw] = false;
     w[nw++] = std::sqrt(e.l * e.Kp / e.I1);
+    dashpot[nw] = true;
     w[nw++] = std::sqrt(4.0 * e.K1 / (e.l * e.I1));
+    dashpot[nw] = true;
     w[nw++] = std::sqrt(4.0 * e.K3 / (e.l * e.I3));
-    for (int k = 0; k < nw; ++k)
-      if (w[k] > 0) best = std::min(best, 2.0 / w[k]);
+    for (int k = 0; k < nw; ++k) {
+      if (!(w[k] > 0)) continue;
+      best = std::min(best, 2.0 / w[k]);
+      if (dashpot[k] && p->damping_int > 0) best = std::min(best, 2.0 / (p->damping_int * w[k] * w[k]));
+    }
   }
   if (!std::isfinite(best)) return fail(nullptr, ROD_E_INVALID, "rod has no elastic mode");
   *dt_out = 0.5 * best;
@@ -1214,6 +1235,8 @@ rod_status rod_set_chunking(rod_ctx* c, int32_t min_elements, int32_t chunk_elem
       return fail(c, ROD_E_UNSUPPORTED, "a rod with a haptic mailbox cannot be chunked");
     if (c->env_nodes && c->n[r] > min_elements)
       return fail(c, ROD_E_UNSUPPORTED, "chunked rods do not collide with the environment");
+    if (c->rods[r].damp_int > 0.f && c->n[r] > min_elements)
+      return fail(c, ROD_E_UNSUPPORTED, "rods with internal friction cannot be chunked");
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (void** p : {(void**)&c->d_chunks, (void**)&c->d_block_chunk, (void**)&c->d_pub,
@@ -1478,6 +1501,9 @@ rod_status rod_set_environment(rod_ctx* c, int32_t n_tris, const double* tris, d
   if (!bt.empty()) {
     if (!c->groups.empty())
       return fail(c, ROD_E_UNSUPPORTED, "rods in groups do not collide with the environment");
+    for (const auto& d : c->rods)
+      if (d.damp_int > 0.f)
+        return fail(c, ROD_E_UNSUPPORTED, "rods with internal friction do not collide with the environment");
     if (c->n_chunks) return fail(c, ROD_E_UNSUPPORTED, "chunked rods do not collide with the environment");
   }
   std::vector<corde::EnvNode> nodes;
@@ -1596,12 +1622,12 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
         shape_of[c->rod_ids[chosen[bi].first + i]] = chosen[bi].waves * 16 + chosen[bi].elems;
     std::vector<std::pair<int, float>> us_of;
     for (const auto& b : chosen)
-      us_of.push_back({(b.waves * 16 + b.elems) * 4 + b.feat, b.us_per_step});
+      us_of.push_back({(b.waves * 16 + b.elems) * 8 + b.feat, b.us_per_step});
     st = make_buckets(c, [&](int r, int* w, int* e) { *w = shape_of[r] / 16; *e = shape_of[r] % 16; });
     for (auto& b : c->buckets) {
       b.us_per_step = 0.f;
       for (const auto& u : us_of)
-        if (u.first == (b.waves * 16 + b.elems) * 4 + b.feat) b.us_per_step += u.second;
+        if (u.first == (b.waves * 16 + b.elems) * 8 + b.feat) b.us_per_step += u.second;
     }
   }
   c->steps_per_launch = steps_per_launch;
@@ -1648,6 +1674,8 @@ rod_status rod_adjoint_forward(rod_ctx* c, int32_t n_steps, int32_t ckpt_every, 
   if (!c->groups.empty()) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not step grouped rods");
   if (c->n_haptic) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not step rods with a haptic mailbox");
   if (c->env_nodes) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not step rods against an environment");
+  for (const auto& r : c->rods)
+    if (r.damp_int > 0.f) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not differentiate internal friction");
   c->adj_ready = false;
   const size_t S = state_floats(c);
   const int ck = std::min(ckpt_every, n_steps);

@@ -45,6 +45,7 @@ class rod_params(C.Structure):
         ("clamp_amp", C.c_double * 3), ("clamp_twist_amp", C.c_double),
         ("clamp_twist_axis", C.c_double * 3), ("clamp_freq", C.c_double),
         ("clamp_phase_x", C.c_double), ("clamp_phase_twist", C.c_double),
+        ("damping_int", C.c_double),
     ]
 
 
@@ -151,6 +152,7 @@ def make_params(spec):
     p.clamp_freq = float(spec.clamp_freq)
     p.clamp_phase_x = float(spec.clamp_phase_x)
     p.clamp_phase_twist = float(spec.clamp_phase_twist)
+    p.damping_int = float(spec.damp_int)
     return p, keep
 
 

@@ -88,6 +88,8 @@ def test_null_handle_calls(L):
 def test_stable_dt_matches_oracle(L, oracle):
     specs = [W.config0(dt=1e-6).rods[0][0]] + [s for s, _ in W.config1(dt=1e-7).rods]
     specs += [s for s, _ in W.config3(n_rods=40, n_min=8, n_max=64).rods[:40]]
+    # with internal friction: weak (elastic limits bind) and strong (dashpot limits bind)
+    specs += [s.replace(damp_int=td) for s in specs[:6] for td in (1e-9, 1e-3)]
     for s in specs:
         s = s.replace(dt=1.0)
         a = R.stable_dt(s)
