@@ -373,7 +373,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--steps-per-launch", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=20000)
+    ap.add_argument("--cpu-steps", type=int, default=60000)
     ap.add_argument("--shape", default="", help="W,E kernel shape (default: autotune)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (4096 rods), long-rod and adjoint measurements")
