@@ -391,6 +391,7 @@ struct RodLane {
   V3 imp0;         // lane 0: momentum passed to point 0 (forces x dt + impulses)
   V3 en[E];        // environment collision of each slot's point this step: normal, depth
   float ed[E];
+  bool env_any;    // some point of this wavefront collides this step (uniform over the wave)
   float dt;
 
   // Loads the coefficients of slots [off, off + nloc) (the whole rod by default).  A window
@@ -691,11 +692,15 @@ struct RodLane {
   }
 
   // Candidate lists of the slots (see kEnvCand): where each was built and its length, in HBM
-  // between launches and in LDS (lc, one float4 per slot) during one.
-  __device__ __forceinline__ void env_load(const RodDev& rd, float4* lc) const {
+  // between launches and in LDS (lc, one float4 per slot) during one; lr: the slots' sphere
+  // radii, in LDS for the launch.
+  __device__ __forceinline__ void env_load(const RodDev& rd, float4* lc, float* lr) const {
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      if (ok[e]) lc[j0 + e] = rd.env_cache[rd.slot_off + off + j0 + e];
+      if (ok[e]) {
+        lc[j0 + e] = rd.env_cache[rd.slot_off + off + j0 + e];
+        lr[j0 + e] = rd.rho[rd.slot_off + off + j0 + e];
+      }
   }
   __device__ __forceinline__ void env_store(const RodDev& rd, const float4* lc) const {
 #pragma unroll
@@ -704,15 +709,15 @@ struct RodLane {
   }
 
   // Environment collision detection from the step-start positions (points 1..n).  Each thread
-  // reads and writes only its own slots' entries of lc.
-  __device__ __forceinline__ void env_detect(const RodDev& rd, float4* lc) {
+  // reads and writes only its own slots' entries of lc and lr.
+  __device__ __forceinline__ void env_detect(const RodDev& rd, float4* lc, const float* lr) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       en[e] = {0.f, 0.f, 0.f};
       ed[e] = 0.f;
       if (!ok[e]) continue;
       const int slot = rd.slot_off + off + j0 + e;
-      const float r = rd.rho[slot];
+      const float r = lr[j0 + e];
       const V3 c = X[e];
       int* list = rd.env_cand + (size_t)slot * kEnvCand;
       V3 acc = {0.f, 0.f, 0.f};
@@ -748,12 +753,17 @@ struct RodLane {
       }
       env_finish(acc, dmax, en[e], ed[e]);
     }
+    bool mine = false;
+#pragma unroll
+    for (int e = 0; e < E; ++e) mine = mine || ed[e] > 0.f;
+    env_any = __ballot(mine) != 0ull;
   }
 
   // Collision response impulses (after a constraint iteration's distance sweeps): a point whose
   // predicted motion along n falls short of its depth is pushed out, with Coulomb friction
   // against its tangential velocity, at most mu times the normal impulse.
   __device__ __forceinline__ void env_impulses(const RodDev& rd) {
+    if (!env_any) return;   // nothing of this wavefront touches the mesh (a uniform branch)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const V3 n = en[e];
@@ -847,7 +857,8 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
   L.load_params(rd, prm, prm_stride);
   L.load_state(rd, gx, gv, gq, gw);
   __shared__ float4 lcand[(F & kFeatEnv) ? 64 * W * E : 1];
-  if (F & kFeatEnv) L.env_load(rd, lcand);
+  __shared__ float lrad[(F & kFeatEnv) ? 64 * W * E : 1];
+  if (F & kFeatEnv) L.env_load(rd, lcand, lrad);
   int par = 0;
   V3 xc = {rd.cx0[0], rd.cx0[1], rd.cx0[2]}, wc = {0.f, 0.f, 0.f};
   Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
@@ -868,7 +879,7 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
       float* base = traj + (long long)s * traj_stride;
       L.store_state(rd, base, base + 3 * n_pts, base + 6 * n_pts, base + 6 * n_pts + 4 * n_frames);
     }
-    if (F & kFeatEnv) L.env_detect(rd, lcand);   // environment collisions (Fig. 5: detection first)
+    if (F & kFeatEnv) L.env_detect(rd, lcand, lrad);   // environment collisions (Fig. 5: detection first)
     V3 xl, vl, wn;
     Q4 qn;
     L.template exchange_a<(F & kFeatDamp) != 0>(mb, par, xl, qn, vl, wn);

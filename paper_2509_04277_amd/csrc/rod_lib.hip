@@ -1511,6 +1511,18 @@ rod_status rod_set_environment(rod_ctx* c, int32_t n_tris, const double* tris, d
   if (!bt.empty()) build_env_node(bt, 0, (int)bt.size(), (float)(1e-6 * (1.0 + cmax)), nodes, out);
   HIP_TRY(c, hipStreamSynchronize(c->stream));   // no launch still reads the old mesh
   for (hipStream_t st : c->bstreams) HIP_TRY(c, hipStreamSynchronize(st));
+  // first back to no mesh: plain kernels, no pointers to the old tables, which are freed
+  auto set_rods = [&](int n_nodes, float mu) -> hipError_t {
+    for (auto& d : c->rods) {
+      d.env_n_nodes = n_nodes;
+      d.env_nodes = n_nodes ? c->d_env_nodes : nullptr;
+      d.env_tris = n_nodes ? c->d_env_tris : nullptr;
+      d.env_cache = n_nodes ? c->d_env_cache : nullptr;
+      d.env_cand = n_nodes ? c->d_env_cand : nullptr;
+      d.env_mu = mu;
+    }
+    return hipMemcpy(c->d_rods, c->rods.data(), sizeof(RodDev) * c->n_rods, hipMemcpyHostToDevice);
+  };
   auto free_env = [&]() {
     for (void** p : {(void**)&c->d_env_nodes, (void**)&c->d_env_tris, (void**)&c->d_env_cache,
                      (void**)&c->d_env_cand}) {
@@ -1518,41 +1530,36 @@ rod_status rod_set_environment(rod_ctx* c, int32_t n_tris, const double* tris, d
       *p = nullptr;
     }
   };
-  free_env();
   c->env_nodes = c->env_tris = 0;
+  HIP_TRY(c, set_rods(0, 0.f));
+  free_env();
+  rod_status st = rebucket(c);
+  if (st != ROD_OK || nodes.empty()) return st;
   size_t slots = 0;
   for (int r = 0; r < c->n_rods; ++r) slots += (size_t)c->n[r];
-  if (!nodes.empty()) {
-    if (hipMalloc((void**)&c->d_env_nodes, sizeof(corde::EnvNode) * nodes.size()) != hipSuccess ||
-        hipMalloc((void**)&c->d_env_tris, sizeof(corde::EnvTri) * out.size()) != hipSuccess ||
-        hipMalloc((void**)&c->d_env_cache, sizeof(float4) * slots) != hipSuccess ||
-        hipMalloc((void**)&c->d_env_cand, sizeof(int32_t) * slots * corde::kEnvCand) != hipSuccess) {
-      free_env();
-      for (auto& d : c->rods) d.env_n_nodes = 0;
-      (void)hipMemcpy(c->d_rods, c->rods.data(), sizeof(RodDev) * c->n_rods, hipMemcpyHostToDevice);
-      (void)rebucket(c);
-      return fail(c, ROD_E_NOMEM, "environment tables");
-    }
-    HIP_TRY(c, hipMemcpy(c->d_env_nodes, nodes.data(), sizeof(corde::EnvNode) * nodes.size(),
-                         hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->d_env_tris, out.data(), sizeof(corde::EnvTri) * out.size(),
-                         hipMemcpyHostToDevice));
-    // no candidate list yet: every point builds one at its first step
-    const std::vector<float4> far(slots, make_float4(1e30f, 1e30f, 1e30f, 0.f));
-    HIP_TRY(c, hipMemcpy(c->d_env_cache, far.data(), sizeof(float4) * slots, hipMemcpyHostToDevice));
-    c->env_nodes = (int)nodes.size();
-    c->env_tris = (int)out.size();
+  if (hipMalloc((void**)&c->d_env_nodes, sizeof(corde::EnvNode) * nodes.size()) != hipSuccess ||
+      hipMalloc((void**)&c->d_env_tris, sizeof(corde::EnvTri) * out.size()) != hipSuccess ||
+      hipMalloc((void**)&c->d_env_cache, sizeof(float4) * slots) != hipSuccess ||
+      hipMalloc((void**)&c->d_env_cand, sizeof(int32_t) * slots * corde::kEnvCand) != hipSuccess) {
+    free_env();
+    return fail(c, ROD_E_NOMEM, "environment tables");
   }
-  for (auto& d : c->rods) {
-    d.env_n_nodes = c->env_nodes;
-    d.env_nodes = c->d_env_nodes;
-    d.env_tris = c->d_env_tris;
-    d.env_cache = c->d_env_cache;
-    d.env_cand = c->d_env_cand;
-    d.env_mu = (float)mu;
+  // no candidate list yet: every point builds one at its first step
+  const std::vector<float4> far(slots, make_float4(1e30f, 1e30f, 1e30f, 0.f));
+  hipError_t e = hipMemcpy(c->d_env_nodes, nodes.data(), sizeof(corde::EnvNode) * nodes.size(),
+                           hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->d_env_tris, out.data(), sizeof(corde::EnvTri) * out.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_env_cache, far.data(), sizeof(float4) * slots, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = set_rods((int)nodes.size(), (float)mu);
+  if (e != hipSuccess) {
+    (void)set_rods(0, 0.f);
+    free_env();
+    return hip_fail(c, e, "rod_set_environment");
   }
-  HIP_TRY(c, hipMemcpy(c->d_rods, c->rods.data(), sizeof(RodDev) * c->n_rods, hipMemcpyHostToDevice));
-  if (c->env_nodes) c->adj_ready = false;
+  c->env_nodes = (int)nodes.size();
+  c->env_tris = (int)out.size();
+  c->adj_ready = false;
   return rebucket(c);   // the rods move to the kernel variant with the collision code
 }
 
