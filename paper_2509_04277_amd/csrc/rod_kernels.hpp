@@ -113,7 +113,7 @@ struct RodDev {
   const EnvNode* env_nodes;
   const EnvTri* env_tris;
   float4* env_cache;  // per slot: where its candidate list was built, list length (int bits)
-  int32_t* env_cand;  // per slot: kEnvCand candidate triangles
+  int2* env_cand;     // per slot: kEnvCand candidates (triangle, bits of its build distance)
   const float* rho;   // per slot: sphere radius of point slot + 1
   float env_mu;       // friction coefficient against the environment
   float damp_int;     // internal friction: Kelvin-Voigt retardation time tau_d [s] (0: none)
@@ -367,11 +367,12 @@ __device__ __forceinline__ void env_finish(V3 acc, float dmax, V3& n, float& dep
 }
 
 // Candidate triangles cached per point: every triangle within (1 + m) r of the point where the
-// list was built, m = kEnvMargin.  While the point stays within m r of that place, the
-// triangles within r of it are all on the list, so the narrow phase runs over the list alone
-// (in tree order, as a walk would visit them); a point that moved farther rebuilds its list
-// with a walk.  A list that overflows makes the point walk the tree every step until its next
-// rebuild.
+// list was built, m = kEnvMargin, with its distance from there.  While the point stays within
+// m r of that place, the triangles within r of it are all on the list, so the narrow phase runs
+// over the list alone (in tree order, as a walk would visit them), and skips, without loading
+// it, every triangle whose build distance minus the point's movement is still at least r (its
+// distance now is no smaller).  A point that moved farther rebuilds its list with a walk.  A
+// list that overflows makes the point walk the tree every step until its next rebuild.
 constexpr int kEnvCand = 32;
 constexpr float kEnvMargin = 1.0f;
 
@@ -719,34 +720,45 @@ struct RodLane {
       const int slot = rd.slot_off + off + j0 + e;
       const float r = lr[j0 + e];
       const V3 c = X[e];
-      int* list = rd.env_cand + (size_t)slot * kEnvCand;
+      int2* list = rd.env_cand + (size_t)slot * kEnvCand;
       V3 acc = {0.f, 0.f, 0.f};
       float dmax = 0.f;
       const float4 cp = lc[j0 + e];
       const int have = __float_as_int(cp.w);
-      const V3 moved = c - V3{cp.x, cp.y, cp.z};
-      if (dot(moved, moved) > (kEnvMargin * r) * (kEnvMargin * r)) {   // rebuild the list here
+      const V3 mv = c - V3{cp.x, cp.y, cp.z};
+      const float moved2 = dot(mv, mv);
+      if (moved2 > (kEnvMargin * r) * (kEnvMargin * r)) {   // rebuild the list here
         const float reach = (1.f + kEnvMargin) * r;
         int cnt = 0;
         env_walk(rd, c, reach, [&](int k) {
-          if (env_hit(rd.env_tris[k], c, r, acc, dmax) < reach) {
-            if (cnt < kEnvCand) list[cnt] = k;
+          const float dist = env_hit(rd.env_tris[k], c, r, acc, dmax);
+          if (dist < reach) {
+            if (cnt < kEnvCand) list[cnt] = make_int2(k, __float_as_int(dist));
             ++cnt;
           }
         });
         lc[j0 + e] = make_float4(c.x, c.y, c.z, __int_as_float(cnt));
       } else if (have <= kEnvCand) {
-        // four candidates at a time: one load of their indices, then their triangles together
+        // a candidate can touch the sphere only if its build distance, less the movement since
+        // (and a rounding margin), is below r; four entries at a time: one load of the entries,
+        // then the triangles that can touch together
+        const float moved = sqrtf(moved2);
         for (int k0 = 0; k0 < have; k0 += 4) {
-          const int4 ix = *reinterpret_cast<const int4*>(list + k0);
-          const int id[4] = {ix.x, ix.y, ix.z, ix.w};
+          const int4 e01 = *reinterpret_cast<const int4*>(list + k0);
+          const int4 e23 = *reinterpret_cast<const int4*>(list + k0 + 2);
+          const int id[4] = {e01.x, e01.z, e23.x, e23.z};
+          const float db[4] = {__int_as_float(e01.y), __int_as_float(e01.w), __int_as_float(e23.y),
+                               __int_as_float(e23.w)};
+          bool near[4];
           EnvTri t[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (k0 + u < have) t[u] = rd.env_tris[id[u]];
+          for (int u = 0; u < 4; ++u) {
+            near[u] = k0 + u < have && db[u] - moved < r * (1.f + 1e-5f) + 1e-5f * db[u];
+            if (near[u]) t[u] = rd.env_tris[id[u]];
+          }
 #pragma unroll
           for (int u = 0; u < 4; ++u)
-            if (k0 + u < have) env_hit(t[u], c, r, acc, dmax);
+            if (near[u]) env_hit(t[u], c, r, acc, dmax);
         }
       } else {
         env_walk(rd, c, r, [&](int k) { env_hit(rd.env_tris[k], c, r, acc, dmax); });

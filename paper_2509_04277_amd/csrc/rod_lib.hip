@@ -164,7 +164,7 @@ struct rod_ctx {
   corde::EnvNode* d_env_nodes = nullptr;
   corde::EnvTri* d_env_tris = nullptr;
   float4* d_env_cache = nullptr;   // per slot: candidate-list position and length
-  int32_t* d_env_cand = nullptr;   // per slot: candidate triangles
+  int2* d_env_cand = nullptr;      // per slot: candidate triangles and build distances
   int env_nodes = 0, env_tris = 0;
   // adjoint rollout (rod_adjoint_forward / rod_adjoint_backward)
   bool adj_ready = false;
@@ -1540,7 +1540,7 @@ rod_status rod_set_environment(rod_ctx* c, int32_t n_tris, const double* tris, d
   if (hipMalloc((void**)&c->d_env_nodes, sizeof(corde::EnvNode) * nodes.size()) != hipSuccess ||
       hipMalloc((void**)&c->d_env_tris, sizeof(corde::EnvTri) * out.size()) != hipSuccess ||
       hipMalloc((void**)&c->d_env_cache, sizeof(float4) * slots) != hipSuccess ||
-      hipMalloc((void**)&c->d_env_cand, sizeof(int32_t) * slots * corde::kEnvCand) != hipSuccess) {
+      hipMalloc((void**)&c->d_env_cand, sizeof(int2) * slots * corde::kEnvCand) != hipSuccess) {
     free_env();
     return fail(c, ROD_E_NOMEM, "environment tables");
   }
