@@ -1573,7 +1573,9 @@ rod_status rod_environment_info(const rod_ctx* c, int32_t* n_nodes, int32_t* n_t
 rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launch, rod_tuning* out) {
   if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
   if (!c->have_state) return fail(c, ROD_E_ORDER, "rod_autotune before rod_set_state");
-  if (probe_steps < 1 || steps_per_launch < 1) return fail(c, ROD_E_INVALID, "probe sizes must be >= 1");
+  if (probe_steps < 1 || steps_per_launch < 0) return fail(c, ROD_E_INVALID, "bad probe sizes");
+  const bool pick_k = steps_per_launch == 0;   // also choose the steps per launch
+  if (pick_k) steps_per_launch = std::min(10, probe_steps);
   // save the state, probe the candidate shapes of every bucket, restore
   const size_t bx = sizeof(float) * 3 * c->total_pts, bq = sizeof(float) * 4 * c->total_frames,
                bw = sizeof(float) * 3 * c->total_frames;
@@ -1636,6 +1638,36 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
       for (const auto& u : us_of)
         if (u.first == (b.waves * 16 + b.elems) * 8 + b.feat) b.us_per_step += u.second;
     }
+  }
+  if (st == ROD_OK && pick_k) {
+    // steps per launch: time the whole handle at each k (probe steps rounded up to whole
+    // launches) and keep the smallest k within 5 % of the best time per step (a larger k
+    // only delays the host's view of the state)
+    static const int ks[] = {1, 2, 5, 10, 20, 50, 100, 200, 500, 1000};
+    float us_k[10];
+    float best = INFINITY;
+    int nk = 0;
+    for (int k : ks) {
+      if (k > probe_steps && nk > 0) break;
+      const int steps = ((probe_steps + k - 1) / k) * k;
+      float ms_best = INFINITY;
+      for (int rep = 0; rep < 2 && st == ROD_OK; ++rep) {
+        st = launch_steps(c, steps, k, true);
+        float ms = 0;
+        int nl = 0;
+        if (st == ROD_OK) st = rod_last_step_time(c, &ms, &nl);
+        ms_best = std::min(ms_best, ms);
+      }
+      if (st != ROD_OK) break;
+      us_k[nk++] = 1000.f * ms_best / steps;
+      best = std::min(best, us_k[nk - 1]);
+    }
+    if (st == ROD_OK)
+      for (int i = 0; i < nk; ++i)
+        if (us_k[i] <= 1.05f * best) {
+          steps_per_launch = ks[i];
+          break;
+        }
   }
   c->steps_per_launch = steps_per_launch;
   c->steps_done = saved_steps;

@@ -388,6 +388,9 @@ class RodBatch:
         _check(lib().rod_set_chunking(self.h, int(min_elements), int(chunk_elements)), self.h)
 
     def autotune(self, probe_steps: int = 200, steps_per_launch: int = 10):
+        """rod_autotune: time each admissible kernel shape per bucket and keep the fastest;
+        steps_per_launch = 0 also picks the steps per launch (the smallest count whose time per
+        step is within 5 % of the best).  State and step counter are left as they were."""
         t = rod_tuning()
         _check(lib().rod_autotune(self.h, int(probe_steps), int(steps_per_launch), C.byref(t)),
                self.h)

@@ -268,6 +268,29 @@ def test_autotune_keeps_state_and_picks_a_shape():
         assert np.array_equal(a, c)
 
 
+def test_autotune_chooses_steps_per_launch(oracle):
+    """steps_per_launch = 0: the autotuner also picks the steps per launch (state and step
+    counter untouched); stepping with its choice matches the oracle."""
+    wl = W.config0(n=64)
+    spec, st = wl.rods[0]
+    b = R.RodBatch([spec])
+    b.set_state_rods([st])
+    before = b.get_state()
+    t = b.autotune(probe_steps=200, steps_per_launch=0)
+    _say("autotune (steps per launch too) chose %s" % t)
+    assert t["steps_per_launch"] in (1, 2, 5, 10, 20, 50, 100, 200)
+    assert b.tuning["steps_per_launch"] == t["steps_per_launch"]
+    after = b.get_state()
+    assert b.time()[1] == 0
+    for u, v in zip(before, after):
+        assert np.array_equal(u, v)
+    b.step(300)
+    x = b.get_state_rods()[0][0]
+    b.close()
+    ref, _ = oracle.Rod(spec).rollout(st, 300)
+    assert np.abs(x - ref.x).max() <= 1e-4
+
+
 def test_batch_buckets_and_autotune_vs_oracle(oracle):
     """Uneven batch (per-rod dt from the stability rule, mixed variants) in several kernel-shape
     buckets, before and after autotuning, against the oracle rod by rod."""
