@@ -231,7 +231,8 @@ def contact_extras(R, W):
         out[name] = {"us_per_step": 1e3 * ms / 2000}
     out["overhead"] = out["contact"]["us_per_step"] / out["no_contact"]["us_per_step"] - 1.0
     out["workload"] = ("2 x 128-element inextensible rods crossing, one falling onto the other; "
-                       "contact: both rods in one workgroup, sphere broad phase every step")
+                       "contact: both rods in one workgroup, candidate lists rebuilt when a point "
+                       "has moved past their margin")
     return out
 
 

@@ -963,11 +963,18 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
 // group's first rod and [64 W, 128 W) the second, each exactly as rod_resident_kernel steps
 // one rod; a single rod leaves the second half idle (a rod of no elements taking the same
 // barriers).  Both rods have the same number of constraint iterations.
-//   Step start: every point writes its position and sphere radius to LDS; with contact, one
-//   thread per group of 8 consecutive points builds a bounding sphere, one thread per sphere
-//   marks the spheres overlapping it, and every point lists (in (rod, point) order, at most
-//   kMaxContacts) the points of overlapping spheres whose spheres overlap its own, leaving out
-//   points of its own rod within self_skip of it.
+//   Step start: every point writes its position and sphere radius to LDS.  With contact
+//   (compiled in when CT), every point then lists (in (rod, point) order, at most
+//   kMaxContacts) the points whose spheres overlap its own, leaving out points of its own rod
+//   within self_skip of it.  It takes them from a candidate list (at most kContactCand
+//   points, same order) of the points that were within contact distance + margin of it when
+//   the list was built; the lists are rebuilt, for the whole group, only when some point has
+//   moved more than 0.45 x margin since, so every contact is among the candidates and the
+//   contacts found are exactly those of a scan of all points.  A build groups 8 consecutive
+//   points into a bounding sphere (one thread each), marks the pairs of spheres that come
+//   within the margin of each other, and scans the points of those spheres; a point with too
+//   many candidates falls back to its exact contacts and forces a new build next step.  The
+//   build positions and lists are kept in device memory between launches.
 //   Every constraint iteration, after the distance sweeps: points publish velocity and inverse
 //   mass; bound points apply the zero-length distance impulse (two-way, or one-way with the
 //   second rod the master); then, with contact, points publish again and every point applies
@@ -975,6 +982,7 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
 //   impulse removing the predicted penetration along the step-start normal and a friction
 //   impulse opposing the relative tangential velocity, at most mu times the normal one.
 constexpr int kMaxContacts = 8;    // contacts per point (more sets status bit 8)
+constexpr int kContactCand = 16;   // candidate partners per point kept between list builds
 constexpr int kSphereSize = 8;     // points per bounding sphere
 
 struct GroupDev {
@@ -982,26 +990,35 @@ struct GroupDev {
   int32_t bind_mode;   // 0 none, 1 one-way (rod[1] is the master), 2 two-way
   int32_t contact;     // 1: sphere contact between and within the group's rods
   float mu;            // friction coefficient
+  float margin;        // contact candidates: pairs within contact distance + margin [m]
 };
 
-template <int W, int E>
+template <int W, int E, bool CT>
 __global__ __launch_bounds__(128 * W) void rod_group_kernel(
     const RodDev* __restrict__ rods, const GroupDev* __restrict__ groups,
     const int* __restrict__ partner, const float* __restrict__ rho_slot,
+    float4* __restrict__ cbuild, uint16_t* __restrict__ ccand,
     const float* __restrict__ prm, int prm_stride, float* __restrict__ gx, float* __restrict__ gv,
     float* __restrict__ gq, float* __restrict__ gw, const float* __restrict__ fext,
     const float* __restrict__ text, int n_steps, long long steps_done, int* __restrict__ status) {
   constexpr int CAP = 64 * W * E;                                   // slots per rod
-  constexpr int SMAX = 2 * ((CAP + kSphereSize - 1) / kSphereSize);  // spheres per group
+  constexpr int CC = CT ? CAP : 1;                                  // contact-list slots
+  constexpr int SMAX = CT ? 2 * ((CAP + kSphereSize - 1) / kSphereSize) : 1;  // spheres
+  constexpr int SW = (SMAX + 31) / 32;
   __shared__ Mailbox<W> mb[2];
   __shared__ float cbuf[2][kClampChunk][10];
-  __shared__ float4 xs[2][CAP];      // step-start position and sphere radius
+  // step-start position and sphere radius, double-buffered by step parity: a wavefront that
+  // starts the next step does not overwrite what another still reads for this one
+  __shared__ float4 xs[2][2][CAP];
   // velocity and inverse mass, double-buffered by publication parity: the reads after one
   // publication and the writes two publications later are separated by a barrier
   __shared__ float4 vw[2][2][CAP];
-  __shared__ float4 sph[SMAX];                           // bounding spheres: centre, radius
-  __shared__ uint32_t sov[SMAX][(SMAX + 31) / 32];       // sphere-overlap bitmask
-  __shared__ uint16_t lst[2][CAP][kMaxContacts];         // contacts: sub * CAP + slot
+  __shared__ float4 sph[SMAX];                            // bounding spheres: centre, radius
+  __shared__ uint32_t sov[SMAX][SW];                      // sphere pairs within the margin
+  __shared__ uint16_t cand[2][kContactCand][CC];          // candidates: sub * CAP + slot
+  __shared__ uint16_t lst[2][kMaxContacts][CC];           // this step's contacts
+  __shared__ float4 xbl[2][CC];      // each point's position when its candidates were listed
+  __shared__ int moved[2][2 * W];                         // per wavefront and step parity
   const GroupDev gp = groups[blockIdx.x];
   const int sub = threadIdx.x >= 64 * W ? 1 : 0;
   const bool active = gp.rod[sub] >= 0;
@@ -1015,21 +1032,36 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
     any_driven = any_driven || (r1.driven && r1.clamp);
     nrod[1] = r1.n;
   }
-  const bool moved = !(gp.bind_mode == 1 && sub == 1);
-  const bool contact = gp.contact != 0;
+  const bool moved_rod = !(gp.bind_mode == 1 && sub == 1);
+  const bool contact = CT && gp.contact != 0;
   RodLane<W, E> L;
   L.load_params(rd, prm, prm_stride);
   L.load_state(rd, gx, gv, gq, gw);
-  int part[E], cnt[E];
+  int part[E], cnt[E], ncand[E];
   float rho[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     part[e] = (L.ok[e] && gp.bind_mode) ? partner[rd.slot_off + L.j0 + e] : -1;
     rho[e] = L.ok[e] ? rho_slot[rd.slot_off + L.j0 + e] : 0.f;
     cnt[e] = 0;
+    ncand[e] = 0;
+  }
+  if (contact) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (!L.ok[e]) continue;
+      const int i = L.j0 + e, gs = rd.slot_off + i;
+      const float4 b = cbuild[gs];   // NaN position: no valid list
+      xbl[sub][i] = b;
+      ncand[e] = min(max(__float_as_int(b.w), 0), kContactCand);
+      for (int c = 0; c < ncand[e]; ++c) cand[sub][c][i] = ccand[(size_t)gs * kContactCand + c];
+    }
   }
   const int skip = rd.self_skip;
-  int par = 0;
+  const float reb2 = (0.45f * gp.margin) * (0.45f * gp.margin);
+  const int s0 = (nrod[0] + kSphereSize - 1) / kSphereSize;
+  const int ns = s0 + (nrod[1] + kSphereSize - 1) / kSphereSize;
+  int par = 0, xp = 0;
   V3 xc = {rd.cx0[0], rd.cx0[1], rd.cx0[2]}, wc = {0.f, 0.f, 0.f};
   Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
   const float dt = rd.dt;
@@ -1041,76 +1073,125 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
       if (L.ok[e]) vw[bpar][sub][L.j0 + e] = make_float4(L.Vv[e].x, L.Vv[e].y, L.Vv[e].z, L.P[P_WINV][e]);
     __syncthreads();
   };
+  // candidates of slot e's point: points of overlapping spheres (sov) within contact distance
+  // + mm, in (rod, point) order; returns how many there are (only the first kContactCand kept)
+  auto scan = [&](int e, float mm) {
+    const int i = L.j0 + e;
+    const int own = sub * s0 + i / kSphereSize;
+    const V3 xi = L.X[e];
+    int n = 0;
+    for (int wd = 0; wd < SW; ++wd) {
+      uint32_t bits = wd * 32 < ns ? sov[own][wd] : 0u;
+      while (bits) {
+        const int k = wd * 32 + __builtin_ctz(bits);
+        bits &= bits - 1;
+        const int r = k < s0 ? 0 : 1, kk = k < s0 ? k : k - s0;
+        const int a = kk * kSphereSize, b = min(a + kSphereSize, nrod[r]);
+        for (int j = a; j < b; ++j) {
+          if (r == sub && abs(j - i) <= skip) continue;
+          const float4 p = xs[xp][r][j];
+          const float dx = xi.x - p.x, dy = xi.y - p.y, dz = xi.z - p.z, D = rho[e] + p.w + mm;
+          const float d2 = dx * dx + dy * dy + dz * dz;
+          if (!(d2 < D * D) || !(d2 > 0.f)) continue;
+          if (n < kContactCand) cand[sub][n][i] = (uint16_t)(r * CAP + j);
+          ++n;
+        }
+      }
+    }
+    return n;
+  };
 
   for (int s = 0; s < n_steps; ++s) {
     // ---- step start: positions and radii; contact lists
+    xp = s & 1;
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      if (L.ok[e]) xs[sub][L.j0 + e] = make_float4(L.X[e].x, L.X[e].y, L.X[e].z, rho[e]);
+      if (L.ok[e]) xs[xp][sub][L.j0 + e] = make_float4(L.X[e].x, L.X[e].y, L.X[e].z, rho[e]);
+    if (contact) {
+      bool mv = false;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (!L.ok[e]) continue;
+        const float4 b = xbl[sub][L.j0 + e];
+        const V3 d = L.X[e] - V3{b.x, b.y, b.z};
+        mv = mv || !(dot(d, d) <= reb2);
+      }
+      const bool wmv = __ballot(mv) != 0ull;
+      if ((threadIdx.x & 63) == 0) moved[s & 1][threadIdx.x >> 6] = wmv ? 1 : 0;
+    }
     __syncthreads();
     if (contact) {
-      const int s0 = (nrod[0] + kSphereSize - 1) / kSphereSize;
-      const int ns = s0 + (nrod[1] + kSphereSize - 1) / kSphereSize;
-      const int t = threadIdx.x;
-      if (t < ns) {
-        const int r = t < s0 ? 0 : 1, k = t < s0 ? t : t - s0;
-        const int a = k * kSphereSize, b = min(a + kSphereSize, nrod[r]);
-        float cx = 0.f, cy = 0.f, cz = 0.f, rm = 0.f;
-        for (int j = a; j < b; ++j) {
-          const float4 p = xs[r][j];
-          cx += p.x; cy += p.y; cz += p.z;
-          rm = fmaxf(rm, p.w);
+      bool rebuild = false;
+#pragma unroll
+      for (int k = 0; k < 2 * W; ++k) rebuild = rebuild || moved[s & 1][k] != 0;
+      if (rebuild) {   // uniform over the workgroup
+        const int t = threadIdx.x;
+        if (t < ns) {
+          const int r = t < s0 ? 0 : 1, k = t < s0 ? t : t - s0;
+          const int a = k * kSphereSize, b = min(a + kSphereSize, nrod[r]);
+          float cx = 0.f, cy = 0.f, cz = 0.f, rm = 0.f;
+          for (int j = a; j < b; ++j) {
+            const float4 p = xs[xp][r][j];
+            cx += p.x; cy += p.y; cz += p.z;
+            rm = fmaxf(rm, p.w);
+          }
+          const float inv = 1.0f / (float)(b - a);
+          cx *= inv; cy *= inv; cz *= inv;
+          float d2 = 0.f;
+          for (int j = a; j < b; ++j) {
+            const float4 p = xs[xp][r][j];
+            d2 = fmaxf(d2, (p.x - cx) * (p.x - cx) + (p.y - cy) * (p.y - cy) + (p.z - cz) * (p.z - cz));
+          }
+          sph[t] = make_float4(cx, cy, cz, sqrtf(d2) + rm);
         }
-        const float inv = 1.0f / (float)(b - a);
-        cx *= inv; cy *= inv; cz *= inv;
-        float d2 = 0.f;
-        for (int j = a; j < b; ++j) {
-          const float4 p = xs[r][j];
-          d2 = fmaxf(d2, (p.x - cx) * (p.x - cx) + (p.y - cy) * (p.y - cy) + (p.z - cz) * (p.z - cz));
-        }
-        sph[t] = make_float4(cx, cy, cz, sqrtf(d2) + rm);
-      }
-      __syncthreads();
-      if (t < ns) {
-        const float4 me = sph[t];
-        for (int wd = 0; wd < (ns + 31) / 32; ++wd) {
+        __syncthreads();
+        // one 32-sphere word of one sphere's row per thread; neighbouring threads take
+        // neighbouring rows of the same word (same sphere read by all of them)
+        for (int task = t; task < ns * SW; task += 128 * W) {
+          const int row = task % ns, wd = task / ns;
+          const float4 me = sph[row];
           uint32_t bits = 0;
           for (int bb = 0; bb < 32; ++bb) {
             const int k = wd * 32 + bb;
             if (k < ns) {
               const float4 o = sph[k];
-              const float dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z, rr = me.w + o.w;
+              const float dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z;
+              const float rr = me.w + o.w + gp.margin;
               if (dx * dx + dy * dy + dz * dz < rr * rr) bits |= 1u << bb;
             }
           }
-          sov[t][wd] = bits;
+          sov[row][wd] = bits;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if (!L.ok[e]) continue;
+          int n = scan(e, gp.margin);
+          float4 b = make_float4(L.X[e].x, L.X[e].y, L.X[e].z, 0.f);
+          if (n > kContactCand) {   // too many candidates: this step's exact contacts only
+            n = min(scan(e, 0.f), kContactCand);
+            b.x = __int_as_float(0x7fc00000);   // build again next step
+          }
+          ncand[e] = n;
+          b.w = __int_as_float(n);
+          xbl[sub][L.j0 + e] = b;
         }
       }
-      __syncthreads();
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         cnt[e] = 0;
         if (!L.ok[e]) continue;
         const int i = L.j0 + e;
-        const int own = sub * s0 + i / kSphereSize;
         const V3 xi = L.X[e];
-        for (int wd = 0; wd < (ns + 31) / 32; ++wd) {
-          uint32_t bits = sov[own][wd];
-          while (bits) {
-            const int k = wd * 32 + __builtin_ctz(bits);
-            bits &= bits - 1;
-            const int r = k < s0 ? 0 : 1, kk = k < s0 ? k : k - s0;
-            const int a = kk * kSphereSize, b = min(a + kSphereSize, nrod[r]);
-            for (int j = a; j < b; ++j) {
-              if (r == sub && abs(j - i) <= skip) continue;
-              const float4 p = xs[r][j];
-              const float dx = xi.x - p.x, dy = xi.y - p.y, dz = xi.z - p.z, D = rho[e] + p.w;
-              const float d2 = dx * dx + dy * dy + dz * dz;
-              if (!(d2 < D * D) || !(d2 > 0.f)) continue;
-              if (cnt[e] < kMaxContacts) lst[sub][i][cnt[e]++] = (uint16_t)(r * CAP + j);
-              else overflow = true;
-            }
-          }
+        for (int c = 0; c < ncand[e]; ++c) {
+          const int gidx = cand[sub][c][i];
+          const int r = gidx >= CAP ? 1 : 0, j = gidx - r * CAP;
+          const float4 p = xs[xp][r][j];
+          const float dx = xi.x - p.x, dy = xi.y - p.y, dz = xi.z - p.z, D = rho[e] + p.w;
+          const float d2 = dx * dx + dy * dy + dz * dz;
+          if (!(d2 < D * D) || !(d2 > 0.f)) continue;
+          if (cnt[e] < kMaxContacts) lst[sub][cnt[e]++][i] = (uint16_t)gidx;
+          else overflow = true;
         }
       }
     }
@@ -1130,8 +1211,8 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
         publish();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          if (part[e] >= 0 && moved) {
-            const float4 ox = xs[1 - sub][part[e]];
+          if (part[e] >= 0 && moved_rod) {
+            const float4 ox = xs[xp][1 - sub][part[e]];
             const float4 ov = vw[bpar][1 - sub][part[e]];
             const V3 p = fma3(dt, L.Vv[e], L.X[e]);
             const V3 po = fma3(dt, V3{ov.x, ov.y, ov.z}, V3{ox.x, ox.y, ox.z});
@@ -1155,9 +1236,9 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
           V3 acc = {0.f, 0.f, 0.f};
           int act = 0;
           for (int c = 0; c < cnt[e]; ++c) {
-            const int gidx = lst[sub][i][c];
+            const int gidx = lst[sub][c][i];
             const int r = gidx >= CAP ? 1 : 0, j = gidx - r * CAP;
-            const float4 ox = xs[r][j];
+            const float4 ox = xs[xp][r][j];
             const float4 ov = vw[bpar][r][j];
             const V3 xj = {ox.x, ox.y, ox.z}, vj = {ov.x, ov.y, ov.z};
             const float wsum = wi + ov.w;
@@ -1186,6 +1267,15 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
   if (active) {
     const float chk = L.store_state(rd, gx, gv, gq, gw);
     if (!__builtin_isfinite(chk)) atomicOr(status, 1);
+  }
+  if (contact) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (!L.ok[e]) continue;
+      const int i = L.j0 + e, gs = rd.slot_off + i;
+      cbuild[gs] = xbl[sub][i];
+      for (int c = 0; c < ncand[e]; ++c) ccand[(size_t)gs * kContactCand + c] = cand[sub][c][i];
+    }
   }
   if (overflow) atomicOr(status, 8);
 }

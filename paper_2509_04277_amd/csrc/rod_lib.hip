@@ -84,18 +84,29 @@ const KernelEntry* find_kernel(int w, int e) {
 GridFn grid_kernel() { return corde::rod_grid_kernel<kGridWaves, kGridElems>; }
 
 using GroupFn = void (*)(const RodDev*, const corde::GroupDev*, const int*, const float*,
+                         float4*, uint16_t*,
                          const float*, int, float*, float*, float*, float*, const float*,
                          const float*, int, long long, int*);
 struct GroupEntry {
   int waves, elems;
+  bool contact;   // contact compiled in (binding-only kernels leave its LDS out)
   GroupFn fn;
 };
 // Shapes of the rod-group kernel (bindings, contact), per rod; a workgroup holds 2 x 64 waves
 // threads (at most 8 wavefronts: with 16 the register budget halves and the kernel spills).
 const GroupEntry kGroups[] = {
-    {2, 2, corde::rod_group_kernel<2, 2>}, {4, 2, corde::rod_group_kernel<4, 2>},
-    {2, 4, corde::rod_group_kernel<2, 4>}, {2, 8, corde::rod_group_kernel<2, 8>},
+    {1, 2, false, corde::rod_group_kernel<1, 2, false>},
+    {2, 2, false, corde::rod_group_kernel<2, 2, false>},
+    {4, 2, false, corde::rod_group_kernel<4, 2, false>},
+    {2, 4, false, corde::rod_group_kernel<2, 4, false>},
+    {2, 8, false, corde::rod_group_kernel<2, 8, false>},
+    {1, 2, true, corde::rod_group_kernel<1, 2, true>},
+    {2, 2, true, corde::rod_group_kernel<2, 2, true>},
+    {4, 2, true, corde::rod_group_kernel<4, 2, true>},
 };
+// contact candidate lists: pairs within contact distance + this fraction of the largest
+// sphere radius of the group's rods
+constexpr float kContactMarginRel = 0.5f;
 constexpr int kGroupMax = 1024;     // longest rod a group may hold
 constexpr int kContactMax = 512;    // longest rod of a group with contact
 
@@ -149,6 +160,10 @@ struct rod_ctx {
   corde::GroupDev* d_groups = nullptr;
   int* d_partner = nullptr;
   float* d_rho = nullptr;                       // per slot: sphere radius of point slot + 1
+  std::vector<float> rmax;                      // per rod: largest sphere radius
+  // contact candidate lists per slot: build position + count, kContactCand partner indices
+  float4* d_cbuild = nullptr;
+  uint16_t* d_ccand = nullptr;
   std::vector<int> rod_ids;
   int* d_rod_ids = nullptr;
   int steps_per_launch = 10;
@@ -646,10 +661,11 @@ rod_status launch_pair_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long
                               hipStream_t stream) {
   const GroupEntry* k = nullptr;
   for (const auto& e : kGroups)
-    if (e.waves == b.waves && e.elems == b.elems) k = &e;
+    if (e.waves == b.waves && e.elems == b.elems && (int)e.contact == b.feat) k = &e;
   if (!k) return fail(c, ROD_E_UNSUPPORTED, "group kernel shape not built");
   hipLaunchKernelGGL(k->fn, dim3(b.count), dim3(128 * k->waves), 0, stream, c->d_rods,
-                     c->d_groups + b.first, c->d_partner, c->d_rho, c->d_prm, c->prm_stride,
+                     c->d_groups + b.first, c->d_partner, c->d_rho, c->d_cbuild, c->d_ccand,
+                     c->d_prm, c->prm_stride,
                      c->d_x, c->d_v, c->d_q, c->d_w, c->d_fext, c->d_text, ks, done, c->d_status);
   HIP_TRY(c, hipGetLastError());
   return ROD_OK;
@@ -662,7 +678,7 @@ rod_status rebuild_groups(rod_ctx* c) {
   std::vector<int> group_of(c->n_rods, -1);
   for (const auto& p : c->bind_pairs) {
     group_of[p[0]] = group_of[p[1]] = (int)gs.size();
-    gs.push_back({{p[0], p[1]}, c->bind_mode, 0, 0.f});
+    gs.push_back({{p[0], p[1]}, c->bind_mode, 0, 0.f, 0.f});
   }
   for (const auto& cs : c->contact_sets) {
     const int a = cs[0], b = cs[1];
@@ -674,12 +690,14 @@ rod_status rebuild_groups(rod_ctx* c) {
       return fail(c, ROD_E_INVALID, "contact set of rods in different groups");
     } else {
       g = (int)gs.size();
-      gs.push_back({{a, b}, 0, 0, 0.f});
+      gs.push_back({{a, b}, 0, 0, 0.f, 0.f});
       group_of[a] = g;
       if (b >= 0) group_of[b] = g;
     }
     gs[g].contact = 1;
     gs[g].mu = c->contact_mu;
+    gs[g].margin = kContactMarginRel * std::max(c->rmax[gs[g].rod[0]],
+                                                gs[g].rod[1] >= 0 ? c->rmax[gs[g].rod[1]] : 0.f);
   }
   if (!gs.empty() && c->env_nodes)
     return fail(c, ROD_E_UNSUPPORTED, "rods in groups do not collide with the environment");
@@ -702,7 +720,7 @@ rod_status rebuild_groups(rod_ctx* c) {
                                         "and must not be chunked");
   }
   auto shape_of = [&](int n, int* w, int* e) {
-    *w = n <= 512 ? (n <= 256 ? 2 : 4) : 2;
+    *w = n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 4 : 2;
     *e = n <= 512 ? 2 : 8;
   };
   auto nmax = [&](const corde::GroupDev& g) {
@@ -714,7 +732,7 @@ rod_status rebuild_groups(rod_ctx* c) {
     shape_of(nmax(gs[g]), &w, &e);
     const long long cost = (long long)(c->n[gs[g].rod[0]] + (gs[g].rod[1] >= 0 ? c->n[gs[g].rod[1]] : 0)) *
                            (4 + c->rods[gs[g].rod[0]].n_iter);
-    key.push_back({((long long)(w * 16 + e) << 32) | (0x7fffffffLL - cost), g});
+    key.push_back({((long long)((w * 16 + e) * 2 + gs[g].contact) << 32) | (0x7fffffffLL - cost), g});
   }
   std::sort(key.begin(), key.end());
   HIP_TRY(c, hipStreamSynchronize(c->stream));   // no launch may still read the old tables
@@ -729,8 +747,9 @@ rod_status rebuild_groups(rod_ctx* c) {
     c->groups.push_back(g);
     c->bound[g.rod[0]] = 1;
     if (g.rod[1] >= 0) c->bound[g.rod[1]] = 1;
-    if (c->pair_buckets.empty() || c->pair_buckets.back().waves != w || c->pair_buckets.back().elems != e)
-      c->pair_buckets.push_back({w, e, i, 0, 0, 0.f});
+    if (c->pair_buckets.empty() || c->pair_buckets.back().waves != w ||
+        c->pair_buckets.back().elems != e || c->pair_buckets.back().feat != g.contact)
+      c->pair_buckets.push_back({w, e, i, 0, 0, 0.f, g.contact});
     c->pair_buckets.back().count++;
     c->pair_buckets.back().max_n = std::max(c->pair_buckets.back().max_n, nmax(g));
   }
@@ -746,6 +765,17 @@ rod_status rebuild_groups(rod_ctx* c) {
     HIP_TRY(c, hipMemcpy(c->d_partner, c->partner.data(), sizeof(int) * c->partner.size(),
                          hipMemcpyHostToDevice));
     c->adj_ready = false;   // the adjoint does not step grouped rods
+    bool any_contact = false;
+    for (const auto& g : c->groups) any_contact = any_contact || g.contact;
+    if (any_contact) {
+      const size_t slots = (size_t)c->total_frames;
+      if (!c->d_cbuild && (hipMalloc((void**)&c->d_cbuild, sizeof(float4) * slots) != hipSuccess ||
+                           hipMalloc((void**)&c->d_ccand, sizeof(uint16_t) * corde::kContactCand * slots) !=
+                               hipSuccess))
+        return fail(c, ROD_E_NOMEM, "contact lists");
+      // all bytes 0xff: NaN build positions, so every group builds its lists at its first step
+      HIP_TRY(c, hipMemsetAsync(c->d_cbuild, 0xff, sizeof(float4) * slots, c->stream));
+    }
   }
   return make_buckets(c, [&](int r, int* w, int* e) { default_shape(c->n[r], w, e); });
 }
@@ -998,6 +1028,11 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
     c->rods.push_back(make_dev(p, slot, pt, fr, winv0));
     c->haptic.push_back({});
     c->n.push_back(p.n_elements);
+    {
+      double rm = 0.0;
+      for (int j = 0; j < p.n_elements; ++j) rm = std::max(rm, p.radius[j]);
+      c->rmax.push_back((float)rm);
+    }
     if (p.f_ext)
       for (int i = 0; i < 3 * (p.n_elements + 1); ++i) fext[(size_t)3 * pt + i] = (float)p.f_ext[i];
     if (p.tau_ext)
@@ -1059,7 +1094,8 @@ rod_status rod_destroy(rod_ctx* c) {
                   (void*)c->d_gacc, (void*)c->d_groups, (void*)c->d_partner, (void*)c->d_rho,
                   (void*)c->d_chunks, (void*)c->d_block_chunk, (void*)c->d_pub,
                   (void*)c->d_flags, (void*)c->d_env_nodes, (void*)c->d_env_tris,
-                  (void*)c->d_env_cache, (void*)c->d_env_cand})
+                  (void*)c->d_env_cache, (void*)c->d_env_cand, (void*)c->d_cbuild,
+                  (void*)c->d_ccand})
     if (p) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);

@@ -62,7 +62,7 @@ def test_crossing_rods_vs_oracle(mu):
     _say("c6 crossing rods 2x128, mu %.1f, %d steps at 10 per launch" % (mu, n_steps))
     gpu, info = _gpu(rods, [[0, 1]], mu, n_steps)
     _say("buckets %s" % info)
-    assert info == [(2, 2, 2, 0.0)]
+    assert info == [(1, 2, 2, 0.0)]
     ref, most = O.rollout_group([s for s, _ in rods], [st for _, st in rods], n_steps, mu=mu)
     assert most >= 1
     _compare(gpu, ref, rods, "c6")
@@ -96,7 +96,7 @@ def test_coiled_rod_self_contact_vs_oracle():
     spec, st = coiled()
     gpu, info = _gpu([(spec, st)], [[0, -1]], 0.2, 200)
     _say("coiled rod, self contact, 200 steps; buckets %s" % info)
-    assert info == [(2, 2, 1, 0.0)]
+    assert info == [(1, 2, 1, 0.0)]
     ref, most = O.rollout_group([spec], [st], 200, mu=0.2)
     assert most >= 1
     _compare(gpu, ref, [(spec, st)], "coiled")
@@ -105,6 +105,56 @@ def test_coiled_rod_self_contact_vs_oracle():
     closest = min(np.linalg.norm(x[i] - x[j]) for i in range(1, 49) for j in range(i + skip + 1, 49))
     _say("  closest non-neighbour points %.5f (contact distance 0.02)" % closest)
     assert closest >= 0.98 * 0.02
+
+
+def test_contact_lists_across_launches_and_new_states():
+    """The candidate lists are kept between launches and rebuilt only when points have moved;
+    the contacts found do not depend on when that happens: 1, 7 or 100 steps per launch give
+    bitwise the same states, and so does a handle that ran on and then got its state reset."""
+    rods = _crossing()
+    outs = [_gpu(rods, [[0, 1]], 0.3, 2000, spl=k)[0] for k in (1, 7, 100)]
+    b = R.RodBatch([s for s, _ in rods])
+    b.set_contact([[0, 1]], 0.3)
+    b.set_state_rods([st for _, st in rods])
+    b.step(1300, 10)
+    b.set_state_rods([st for _, st in rods])
+    b.step(2000, 10)
+    b.sync()
+    outs.append(b.get_state_rods())
+    b.close()
+    ref, most = O.rollout_group([s for s, _ in rods], [st for _, st in rods], 2000, mu=0.3)
+    _say("crossing rods, 2000 steps at 1 / 7 / 100 per launch and after a reset; contacts %d" % most)
+    assert most >= 1
+    for o in outs[1:]:
+        for a, c in zip(o, outs[0]):
+            for u, v in zip(a, c):
+                assert np.array_equal(u, v)
+    _compare(outs[0], ref, rods, "c6")
+
+
+def test_dense_side_by_side_contact_vs_oracle():
+    """Two parallel rods whose elements are much shorter than their radius, one pressed
+    sideways onto the other: every point near the other rod has more candidate partners (pairs
+    within contact distance + margin) than a list holds, so each list build falls back to the
+    exact contacts, which stay few."""
+    n, r = 64, 0.01
+    L = n * 0.08 * r
+    a, sa = W.straight_rod(n, L=L, radius=r, young=1e7, inextensible=True, gravity=(0, 0, 0),
+                           damp=0.5)
+    b, sb = W.straight_rod(n, L=L, radius=r, young=1e6, inextensible=True,
+                           gravity=(0, -9.81, 0), damp=0.5)
+    off = np.array([0.0, 1.99 * r, 0.0])
+    sb = sb.copy()
+    sb.x = sb.x + off
+    b = b.replace(clamp_x0=tuple(np.asarray(b.clamp_x0) + off))
+    dt = min(R.stable_dt(a), R.stable_dt(b))
+    rods = [(a.replace(dt=dt), sa), (b.replace(dt=dt), sb)]
+    n_steps = 400
+    gpu, info = _gpu(rods, [[0, 1]], 0.2, n_steps)
+    ref, most = O.rollout_group([s for s, _ in rods], [st for _, st in rods], n_steps, mu=0.2)
+    _say("side by side 2x%d, l = 0.08 r, %d steps: most contacts of a point %d" % (n, n_steps, most))
+    assert 1 <= most <= 8
+    _compare(gpu, ref, rods, "side by side")
 
 
 def test_cleared_contact_steps_plainly():
