@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -34,6 +35,7 @@ using GridFn = void (*)(const RodDev*, const corde::GridChunk*, const int*, cons
 // Long-rod kernel shape: 4 wavefronts (one per SIMD) x 2 elements per lane = 512-slot windows.
 constexpr int kGridWaves = 4, kGridElems = 2;
 constexpr int kResidentMax = 2048;   // longest rod stepped by a single workgroup
+constexpr int kMaxDevices = 64;       // devices of one process the library keeps state for
 constexpr int kLongMax = 1 << 17;    // longest rod accepted (its chunks must be co-resident)
 
 using AdjointFn = void (*)(const RodDev*, const int*, const float*, int, const float*, long long,
@@ -615,7 +617,12 @@ rod_status setup_long_rods(rod_ctx* c) {
   return ROD_OK;
 }
 
-// Chunked long rods: one cooperative launch of ks steps.
+// Chunked long rods: one ordinary launch of ks steps.  The chunks wait on their neighbours, so
+// all workgroups of the grid must be resident together: the grid fits the device (checked when
+// the chunks are set up), and every chunked run of the process is ordered after the previous
+// one on the same device (LongGate), so two such grids never hold the compute units against
+// each other.  A workgroup whose neighbour still does not arrive gives up after a bounded wait
+// (status 4) instead of hanging.
 rod_status launch_long(rod_ctx* c, float* x, float* v, float* q, float* w, int ks, long long done,
                        hipStream_t stream) {
   if (!c->n_chunks) return ROD_OK;
@@ -633,9 +640,23 @@ rod_status launch_long(rod_ctx* c, float* x, float* v, float* q, float* w, int k
   int* fl = c->d_flags;
   void* args[] = {&rods, &chunks, &bc, &prm, &stride, &x, &v, &q, &w, &fe, &te, &ks, &done,
                   &st, &pub, &ps, &nc, &fl, &spin};
-  HIP_TRY(c, hipLaunchCooperativeKernel((const void*)grid_kernel(), dim3(c->n_chunks),
-                                        dim3(64 * kGridWaves), args, 0, stream));
+  HIP_TRY(c, hipLaunchKernel((const void*)grid_kernel(), dim3(c->n_chunks), dim3(64 * kGridWaves),
+                             args, 0, stream));
   return ROD_OK;
+}
+
+// Orders the chunked runs of all handles of the process, per device: a run waits for the
+// event recorded after the previous one (if another stream recorded it) and records it anew.
+// The events live until the process ends.
+struct LongGate {
+  std::mutex m;
+  hipEvent_t ev[kMaxDevices] = {};
+  hipStream_t last[kMaxDevices] = {};   // stream of the last record (valid where rec)
+  bool rec[kMaxDevices] = {};
+};
+LongGate& long_gate() {
+  static LongGate* g = new LongGate;   // never destroyed: handles may outlive static teardown
+  return *g;
 }
 
 // Zeroes the long-rod step flags (whenever the step counter restarts).
@@ -821,9 +842,15 @@ rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it, int buck
       HIP_TRY(c, hipStreamWaitEvent(c->stream, c->bevents[gi], 0));
     }
   }
-  // chunked long rods on the handle's stream, after the buckets: their cooperative launch
-  // must find every chunk's workgroup resident together
+  // chunked long rods on the handle's stream, after the buckets (all of a chunked grid's
+  // workgroups must be resident together), and after any other handle's chunked run
   if (bucket < 0 && c->n_chunks) {
+    const int dev = c->device;
+    if (dev < 0 || dev >= kMaxDevices) return fail(c, ROD_E_DEVICE, "device index out of range");
+    LongGate& g = long_gate();
+    std::lock_guard<std::mutex> lock(g.m);
+    if (!g.ev[dev]) HIP_TRY(c, hipEventCreateWithFlags(&g.ev[dev], hipEventDisableTiming));
+    if (g.rec[dev] && g.last[dev] != c->stream) HIP_TRY(c, hipStreamWaitEvent(c->stream, g.ev[dev], 0));
     for (int done = 0; done < n_steps; done += spl) {
       const int ks = std::min(spl, n_steps - done);
       rod_status rs = launch_long(c, c->d_x, c->d_v, c->d_q, c->d_w, ks, c->steps_done + done,
@@ -831,6 +858,9 @@ rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it, int buck
       if (rs != ROD_OK) return rs;
       ++launches;
     }
+    HIP_TRY(c, hipEventRecord(g.ev[dev], c->stream));
+    g.last[dev] = c->stream;
+    g.rec[dev] = true;
   }
   if (time_it) HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
   c->timed = time_it;

@@ -154,6 +154,33 @@ def test_launch_split_and_restart_are_bitwise():
             assert np.array_equal(a, c)
 
 
+def test_chunked_handles_on_two_streams_are_bitwise_alone():
+    """Two handles with chunked rods on two streams, stepped in interleaved calls: the library
+    orders their chunked runs (each grid has the device to itself), and each handle ends
+    bitwise where it ends alone."""
+    import torch
+    rods = [W.config2(16384, True).rods[0], W.config2(9000, False).rods[0]]
+    alone = [_run([r], 300, 10)[0][0] for r in rods]
+    streams = [torch.cuda.Stream() for _ in rods]
+    hs = []
+    for r, s in zip(rods, streams):
+        h = R.RodBatch([r[0]], stream=s.cuda_stream)
+        h.set_state_rods([r[1]])
+        hs.append(h)
+    _say("two handles (1x16384 inext, 1x9000 ext) on two streams, 3 x 100 steps each, interleaved")
+    for _ in range(3):
+        for h in hs:
+            h.step(100, 10)
+    got = []
+    for h in hs:
+        h.sync()
+        got.append(h.get_state_rods()[0])
+        h.close()
+    for a, b in zip(got, alone):
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+
+
 def test_mixed_handle_long_and_short(oracle):
     """One handle holding resident rods and a chunked rod: one rod_step advances all."""
     rods = W.config0().rods + W.config2(3000, True).rods + W.config2(700, False).rods
