@@ -993,6 +993,16 @@ struct GroupDev {
   float margin;        // contact candidates: pairs within contact distance + margin [m]
 };
 
+// 16-bit entry k (0..3) of a quad of list entries
+__device__ __forceinline__ int quad_get(uint2 q, int k) {
+  const uint32_t w = k < 2 ? q.x : q.y;
+  return (int)((k & 1) ? w >> 16 : w & 0xffffu);
+}
+__device__ __forceinline__ void quad_put(uint2& q, int k, uint32_t v) {
+  uint32_t& w = k < 2 ? q.x : q.y;
+  w = (k & 1) ? ((w & 0xffffu) | (v << 16)) : ((w & 0xffff0000u) | v);
+}
+
 template <int W, int E, bool CT>
 __global__ __launch_bounds__(128 * W) void rod_group_kernel(
     const RodDev* __restrict__ rods, const GroupDev* __restrict__ groups,
@@ -1015,8 +1025,10 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
   __shared__ float4 vw[2][2][CAP];
   __shared__ float4 sph[SMAX];                            // bounding spheres: centre, radius
   __shared__ uint32_t sov[SMAX][SW];                      // sphere pairs within the margin
-  __shared__ uint16_t cand[2][kContactCand][CC];          // candidates: sub * CAP + slot
-  __shared__ uint16_t lst[2][kMaxContacts][CC];           // this step's contacts
+  // candidates (sub * CAP + slot) and this step's contacts, four 16-bit entries per quad,
+  // quad-major so that a wavefront reads consecutive quads
+  __shared__ uint2 cand[2][kContactCand / 4][CC];
+  __shared__ uint2 lst[2][kMaxContacts / 4][CC];
   __shared__ float4 xbl[2][CC];      // each point's position when its candidates were listed
   __shared__ int moved[2][2 * W];                         // per wavefront and step parity
   const GroupDev gp = groups[blockIdx.x];
@@ -1054,7 +1066,8 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
       const float4 b = cbuild[gs];   // NaN position: no valid list
       xbl[sub][i] = b;
       ncand[e] = min(max(__float_as_int(b.w), 0), kContactCand);
-      for (int c = 0; c < ncand[e]; ++c) cand[sub][c][i] = ccand[(size_t)gs * kContactCand + c];
+      for (int c = 0; c < ncand[e]; ++c)
+        quad_put(cand[sub][c >> 2][i], c & 3, ccand[(size_t)gs * kContactCand + c]);
     }
   }
   const int skip = rd.self_skip;
@@ -1093,7 +1106,7 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
           const float dx = xi.x - p.x, dy = xi.y - p.y, dz = xi.z - p.z, D = rho[e] + p.w + mm;
           const float d2 = dx * dx + dy * dy + dz * dz;
           if (!(d2 < D * D) || !(d2 > 0.f)) continue;
-          if (n < kContactCand) cand[sub][n][i] = (uint16_t)(r * CAP + j);
+          if (n < kContactCand) quad_put(cand[sub][n >> 2][i], n & 3, (uint32_t)(r * CAP + j));
           ++n;
         }
       }
@@ -1183,15 +1196,31 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
         if (!L.ok[e]) continue;
         const int i = L.j0 + e;
         const V3 xi = L.X[e];
-        for (int c = 0; c < ncand[e]; ++c) {
-          const int gidx = cand[sub][c][i];
-          const int r = gidx >= CAP ? 1 : 0, j = gidx - r * CAP;
-          const float4 p = xs[xp][r][j];
-          const float dx = xi.x - p.x, dy = xi.y - p.y, dz = xi.z - p.z, D = rho[e] + p.w;
-          const float d2 = dx * dx + dy * dy + dz * dz;
-          if (!(d2 < D * D) || !(d2 > 0.f)) continue;
-          if (cnt[e] < kMaxContacts) lst[sub][cnt[e]++][i] = (uint16_t)gidx;
-          else overflow = true;
+        const float4* xsp = &xs[xp][0][0];   // indexed by sub * CAP + slot
+        // four candidates at a time: one quad read, then their four position reads together
+#pragma unroll
+        for (int q = 0; q < kContactCand; q += 4) {
+          if (q >= ncand[e]) break;
+          const uint2 w = cand[sub][q >> 2][i];
+          int g[4];
+          float4 p[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) g[k] = q + k < ncand[e] ? quad_get(w, k) : quad_get(w, 0);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) p[k] = xsp[g[k]];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            if (q + k >= ncand[e]) break;
+            const float dx = xi.x - p[k].x, dy = xi.y - p[k].y, dz = xi.z - p[k].z, D = rho[e] + p[k].w;
+            const float d2 = dx * dx + dy * dy + dz * dz;
+            if (!(d2 < D * D) || !(d2 > 0.f)) continue;
+            if (cnt[e] < kMaxContacts) {
+              quad_put(lst[sub][cnt[e] >> 2][i], cnt[e] & 3, (uint32_t)g[k]);
+              ++cnt[e];
+            } else {
+              overflow = true;
+            }
+          }
         }
       }
     }
@@ -1233,29 +1262,45 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
           const V3 xi = L.X[e], vi = L.Vv[e];
           const V3 pi = fma3(dt, vi, xi);
           const float wi = L.P[P_WINV][e];
-          V3 acc = {0.f, 0.f, 0.f};
-          int act = 0;
-          for (int c = 0; c < cnt[e]; ++c) {
-            const int gidx = lst[sub][c][i];
-            const int r = gidx >= CAP ? 1 : 0, j = gidx - r * CAP;
-            const float4 ox = xs[xp][r][j];
-            const float4 ov = vw[bpar][r][j];
+          const float4* xsp = &xs[xp][0][0];     // indexed by sub * CAP + slot
+          const float4* vwp = &vw[bpar][0][0];
+          // the impulse on this point from partner (ox, ov); false if that contact is inactive
+          auto impulse = [&](float4 ox, float4 ov, V3& imp) {
             const V3 xj = {ox.x, ox.y, ox.z}, vj = {ov.x, ov.y, ov.z};
             const float wsum = wi + ov.w;
-            if (!(wsum > 0.f)) continue;
+            if (!(wsum > 0.f)) return false;
             const V3 d0 = xi - xj;
             const V3 nrm = rsqrtf(dot(d0, d0)) * d0;        // step-start normal, towards i
             const V3 pj = fma3(dt, vj, xj);
             const float sep = dot(pi - pj, nrm) - (rho[e] + ox.w);
-            if (!(sep < 0.f)) continue;
+            if (!(sep < 0.f)) return false;
             const float lam = -sep / (dt * wsum);
             const V3 vr = vi - vj;
             const V3 vt = fnma3(dot(vr, nrm), nrm, vr);
             const float vtl = sqrtf(dot(vt, vt));
-            V3 imp = (wi * lam) * nrm;
+            imp = (wi * lam) * nrm;
             if (vtl > 0.f) imp = fnma3(wi * fminf(vtl / wsum, gp.mu * lam) / vtl, vt, imp);
-            acc = acc + imp;
-            ++act;
+            return true;
+          };
+          V3 acc = {0.f, 0.f, 0.f};
+          int act = 0;
+          // two contacts at a time (their four reads together), summed in list order
+#pragma unroll
+          for (int c = 0; c < kMaxContacts; c += 2) {
+            if (c >= cnt[e]) break;
+            const uint2 w = lst[sub][c >> 2][i];
+            const int ga = quad_get(w, c & 3);
+            const int gb = c + 1 < cnt[e] ? quad_get(w, (c & 3) + 1) : ga;
+            const float4 oxa = xsp[ga], ova = vwp[ga], oxb = xsp[gb], ovb = vwp[gb];
+            V3 imp;
+            if (impulse(oxa, ova, imp)) {
+              acc = acc + imp;
+              ++act;
+            }
+            if (c + 1 < cnt[e] && impulse(oxb, ovb, imp)) {
+              acc = acc + imp;
+              ++act;
+            }
           }
           if (act) L.Vv[e] = fma3(1.0f / (float)act, acc, L.Vv[e]);
         }
@@ -1274,7 +1319,8 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
       if (!L.ok[e]) continue;
       const int i = L.j0 + e, gs = rd.slot_off + i;
       cbuild[gs] = xbl[sub][i];
-      for (int c = 0; c < ncand[e]; ++c) ccand[(size_t)gs * kContactCand + c] = cand[sub][c][i];
+      for (int c = 0; c < ncand[e]; ++c)
+        ccand[(size_t)gs * kContactCand + c] = (uint16_t)quad_get(cand[sub][c >> 2][i], c & 3);
     }
   }
   if (overflow) atomicOr(status, 8);
