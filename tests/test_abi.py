@@ -74,8 +74,9 @@ def test_create_rejects_bad_arrays_and_counts(L):
 
 
 def test_rod_too_long_is_unsupported(L):
-    spec, _ = W.straight_rod(1 << 20)
-    assert _create_status(L, [spec])[0] == -6
+    for n in (1 << 20, (1 << 17) + 1):   # the longest accepted rod has 2^17 elements
+        spec, _ = W.straight_rod(n)
+        assert _create_status(L, [spec])[0] == -6
 
 
 def test_null_handle_calls(L):

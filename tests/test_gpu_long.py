@@ -136,6 +136,16 @@ def test_c2_65536_short_run(oracle):
     _vs_oracle(oracle, wl.rods, gpu, 200, "c2-65536")
 
 
+def test_longest_accepted_rod_short_run(oracle):
+    """The longest rod a handle accepts (2^17 elements, 283 chunks resident together), 50 steps
+    at 25 per launch, every point against the oracle."""
+    wl = W.config2(1 << 17, True)
+    _say("longest rod: 1x131072 inext, 50 steps at 25 per launch")
+    gpu, info = _run(wl.rods, 50, 25)
+    assert info == [(4, 2, 1, 0.0)]
+    _vs_oracle(oracle, wl.rods, gpu, 50, "c2-131072")
+
+
 def test_launch_split_and_restart_are_bitwise():
     """Chunk flags carry absolute step numbers across launches; rod_set_state restarts them."""
     wl = W.config2(4096, True)
