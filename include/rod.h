@@ -170,8 +170,13 @@ rod_status rod_bucket_info(const rod_ctx* ctx, int32_t bucket, rod_tuning* t, in
  * elements per chunk (0 = the most a 512-element window holds, 512 - 2 H; otherwise clamped to
  * [2 H + 2, 512 - 2 H]; chunk sizes are even and about equal).  The other rods return to their
  * default shapes (as after rod_create).  A held adjoint rollout is dropped if any rod ends up
- * chunked.  Errors: INVALID, UNSUPPORTED (too many constraint iterations to split a rod, or
- * more chunks than the device holds at once; the default split is then restored), DEVICE. */
+ * chunked.  All chunks of a handle must be resident on the device together: the handle's
+ * chunked steps run after those of any other handle of the process on the same device (stream
+ * order through one event per device), and a chunk whose neighbour does not arrive gives up
+ * after a bounded wait (rod_sync then reports ROD_E_TIMEOUT), for instance when another
+ * process holds the compute units.  Errors: INVALID, UNSUPPORTED (too many constraint
+ * iterations to split a rod, or more chunks than the device holds at once; the default split
+ * is then restored), DEVICE. */
 rod_status rod_set_chunking(rod_ctx* ctx, int32_t min_elements, int32_t chunk_elements);
 
 /* ---- Binding constraints (Sec. 2.1 "Constraints"; Sec. 3.4 variants 1 and 2) ----------
@@ -198,8 +203,12 @@ rod_status rod_set_bindings(rod_ctx* ctx, int32_t n_pairs, const int32_t* pairs,
  * penetration and a Coulomb friction impulse (coefficient mu) opposing the relative tangential
  * velocity.  A set's rods share one workgroup (with a bound pair: the same two rods); they
  * must be inextensible with equal dt and n_constraint_iters, at most 512 elements each, and
- * a point may have at most 8 contacts (more: rod_sync reports ROD_E_UNSUPPORTED).  n_sets = 0
- * removes all contact sets.  Errors: INVALID, UNSUPPORTED, NOMEM, DEVICE. */
+ * a point may have at most 8 contacts (more: rod_sync reports ROD_E_UNSUPPORTED).  The first
+ * call with contact allocates 48 bytes per element of the handle for per-point candidate lists
+ * (pairs within contact distance + half the largest radius of the set), which the kernel keeps
+ * between launches and rebuilds only when a point has moved far enough to need it; the
+ * contacts found are those of a check of all point pairs.  n_sets = 0 removes all contact
+ * sets.  Errors: INVALID, UNSUPPORTED, NOMEM, DEVICE. */
 rod_status rod_set_contact(rod_ctx* ctx, int32_t n_sets, const int32_t* sets, double mu);
 
 /* ---- Environment collision (Sec. 2.2 "Collisions"; Sec. 2.1 contact constraints) --------
