@@ -164,9 +164,11 @@ rod_status rod_get_tuning(const rod_ctx* ctx, rod_tuning* t);
 rod_status rod_bucket_info(const rod_ctx* ctx, int32_t bucket, rod_tuning* t, int32_t* n_rods);
 
 /* Step every rod longer than min_elements (1..2048; default 2048) with the chunked long-rod
- * kernel: one workgroup per chunk, neighbouring chunks trading H = 2 n_constraint_iters + 4
- * (rounded up to even) halo elements per side once per step, so a rod of up to 2048
- * elements can also be spread over several compute units.  chunk_elements sets the owned
+ * kernel: one workgroup per chunk, neighbouring chunks trading H = T (2 n_constraint_iters + 2)
+ * + 2 (rounded up to even) halo elements per side once every T steps, so a rod of up to 2048
+ * elements can also be spread over several compute units.  T (1..16) is the largest for which
+ * each halo takes at most a quarter of a 512-element window, 2 H + 2 <= chunk_elements (if
+ * set) and the rod needs at most one chunk per compute unit.  chunk_elements sets the owned
  * elements per chunk (0 = the most a 512-element window holds, 512 - 2 H; otherwise clamped to
  * [2 H + 2, 512 - 2 H]; chunk sizes are even and about equal).  The other rods return to their
  * default shapes (as after rod_create).  A held adjoint rollout is dropped if any rod ends up

@@ -1329,19 +1329,22 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
 // ---------------------------------------------------------------------------------------
 // Long rods: several workgroups per rod.  Chunk k owns slots [s0, s0 + c) and holds the window
 // [win0, win0 + nwin) = owned slots plus a halo of H slots on each side (fewer at the rod
-// ends).  Every step is computed on the whole window; slots farther than one step's dependency
-// radius (2 n_iter + 2) from a window edge are exact, so with H at least that radius the owned
-// slots are exact.  After each step the chunk publishes its first H owned slots (for the left
-// neighbour's right halo) and its last H + 1 owned slots (for the right neighbour's left halo
-// and halo-edge point) to a double-buffered mailbox in global memory, raises its flag to the
-// step count with release semantics, waits for both neighbours' flags (acquire) and refills
-// its halos: one exchange per step instead of one per phase.
+// ends).  Every step is computed on the whole window; the window edges perturb the slots within
+// one step's dependency radius (2 n_iter + 2) of them, and that front moves inwards by the
+// radius every step, so with H >= T radius the owned slots stay exact for T steps.  Every T
+// steps (except after the launch's last, whose owned slots are stored and whose halos the
+// next launch loads from the neighbours' stored slots) the chunk publishes its first H owned
+// slots (for the left neighbour's right halo) and its last H + 1 owned slots (for the right
+// neighbour's left halo and halo-edge point) to a double-buffered mailbox in global memory,
+// raises its flag to the step count, waits for both neighbours' flags and refills its halos:
+// one exchange per T steps instead of one per phase.
 struct GridChunk {
   int32_t rod;             // rod index
   int32_t s0, c;           // owned slots
   int32_t win0, nwin;      // window slots
   int32_t left, right;     // neighbour chunk indices (-1 at the rod's ends)
   int32_t halo;            // H
+  int32_t every;           // T: steps between halo exchanges (H >= T (2 n_iter + 2))
 };
 
 constexpr int kPubSlotFloats = 13;   // x, v (point j+1), q, w (frame j)
@@ -1377,6 +1380,7 @@ __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
   Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
   const int own_lo = ck.s0 - ck.win0, own_hi = own_lo + ck.c;
   const int H = ck.halo;
+  int xk = 0;   // halo exchanges so far in this launch
   if (threadIdx.x == 0) abort_flag = 0;
   __syncthreads();
 
@@ -1396,8 +1400,11 @@ __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
     }
     L.integrate_velocities(rd, xc, qc);
 
-    // ---- publish boundary slots: part 0 = owned [0, H), part 1 = owned [c - H - 1, c)
-    const int pp = (int)(gs & 1);
+    if ((s + 1) % ck.every != 0 || s + 1 == n_steps) continue;   // (uniform over the chunk)
+    // ---- publish boundary slots: part 0 = owned [0, H), part 1 = owned [c - H - 1, c), into
+    // the mailbox buffer of this launch's exchange count parity
+    const int pp = xk & 1;
+    ++xk;
     float* mine = pub + ((long long)(pp * n_chunks + ci) * 2) * pub_slots * kPubSlotFloats;
 #pragma unroll
     for (int e = 0; e < E; ++e) {

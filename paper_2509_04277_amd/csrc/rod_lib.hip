@@ -36,7 +36,8 @@ using GridFn = void (*)(const RodDev*, const corde::GridChunk*, const int*, cons
 constexpr int kGridWaves = 4, kGridElems = 2;
 constexpr int kResidentMax = 2048;   // longest rod stepped by a single workgroup
 constexpr int kMaxDevices = 64;       // devices of one process the library keeps state for
-constexpr int kLongMax = 1 << 17;    // longest rod accepted (its chunks must be co-resident)
+constexpr int kLongMax = 1 << 17;
+constexpr int kMaxExchangeEvery = 16;  // most steps between two halo exchanges of a chunked rod    // longest rod accepted (its chunks must be co-resident)
 
 using AdjointFn = void (*)(const RodDev*, const int*, const float*, int, const float*, long long,
                            int, int, int, long long, int, const float*, int, float*, float*,
@@ -537,25 +538,42 @@ rod_status rebucket(rod_ctx* c) {
 
 // Splits every rod longer than chunk_above into chunks owning c slots (even, at least 2 H + 2
 // when there are several, about chunk_target if set) with windows of at most
-// 64 kGridWaves kGridElems slots, H = 2 n_iter + 4 (rounded up to even) halo slots per side;
-// maps chunks to blocks so that neighbours share an XCD.
+// 64 kGridWaves kGridElems slots and H = T (2 n_iter + 2) + 2 (rounded up to even) halo slots
+// per side, enough for T steps between halo exchanges; T (at most kMaxExchangeEvery) is the
+// largest whose halos take at most a quarter of a window each, fit chunk_target if set, and
+// keep the rod within one chunk per compute unit (or 1).  Maps chunks to blocks so that
+// neighbours share an XCD.
 rod_status setup_long_rods(rod_ctx* c) {
   std::vector<corde::GridChunk> ch;
   int hmax = 0;
   const int K = 64 * kGridWaves * kGridElems;
+  int cus = 0;
+  HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
   for (int r = 0; r < c->n_rods; ++r) {
     const int n = c->n[r];
     if (n <= c->chunk_above) continue;
     if (c->rods[r].damp_int > 0.f)
       return fail(c, ROD_E_UNSUPPORTED, "rods with internal friction cannot be chunked");
     c->long_rods.push_back(r);
-    int H = 2 * c->rods[r].n_iter + 4;
-    H += H & 1;
+    const int rad = 2 * c->rods[r].n_iter + 2;   // one step's dependency radius in slots
+    auto halo_of = [&](int t) { const int h = t * rad + 2; return h + (h & 1); };
+    auto chunks_of = [&](int h) {
+      int cm = (K - 2 * h) & ~1;
+      if (c->chunk_target > 0) cm = std::min(cm, std::max(c->chunk_target, 2 * h + 2) & ~1);
+      int g = (n + cm - 1) / cm;
+      while (g > 1 && ((n / g) & ~1) < 2 * h + 2) --g;
+      return g;
+    };
+    int T = 1;
+    for (int t = 2; t <= kMaxExchangeEvery; ++t) {
+      const int h = halo_of(t);
+      if (4 * h > K || (c->chunk_target > 0 && 2 * h + 2 > c->chunk_target) || chunks_of(h) > cus)
+        break;
+      T = t;
+    }
+    const int H = halo_of(T);
     hmax = std::max(hmax, H);
-    int cmax = (K - 2 * H) & ~1;
-    if (c->chunk_target > 0) cmax = std::min(cmax, std::max(c->chunk_target, 2 * H + 2) & ~1);
-    int G = (n + cmax - 1) / cmax;
-    while (G > 1 && ((n / G) & ~1) < 2 * H + 2) --G;
+    const int G = chunks_of(H);
     int base = (n / G) & ~1;
     int rem = n - base * G;   // distributed two slots at a time
     int s0 = 0;
@@ -573,6 +591,7 @@ rod_status setup_long_rods(rod_ctx* c) {
       g.left = k > 0 ? first + k - 1 : -1;
       g.right = k < G - 1 ? first + k + 1 : -1;
       g.halo = H;
+      g.every = T;
       if (g.nwin > K || (G > 1 && cc < 2 * H + 2))
         return fail(c, ROD_E_UNSUPPORTED, "rod " + std::to_string(r) +
                     ": too many constraint iterations to split it into chunks");
@@ -607,9 +626,7 @@ rod_status setup_long_rods(rod_ctx* c) {
   HIP_TRY(c, hipMemcpy(c->d_block_chunk, block_chunk.data(), sizeof(int) * G, hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemset(c->d_flags, 0, sizeof(int) * G));
   // every chunk must be resident at once (the chunks wait on each other)
-  int per_cu = 0, cus = 0, dev = 0;
-  HIP_TRY(c, hipGetDevice(&dev));
-  HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int per_cu = 0;
   HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, grid_kernel(), 64 * kGridWaves, 0));
   if ((long long)per_cu * cus < G)
     return fail(c, ROD_E_UNSUPPORTED, "long rods need " + std::to_string(G) +
