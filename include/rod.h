@@ -31,6 +31,8 @@
  *     without waiting.  on_device = 0: host pointers; the call synchronises the stream.
  *   - All work is enqueued on the HIP stream given at creation (NULL = default stream) and is
  *     stream-ordered.  Calls on one handle must not be made concurrently from two threads.
+ *   - A handle lives on the device that is current at rod_create (its stream must belong to
+ *     it); later calls must be made with that device current (rod_step: ROD_E_DEVICE if not).
  *   - Non-finite state seen by a kernel is latched on the device; the next call that
  *     synchronises (rod_sync, host rod_get_state) returns ROD_E_UNSTABLE.
  */

@@ -1207,6 +1207,11 @@ rod_status rod_step(rod_ctx* c, int32_t n_steps, int32_t steps_per_launch) {
   if (n_steps < 0) return fail(c, ROD_E_INVALID, "n_steps must be >= 0");
   if (steps_per_launch < 0) return fail(c, ROD_E_INVALID, "steps_per_launch must be >= 0");
   if (n_steps == 0) return ROD_OK;
+  int dev = -1;
+  HIP_TRY(c, hipGetDevice(&dev));
+  if (dev != c->device)
+    return fail(c, ROD_E_DEVICE, "the handle's device (" + std::to_string(c->device) +
+                ") is not the current device (" + std::to_string(dev) + ")");
   const int spl = steps_per_launch > 0 ? steps_per_launch : std::max(1, c->steps_per_launch);
   return launch_steps(c, n_steps, spl, true);
 }
