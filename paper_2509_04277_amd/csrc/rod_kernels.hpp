@@ -1347,7 +1347,10 @@ struct GridChunk {
   int32_t every;           // T: steps between halo exchanges (H >= T (2 n_iter + 2))
 };
 
-constexpr int kPubSlotFloats = 13;   // x, v (point j+1), q, w (frame j)
+// Mailbox part: the 13 words (x, v of point j+1; q, w of frame j) of up to pub_slots slots,
+// word-major (word k of slot i at k pub_slots + i), so that a wavefront's store or load of one
+// word covers consecutive addresses.
+constexpr int kPubSlotFloats = 13;
 
 // Mailbox words are read and written as device-scope relaxed atomics (coherent across the
 // XCDs' L2 caches without writing back or invalidating them); the step flags order them.
@@ -1413,12 +1416,12 @@ __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
       const bool p0 = L.ok[e] && o >= 0 && o < H && ck.left >= 0;
       const bool p1 = L.ok[e] && o >= ck.c - H - 1 && o < ck.c && ck.right >= 0;
       if (p0 || p1) {
-        float* d = mine + (p0 ? o : pub_slots + o - (ck.c - H - 1)) * kPubSlotFloats;
+        float* d = p0 ? mine + o : mine + pub_slots * kPubSlotFloats + (o - (ck.c - H - 1));
         const float v[kPubSlotFloats] = {L.X[e].x, L.X[e].y, L.X[e].z, L.Vv[e].x, L.Vv[e].y,
                                          L.Vv[e].z, L.Qf[e].w, L.Qf[e].x, L.Qf[e].y, L.Qf[e].z,
                                          L.Om[e].x, L.Om[e].y, L.Om[e].z};
 #pragma unroll
-        for (int k = 0; k < kPubSlotFloats; ++k) put_coherent(d + k, v[k]);
+        for (int k = 0; k < kPubSlotFloats; ++k) put_coherent(d + k * pub_slots, v[k]);
       }
     }
     // this thread's mailbox stores are complete (device-visible) before the barrier, and the
@@ -1457,12 +1460,12 @@ __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
     for (int e = 0; e < E; ++e) {
       const int o = L.j0 + e - own_lo;
       const float* src = nullptr;
-      if (L.ok[e] && o < 0 && lp) src = lp + (o + H + 1) * kPubSlotFloats;   // slot s0 + o
-      if (L.ok[e] && o >= ck.c && rp) src = rp + (o - ck.c) * kPubSlotFloats;
+      if (L.ok[e] && o < 0 && lp) src = lp + (o + H + 1);   // slot s0 + o
+      if (L.ok[e] && o >= ck.c && rp) src = rp + (o - ck.c);
       if (src) {
         float v[kPubSlotFloats];
 #pragma unroll
-        for (int k = 0; k < kPubSlotFloats; ++k) v[k] = get_coherent(src + k);
+        for (int k = 0; k < kPubSlotFloats; ++k) v[k] = get_coherent(src + k * pub_slots);
         L.X[e] = {v[0], v[1], v[2]};
         L.Vv[e] = {v[3], v[4], v[5]};
         L.Qf[e] = {v[6], v[7], v[8], v[9]};
@@ -1470,8 +1473,9 @@ __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
       }
     }
     if (L.g == 0 && L.ghost && lp) {   // halo-edge point: point win0 = point of slot win0 - 1
-      L.bx = {get_coherent(lp), get_coherent(lp + 1), get_coherent(lp + 2)};
-      L.bv = {get_coherent(lp + 3), get_coherent(lp + 4), get_coherent(lp + 5)};
+      const int ps = pub_slots;
+      L.bx = {get_coherent(lp), get_coherent(lp + ps), get_coherent(lp + 2 * ps)};
+      L.bv = {get_coherent(lp + 3 * ps), get_coherent(lp + 4 * ps), get_coherent(lp + 5 * ps)};
     }
   }
   const float chk = L.store_state(rd, gx, gv, gq, gw, own_lo, own_hi);

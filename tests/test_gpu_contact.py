@@ -157,6 +157,41 @@ def test_dense_side_by_side_contact_vs_oracle():
     _compare(gpu, ref, rods, "side by side")
 
 
+def _unequal(gap=1e-3):
+    """A 300-element bar along x (1 m, no gravity) and a 60-element rod along y (0.5 m) that
+    falls across its middle from gap above; both radius 4 mm, inextensible, static clamps."""
+    import math
+    r = 0.004
+    out = []
+    q_y = (math.cos(math.pi / 4), -math.sin(math.pi / 4), 0.0, 0.0)
+    for n, L, base, d3, q0, young, grav in (
+            (300, 1.0, (0.0, 0.0, 0.0), (1.0, 0.0, 0.0), W.Q_ALONG_X, 1e7, (0.0, 0.0, 0.0)),
+            (60, 0.5, (0.5, -0.25, 2 * r + gap), (0.0, 1.0, 0.0), q_y, 1e6, (0.0, 0.0, -9.81))):
+        l = L / n
+        x = np.asarray(base)[None, :] + np.outer(np.arange(n + 1) * l, d3)
+        q = np.tile(np.asarray(q0, dtype=np.float64), (n, 1))
+        spec = W.RodSpec(n=n, inextensible=True, n_iter=10, clamp=True, dt=1e-5, gravity=grav,
+                         damp_lin=0.5, damp_ang=0.5, poisson=0.5, density=1000.0,
+                         seg_len=np.full(n, l), radius=np.full(n, r), young=np.full(n, young),
+                         clamp_x0=tuple(base), clamp_q0=tuple(q0))
+        out.append((spec, W.RodState(x=x, v=np.zeros_like(x), q=q, w=np.zeros((n, 3)))))
+    dt = min(R.stable_dt(s) for s, _ in out)
+    return [(s.replace(dt=dt), st) for s, st in out]
+
+
+def test_rods_of_different_lengths_vs_oracle():
+    """Contact between a 300-element and a 60-element rod (one workgroup of two 4 x 2 halves,
+    the short rod's half mostly idle)."""
+    rods = _unequal()
+    n_steps = 1500
+    gpu, info = _gpu(rods, [[0, 1]], 0.2, n_steps)
+    ref, most = O.rollout_group([s for s, _ in rods], [st for _, st in rods], n_steps, mu=0.2)
+    _say("300 + 60 elements crossing, %d steps: buckets %s, contacts %d" % (n_steps, info, most))
+    assert info == [(4, 2, 2, 0.0)]
+    assert most >= 1
+    _compare(gpu, ref, rods, "unequal")
+
+
 def test_cleared_contact_steps_plainly():
     rods = _crossing()
     b = R.RodBatch([s for s, _ in rods])
