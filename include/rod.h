@@ -285,9 +285,12 @@ rod_status rod_haptic_get_force(rod_ctx* ctx, int32_t rod, rod_haptic_force* out
 
 /* Per bucket, time every built shape that holds its longest rod on probe_steps steps (the
  * state is saved and restored, the step counter unchanged) and keep the fastest; sets the
- * handle's steps_per_launch.  steps_per_launch = 0: the shapes are timed at 10 steps per launch,
- * then the whole handle at 1, 2, 5, 10, 20, 50, ..., 1000 steps per launch (up to probe_steps),
- * and the smallest that comes within 5 % of the best time per step is kept.  Rods with a haptic
+ * handle's steps_per_launch.  steps_per_launch = 0: first, while the long-rod split is the
+ * default one, the whole handle is timed with its rods of more than 512 elements in one
+ * workgroup each and chunked as by rod_set_chunking(ctx, 512, 0), and the faster split is kept
+ * (a chunked rod is not differentiated by the adjoint); then the shapes are timed at 10 steps
+ * per launch, then the whole handle at 1, 2, 5, 10, 20, 50, ..., 1000 steps per launch (up to
+ * probe_steps), and the smallest that comes within 5 % of the best time per step is kept.  Rods with a haptic
  * mailbox read its pose and write force records during the probes.  out (nullable) receives
  * rod_get_tuning(). */
 rod_status rod_autotune(rod_ctx* ctx, int32_t probe_steps, int32_t steps_per_launch,

@@ -35,6 +35,7 @@ using GridFn = void (*)(const RodDev*, const corde::GridChunk*, const int*, cons
 // Long-rod kernel shape: 4 wavefronts (one per SIMD) x 2 elements per lane = 512-slot windows.
 constexpr int kGridWaves = 4, kGridElems = 2;
 constexpr int kResidentMax = 2048;   // longest rod stepped by a single workgroup
+constexpr int kChunkTry = 512;       // rods longer than this may be chunked by rod_autotune
 constexpr int kMaxDevices = 64;       // devices of one process the library keeps state for
 constexpr int kLongMax = 1 << 17;
 constexpr int kMaxExchangeEvery = 16;  // most steps between two halo exchanges of a chunked rod    // longest rod accepted (its chunks must be co-resident)
@@ -1683,6 +1684,33 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
   }
   const long long saved_steps = c->steps_done;
   rod_status st = ROD_OK;
+  // whole-handle time per step at steps_per_launch (best of two probes)
+  auto whole = [&](float* us) -> rod_status {
+    float ms_best = INFINITY;
+    for (int rep = 0; rep < 2; ++rep) {
+      rod_status s2 = launch_steps(c, probe_steps, steps_per_launch, true);
+      float ms = 0;
+      int nl = 0;
+      if (s2 == ROD_OK) s2 = rod_last_step_time(c, &ms, &nl);
+      if (s2 != ROD_OK) return s2;
+      ms_best = std::min(ms_best, ms);
+    }
+    *us = 1000.f * ms_best / probe_steps;
+    return ROD_OK;
+  };
+  // steps_per_launch = 0 also decides whether the rods of more than kChunkTry elements step
+  // chunked over several compute units or in one workgroup each (while the split is the
+  // default one): the faster of the two is kept
+  if (pick_k && c->chunk_above == kResidentMax && c->chunk_target == 0) {
+    bool any = false;
+    for (int r = 0; r < c->n_rods; ++r) any = any || (c->n[r] > kChunkTry && c->n[r] <= kResidentMax);
+    float us_one = 0.f, us_chunked = 0.f;
+    if (any) st = whole(&us_one);
+    if (any && st == ROD_OK && rod_set_chunking(c, kChunkTry, 0) == ROD_OK) {
+      st = whole(&us_chunked);
+      if (st == ROD_OK && !(us_chunked < us_one)) st = rod_set_chunking(c, kResidentMax, 0);
+    }
+  }
   // per bucket: time every built shape that holds its longest rod without idling most lanes
   std::vector<rod_ctx::Bucket> chosen = c->buckets;
   for (size_t bi = 0; bi < chosen.size() && st == ROD_OK; ++bi) {
@@ -1797,7 +1825,9 @@ rod_status rod_adjoint_forward(rod_ctx* c, int32_t n_steps, int32_t ckpt_every, 
       return fail(c, ROD_E_UNSUPPORTED, "adjoint supports at most 10 constraint iterations");
   for (const auto& b : c->buckets)
     if (!adjoint_shape(b.max_n)) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
-  if (c->n_chunks) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
+  if (c->n_chunks)
+    return fail(c, ROD_E_UNSUPPORTED,
+                "chunked rods are not differentiated (rod_set_chunking(ctx, 2048, 0) restores the default split)");
   if (!c->groups.empty()) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not step grouped rods");
   if (c->n_haptic) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not step rods with a haptic mailbox");
   if (c->env_nodes) return fail(c, ROD_E_UNSUPPORTED, "the adjoint does not step rods against an environment");
@@ -1838,7 +1868,9 @@ rod_status rod_adjoint_backward(rod_ctx* c, const float* dl_dtips, float* dl_dbe
                                 float* dl_dw, int32_t on_device) {
   if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
   if (!c->adj_ready) return fail(c, ROD_E_ORDER, "rod_adjoint_backward without rod_adjoint_forward");
-  if (c->n_chunks) return fail(c, ROD_E_UNSUPPORTED, "rod too long for the adjoint kernel");
+  if (c->n_chunks)
+    return fail(c, ROD_E_UNSUPPORTED,
+                "chunked rods are not differentiated (rod_set_chunking(ctx, 2048, 0) restores the default split)");
   if (!dl_dtips) return fail(c, ROD_E_INVALID, "null dL/dtip");
   const size_t S = state_floats(c);
   const size_t P3 = (size_t)3 * c->total_pts, F4 = (size_t)4 * c->total_frames;

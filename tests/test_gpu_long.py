@@ -146,6 +146,29 @@ def test_longest_accepted_rod_short_run(oracle):
     _vs_oracle(oracle, wl.rods, gpu, 50, "c2-131072")
 
 
+def test_autotune_chunks_a_lone_long_rod(oracle):
+    """rod_autotune with steps_per_launch = 0 times a lone 2048-element rod in one workgroup and
+    chunked, keeps the faster (chunked: about 5 against 8.5 us per step), leaves state and step
+    counter as they were, and the rod then steps as the oracle does."""
+    wl = W.config2(2048, True)
+    spec, st = wl.rods[0]
+    b = R.RodBatch([spec])
+    b.set_state_rods([st])
+    before = b.get_state()
+    t = b.autotune(probe_steps=100, steps_per_launch=0)
+    info = b.buckets()
+    _say("autotune on 1x2048 inext chose %s, buckets %s" % (t, info))
+    assert info == [(4, 2, 1, 0.0)]   # the chunked long-rod bucket
+    assert b.time()[1] == 0
+    for u, v in zip(before, b.get_state()):
+        assert np.array_equal(u, v)
+    b.step(300)
+    b.sync()
+    gpu = b.get_state_rods()
+    b.close()
+    _vs_oracle(oracle, wl.rods, gpu, 300, "autotuned-2048")
+
+
 def test_launch_split_and_restart_are_bitwise():
     """Chunk flags carry absolute step numbers across launches; rod_set_state restarts them."""
     wl = W.config2(4096, True)
