@@ -668,6 +668,45 @@ struct RodLane {
     }
     V3 dvb = {0.f, 0.f, 0.f};
     V3 nv[E];
+    if constexpr (E % 2 == 0) {
+      // Even E: slot e has the parity of e (lane and window starts are even).  Half-sweep 1
+      // pairs slots (0, 1), (2, 3), ..., half-sweep 0 pairs (1, 2), (3, 4), ...: the two slots
+      // of a pair are the ends of one segment, whose impulse is computed once from the
+      // operands both ends would use (slot a's next-segment coefficients are slot a + 1's own),
+      // so the result is the same as computing it at each end.  In half-sweep 0 slots 0 and
+      // E - 1 act on the segments that cross to the lanes below and above.
+      auto pair = [&](int a) {   // the segment between slots a and a + 1 (slot a + 1's)
+        const V3 d = fma3(dt, Vv[a + 1] - Vv[a], Ev[a + 1]);
+        const V3 im = impulse_d(d, P[P_CI][a + 1], P[P_CIL][a + 1]);
+        nv[a] = fma3(P[P_WINV][a], im, Vv[a]);
+        nv[a + 1] = fnma3(P[P_WINV][a + 1], im, Vv[a + 1]);
+        if (dsnap) {
+          dsnap[a] = d;
+          dsnap[a + 1] = d;
+        }
+      };
+      if (h == 0) {
+        const V3 d0 = fma3(dt, Vv[0] - vlo, Ev[0]);
+        const V3 im0 = impulse_d(d0, P[P_CI][0], P[P_CIL][0]);
+        nv[0] = fnma3(P[P_WINV][0], im0, Vv[0]);
+        if (dsnap) dsnap[0] = d0;
+        dvb = P[P_WINV_PREV][0] * im0;   // base point: left end of segment 0
+        imp0 = imp0 + im0;
+#pragma unroll
+        for (int a = 1; a + 1 < E; a += 2) pair(a);
+        const V3 dl = fma3(dt, vhi - Vv[E - 1], enext);
+        const V3 iml = impulse_d(dl, P[P_CI_NEXT][E - 1], P[P_CIL_NEXT][E - 1]);
+        nv[E - 1] = fma3(P[P_WINV][E - 1], iml, Vv[E - 1]);
+        if (dsnap) dsnap[E - 1] = dl;
+      } else {
+#pragma unroll
+        for (int a = 0; a < E; a += 2) pair(a);
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) Vv[e] = nv[e];
+      if (g == 0 && h == 0 && !rd.clamp && !ghost) bv = bv + dvb;
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int j = j0 + e;
