@@ -235,6 +235,36 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
             }
             V3 nv[E];
             V3 dbase = {0.f, 0.f, 0.f};
+            if constexpr (E % 2 == 0) {
+              // even E: the slots pair up as the two ends of one segment as in the forward
+              // half-sweep (both ends saw the same segment vector and their coefficients agree:
+              // a slot's next-segment ones are the next slot's own, its inverse mass is the next
+              // slot's previous one), so one adjoint serves both ends
+              auto pair = [&](int a) {
+                const V3 db = impulse_adjoint(ds[it][h][a + 1], L.P[P_CI][a + 1], L.P[P_CIL][a + 1],
+                                              L.P[P_WINV_PREV][a + 1], L.P[P_WINV][a + 1], AVc[a],
+                                              AVc[a + 1]);
+                nv[a] = fnma3(dt, db, AVc[a]);           // left end
+                nv[a + 1] = fma3(dt, db, AVc[a + 1]);    // right end
+                EB[a + 1] = EB[a + 1] + db;
+              };
+              if (h == 0) {
+                const V3 db0 = impulse_adjoint(ds[it][0][0], L.P[P_CI][0], L.P[P_CIL][0],
+                                               L.P[P_WINV_PREV][0], L.P[P_WINV][0], glo, AVc[0]);
+                nv[0] = fma3(dt, db0, AVc[0]);
+                EB[0] = EB[0] + db0;
+                dbase = db0;
+#pragma unroll
+                for (int a = 1; a + 1 < E; a += 2) pair(a);
+                const V3 dbl = impulse_adjoint(ds[it][0][E - 1], L.P[P_CI_NEXT][E - 1],
+                                               L.P[P_CIL_NEXT][E - 1], L.P[P_WINV][E - 1], WN[E - 1],
+                                               AVc[E - 1], ghi);
+                nv[E - 1] = fnma3(dt, dbl, AVc[E - 1]);
+              } else {
+#pragma unroll
+                for (int a = 0; a < E; a += 2) pair(a);
+              }
+            } else {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
               const int j = j0 + e;
@@ -252,6 +282,7 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
               nv[e] = sel(is_hi, fma3(dt, db_h, AVc[e]), fnma3(dt, db_l, AVc[e]));
               EB[e] = sel(is_hi, EB[e] + db_h, EB[e]);
               if (e == 0) dbase = db_h;
+            }
             }
 #pragma unroll
             for (int e = 0; e < E; ++e) AVc[e] = nv[e];
