@@ -1706,9 +1706,12 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
     for (int r = 0; r < c->n_rods; ++r) any = any || (c->n[r] > kChunkTry && c->n[r] <= kResidentMax);
     float us_one = 0.f, us_chunked = 0.f;
     if (any) st = whole(&us_one);
+    const std::string err0 = c->err;   // a refused split (e.g. a rod with a mailbox) is no error
     if (any && st == ROD_OK && rod_set_chunking(c, kChunkTry, 0) == ROD_OK) {
       st = whole(&us_chunked);
       if (st == ROD_OK && !(us_chunked < us_one)) st = rod_set_chunking(c, kResidentMax, 0);
+    } else if (st == ROD_OK) {
+      c->err = err0;
     }
   }
   // per bucket: time every built shape that holds its longest rod without idling most lanes
