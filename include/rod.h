@@ -114,7 +114,8 @@ typedef struct rod_tuning {
  * enqueuing work on hip_stream (a hipStream_t, NULL = default).  Derives all per-element
  * coefficients (masses, inertias, stiffnesses of eqs. (2), (3), (8)) in FP64 on the host.
  * Rods of up to 2048 elements are stepped by one workgroup each; longer rods are split into
- * chunks of about 500 elements, one workgroup per chunk, that exchange halos once per step
+ * chunks of up to about 500 elements, one workgroup per chunk, that exchange halos once every
+ * few steps (see rod_set_chunking)
  * (all chunks of a handle must be resident on the device at once: ROD_E_UNSUPPORTED if not,
  * and for any rod longer than 131072 elements).
  * The state is zero until rod_set_state().  Errors: INVALID (bad sizes/values), NOMEM,
