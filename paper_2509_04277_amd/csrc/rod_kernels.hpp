@@ -1070,6 +1070,7 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
   __shared__ uint2 lst[2][kMaxContacts / 4][CC];
   __shared__ float4 xbl[2][CC];      // each point's position when its candidates were listed
   __shared__ int moved[2][2 * W];                         // per wavefront and step parity
+  __shared__ int touching[2][2 * W];                      // ditto: some point has a contact
   const GroupDev gp = groups[blockIdx.x];
   const int sub = threadIdx.x >= 64 * W ? 1 : 0;
   const bool active = gp.rod[sub] >= 0;
@@ -1119,6 +1120,7 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
   const float dt = rd.dt;
   int bpar = 0;
   bool overflow = false;
+  bool touch = false;   // some point of the group has a contact this step
   auto publish = [&]() {
 #pragma unroll
     for (int e = 0; e < E; ++e)
@@ -1262,6 +1264,17 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
           }
         }
       }
+      // the iterations' contact rounds (a publication and its barrier each) are skipped in
+      // steps where no point of the group touches anything
+      bool mine = false;
+#pragma unroll
+      for (int e = 0; e < E; ++e) mine = mine || cnt[e] > 0;
+      const bool wt = __ballot(mine) != 0ull;
+      if ((threadIdx.x & 63) == 0) touching[s & 1][threadIdx.x >> 6] = wt ? 1 : 0;
+      __syncthreads();
+      touch = false;
+#pragma unroll
+      for (int k = 0; k < 2 * W; ++k) touch = touch || touching[s & 1][k] != 0;
     }
 
     // ---- the step
@@ -1292,7 +1305,7 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
         }
         bpar ^= 1;
       }
-      if (contact) {
+      if (contact && touch) {   // (uniform over the workgroup)
         publish();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
