@@ -15,18 +15,25 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "corde_oracle.c")
-LIB = os.path.join(HERE, "libcorde_oracle.so")
+# CORDE_ORACLE_LIB names a library built elsewhere by build(src=..., lib=...): the mutation test
+# loads copies of the oracle with planted mistakes this way, one process each.
+PREBUILT = os.environ.get("CORDE_ORACLE_LIB")
+LIB = PREBUILT or os.path.join(HERE, "libcorde_oracle.so")
 
 
-def build(force: bool = False) -> str:
-    """Compile corde_oracle.c with gcc (FP64, -O2, no fast-math)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
+def build(force: bool = False, src: str = SRC, lib: str = None) -> str:
+    """Compile corde_oracle.c (or the copy ``src``) with gcc (FP64, -O2, no fast-math)."""
+    if lib is None:
+        if PREBUILT:
+            return PREBUILT
+        lib = LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+        tmp = lib + ".tmp%d" % os.getpid()
         subprocess.check_call(
             ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-             "-ffp-contract=off", "-Wall", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+             "-ffp-contract=off", "-Wall", "-I", HERE, "-o", tmp, src, "-lm"])
+        os.replace(tmp, lib)
+    return lib
 
 
 class _Rod(C.Structure):
