@@ -821,15 +821,13 @@ rod_status rebuild_groups(rod_ctx* c) {
 
 // n_steps steps of every rod, spl steps per launch; bucket < 0: all buckets, else that one.
 rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it, int bucket = -1) {
-  if (time_it) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-  int launches = 0;
   // the buckets (and the bound-pair buckets) are independent: with several, each steps on its
   // own stream (forked from and joined back to the handle's stream)
   const int nb = bucket >= 0 ? 1 : (int)c->buckets.size();
   const int np = bucket >= 0 ? 0 : (int)c->pair_buckets.size();
   const int ng = nb + np;
   const bool fork = ng > 1;
-  if (fork) {
+  if (fork) {   // streams and events made on first use, before the timed interval opens
     while ((int)c->bstreams.size() < ng) {
       hipStream_t st = nullptr;
       hipEvent_t ev = nullptr;
@@ -839,8 +837,10 @@ rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it, int buck
       c->bevents.push_back(ev);
     }
     if (!c->ev_fork) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-    HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
   }
+  if (time_it) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+  int launches = 0;
+  if (fork) HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
   for (int gi = 0; gi < ng; ++gi) {
     hipStream_t st = c->stream;
     if (fork) {
