@@ -341,3 +341,29 @@ def test_c3_full_size_sampled(oracle):
     for i, (x, v, q, w) in enumerate(got):   # every rod: finite, unit quaternions
         assert np.isfinite(x).all() and np.isfinite(v).all()
         assert np.abs(np.linalg.norm(q.astype(np.float64), axis=1) - 1).max() <= 1e-6, i
+
+
+def test_first_multi_bucket_step_time_excludes_stream_setup():
+    """The per-bucket streams are made on a handle's first multi-bucket step, outside the interval
+    that rod_last_step_time() reports: the first step's time matches the next ones' (stream
+    creation costs milliseconds, these steps tens of microseconds)."""
+    wl = W.config3(n_rods=64, n_min=32, n_max=1500)
+    rods = [(s.replace(dt=R.stable_dt(s)), st) for s, st in wl.rods]
+    warm = R.RodBatch([s for s, _ in rods])   # first launches of these kernels: not timed here
+    warm.set_state_rods([st for _, st in rods])
+    warm.step(1, 1)
+    warm.sync()
+    warm.close()
+    b = R.RodBatch([s for s, _ in rods])   # a new handle makes its own streams
+    n_buckets = len(b.buckets())
+    assert n_buckets >= 3
+    b.set_state_rods([st for _, st in rods])
+    times = []
+    for _ in range(4):
+        b.step(20, 20)
+        b.sync()
+        times.append(b.last_step_time()[0])
+    b.close()
+    _say("20-step times of a %d-bucket handle: %s ms" % (n_buckets, times))
+    steady = float(np.median(times[1:]))
+    assert times[0] < 3.0 * steady + 0.2, times
