@@ -252,6 +252,50 @@ void oracle_rollout_pair(const oracle_rod* a, const oracle_rod* b, const oracle_
                          double t0, int32_t n_steps, double* xa, double* va, double* qa, double* wa,
                          double* xb, double* vb, double* qb, double* wb);
 
+
+/* ---- Reference derivatives (corde_oracle_grad.cpp, C++) --------------------------------
+ * Derivatives of the tip trajectory tip(s) = x_N after step s (s = 0 .. n_steps-1) of a
+ * rollout of the plain step from time t0, with respect to the initial state (x, v, q, w; q by
+ * its four stored components) and the multipliers m_b of K_1 = K_2 and m_t of K_3 (eq. (3)),
+ * taken at m_b = m_t = 1.  Rods with internal friction are refused (nonzero return); 0 = done. */
+
+/* The rollout through the templated restatement of the step in corde_oracle_grad.cpp,
+ * evaluated in plain doubles; it must equal oracle_rollout bitwise.  tip nullable. */
+int32_t oracle_grad_rollout(const oracle_rod* rod, double t0, int32_t n_steps, double* x,
+                            double* v, double* q, double* w, double* tip);
+
+/* Forward mode: tip (nullable, n_steps x 3) and its directional derivative dtip (n_steps x 3)
+ * along the initial-state direction (dx, dv, dq, dw; each nullable = 0) and multiplier
+ * direction (dmb, dmt). */
+int32_t oracle_jvp(const oracle_rod* rod, double t0, int32_t n_steps, const double* x,
+                   const double* v, const double* q, const double* w, const double* dx,
+                   const double* dv, const double* dq, const double* dw, double dmb, double dmt,
+                   double* tip, double* dtip);
+
+/* Reverse mode: for the cotangent ct (n_steps x 3) the gradient of L = sum_s ct[s] . tip(s):
+ * gx, gv ((N+1) x 3), gq (N x 4), gw (N x 3), gmb, gmt.  round_fp32 = 1 rounds the stored state
+ * to FP32 after every step of the forward pass (the rounding's derivative taken as 1): the
+ * gradient of an FP32-storage trajectory.  tip (nullable) receives the forward trajectory. */
+int32_t oracle_vjp(const oracle_rod* rod, double t0, int32_t n_steps, const double* x,
+                   const double* v, const double* q, const double* w, const double* ct,
+                   int32_t round_fp32, double* gx, double* gv, double* gq, double* gw,
+                   double* gmb, double* gmt, double* tip);
+
+/* oracle_vjp for n_rods independent rods on n_threads threads (0 = all hardware threads);
+ * per-rod pointer arrays; tip nullable. */
+int32_t oracle_vjp_many(int32_t n_rods, const oracle_rod* rods, double t0, int32_t n_steps,
+                        const double* const* x, const double* const* v, const double* const* q,
+                        const double* const* w, const double* const* ct, int32_t round_fp32,
+                        double* const* gx, double* const* gv, double* const* gq,
+                        double* const* gw, double* gmb, double* gmt, double* const* tip,
+                        int32_t n_threads);
+
+/* oracle_rollout of n_rods independent rods (in place, no tips) on n_threads threads
+ * (0 = all hardware threads). */
+int32_t oracle_rollout_many(int32_t n_rods, const oracle_rod* rods, double t0, int32_t n_steps,
+                            double* const* x, double* const* v, double* const* q,
+                            double* const* w, int32_t n_threads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,23 +15,35 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "corde_oracle.c")
+GRAD_SRC = os.path.join(HERE, "corde_oracle_grad.cpp")
+HDR = os.path.join(HERE, "corde_oracle.h")
 # CORDE_ORACLE_LIB names a library built elsewhere by build(src=..., lib=...): the mutation test
 # loads copies of the oracle with planted mistakes this way, one process each.
 PREBUILT = os.environ.get("CORDE_ORACLE_LIB")
 LIB = PREBUILT or os.path.join(HERE, "libcorde_oracle.so")
 
 
-def build(force: bool = False, src: str = SRC, lib: str = None) -> str:
-    """Compile corde_oracle.c (or the copy ``src``) with gcc (FP64, -O2, no fast-math)."""
+def build(force: bool = False, src: str = SRC, lib: str = None, grad_src: str = GRAD_SRC) -> str:
+    """Compile corde_oracle.c (or the copy ``src``) with gcc and corde_oracle_grad.cpp (or the
+    copy ``grad_src``) with g++ into one library (FP64, -O2, no fast-math, no contraction)."""
     if lib is None:
         if PREBUILT:
             return PREBUILT
         lib = LIB
-    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+    deps = [src, grad_src, HDR]
+    if force or not os.path.exists(lib) or any(os.path.getmtime(lib) < os.path.getmtime(d)
+                                               for d in deps):
         tmp = lib + ".tmp%d" % os.getpid()
-        subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-             "-ffp-contract=off", "-Wall", "-I", HERE, "-o", tmp, src, "-lm"])
+        obj_c, obj_cc = tmp + ".c.o", tmp + ".cc.o"
+        common = ["-O2", "-fPIC", "-fno-fast-math", "-ffp-contract=off", "-Wall", "-I", HERE]
+        try:
+            subprocess.check_call(["gcc", "-std=c11"] + common + ["-c", "-o", obj_c, src])
+            subprocess.check_call(["g++", "-std=c++17"] + common + ["-c", "-o", obj_cc, grad_src])
+            subprocess.check_call(["g++", "-shared", "-pthread", "-o", tmp, obj_c, obj_cc, "-lm"])
+        finally:
+            for o in (obj_c, obj_cc):
+                if os.path.exists(o):
+                    os.remove(o)
         os.replace(tmp, lib)
     return lib
 
@@ -121,6 +133,21 @@ def lib():
         L.oracle_rollout_env.restype = None
         L.oracle_rollout_env.argtypes = [C.POINTER(_Rod), C.POINTER(_Env), C.c_double, C.c_int32,
                                          _DP, _DP, _DP, _DP, C.POINTER(C.c_int32)]
+        L.oracle_grad_rollout.restype = C.c_int32
+        L.oracle_grad_rollout.argtypes = [C.POINTER(_Rod), C.c_double, C.c_int32] + [_DP] * 5
+        L.oracle_jvp.restype = C.c_int32
+        L.oracle_jvp.argtypes = ([C.POINTER(_Rod), C.c_double, C.c_int32] + [_DP] * 8 +
+                                 [C.c_double, C.c_double, _DP, _DP])
+        L.oracle_vjp.restype = C.c_int32
+        L.oracle_vjp.argtypes = ([C.POINTER(_Rod), C.c_double, C.c_int32] + [_DP] * 5 +
+                                 [C.c_int32] + [_DP] * 7)
+        _PP = C.POINTER(_DP)
+        L.oracle_vjp_many.restype = C.c_int32
+        L.oracle_vjp_many.argtypes = ([C.c_int32, C.POINTER(_Rod), C.c_double, C.c_int32] +
+                                      [_PP] * 5 + [C.c_int32] + [_PP] * 4 + [_DP, _DP, _PP, C.c_int32])
+        L.oracle_rollout_many.restype = C.c_int32
+        L.oracle_rollout_many.argtypes = ([C.c_int32, C.POINTER(_Rod), C.c_double, C.c_int32] +
+                                          [_PP] * 4 + [C.c_int32])
         _lib = L
     return _lib
 
@@ -308,6 +335,57 @@ class Rod:
         st.x, st.v, st.q, st.w = x, v, q, w
         return st, fb
 
+    # --- reference derivatives (corde_oracle_grad.cpp) -----------------------------
+    def _state64(self, state):
+        return (_f64(state.x, (self.n + 1, 3)).copy(), _f64(state.v, (self.n + 1, 3)).copy(),
+                _f64(state.q, (self.n, 4)).copy(), _f64(state.w, (self.n, 3)).copy())
+
+    def grad_rollout(self, state, n_steps, t0=0.0):
+        """The rollout through the templated step of the gradient code, in doubles:
+        (new state, tip trajectory); equals ``rollout`` bitwise."""
+        x, v, q, w = self._state64(state)
+        tr = np.zeros((int(n_steps), 3))
+        rc = lib().oracle_grad_rollout(C.byref(self.c), float(t0), int(n_steps), _p(x), _p(v),
+                                       _p(q), _p(w), _p(tr))
+        if rc != 0:
+            raise ValueError("oracle_grad_rollout refused the rod (code %d)" % rc)
+        st = state.copy()
+        st.x, st.v, st.q, st.w = x, v, q, w
+        return st, tr
+
+    def jvp(self, state, n_steps, dstate=None, dmb=0.0, dmt=0.0, t0=0.0):
+        """Forward mode: (tip trajectory, its derivative along dstate (a RodState of
+        directions, or None) and the multiplier directions dmb, dmt)."""
+        x, v, q, w = self._state64(state)
+        if dstate is not None:
+            dx, dv, dq, dw = self._state64(dstate)
+        else:
+            dx = dv = dq = dw = None
+        tip = np.zeros((int(n_steps), 3))
+        dtip = np.zeros((int(n_steps), 3))
+        rc = lib().oracle_jvp(C.byref(self.c), float(t0), int(n_steps), _p(x), _p(v), _p(q),
+                              _p(w), _p(dx), _p(dv), _p(dq), _p(dw), float(dmb), float(dmt),
+                              _p(tip), _p(dtip))
+        if rc != 0:
+            raise ValueError("oracle_jvp refused the rod (code %d)" % rc)
+        return tip, dtip
+
+    def vjp(self, state, n_steps, ct, round_fp32=False, t0=0.0):
+        """Reverse mode: gradient of sum_s ct[s] . tip(s) as a dict with x, v, q, w (state
+        shapes), bend, twist (multiplier gradients) and tip (the forward trajectory)."""
+        x, v, q, w = self._state64(state)
+        ct = _f64(ct, (int(n_steps), 3))
+        g = {k: np.zeros_like(a) for k, a in (("x", x), ("v", v), ("q", q), ("w", w))}
+        gb, gt = C.c_double(0.0), C.c_double(0.0)
+        tip = np.zeros((int(n_steps), 3))
+        rc = lib().oracle_vjp(C.byref(self.c), float(t0), int(n_steps), _p(x), _p(v), _p(q),
+                              _p(w), _p(ct), int(round_fp32), _p(g["x"]), _p(g["v"]),
+                              _p(g["q"]), _p(g["w"]), C.byref(gb), C.byref(gt), _p(tip))
+        if rc != 0:
+            raise ValueError("oracle_vjp refused the rod (code %d)" % rc)
+        g["bend"], g["twist"], g["tip"] = float(gb.value), float(gt.value), tip
+        return g
+
     def stable(self, state, n_steps, t0=0.0, energy_factor=1.01):
         x, v = _f64(state.x, (self.n + 1, 3)), _f64(state.v, (self.n + 1, 3))
         q, w = _f64(state.q, (self.n, 4)), _f64(state.w, (self.n, 3))
@@ -424,3 +502,49 @@ def bisect_dt_max(spec, state, n_steps, lo=1e-9, hi=1e-1, rel=1e-3, t0=0.0):
         else:
             hi = mid
     return lo
+
+
+def _ptrs(arrs):
+    return (_DP * len(arrs))(*[_p(a) for a in arrs])
+
+
+def vjp_many(specs_states, n_steps, cts, round_fp32=False, n_threads=0, t0=0.0):
+    """``Rod.vjp`` for many independent rods, spread over n_threads threads in the oracle's
+    own thread pool (0 = all hardware threads).  Returns a list of gradient dicts."""
+    rods = [Rod(s) for s, _ in specs_states]
+    arr = (_Rod * len(rods))(*[r.c for r in rods])
+    ins = [r._state64(st) for r, (_, st) in zip(rods, specs_states)]
+    cts = [_f64(c, (int(n_steps), 3)) for c in cts]
+    outs = [{k: np.zeros_like(a) for k, a in zip(("x", "v", "q", "w"), s4)} for s4 in ins]
+    tips = [np.zeros((int(n_steps), 3)) for _ in rods]
+    gb = np.zeros(len(rods))
+    gt = np.zeros(len(rods))
+    rc = lib().oracle_vjp_many(len(rods), arr, float(t0), int(n_steps),
+                               *[_ptrs([s4[k] for s4 in ins]) for k in range(4)], _ptrs(cts),
+                               int(round_fp32),
+                               *[_ptrs([o[k] for o in outs]) for k in ("x", "v", "q", "w")],
+                               _p(gb), _p(gt), _ptrs(tips), int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle_vjp_many refused a rod (code %d)" % rc)
+    for o, b, t, tp in zip(outs, gb, gt, tips):
+        o["bend"], o["twist"], o["tip"] = float(b), float(t), tp
+    return outs
+
+
+def rollout_many_threads(specs_states, n_steps, n_threads=0, t0=0.0):
+    """oracle rollouts of many independent rods on n_threads threads of the oracle's own pool
+    (0 = all hardware threads); returns the new states."""
+    rods = [Rod(s) for s, _ in specs_states]
+    arr = (_Rod * len(rods))(*[r.c for r in rods])
+    ins = [r._state64(st) for r, (_, st) in zip(rods, specs_states)]
+    rc = lib().oracle_rollout_many(len(rods), arr, float(t0), int(n_steps),
+                                   *[_ptrs([s4[k] for s4 in ins]) for k in range(4)],
+                                   int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle_rollout_many refused a rod")
+    out = []
+    for (_, st), (x, v, q, w) in zip(specs_states, ins):
+        o = st.copy()
+        o.x, o.v, o.q, o.w = x, v, q, w
+        out.append(o)
+    return out

@@ -1,9 +1,10 @@
 """The oracle's pins catch plausible mistakes: each case below plants one mistake in a scratch
-copy of oracle/corde_oracle.c (a flipped sign, a wrong index, a dropped term, a wrong material
-constant), builds it as its own library and runs the CPU pin tests against it in a fresh
-process.  Every mutant must fail at least one pin; the unchanged copy, built the same way, must
-pass them all.  Each planted text must occur exactly once in the oracle, so the cases follow
-the source as it changes."""
+copy of oracle/corde_oracle.c or of its derivative code oracle/corde_oracle_grad.cpp (a flipped
+sign, a wrong index, a dropped term, a wrong material constant, a wrong differentiation rule),
+builds it as its own library and runs the CPU pin tests against it in a fresh process.  Every
+mutant must fail at least one pin; the unchanged copy, built the same way, must pass them all.
+Each planted text must occur exactly once in its file, so the cases follow the source as it
+changes."""
 import os
 import subprocess
 import sys
@@ -14,12 +15,13 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 REPO = os.path.dirname(HERE)
 SRC = os.path.join(REPO, "oracle", "corde_oracle.c")
+GRAD_SRC = os.path.join(REPO, "oracle", "corde_oracle_grad.cpp")
 
 PINS = ["test_oracle_algebra.py", "test_oracle_mechanics.py", "test_oracle_binding.py",
         "test_oracle_contact.py", "test_oracle_env.py", "test_oracle_damping.py",
-        "test_oracle_feedback.py"]
+        "test_oracle_feedback.py", "test_oracle_grad.py"]
 
-# (name, text in the oracle, planted replacement)
+# (name, text in the oracle, planted replacement); GRAD_MUTANTS: the same in the derivative code
 MUTANTS = [
     ("gyroscopic sign (Euler's equations)",
      "tq[a] = tau[3 * j + a] - gyro[a];", "tq[a] = tau[3 * j + a] + gyro[a];"),
@@ -57,6 +59,19 @@ MUTANTS = [
      "F[3 * (j + 1) + c] -= td * e.Ks * sd * t[c];", "F[3 * (j + 1) + c] += td * e.Ks * sd * t[c];"),
 ]
 
+GRAD_MUTANTS = [
+    ("forward mode: product rule without the second term",
+     "return Dual(a.v * b.v, a.d * b.v + a.v * b.d);", "return Dual(a.v * b.v, a.d * b.v);"),
+    ("forward mode: derivative of the square root without its 1/2",
+     "return Dual(s, a.d / (2.0 * s));", "return Dual(s, a.d / s);"),
+    ("reverse mode: quotient rule with the wrong sign on the divisor",
+     "return make(r, a.i, 1.0 / b.v, b.i, -r / b.v);", "return make(r, a.i, 1.0 / b.v, b.i, r / b.v);"),
+    ("reverse mode: square-root partial doubled",
+     "return make(s, a.i, 0.5 / s, -1, 0.0);", "return make(s, a.i, 1.0 / s, -1, 0.0);"),
+    ("templated step: gyroscopic sign flipped",
+     "tq[a] = tau[3 * j + a] - gyro[a];", "tq[a] = tau[3 * j + a] + gyro[a];"),
+]
+
 
 def _run_pins(lib, log):
     env = dict(os.environ, CORDE_ORACLE_LIB=lib)
@@ -71,17 +86,20 @@ def _run_pins(lib, log):
 @pytest.mark.slow
 def test_every_planted_mistake_fails_a_pin(tmp_path):
     from oracle import oracle as O
-    src = open(SRC).read()
-    jobs = [("unchanged", None, None)] + MUTANTS
+    src = {SRC: open(SRC).read(), GRAD_SRC: open(GRAD_SRC).read()}
+    jobs = ([("unchanged", SRC, None, None)] + [(n, SRC, o, w) for n, o, w in MUTANTS] +
+            [(n, GRAD_SRC, o, w) for n, o, w in GRAD_MUTANTS])
     libs = []
-    for k, (name, old, new) in enumerate(jobs):
-        text = src
-        if old is not None:
-            assert src.count(old) == 1, "planted text for %r not found once in the oracle" % name
-            text = src.replace(old, new)
-        path = tmp_path / ("m%02d.c" % k)
-        path.write_text(text)
-        libs.append(O.build(force=True, src=str(path), lib=str(tmp_path / ("m%02d.so" % k))))
+    for k, (name, target, old, new) in enumerate(jobs):
+        paths = {}
+        for f, text in src.items():
+            if f == target and old is not None:
+                assert text.count(old) == 1, "planted text for %r not found once" % name
+                text = text.replace(old, new)
+            paths[f] = tmp_path / ("m%02d_%s" % (k, os.path.basename(f)))
+            paths[f].write_text(text)
+        libs.append(O.build(force=True, src=str(paths[SRC]), grad_src=str(paths[GRAD_SRC]),
+                            lib=str(tmp_path / ("m%02d.so" % k))))
     with ThreadPoolExecutor(max_workers=4) as ex:
         results = list(ex.map(lambda a: _run_pins(*a),
                               [(lib, str(tmp_path / ("m%02d.log" % k))) for k, lib in enumerate(libs)]))
