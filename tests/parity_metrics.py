@@ -1,0 +1,101 @@
+"""Whole-state parity metrics shared by the GPU parity tests and the CPU test that shows each
+bar can fail (a 10 % change of one coefficient of the method, made in the oracle, must break
+at least one bar on the configurations that cover it).
+
+Compared quantities, GPU (FP32) against the oracle (FP64), after a run and over a window of
+its last k steps:
+  x     positions, max over points of |dx|, relative to the largest displacement of a point
+        over the run (small when nothing moves much: floored at 1e-3 of the rod length);
+  tip   |dx| of the last point, against 1e-4 of the rod length (the method's target);
+  q     frames, max |dq| over frames after aligning the sign of each quaternion;
+  u     Darboux vectors u_j = (2 / lbar_j) vec(conj(q_j) q_{j+1}) (eqs. (5)-(6)), max |du|
+        relative to max |u| of the oracle (floored at 1 / rod length);
+  vbar  window-mean point velocities (x(T) - x(T-k)) / (k dt), relative to their max (floored
+        at 1e-3 of the rod length per window), robust to stiff-mode noise in v itself;
+  wbar  window-mean body rates 2 vec(conj(q(T-k)) q(T)) / (k dt), relative likewise (floored
+        at 1e-3 rad per window);
+  unit  max | |q| - 1 | of the GPU frames.
+No GPU import here: the module runs on the CPU too.
+"""
+import numpy as np
+
+# Bars per quantity (see the module docstring for the normalisations).
+TOL = {"x": 1e-3, "tip": 1e-4, "q": 1e-4, "u": 1e-3, "vbar": 1e-3, "wbar": 1e-3, "unit": 1e-6}
+# Bars of the parity configurations (the same unless stated).
+BARS = {"c0": TOL, "c0-swing": TOL, "c1": TOL, "edge": TOL, "c2": TOL}
+
+
+def _qalign(q, ref):
+    s = np.sign(np.sum(q * ref, axis=1))
+    s[s == 0] = 1.0
+    return q * s[:, None]
+
+
+def _qmul(a, b):
+    aw, ax, ay, az = a[..., 0], a[..., 1], a[..., 2], a[..., 3]
+    bw, bx, by, bz = b[..., 0], b[..., 1], b[..., 2], b[..., 3]
+    return np.stack([aw * bw - ax * bx - ay * by - az * bz,
+                     aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx,
+                     aw * bz + ax * by - ay * bx + az * bw], axis=-1)
+
+
+def _conj(q):
+    return q * np.array([1.0, -1.0, -1.0, -1.0])
+
+
+def darboux(q, seg_len):
+    """u_j = (2 / lbar_j) vec(conj(q_j) q_{j+1}) for the joints j = 0 .. N-2."""
+    q = np.asarray(q, dtype=np.float64)
+    if len(q) < 2:
+        return np.zeros((0, 3))
+    lbar = 0.5 * (seg_len[:-1] + seg_len[1:])
+    r = _qmul(_conj(q[:-1]), q[1:])
+    return (2.0 / lbar)[:, None] * r[:, 1:]
+
+
+def errors(spec, x0, got_a, got_b, ref_a, ref_b, k, seg_len=None, disp=None, length=None):
+    """Metric values (normalised as in the module docstring) for one rod.  x0: initial
+    positions; got_a/got_b, ref_a/ref_b: (x, v, q, w) of the GPU and the oracle k steps before
+    the end and at the end.  For a piece of a rod (consecutive points and the frames between
+    them): seg_len of the piece, and the whole rod's largest displacement and length."""
+    seg_len = spec.seg_len if seg_len is None else seg_len
+    L = float(np.sum(spec.seg_len)) if length is None else float(length)
+    f = lambda a: np.asarray(a, dtype=np.float64)
+    xa, qa = f(got_a[0]), f(got_a[2])
+    xb, qb = f(got_b[0]), f(got_b[2])
+    rxa, rqa = f(ref_a[0]), f(ref_a[2])
+    rxb, rqb = f(ref_b[0]), f(ref_b[2])
+    out = {}
+    if disp is None:
+        disp = float(np.linalg.norm(rxb - f(x0), axis=1).max())
+    disp = max(disp, 1e-3 * L)
+    out["x"] = float(np.abs(xb - rxb).max()) / disp
+    out["tip"] = float(np.linalg.norm(xb[-1] - rxb[-1])) / L
+    out["q"] = float(np.abs(_qalign(qb, rqb) - rqb).max())
+    u, ru = darboux(qb, seg_len), darboux(rqb, seg_len)
+    out["u"] = float(np.abs(u - ru).max() / max(np.abs(ru).max(), 1.0 / L)) if len(ru) else 0.0
+    dtk = k * spec.dt
+    vb, rvb = (xb - xa) / dtk, (rxb - rxa) / dtk
+    out["vbar"] = float(np.abs(vb - rvb).max() / max(np.abs(rvb).max(), 1e-3 * L / dtk))
+    wr = lambda p, q: 2.0 * _qmul(_conj(p), _qalign(q, p))[:, 1:] / dtk
+    wb, rwb = wr(qa, qb), wr(rqa, rqb)
+    out["wbar"] = float(np.abs(wb - rwb).max() / max(np.abs(rwb).max(), 1e-3 / dtk))
+    out["unit"] = float(np.abs(np.linalg.norm(qb, axis=1) - 1).max())
+    return out
+
+
+def worst(all_errs):
+    """Largest value of each metric over several rods."""
+    keys = all_errs[0].keys()
+    return {k: max(e[k] for e in all_errs) for k in keys}
+
+
+def violations(errs, tol=None):
+    """Metrics above their bars (the unit-norm check only applies to FP32 results)."""
+    tol = TOL if tol is None else tol
+    return {k: v for k, v in errs.items() if k in tol and v > tol[k]}
+
+
+def fmt(errs):
+    return " ".join("%s %.2e" % (k, v) for k, v in errs.items())

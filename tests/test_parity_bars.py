@@ -1,0 +1,107 @@
+"""The GPU parity bars can fail: on each parity configuration, the FP64 oracle with one
+coefficient of the method changed by 10 % (or one constraint iteration in ten dropped) is
+compared with the unchanged oracle by the same whole-state metrics and bars as the GPU
+(parity_metrics), and must break at least one bar wherever the table below says the
+configuration covers that coefficient.  Every step of the method is covered somewhere:
+
+  external forces (gravity, linear and angular damping, clamp drive)   Sec. 2.1, Fig. 5
+  stretch / shear (K_s of eq. (2), K_p of eq. (8))                      eqs. (2), (8)
+  bend / twist (K_1 = K_2, K_3 of eq. (3))                              eqs. (3), (5), (6)
+  force integration (masses and inertias: the density)                  Sec. 2.1
+  distance constraints (the number of constraint iterations)            Sec. 2.1
+  velocity integration (the time step)                                  Sec. 2.1
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2509_04277_amd import workloads as W
+import parity_cases
+import parity_metrics as PM
+
+
+def _g(s, f):
+    return s.replace(gravity=tuple(f * g for g in s.gravity))
+
+
+# 10 % changes, each of one coefficient (K_s alone: E up, the other stiffnesses scaled back)
+CHANGES = {
+    "gravity": lambda s: _g(s, 1.1),
+    "damp_lin": lambda s: s.replace(damp_lin=1.1 * s.damp_lin),
+    "damp_ang": lambda s: s.replace(damp_ang=1.1 * s.damp_ang),
+    "drive": lambda s: s.replace(clamp_amp=tuple(1.1 * a for a in s.clamp_amp),
+                                 clamp_twist_amp=1.1 * s.clamp_twist_amp),
+    "K_s": lambda s: s.replace(young=1.1 * s.young, kp_scale=s.kp_scale / 1.1,
+                               bend_scale=s.bend_scale / 1.1, twist_scale=s.twist_scale / 1.1),
+    "K_p": lambda s: s.replace(kp_scale=1.1 * s.kp_scale),
+    "bend": lambda s: s.replace(bend_scale=1.1 * s.bend_scale),
+    "twist": lambda s: s.replace(twist_scale=1.1 * s.twist_scale),
+    "mass": lambda s: s.replace(density=1.1 * s.density),
+    "n_iter": lambda s: s.replace(n_iter=s.n_iter - max(1, s.n_iter // 10)) if s.inextensible else s,
+    "dt": lambda s: s.replace(dt=1.1 * s.dt),
+}
+
+# configuration: (rods, steps, window, bar set, coefficients it must detect)
+ALL = tuple(CHANGES)
+
+
+def _configs(oracle):
+    return {
+        "c0": (W.config0().rods, 2000, 10, "c0",
+               ("gravity", "K_s", "K_p", "bend", "twist", "mass", "dt")),
+        "c0-swing": (W.config0(dt=1e-4).rods, 3000, 50, "c0-swing",
+                     ("gravity", "damp_lin", "K_s", "K_p", "bend", "twist", "mass", "dt")),
+        "c1-2000": (W.config1().rods, 2000, 10, "c1", ("twist", "mass", "n_iter", "dt", "drive")),
+        "edge": (parity_cases.edge_rods(oracle), 400, 37, "edge", ALL),
+    }
+
+
+def _window(oracle, rods, n, k):
+    a = [oracle.Rod(s).rollout(st, n - k)[0] for s, st in rods]
+    b = [oracle.Rod(s).rollout(sa, k, t0=(n - k) * s.dt)[0] for (s, _), sa in zip(rods, a)]
+    return a, b
+
+
+def _differs(a, b):
+    return any(not np.array_equal(np.asarray(getattr(a, f.name), dtype=object),
+                                  np.asarray(getattr(b, f.name), dtype=object))
+               for f in dataclasses.fields(a))
+
+
+def _t(st):
+    return (st.x, st.v, st.q, st.w)
+
+
+def _worst(rods, pa, pb, a, b, k):
+    return PM.worst([PM.errors(s, st.x, _t(x), _t(y), _t(u), _t(v), k)
+                     for (s, st), x, y, u, v in zip(rods, pa, pb, a, b)])
+
+
+def test_every_step_is_covered(oracle):
+    """Together the configurations cover every coefficient of CHANGES."""
+    covered = set()
+    for _, _, _, _, must in _configs(oracle).values():
+        covered |= set(must)
+    assert covered == set(CHANGES)
+
+
+@pytest.mark.parametrize("name", ["c0", "c0-swing", "c1-2000", "edge"])
+def test_bars_fail_on_changed_coefficients(oracle, name):
+    rods, n, k, bars, must = _configs(oracle)[name]
+    a, b = _window(oracle, rods, n, k)
+    same = _worst(rods, a, b, a, b, k)
+    same.pop("unit")
+    assert all(v == 0.0 for v in same.values())
+    missed = []
+    for coef in must:
+        prods = [(CHANGES[coef](s), st) for s, st in rods]
+        assert any(_differs(ps, s) for (ps, _), (s, _) in zip(prods, rods)), coef
+        pa, pb = _window(oracle, prods, n, k)
+        w = _worst(rods, pa, pb, a, b, k)
+        w.pop("unit")   # an FP64 oracle keeps unit quaternions whatever its coefficients
+        bad = PM.violations(w, PM.BARS[bars])
+        print("%s, %s x1.1: %s -> above the bars: %s" % (name, coef, PM.fmt(w), sorted(bad)))
+        if not bad:
+            missed.append(coef)
+    assert not missed, "%s: a 10 %% change of %s passes every bar" % (name, missed)
