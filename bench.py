@@ -32,18 +32,58 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_name, elements, spl):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they match this source."""
-    path = os.path.join(REPO, "profiles", "traffic.json")
+def _counters(kernel_name, elements, spl):
+    """Figures of committed rocprofv3 counter runs of this kernel on this workload, if they
+    were taken on the current kernel sources (else None)."""
+    path = os.path.join(REPO, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
-    d = json.load(open(path))
-    e = d.get(kernel_name)
+    e = json.load(open(path)).get(kernel_name)
     if not e or e.get("source_hash") != kernel_source_hash():
         return None
     if e.get("elements") != elements or e.get("steps_per_launch") != spl:
         return None
-    return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+    return e
+
+
+def measured_traffic(kernel_name, elements, spl):
+    """HBM bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE), or None."""
+    e = _counters(kernel_name, elements, spl)
+    return None if e is None else e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+
+
+def measured_wave_shares(kernel_name, elements, spl):
+    """Shares of wavefront time from SQ counters: VALU issue (SQ_ACTIVE_INST_VALU /
+    SQ_WAVE_CYCLES) and waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES: barriers, and the few memory
+    waits of a register-resident kernel), or None."""
+    e = _counters(kernel_name, elements, spl)
+    if e is None or "valu_active_share" not in e:
+        return None
+    return {"valu_issue_frac": e["valu_active_share"], "barrier_share": e["wait_any_share"],
+            "valu_insts_per_wave_step": e.get("valu_insts_per_wave_step")}
+
+
+def host_cpu():
+    """Model name and logical CPU counts of the machine running the oracle."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def oracle_threads():
+    """Worker threads for the oracle's own pool: the CPUs this process may use, at most 16
+    (the host share of one GPU)."""
+    return max(1, min(16, host_cpu()["usable_cpus"] or 1))
 
 
 COPY_FLOATS = 64 << 20                # 256 MiB FP32 copy: 512 MiB of HBM traffic per dispatch
@@ -75,9 +115,39 @@ def cpu_baseline(wl, n_steps):
         O.Rod(spec).rollout(st, n_steps)
     dt = time.perf_counter() - t
     return {"value": wl.n_elements * n_steps / dt, "unit": "element-steps/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "host": host_cpu(),
             "sample": "FP64 C oracle, both 512-element rods of the same workload, %d steps "
-                      "(%.1f s), one thread" % (n_steps, dt)}
+                      "(%.1f s), one thread (each rod's steps are a sequential chain)" % (n_steps, dt)}
+
+
+def cpu_oracle_many(W, R):
+    """The FP64 oracle on the batched (4096 rods) and adjoint (256 x 256) workloads, rods spread
+    over the host's cores by the oracle's thread pool: a bounded sample of each."""
+    from oracle import oracle as O
+    nt = oracle_threads()
+    out = {"threads": nt, "host": host_cpu()}
+    wl = W.config3()
+    rods = [(s.replace(dt=R.stable_dt(s)), st) for s, st in wl.rods]
+    steps = 20
+    t = time.perf_counter()
+    O.rollout_many_threads(rods, steps, n_threads=nt)
+    dt = time.perf_counter() - t
+    out["batch"] = {"element_steps_per_s": wl.n_elements * steps / dt, "seconds": dt,
+                    "sample": "all 4096 rods, %d of the %d steps" % (steps, wl.n_steps)}
+    wl = W.config4()
+    rods = [(s.replace(dt=R.stable_dt(s)), st) for s, st in wl.rods][:64]
+    t = time.perf_counter()
+    O.rollout_many_threads(rods, wl.n_steps, n_threads=nt)
+    f_s = time.perf_counter() - t
+    import numpy as np
+    ct = [np.ones((wl.n_steps, 3)) for _ in rods]
+    t = time.perf_counter()
+    O.vjp_many(rods, wl.n_steps, ct, n_threads=nt)
+    g_s = time.perf_counter() - t
+    out["adjoint"] = {"forward_s": f_s, "vjp_s": g_s, "vjp_over_forward": g_s / f_s,
+                      "sample": "64 of the 256 rods, all %d steps (forward rollout; reverse-mode "
+                                "gradient with its own forward pass)" % wl.n_steps}
+    return out
 
 
 def batch_extras(R, W):
@@ -183,12 +253,23 @@ def adjoint_extras(R, W):
             fwd.append(t_f)
             afwd.append(t_af)
             bwd.append(t_b)
+    # the plain forward at the autotuned kernel shape and steps per launch
+    b.set_state_rods([st for _, st in rods])
+    tuned = b.autotune(probe_steps=n_steps, steps_per_launch=0)
+    tfwd = []
+    for rep in range(4):
+        b.set_state_rods([st for _, st in rods])
+        _, t_f = timed(lambda: (b.step(n_steps), b.sync()))
+        if rep:
+            tfwd.append(t_f)
     b.close()
-    fwd_ms, afwd_ms, bwd_ms = (float(np.median(v)) for v in (fwd, afwd, bwd))
+    fwd_ms, afwd_ms, bwd_ms, tfwd_ms = (float(np.median(v)) for v in (fwd, afwd, bwd, tfwd))
     return {"workload": "256 rods x 256 elements, inextensible, %d steps, checkpoints every %d"
                         % (n_steps, ckpt),
             "forward_ms": fwd_ms, "adjoint_forward_ms": afwd_ms, "adjoint_backward_ms": bwd_ms,
-            "adjoint_over_forward": (afwd_ms + bwd_ms) / fwd_ms}
+            "adjoint_over_forward": (afwd_ms + bwd_ms) / fwd_ms,
+            "tuned_forward": {"ms": tfwd_ms, "tuning": tuned},
+            "adjoint_over_tuned_forward": (afwd_ms + bwd_ms) / tfwd_ms}
 
 
 def binding_extras(R, W):
@@ -343,32 +424,35 @@ def environment_extras(R, W):
     return out
 
 
-def long_rod_extras(R, W):
-    """c2: us/step vs rod length and steps per launch.  Rods up to 2048 elements run in one
-    workgroup ("single") and, for comparison, split over several ("chunked"); longer rods are
-    always chunked (one workgroup per ~500 elements, halo exchange through HBM every step)."""
+def long_rod_extras(R, W, sizes=(1024, 2048, 4096, 16384, 65536), variants=(False, True),
+                    ks=(1, 10, 100)):
+    """c2: us/step vs rod length and steps per launch over the workload's 5000 steps.  Rods up
+    to 2048 elements run in one workgroup ("single") and, for comparison, split over several
+    ("chunked"); longer rods are always chunked (one workgroup per ~500 elements, halo exchange
+    through global memory every few steps)."""
     out = []
-    for n in (1024, 2048, 4096, 16384, 65536):
-        for inext in (False, True):
+    for n in sizes:
+        for inext in variants:
             wl = W.config2(n, inext)
             spec, st = wl.rods[0]
             for mode in (("single", "chunked") if n <= 2048 else ("chunked",)):
-                for spl in (1, 10, 100):
+                for spl in ks:
                     b = R.RodBatch([spec])
                     if mode == "chunked" and n <= 2048:
                         b.set_chunking(n - 1)
                     b.set_state_rods([st])
                     b.step(200, spl)
-                    b.step(1000, spl)
+                    b.set_state_rods([st])
+                    b.step(wl.n_steps, spl)
                     b.sync()
                     ms, launches = b.last_step_time()
                     b.close()
+                    us = 1e3 * ms / wl.n_steps
                     out.append({"n": n, "inextensible": inext, "mode": mode,
-                                "steps_per_launch": spl, "us_per_step": 1e3 * ms / 1000,
-                                "element_steps_per_s": n * 1000 / (ms / 1e3)})
+                                "steps_per_launch": spl, "steps": wl.n_steps, "us_per_step": us,
+                                "element_steps_per_s": n / (us / 1e6)})
                     print("[bench] long rod n=%d %s %s k=%d: %.2f us/step" % (
-                        n, "inext" if inext else "ext", mode, spl, 1e3 * ms / 1000),
-                        file=sys.stderr, flush=True)
+                        n, "inext" if inext else "ext", mode, spl, us), file=sys.stderr, flush=True)
     return out
 
 
@@ -384,7 +468,12 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (4096 rods), long-rod and adjoint measurements")
     ap.add_argument("--extras", default="batch,long_rod,adjoint,binding,contact,haptic,environment",
-                    help="comma-separated subset of batch,long_rod,adjoint,binding,contact")
+                    help="comma-separated subset of batch,long_rod,adjoint,binding,contact,"
+                         "haptic,environment")
+    ap.add_argument("--long-sizes", default="1024,2048,4096,16384,65536",
+                    help="rod lengths of the long-rod sweep")
+    ap.add_argument("--long-variants", default="ext,inext", help="ext, inext or both")
+    ap.add_argument("--long-k", default="1,10,100", help="steps per launch of the long-rod sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the rods of this workload are independent and a "
@@ -441,6 +530,7 @@ def main():
     bytes_per_launch = BYTES_PER_ELEMENT_STEP * elements * spl
     achieved = bytes_per_launch / launch_s / 1e9
     traffic = measured_traffic(kernel, elements, spl)
+    shares = measured_wave_shares(kernel, elements, spl)
     out = {
         "metric": "element-steps/s",
         "value": value,
@@ -467,15 +557,29 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "measured_copy_GBs": copy["GB/s"],
-                     "frac_of_measured_copy": achieved / copy["GB/s"]},
+                     "frac_of_measured_copy": achieved / copy["GB/s"],
+                     # what binds this small workload (two rods, one workgroup each): VALU issue
+                     # and waiting (mostly the cross-wavefront exchanges' barriers), as shares
+                     # of wavefront time from SQ counters of the same kernel and workload
+                     "valu_issue_frac": shares and shares["valu_issue_frac"],
+                     "barrier_share": shares and shares["barrier_share"],
+                     "valu_insts_per_wave_step": shares and shares["valu_insts_per_wave_step"]},
     }
     if not args.no_extras:
-        fns = {"batch": batch_extras, "long_rod": long_rod_extras, "adjoint": adjoint_extras,
+        sizes = tuple(int(v) for v in args.long_sizes.split(",") if v)
+        variants = tuple(v == "inext" for v in args.long_variants.split(",") if v)
+        ks = tuple(int(v) for v in args.long_k.split(",") if v)
+        fns = {"batch": batch_extras,
+               "long_rod": lambda R_, W_: long_rod_extras(R_, W_, sizes, variants, ks),
+               "adjoint": adjoint_extras,
                "binding": binding_extras, "contact": contact_extras, "haptic": haptic_extras,
                "environment": environment_extras}
         out["extras"] = {k: fns[k](R, W) for k in args.extras.split(",") if k}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+        if not args.no_extras:
+            out["cpu_oracle_all_cores"] = cpu_oracle_many(W, R)
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

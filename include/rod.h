@@ -125,26 +125,35 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
 /* Free all device and host memory of the handle (after finishing its stream's work). */
 rod_status rod_destroy(rod_ctx* ctx);
 
-/* Copy a full state in (layouts above).  Resets the simulation time to t0 [s]. */
+/* Copy a full state in (layouts above): the arrays the paper uploads once at initialisation
+ * (Sec. 2.2).  Resets the simulation time to t0 [s].  Inside the handle, positions and
+ * quaternions are kept as pairs of floats (value + a low part below half its ulp) so that
+ * the small per-step increments are not rounded away; this call sets the low parts to 0. */
 rod_status rod_set_state(rod_ctx* ctx, const float* x, const float* v, const float* q,
                          const float* w, int32_t on_device, double t0);
 
-/* Copy the full state out into caller-owned buffers (any pointer may be NULL to skip). */
+/* Copy the full state out into caller-owned buffers (any pointer may be NULL to skip): the
+ * positions the paper reads back for rendering every launch (Sec. 2.2, Sec. 3.1).  x and q
+ * are the FP32 values nearest to the handle's pairs; a get / set round trip therefore rounds
+ * them once (a resumed run differs from a straight one by that rounding). */
 rod_status rod_get_state(rod_ctx* ctx, float* x, float* v, float* q, float* w, int32_t on_device);
 
-/* Advance every rod by n_steps time steps, steps_per_launch steps per kernel launch
- * (0 = the handle's tuned value).  Each launch loads the state once, keeps it in registers
- * across its steps and stores it once. */
+/* Advance every rod by n_steps time steps (Sec. 2.1 last paragraph; Fig. 5 without its
+ * collision lines unless a mesh, contact or bindings are set), steps_per_launch steps per
+ * kernel launch (0 = the handle's tuned value; the paper runs several time steps per kernel
+ * launch, Sec. 2.2).  Each launch loads the state once, keeps it in registers across its
+ * steps and stores it once. */
 rod_status rod_step(rod_ctx* ctx, int32_t n_steps, int32_t steps_per_launch);
 
 /* Override the static clamp pose of rod `rod` (haptic input, Sec. 2.2); takes effect at the
  * next step.  x0[3], q0[4] as in rod_params; the sinusoidal amplitudes are kept. */
 rod_status rod_set_clamp(rod_ctx* ctx, int32_t rod, const double* x0, const double* q0);
 
-/* Wait for the handle's stream; returns ROD_E_UNSTABLE if a non-finite state was seen,
- * ROD_E_TIMEOUT if chunked long-rod workgroups lost step synchronisation, ROD_E_UNSUPPORTED
- * if a point had more contacts than the kernel holds (the conditions stay latched until the
- * next rod_set_state). */
+/* Wait for the handle's stream (the calls above are stream-ordered and return before the
+ * device finishes; their device-side conditions surface here): ROD_E_UNSTABLE if a non-finite
+ * state was seen, ROD_E_TIMEOUT if chunked long-rod workgroups lost step synchronisation,
+ * ROD_E_UNSUPPORTED if a point had more contacts than the kernel holds (the conditions stay
+ * latched until the next rod_set_state). */
 rod_status rod_sync(rod_ctx* ctx);
 
 /* Simulation time [s] and number of steps taken since rod_set_state(). */
@@ -284,7 +293,9 @@ typedef struct {
  * read in 2^20 attempts). */
 rod_status rod_haptic_get_force(rod_ctx* ctx, int32_t rod, rod_haptic_force* out);
 
-/* Per bucket, time every built shape that holds its longest rod on probe_steps steps (the
+/* The autotuner of the batched form (kernel shape per bucket and steps per launch picked by
+ * measuring; the paper fixes them by hand, Sec. 3.1).
+ * Per bucket, time every built shape that holds its longest rod on probe_steps steps (the
  * state is saved and restored, the step counter unchanged) and keep the fastest; sets the
  * handle's steps_per_launch.  steps_per_launch = 0: first, while the long-rod split is the
  * default one, the whole handle is timed with its rods of more than 512 elements in one
@@ -318,19 +329,22 @@ rod_status rod_set_stiffness_mult(rod_ctx* ctx, const float* bend, const float* 
 /* Advance every rod by n_steps steps from the current state (like rod_step), recording a
  * checkpoint of the whole state every ckpt_every steps (ckpt_every = 1 stores every step and
  * needs no recomputation), and write the tip trajectory to tips (n_rods x n_steps x 3, rod
- * major; nullable).  Device memory: ceil(n_steps / ckpt_every) + ckpt_every states. */
+ * major; nullable).  The handle holds one rollout at a time: this one replaces the previous.
+ * rollout (nullable) receives its number (1, 2, ... per handle), which rod_adjoint_backward
+ * checks.  Device memory: ceil(n_steps / ckpt_every) + ckpt_every states. */
 rod_status rod_adjoint_forward(rod_ctx* ctx, int32_t n_steps, int32_t ckpt_every, float* tips,
-                               int32_t on_device);
+                               int32_t on_device, int64_t* rollout);
 
-/* Reverse pass of the last rod_adjoint_forward() (ROD_E_ORDER without one).  dl_dtips:
+/* Reverse pass of the last rod_adjoint_forward() (ROD_E_ORDER without one, or if rollout is
+ * not 0 and not the number of the held rollout, i.e. a later forward replaced it).  dl_dtips:
  * n_rods x n_steps x 3.  Outputs (any may be NULL): dL/dm_b, dL/dm_t (n_rods each), and
  * dL/d(initial state) in the state layout; dl_dq is the gradient with respect to the four
  * quaternion components as stored (not projected on the unit sphere).  Each checkpoint
  * segment is recomputed forward, then reversed by one kernel launch per bucket.  Synchronises
  * the stream; ROD_E_UNSTABLE if a non-finite adjoint appears. */
-rod_status rod_adjoint_backward(rod_ctx* ctx, const float* dl_dtips, float* dl_dbend,
-                                float* dl_dtwist, float* dl_dx, float* dl_dv, float* dl_dq,
-                                float* dl_dw, int32_t on_device);
+rod_status rod_adjoint_backward(rod_ctx* ctx, int64_t rollout, const float* dl_dtips,
+                                float* dl_dbend, float* dl_dtwist, float* dl_dx, float* dl_dv,
+                                float* dl_dq, float* dl_dw, int32_t on_device);
 
 const char* rod_status_str(rod_status s);
 /* Detail of the last error on this handle (never NULL; "" if none; NULL ctx = global). */

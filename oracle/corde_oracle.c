@@ -22,8 +22,9 @@
  *     impulse linearised at the predicted positions p = x + dt v;
  *   - semi-implicit Euler: v (and omega) first, then x (and q) with the new velocities,
  *     followed by quaternion renormalisation;
- *   - damping is plain velocity damping (a -= gamma v, alpha -= gamma omega); the paper's
- *     internal friction terms are not given and are not modelled.
+ *   - damping is plain velocity damping (a -= gamma v, alpha -= gamma omega), plus, when a rod
+ *     sets a retardation time, Kelvin-Voigt internal friction on the stretch and bend/twist
+ *     strain rates (the paper names the dissipation terms but gives no formula).
  */
 #include "corde_oracle.h"
 
@@ -944,6 +945,23 @@ void oracle_rollout(const oracle_rod* rod, double t0, int32_t n_steps, double* x
         oracle_step(rod, t0 + s * rod->dt, x, v, q, w);
         if (tip)
             for (int c = 0; c < 3; ++c) tip[3 * s + c] = x[3 * rod->n + c];
+    }
+}
+
+/* Rounds n values to the nearest FP32 number (kept as doubles). */
+static void round_fp32(double* a, int n) {
+    for (int i = 0; i < n; ++i) a[i] = (double)(float)a[i];
+}
+
+void oracle_rollout_rounded(const oracle_rod* rod, double t0, int32_t n_steps, double* x,
+                            double* v, double* q, double* w, int32_t mask) {
+    const int n = rod->n;
+    for (int s = 0; s < n_steps; ++s) {
+        oracle_step(rod, t0 + s * rod->dt, x, v, q, w);
+        if (mask & 1) round_fp32(x, 3 * (n + 1));
+        if (mask & 2) round_fp32(v, 3 * (n + 1));
+        if (mask & 4) round_fp32(q, 4 * n);
+        if (mask & 8) round_fp32(w, 3 * n);
     }
 }
 

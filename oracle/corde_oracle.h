@@ -125,6 +125,12 @@ void oracle_rollout_fb(const oracle_rod* rod, double t0, int32_t n_steps, double
 void oracle_rollout(const oracle_rod* rod, double t0, int32_t n_steps,
                     double* x, double* v, double* q, double* w, double* tip);
 
+/* oracle_rollout (no tips) with the state fields named by the bits of mask (1 x, 2 v, 4 q,
+ * 8 w) rounded to FP32 after every step, FP64 arithmetic otherwise: the effect of storing
+ * those fields in FP32 between steps (the floor against which FP32 results are judged). */
+void oracle_rollout_rounded(const oracle_rod* rod, double t0, int32_t n_steps, double* x,
+                            double* v, double* q, double* w, int32_t mask);
+
 /* Same as oracle_rollout, on a private copy of the state, and returns 1 if every step is
  * stable: all values finite, max_j | |e_j| / l_j - 1 | < 0.5, and total energy
  * (kinetic + V) <= E_0 + (energy_factor - 1) |E_0| + 1e-9 J at every step (for E_0 > 0 this

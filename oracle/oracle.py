@@ -91,6 +91,9 @@ def lib():
         L.oracle_rollout.restype = None
         L.oracle_rollout.argtypes = [C.POINTER(_Rod), C.c_double, C.c_int32,
                                      _DP, _DP, _DP, _DP, _DP]
+        L.oracle_rollout_rounded.restype = None
+        L.oracle_rollout_rounded.argtypes = [C.POINTER(_Rod), C.c_double, C.c_int32,
+                                             _DP, _DP, _DP, _DP, C.c_int32]
         L.oracle_stable.restype = C.c_int32
         L.oracle_stable.argtypes = [C.POINTER(_Rod), C.c_double, C.c_int32,
                                     _DP, _DP, _DP, _DP, C.c_double]
@@ -323,6 +326,17 @@ class Rod:
                              _p(w), _p(tr))
         st.x, st.v, st.q, st.w = x, v, q, w
         return st, tr
+
+    def rollout_rounded(self, state, n_steps, mask, t0=0.0):
+        """rollout with the fields of mask (1 x, 2 v, 4 q, 8 w) rounded to FP32 after every
+        step; returns the new state."""
+        st = state.copy()
+        x, v = _f64(st.x, (self.n + 1, 3)).copy(), _f64(st.v, (self.n + 1, 3)).copy()
+        q, w = _f64(st.q, (self.n, 4)).copy(), _f64(st.w, (self.n, 3)).copy()
+        lib().oracle_rollout_rounded(C.byref(self.c), float(t0), int(n_steps), _p(x), _p(v),
+                                     _p(q), _p(w), int(mask))
+        st.x, st.v, st.q, st.w = x, v, q, w
+        return st
 
     def rollout_fb(self, state, n_steps, t0=0.0):
         """Returns (new_state, force on the base point for every step (n_steps, 3))."""

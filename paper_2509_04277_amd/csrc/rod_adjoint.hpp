@@ -118,7 +118,7 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
   S.j0 = j0;
   auto fetch = [&](int i, V3& dtip) {
     const float* base = traj + (long long)i * traj_stride;
-    S.load_state(rd, base, base + 3 * n_pts, base + 6 * n_pts, base + 6 * n_pts + 4 * n_frames);
+    S.load_state(rd, state_at(const_cast<float*>(base), n_pts, n_frames));
     dtip = {0.f, 0.f, 0.f};
     if (dtips && g == tip_lane) {
       const float* pt = dtips + ((long long)rod * tip_steps + tip0 + i) * 3;
@@ -134,11 +134,14 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       L.X[e] = S.X[e];
+      L.XL[e] = S.XL[e];
       L.Vv[e] = S.Vv[e];
       L.Qf[e] = S.Qf[e];
+      L.QL[e] = S.QL[e];
       L.Om[e] = S.Om[e];
     }
     L.bx = S.bx;
+    L.bxl = S.bxl;
     L.bv = S.bv;
     const V3 dtip = dtip_next;
     if (i > 0) fetch(i - 1, dtip_next);
@@ -152,21 +155,20 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
     if (rd.driven && rd.clamp) clamp_pose(rd, rd.t0 + (double)(tstep0 + i + 1) * rd.dt_d, xc, qc, wc);
 
     // ---- recompute the forward step, keeping what the reverse needs
-    V3 xl;
-    Q4 qn;
-    L.exchange_a(mb, par, xl, qn);
-    V3 X0[E], Om0[E];
-    Q4 Q0[E];
+    V3 xl, xll;
+    Q4 qn, qnl;
+    L.exchange_a(mb, par, xl, xll, qn, qnl);
+    V3 Om0[E];
+    Q4 Q0[E], Q0L[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      X0[e] = L.X[e];
       Om0[e] = L.Om[e];
       Q0[e] = L.Qf[e];
+      Q0L[e] = L.QL[e];
     }
-    const V3 bx0 = L.bx;
     {
       V3 F[E], T[E], Ev[E], fs0, enext;
-      L.forces(mb, par, xl, qn, F, T, Ev, fs0, enext);
+      L.forces(mb, par, xl, xll, qn, qnl, F, T, Ev, fs0, enext);
       L.integrate_forces(rd, F, T, fs0, xc, wc, fext, text);
       V3 ds[kAdjointMaxIter][2][E];
 #pragma unroll
@@ -334,8 +336,7 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
       Q4 qb_prev = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const V3 xa = (e == 0) ? xl : X0[e - 1];
-        const V3 d = X0[e] - xa;
+        const V3 d = Ev[e];                                   // the forward's segment vector
         const float len2 = dot(d, d);
         const float il = rsqrtf(len2);
         const V3 t = il * d;
@@ -377,7 +378,10 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
                      2.f * (q.x * c.x + q.y * c.y + q.z * c.z)};
         // joint j between frames j (qa = q) and j+1 (qb)
         const Q4 qb = (e == E - 1) ? qn : Q0[e + 1];
-        const Q4 dq = {qb.w - q.w, qb.x - q.x, qb.y - q.y, qb.z - q.z};
+        const Q4 qbl = (e == E - 1) ? qnl : Q0L[e + 1];
+        const Q4 ql = Q0L[e];
+        const Q4 dq = {(qb.w - q.w) + (qbl.w - ql.w), (qb.x - q.x) + (qbl.x - ql.x),
+                       (qb.y - q.y) + (qbl.y - ql.y), (qb.z - q.z) + (qbl.z - ql.z)};
         const float rw = q.w * qb.w + q.x * qb.x + q.y * qb.y + q.z * qb.z;
         const V3 va = {q.x, q.y, q.z}, vb = {qb.x, qb.y, qb.z}, dv = {dq.x, dq.y, dq.z};
         const V3 rv = {q.w * dv.x - dq.w * va.x - (va.y * dv.z - va.z * dv.y),

@@ -165,15 +165,17 @@ __device__ __forceinline__ float from_upper_lane(float v) {  // lane i <- lane i
 // lane below (its last slot), `hi` receives the KH values `mine_lo` of the lane above (its
 // first slot).  Global lane 0 and the last lane receive 0 (the caller substitutes).  E (the
 // elements per lane) only sets how much register room the reads may use.
+constexpr int kMailboxWords = 11;  // the widest exchange: quaternion (two parts), angular velocity
 template <int W>
 struct Mailbox {
-  float buf[2][W][2][8];
+  float buf[2][W][2][kMailboxWords];
 };
 
 template <int W, int E, int KL, int KH>
 __device__ __forceinline__ void exchange(const float (&mine_hi)[KL], float (&lo)[KL],
                                          const float (&mine_lo)[KH], float (&hi)[KH],
                                          Mailbox<W>& mb, int& parity) {
+  static_assert(KL <= kMailboxWords && KH <= kMailboxWords, "exchange wider than the mailbox");
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int k = 0; k < KL; ++k) lo[k] = from_lower_lane(mine_hi[k]);
@@ -244,15 +246,46 @@ __device__ __forceinline__ V3 impulse_d(V3 d, float ci, float cil) {
   return s * d;
 }
 
-// q <- normalize(q + dt/2 q (x) (0, omega)).
-__device__ __forceinline__ Q4 advance_quat(Q4 q, V3 o, float dt) {
+// x <- x + dt v on a position held as the pair (hi, lo): y = lo + dt v (one rounding), then
+// the Fast2Sum of hi and y, whose rounding error becomes the new low part.
+__device__ __forceinline__ void add_compensated(float& hi, float& lo, float v, float dt) {
+  const float y = __builtin_fmaf(dt, v, lo);
+  const float s = hi + y;
+  lo = y - (s - hi);
+  hi = s;
+}
+__device__ __forceinline__ void advance_position(V3& hi, V3& lo, V3 v, float dt) {
+  add_compensated(hi.x, lo.x, v.x, dt);
+  add_compensated(hi.y, lo.y, v.y, dt);
+  add_compensated(hi.z, lo.z, v.z, dt);
+}
+
+// hi + lo <- hi + lo + d with the Fast2Sum of hi and lo + d.
+__device__ __forceinline__ void add_pair(float& hi, float& lo, float d) {
+  const float y = lo + d;
+  const float s = hi + y;
+  lo = y - (s - hi);
+  hi = s;
+}
+
+// q <- normalize(q + dt/2 q (x) (0, omega)) on a quaternion held as the pair (h, l) (the
+// rotation increment per step is far below the ulp of a unit quaternion's components): the
+// increment, from the high part, is added to the pair; the normalisation then enters as the
+// correction (1/|q| - 1) q, added the same way.  That correction only changes the norm, where
+// the FP32 rounding of the factor does not touch the rotation.
+__device__ __forceinline__ void advance_quat(Q4& h, Q4& l, V3 o, float dt) {
   const float hdt = 0.5f * dt;
-  const Q4 qq = {q.w + hdt * (-q.x * o.x - q.y * o.y - q.z * o.z),
-                 q.x + hdt * (q.w * o.x + q.y * o.z - q.z * o.y),
-                 q.y + hdt * (q.w * o.y - q.x * o.z + q.z * o.x),
-                 q.z + hdt * (q.w * o.z + q.x * o.y - q.y * o.x)};
-  const float inrm = rsqrtf(qq.w * qq.w + qq.x * qq.x + qq.y * qq.y + qq.z * qq.z);
-  return {qq.w * inrm, qq.x * inrm, qq.y * inrm, qq.z * inrm};
+  const Q4 d = {hdt * (-h.x * o.x - h.y * o.y - h.z * o.z), hdt * (h.w * o.x + h.y * o.z - h.z * o.y),
+                hdt * (h.w * o.y - h.x * o.z + h.z * o.x), hdt * (h.w * o.z + h.x * o.y - h.y * o.x)};
+  add_pair(h.w, l.w, d.w);
+  add_pair(h.x, l.x, d.x);
+  add_pair(h.y, l.y, d.y);
+  add_pair(h.z, l.z, d.z);
+  const float eps = rsqrtf(h.w * h.w + h.x * h.x + h.y * h.y + h.z * h.z) - 1.f;
+  add_pair(h.w, l.w, eps * h.w);
+  add_pair(h.x, l.x, eps * h.x);
+  add_pair(h.y, l.y, eps * h.y);
+  add_pair(h.z, l.z, eps * h.z);
 }
 
 __device__ __forceinline__ Q4 qmul(Q4 a, Q4 b) {
@@ -376,16 +409,42 @@ __device__ __forceinline__ void env_finish(V3 acc, float dmax, V3& n, float& dep
 constexpr int kEnvCand = 32;
 constexpr float kEnvMargin = 1.0f;
 
+// Whole-handle state arrays in device memory: x, v (3 floats per point), q (4 per frame, w x y
+// z), w (3 per frame), and the low parts of x and q (layouts of x and q; null: read as 0 and
+// not written).
+struct StateArrays {
+  float *x, *v, *q, *w, *xl, *ql;
+};
+// One whole-handle state stored contiguously (trajectories, checkpoints):
+//   [x (3 n_pts) | v (3 n_pts) | q (4 n_frames) | w (3 n_frames) | xl (3 n_pts) | ql (4 n_frames)]
+__host__ __device__ __forceinline__ StateArrays state_at(float* base, long long n_pts,
+                                                         long long n_frames) {
+  return {base, base + 3 * n_pts, base + 6 * n_pts, base + 6 * n_pts + 4 * n_frames,
+          base + 6 * n_pts + 7 * n_frames, base + 9 * n_pts + 7 * n_frames};
+}
+__host__ __device__ __forceinline__ long long state_floats(long long n_pts, long long n_frames) {
+  return 9 * n_pts + 11 * n_frames;
+}
+
 // Registers of one lane of a rod's workgroup: E slots (frame j, point j+1) plus, in lane 0,
 // the base point.  The member functions are the phases of one time step; the forward kernel
 // and the adjoint kernel call the same functions, so a recomputed step is bit-identical.
+//
+// Positions and quaternions are held as unevaluated sums of two floats (X + XL, Qf + QL; the
+// low part below half an ulp of the high one): the per-step increments dt v and
+// dt/2 q (x) (0, omega) are far below the ulp of a coordinate of a metres-long rod or of a unit
+// quaternion's component, and rounding the sums to one float every step perturbs the
+// trajectory, and the gradients of a rollout, far more than the FP32 rounding of v and omega
+// does.  Increments are added with compensated (Fast2Sum) updates; segment vectors and the
+// quaternion differences of the Darboux vectors take the two parts' differences separately;
+// the low parts travel through HBM between launches.
 template <int W, int E>
 struct RodLane {
-  V3 X[E], Vv[E], Om[E];
-  Q4 Qf[E];
+  V3 X[E], XL[E], Vv[E], Om[E];
+  Q4 Qf[E], QL[E];
   float P[P_NROWS][E];
   bool ok[E];
-  V3 bx, bv;
+  V3 bx, bxl, bv;
   int g, j0, n;
   int off, nloc;   // window of the rod held by this workgroup: slots [off, off + nloc)
   bool ghost;      // off > 0: lane 0's "base point" is point `off`, held fixed (a halo edge)
@@ -431,108 +490,135 @@ struct RodLane {
     }
   }
 
-  __device__ __forceinline__ void load_state(const RodDev& rd, const float* __restrict__ gx,
-                                             const float* __restrict__ gv,
-                                             const float* __restrict__ gq,
-                                             const float* __restrict__ gw) {
+  __device__ __forceinline__ void load_state(const RodDev& rd, const StateArrays& sa) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int j = off + j0 + e;
+      X[e] = XL[e] = Vv[e] = Om[e] = {0.f, 0.f, 0.f};
+      Qf[e] = {1.f, 0.f, 0.f, 0.f};
+      QL[e] = {0.f, 0.f, 0.f, 0.f};
       if (ok[e]) {
-        const float* px = gx + 3 * (rd.pt_off + j + 1);
-        const float* pv = gv + 3 * (rd.pt_off + j + 1);
-        const float* pq = gq + 4 * (rd.fr_off + j);
-        const float* pw = gw + 3 * (rd.fr_off + j);
+        const float* px = sa.x + 3 * (rd.pt_off + j + 1);
+        const float* pv = sa.v + 3 * (rd.pt_off + j + 1);
+        const float* pq = sa.q + 4 * (rd.fr_off + j);
+        const float* pw = sa.w + 3 * (rd.fr_off + j);
         X[e] = {px[0], px[1], px[2]};
         Vv[e] = {pv[0], pv[1], pv[2]};
         Qf[e] = {pq[0], pq[1], pq[2], pq[3]};
         Om[e] = {pw[0], pw[1], pw[2]};
-      } else {
-        X[e] = {0.f, 0.f, 0.f};
-        Vv[e] = {0.f, 0.f, 0.f};
-        Qf[e] = {1.f, 0.f, 0.f, 0.f};
-        Om[e] = {0.f, 0.f, 0.f};
+        if (sa.xl) {
+          const float* pl = sa.xl + 3 * (rd.pt_off + j + 1);
+          XL[e] = {pl[0], pl[1], pl[2]};
+        }
+        if (sa.ql) {
+          const float* pl = sa.ql + 4 * (rd.fr_off + j);
+          QL[e] = {pl[0], pl[1], pl[2], pl[3]};
+        }
       }
     }
-    bx = {0.f, 0.f, 0.f};
-    bv = {0.f, 0.f, 0.f};
+    bx = bxl = bv = {0.f, 0.f, 0.f};
     if (g == 0) {
-      const float* px = gx + 3 * (rd.pt_off + off);
-      const float* pv = gv + 3 * (rd.pt_off + off);
+      const float* px = sa.x + 3 * (rd.pt_off + off);
+      const float* pv = sa.v + 3 * (rd.pt_off + off);
       bx = {px[0], px[1], px[2]};
       bv = {pv[0], pv[1], pv[2]};
+      if (sa.xl) {
+        const float* pl = sa.xl + 3 * (rd.pt_off + off);
+        bxl = {pl[0], pl[1], pl[2]};
+      }
     }
   }
 
   // Writes the slots [own_lo, own_hi) of the window (all by default) and, for a window at the
   // rod's base, the base point; returns a sum of the written values (non-finite if any is).
-  __device__ __forceinline__ float store_state(const RodDev& rd, float* __restrict__ gx,
-                                               float* __restrict__ gv, float* __restrict__ gq,
-                                               float* __restrict__ gw, int own_lo = 0,
-                                               int own_hi = 1 << 30) const {
+  __device__ __forceinline__ float store_state(const RodDev& rd, const StateArrays& sa,
+                                               int own_lo = 0, int own_hi = 1 << 30) const {
     float chk = 0.f;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int jl = j0 + e;
       const int j = off + jl;
       if (ok[e] && jl >= own_lo && jl < own_hi) {
-        float* px = gx + 3 * (rd.pt_off + j + 1);
-        float* pv = gv + 3 * (rd.pt_off + j + 1);
-        float* pq = gq + 4 * (rd.fr_off + j);
-        float* pw = gw + 3 * (rd.fr_off + j);
+        float* px = sa.x + 3 * (rd.pt_off + j + 1);
+        float* pv = sa.v + 3 * (rd.pt_off + j + 1);
+        float* pq = sa.q + 4 * (rd.fr_off + j);
+        float* pw = sa.w + 3 * (rd.fr_off + j);
         px[0] = X[e].x; px[1] = X[e].y; px[2] = X[e].z;
         pv[0] = Vv[e].x; pv[1] = Vv[e].y; pv[2] = Vv[e].z;
         pq[0] = Qf[e].w; pq[1] = Qf[e].x; pq[2] = Qf[e].y; pq[3] = Qf[e].z;
         pw[0] = Om[e].x; pw[1] = Om[e].y; pw[2] = Om[e].z;
+        if (sa.xl) {
+          float* pl = sa.xl + 3 * (rd.pt_off + j + 1);
+          pl[0] = XL[e].x; pl[1] = XL[e].y; pl[2] = XL[e].z;
+        }
+        if (sa.ql) {
+          float* pl = sa.ql + 4 * (rd.fr_off + j);
+          pl[0] = QL[e].w; pl[1] = QL[e].x; pl[2] = QL[e].y; pl[3] = QL[e].z;
+        }
         chk += X[e].x + X[e].y + X[e].z + Vv[e].x + Vv[e].y + Vv[e].z + Qf[e].w + Om[e].x +
                Om[e].y + Om[e].z;
       }
     }
     if (g == 0 && off == 0) {
-      float* px = gx + 3 * rd.pt_off;
-      float* pv = gv + 3 * rd.pt_off;
+      float* px = sa.x + 3 * rd.pt_off;
+      float* pv = sa.v + 3 * rd.pt_off;
       px[0] = bx.x; px[1] = bx.y; px[2] = bx.z;
       pv[0] = bv.x; pv[1] = bv.y; pv[2] = bv.z;
+      if (sa.xl) {
+        float* pl = sa.xl + 3 * rd.pt_off;
+        pl[0] = bxl.x; pl[1] = bxl.y; pl[2] = bxl.z;
+      }
       chk += bx.x + bx.y + bx.z + bv.x + bv.y + bv.z;
     }
     return chk;
   }
 
-  // A: x of each slot's left point (from the lane below; the base point for lane 0) and q of
-  // the right frame (from the lane above).
-  // Exchange A: the left neighbour point's position and the next frame's quaternion; with
+  // Exchange A: the left neighbour point's position (both parts: xl, xll; the base point for
+  // lane 0) and the next frame's quaternion (both parts: qn, qnl; from the lane above); with
   // internal friction (D) also that point's velocity vl and that frame's angular velocity wn.
   template <bool D>
-  __device__ __forceinline__ void exchange_a(Mailbox<W>& mb, int& par, V3& xl, Q4& qn, V3& vl,
-                                             V3& wn) const {
+  __device__ __forceinline__ void exchange_a(Mailbox<W>& mb, int& par, V3& xl, V3& xll, Q4& qn,
+                                             Q4& qnl, V3& vl, V3& wn) const {
+    const V3 a = X[E - 1], al = XL[E - 1];
+    const Q4 b = Qf[0], bl = QL[0];
     if constexpr (D) {
-      float mh[6] = {X[E - 1].x, X[E - 1].y, X[E - 1].z, Vv[E - 1].x, Vv[E - 1].y, Vv[E - 1].z};
-      float ml[7] = {Qf[0].w, Qf[0].x, Qf[0].y, Qf[0].z, Om[0].x, Om[0].y, Om[0].z};
-      float lo[6], hi[7];
-      exchange<W, E, 6, 7>(mh, lo, ml, hi, mb, par);
+      const V3 c = Vv[E - 1], o = Om[0];
+      float mh[9] = {a.x, a.y, a.z, al.x, al.y, al.z, c.x, c.y, c.z};
+      float ml[11] = {b.w, b.x, b.y, b.z, bl.w, bl.x, bl.y, bl.z, o.x, o.y, o.z};
+      float lo[9], hi[11];
+      exchange<W, E, 9, 11>(mh, lo, ml, hi, mb, par);
       xl = {lo[0], lo[1], lo[2]};
-      vl = {lo[3], lo[4], lo[5]};
+      xll = {lo[3], lo[4], lo[5]};
+      vl = {lo[6], lo[7], lo[8]};
       if (g == 0) {
         xl = bx;
+        xll = bxl;
         vl = bv;
       }
       qn = {hi[0], hi[1], hi[2], hi[3]};
-      wn = {hi[4], hi[5], hi[6]};
+      qnl = {hi[4], hi[5], hi[6], hi[7]};
+      wn = {hi[8], hi[9], hi[10]};
     } else {
-      float mh[3] = {X[E - 1].x, X[E - 1].y, X[E - 1].z};
-      float ml[4] = {Qf[0].w, Qf[0].x, Qf[0].y, Qf[0].z};
-      float lo[3], hi[4];
-      exchange<W, E, 3, 4>(mh, lo, ml, hi, mb, par);
+      float mh[6] = {a.x, a.y, a.z, al.x, al.y, al.z};
+      float ml[8] = {b.w, b.x, b.y, b.z, bl.w, bl.x, bl.y, bl.z};
+      float lo[6], hi[8];
+      exchange<W, E, 6, 8>(mh, lo, ml, hi, mb, par);
       xl = {lo[0], lo[1], lo[2]};
-      if (g == 0) xl = bx;
+      xll = {lo[3], lo[4], lo[5]};
+      if (g == 0) {
+        xl = bx;
+        xll = bxl;
+      }
       qn = {hi[0], hi[1], hi[2], hi[3]};
+      qnl = {hi[4], hi[5], hi[6], hi[7]};
       vl = {0.f, 0.f, 0.f};
       wn = {0.f, 0.f, 0.f};
     }
   }
-  __device__ __forceinline__ void exchange_a(Mailbox<W>& mb, int& par, V3& xl, Q4& qn) const {
+  __device__ __forceinline__ void exchange_a(Mailbox<W>& mb, int& par, V3& xl, V3& xll, Q4& qn,
+                                             Q4& qnl) const {
     V3 vl, wn;
-    exchange_a<false>(mb, par, xl, qn, vl, wn);
+    exchange_a<false>(mb, par, xl, xll, qn, qnl, vl, wn);
   }
 
   // F: segment forces (stretch eq. (2), penalty eq. (8)) and joint torques (eq. (3) with the
@@ -544,7 +630,8 @@ struct RodLane {
   // du/dt = (rw (w_{j+1} - w_j) + rv x (w_{j+1} + w_j)) / lbar for the relative rotation
   // r = conj(q_j) q_{j+1}; vl and wn are the exchanged neighbour velocities.
   template <bool D = false>
-  __device__ __forceinline__ void forces(Mailbox<W>& mb, int& par, V3 xl, Q4 qn, V3 (&F)[E],
+  __device__ __forceinline__ void forces(Mailbox<W>& mb, int& par, V3 xl, V3 xll, Q4 qn, Q4 qnl,
+                                         V3 (&F)[E],
                                          V3 (&T)[E], V3 (&Ev)[E], V3& fs0, V3& enext,
                                          float td = 0.f, V3 vl = {0.f, 0.f, 0.f},
                                          V3 wn = {0.f, 0.f, 0.f}) const {
@@ -552,8 +639,11 @@ struct RodLane {
     fs0 = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int e = 0; e < E; ++e) {
+      // segment vector from both parts: the high parts of neighbouring points differ by little
+      // (their difference is exact or nearly so), then the low parts are added
       const V3 xa = (e == 0) ? xl : X[e - 1];
-      const V3 d = X[e] - xa;
+      const V3 xal = (e == 0) ? xll : XL[e - 1];
+      const V3 d = (X[e] - xa) + (XL[e] - xal);
       Ev[e] = d;
       const float len2 = dot(d, d);
       const float il = rsqrtf(len2);
@@ -575,7 +665,11 @@ struct RodLane {
       f = sel(ok[e], f, V3{0.f, 0.f, 0.f});                      // force on point j+1
       const V3 tpen = {-lkp * dot(d2, t), lkp * dot(d1, t), 0.f};  // l K_p e_3 x R^T t
       const Q4 qb = (e == E - 1) ? qn : Qf[e + 1];
-      const Q4 dq = {qb.w - q.w, qb.x - q.x, qb.y - q.y, qb.z - q.z};
+      const Q4 qbl = (e == E - 1) ? qnl : QL[e + 1];
+      const Q4 ql = QL[e];
+      // q_{j+1} - q_j from both parts (neighbouring frames differ by little)
+      const Q4 dq = {(qb.w - q.w) + (qbl.w - ql.w), (qb.x - q.x) + (qbl.x - ql.x),
+                     (qb.y - q.y) + (qbl.y - ql.y), (qb.z - q.z) + (qbl.z - ql.z)};
       const float rw = q.w * qb.w + q.x * qb.x + q.y * qb.y + q.z * qb.z;
       const V3 va = {q.x, q.y, q.z}, dv = {dq.x, dq.y, dq.z};
       const V3 rv = {q.w * dv.x - dq.w * va.x - (va.y * dv.z - va.z * dv.y),
@@ -638,7 +732,7 @@ struct RodLane {
       if (ghost) {
         bv = {0.f, 0.f, 0.f};                                  // fixed halo-edge point
       } else if (rd.clamp) {
-        bv = (1.0f / dt) * (xc - bx);
+        bv = (1.0f / dt) * ((xc - bx) - bxl);
         Om[0] = wc;
       } else {
         V3 Fb = V3{0.f, 0.f, 0.f} - fs0;
@@ -841,15 +935,17 @@ struct RodLane {
   __device__ __forceinline__ void integrate_velocities(const RodDev& rd, V3 xc, Q4 qc) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      X[e] = fma3(dt, Vv[e], X[e]);
-      Qf[e] = advance_quat(Qf[e], Om[e], dt);
+      advance_position(X[e], XL[e], Vv[e], dt);
+      advance_quat(Qf[e], QL[e], Om[e], dt);
     }
     if (g == 0 && !ghost) {
       if (rd.clamp) {
         bx = xc;
+        bxl = {0.f, 0.f, 0.f};
         Qf[0] = qc;
+        QL[0] = {0.f, 0.f, 0.f, 0.f};
       } else {
-        bx = fma3(dt, bv, bx);
+        advance_position(bx, bxl, bv, dt);
       }
     }
   }
@@ -888,16 +984,16 @@ __device__ __forceinline__ void clamp_for_step(const RodDev& rd, float (*cbuf)[1
 
 // Forward kernel: steps one rod per workgroup n_steps times with the state in registers.
 // traj (nullable): the whole-handle state at the start of step s < traj_steps is written to
-// traj + s * traj_stride, laid out as [x (3 n_pts) | v (3 n_pts) | q (4 n_frames) | w (3 n_frames)]
-// (traj_steps = 1 writes a checkpoint of the launch's initial state).
+// traj + s * traj_stride in the contiguous layout of state_at (traj_steps = 1 writes a
+// checkpoint of the launch's initial state).
 // tips (nullable): x_N after step s goes to tips[(rod * tip_steps + steps_done - tip_base + s) * 3].
 // store_final = 0 leaves gx..gw untouched (a recomputation that only needs traj).
 template <int W, int E, int F = 0>
 __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
     const RodDev* __restrict__ rods, const int* __restrict__ rod_ids, const float* __restrict__ prm,
-    int prm_stride, float* __restrict__ gx, float* __restrict__ gv, float* __restrict__ gq,
-    float* __restrict__ gw, const float* __restrict__ fext, const float* __restrict__ text,
-    int n_steps, long long steps_done, int* __restrict__ status, float* __restrict__ traj,
+    int prm_stride, StateArrays st, const float* __restrict__ fext,
+    const float* __restrict__ text, int n_steps, long long steps_done, int* __restrict__ status,
+    float* __restrict__ traj,
     long long traj_stride, int n_pts, int n_frames, float* __restrict__ tips, int tip_steps,
     long long tip_base, int traj_steps, int store_final) {
   __shared__ Mailbox<W> mb;
@@ -906,7 +1002,7 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
   const RodDev rd = rods[rod];
   RodLane<W, E> L;
   L.load_params(rd, prm, prm_stride);
-  L.load_state(rd, gx, gv, gq, gw);
+  L.load_state(rd, st);
   __shared__ float4 lcand[(F & kFeatEnv) ? 64 * W * E : 1];
   __shared__ float lrad[(F & kFeatEnv) ? 64 * W * E : 1];
   if (F & kFeatEnv) L.env_load(rd, lcand, lrad);
@@ -927,15 +1023,15 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
 
   for (int s = 0; s < n_steps; ++s) {
     if (traj && s < traj_steps) {
-      float* base = traj + (long long)s * traj_stride;
-      L.store_state(rd, base, base + 3 * n_pts, base + 6 * n_pts, base + 6 * n_pts + 4 * n_frames);
+      L.store_state(rd, state_at(traj + (long long)s * traj_stride, n_pts, n_frames));
     }
     if (F & kFeatEnv) L.env_detect(rd, lcand, lrad);   // environment collisions (Fig. 5: detection first)
-    V3 xl, vl, wn;
-    Q4 qn;
-    L.template exchange_a<(F & kFeatDamp) != 0>(mb, par, xl, qn, vl, wn);
+    V3 xl, xll, vl, wn;
+    Q4 qn, qnl;
+    L.template exchange_a<(F & kFeatDamp) != 0>(mb, par, xl, xll, qn, qnl, vl, wn);
     V3 Fo[E], T[E], Ev[E], fs0, enext;
-    L.template forces<(F & kFeatDamp) != 0>(mb, par, xl, qn, Fo, T, Ev, fs0, enext, rd.damp_int, vl, wn);
+    L.template forces<(F & kFeatDamp) != 0>(mb, par, xl, xll, qn, qnl, Fo, T, Ev, fs0, enext,
+                                            rd.damp_int, vl, wn);
     clamp_for_step<W>(rd, cbuf, s, n_steps, steps_done, xc, qc, wc, rd.driven && rd.clamp, L.g);
     const bool hfirst = hb && hn == 0;
     if (hfirst && L.g < 64) {   // wave 0, all lanes: take the pose if whole and new
@@ -989,7 +1085,7 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
   }
   if (F & kFeatEnv) L.env_store(rd, lcand);
   if (store_final) {
-    const float chk = L.store_state(rd, gx, gv, gq, gw);
+    const float chk = L.store_state(rd, st);
     if (!__builtin_isfinite(chk)) atomicOr(status, 1);
   }
 }
@@ -1047,9 +1143,9 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
     const RodDev* __restrict__ rods, const GroupDev* __restrict__ groups,
     const int* __restrict__ partner, const float* __restrict__ rho_slot,
     float4* __restrict__ cbuild, uint16_t* __restrict__ ccand,
-    const float* __restrict__ prm, int prm_stride, float* __restrict__ gx, float* __restrict__ gv,
-    float* __restrict__ gq, float* __restrict__ gw, const float* __restrict__ fext,
-    const float* __restrict__ text, int n_steps, long long steps_done, int* __restrict__ status) {
+    const float* __restrict__ prm, int prm_stride, StateArrays st,
+    const float* __restrict__ fext, const float* __restrict__ text, int n_steps,
+    long long steps_done, int* __restrict__ status) {
   constexpr int CAP = 64 * W * E;                                   // slots per rod
   constexpr int CC = CT ? CAP : 1;                                  // contact-list slots
   constexpr int SMAX = CT ? 2 * ((CAP + kSphereSize - 1) / kSphereSize) : 1;  // spheres
@@ -1088,7 +1184,7 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
   const bool contact = CT && gp.contact != 0;
   RodLane<W, E> L;
   L.load_params(rd, prm, prm_stride);
-  L.load_state(rd, gx, gv, gq, gw);
+  L.load_state(rd, st);
   int part[E], cnt[E], ncand[E];
   float rho[E];
 #pragma unroll
@@ -1278,11 +1374,11 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
     }
 
     // ---- the step
-    V3 xl;
-    Q4 qn;
-    L.exchange_a(mb[sub], par, xl, qn);
+    V3 xl, xll;
+    Q4 qn, qnl;
+    L.exchange_a(mb[sub], par, xl, xll, qn, qnl);
     V3 F[E], T[E], Ev[E], fs0, enext;
-    L.forces(mb[sub], par, xl, qn, F, T, Ev, fs0, enext);
+    L.forces(mb[sub], par, xl, xll, qn, qnl, F, T, Ev, fs0, enext);
     clamp_for_step<W>(rd, cbuf[sub], s, n_steps, steps_done, xc, qc, wc, any_driven, L.g);
     L.integrate_forces(rd, F, T, fs0, xc, wc, fext, text);
     for (int it = 0; it < rd.n_iter; ++it) {
@@ -1362,7 +1458,7 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
     L.integrate_velocities(rd, xc, qc);
   }
   if (active) {
-    const float chk = L.store_state(rd, gx, gv, gq, gw);
+    const float chk = L.store_state(rd, st);
     if (!__builtin_isfinite(chk)) atomicOr(status, 1);
   }
   if (contact) {
@@ -1399,10 +1495,10 @@ struct GridChunk {
   int32_t every;           // T: steps between halo exchanges (H >= T (2 n_iter + 2))
 };
 
-// Mailbox part: the 13 words (x, v of point j+1; q, w of frame j) of up to pub_slots slots,
-// word-major (word k of slot i at k pub_slots + i), so that a wavefront's store or load of one
-// word covers consecutive addresses.
-constexpr int kPubSlotFloats = 13;
+// Mailbox part: the 20 words (x, v of point j+1; q, w of frame j; the low parts of x and q) of
+// up to pub_slots slots, word-major (word k of slot i at k pub_slots + i), so that a
+// wavefront's store or load of one word covers consecutive addresses.
+constexpr int kPubSlotFloats = 20;
 
 // Mailbox words are read and written as device-scope relaxed atomics (coherent across the
 // XCDs' L2 caches without writing back or invalidating them); the step flags order them.
@@ -1417,8 +1513,7 @@ template <int W, int E>
 __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
     const RodDev* __restrict__ rods, const GridChunk* __restrict__ chunks,
     const int* __restrict__ block_chunk, const float* __restrict__ prm, int prm_stride,
-    float* __restrict__ gx, float* __restrict__ gv, float* __restrict__ gq, float* __restrict__ gw,
-    const float* __restrict__ fext, const float* __restrict__ text, int n_steps,
+    StateArrays st, const float* __restrict__ fext, const float* __restrict__ text, int n_steps,
     long long steps_done, int* __restrict__ status, float* pub, int pub_slots, int n_chunks,
     int* flags, int spin_limit) {
   __shared__ Mailbox<W> mb;
@@ -1429,7 +1524,7 @@ __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
   const RodDev rd = rods[ck.rod];
   RodLane<W, E> L;
   L.load_params(rd, prm, prm_stride, ck.win0, ck.nwin);
-  L.load_state(rd, gx, gv, gq, gw);
+  L.load_state(rd, st);
   int par = 0;
   V3 xc = {rd.cx0[0], rd.cx0[1], rd.cx0[2]}, wc = {0.f, 0.f, 0.f};
   Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
@@ -1441,11 +1536,11 @@ __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
 
   for (int s = 0; s < n_steps; ++s) {
     const long long gs = steps_done + s;
-    V3 xl;
-    Q4 qn;
-    L.exchange_a(mb, par, xl, qn);
+    V3 xl, xll;
+    Q4 qn, qnl;
+    L.exchange_a(mb, par, xl, xll, qn, qnl);
     V3 F[E], T[E], Ev[E], fs0, enext;
-    L.forces(mb, par, xl, qn, F, T, Ev, fs0, enext);
+    L.forces(mb, par, xl, xll, qn, qnl, F, T, Ev, fs0, enext);
     if (ck.win0 == 0)
       clamp_for_step<W>(rd, cbuf, s, n_steps, steps_done, xc, qc, wc, rd.driven && rd.clamp, L.g);
     L.integrate_forces(rd, F, T, fs0, xc, wc, fext, text);
@@ -1469,9 +1564,11 @@ __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
       const bool p1 = L.ok[e] && o >= ck.c - H - 1 && o < ck.c && ck.right >= 0;
       if (p0 || p1) {
         float* d = p0 ? mine + o : mine + pub_slots * kPubSlotFloats + (o - (ck.c - H - 1));
-        const float v[kPubSlotFloats] = {L.X[e].x, L.X[e].y, L.X[e].z, L.Vv[e].x, L.Vv[e].y,
-                                         L.Vv[e].z, L.Qf[e].w, L.Qf[e].x, L.Qf[e].y, L.Qf[e].z,
-                                         L.Om[e].x, L.Om[e].y, L.Om[e].z};
+        const float v[kPubSlotFloats] = {L.X[e].x,  L.X[e].y,  L.X[e].z,  L.Vv[e].x,
+                                         L.Vv[e].y, L.Vv[e].z, L.Qf[e].w, L.Qf[e].x,
+                                         L.Qf[e].y, L.Qf[e].z, L.Om[e].x, L.Om[e].y,
+                                         L.Om[e].z, L.XL[e].x, L.XL[e].y, L.XL[e].z,
+                                         L.QL[e].w, L.QL[e].x, L.QL[e].y, L.QL[e].z};
 #pragma unroll
         for (int k = 0; k < kPubSlotFloats; ++k) put_coherent(d + k * pub_slots, v[k]);
       }
@@ -1522,15 +1619,18 @@ __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
         L.Vv[e] = {v[3], v[4], v[5]};
         L.Qf[e] = {v[6], v[7], v[8], v[9]};
         L.Om[e] = {v[10], v[11], v[12]};
+        L.XL[e] = {v[13], v[14], v[15]};
+        L.QL[e] = {v[16], v[17], v[18], v[19]};
       }
     }
     if (L.g == 0 && L.ghost && lp) {   // halo-edge point: point win0 = point of slot win0 - 1
       const int ps = pub_slots;
       L.bx = {get_coherent(lp), get_coherent(lp + ps), get_coherent(lp + 2 * ps)};
+      L.bxl = {get_coherent(lp + 13 * ps), get_coherent(lp + 14 * ps), get_coherent(lp + 15 * ps)};
       L.bv = {get_coherent(lp + 3 * ps), get_coherent(lp + 4 * ps), get_coherent(lp + 5 * ps)};
     }
   }
-  const float chk = L.store_state(rd, gx, gv, gq, gw, own_lo, own_hi);
+  const float chk = L.store_state(rd, st, own_lo, own_hi);
   if (!__builtin_isfinite(chk)) atomicOr(status, 1);
 }
 

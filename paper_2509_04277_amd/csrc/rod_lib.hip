@@ -26,12 +26,13 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-using KernelFn = void (*)(const RodDev*, const int*, const float*, int, float*, float*, float*,
-                          float*, const float*, const float*, int, long long, int*, float*,
-                          long long, int, int, float*, int, long long, int, int);
+using corde::StateArrays;
+using KernelFn = void (*)(const RodDev*, const int*, const float*, int, StateArrays, const float*,
+                          const float*, int, long long, int*, float*, long long, int, int, float*,
+                          int, long long, int, int);
 using GridFn = void (*)(const RodDev*, const corde::GridChunk*, const int*, const float*, int,
-                        float*, float*, float*, float*, const float*, const float*, int, long long,
-                        int*, float*, int, int, int*, int);
+                        StateArrays, const float*, const float*, int, long long, int*, float*, int,
+                        int, int*, int);
 // Long-rod kernel shape: 4 wavefronts (one per SIMD) x 2 elements per lane = 512-slot windows.
 constexpr int kGridWaves = 4, kGridElems = 2;
 constexpr int kResidentMax = 2048;   // longest rod stepped by a single workgroup
@@ -89,8 +90,8 @@ GridFn grid_kernel() { return corde::rod_grid_kernel<kGridWaves, kGridElems>; }
 
 using GroupFn = void (*)(const RodDev*, const corde::GroupDev*, const int*, const float*,
                          float4*, uint16_t*,
-                         const float*, int, float*, float*, float*, float*, const float*,
-                         const float*, int, long long, int*);
+                         const float*, int, StateArrays, const float*, const float*, int,
+                         long long, int*);
 struct GroupEntry {
   int waves, elems;
   bool contact;   // contact compiled in (binding-only kernels leave its LDS out)
@@ -130,6 +131,9 @@ struct rod_ctx {
   float* d_prm = nullptr;
   int prm_stride = 0;
   float *d_x = nullptr, *d_v = nullptr, *d_q = nullptr, *d_w = nullptr;
+  // low parts of the positions and quaternions (x = d_x + d_xl, q = d_q + d_ql), zeroed by
+  // rod_set_state
+  float *d_xl = nullptr, *d_ql = nullptr;
   float *d_fext = nullptr, *d_text = nullptr;
   int* d_status = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -187,6 +191,8 @@ struct rod_ctx {
   int env_nodes = 0, env_tris = 0;
   // adjoint rollout (rod_adjoint_forward / rod_adjoint_backward)
   bool adj_ready = false;
+  long long adj_serial = 0;   // number of the held rollout (rollouts are numbered 1, 2, ...)
+  long long adj_count = 0;    // rollouts recorded so far
   int adj_steps = 0, adj_ckpt = 0, adj_nckpt = 0;
   long long adj_step0 = 0;
   float* d_ckpt = nullptr;   // adj_nckpt whole-handle states (checkpoints)
@@ -641,8 +647,7 @@ rod_status setup_long_rods(rod_ctx* c) {
 // one on the same device (LongGate), so two such grids never hold the compute units against
 // each other.  A workgroup whose neighbour still does not arrive gives up after a bounded wait
 // (status 4) instead of hanging.
-rod_status launch_long(rod_ctx* c, float* x, float* v, float* q, float* w, int ks, long long done,
-                       hipStream_t stream) {
+rod_status launch_long(rod_ctx* c, StateArrays sa, int ks, long long done, hipStream_t stream) {
   if (!c->n_chunks) return ROD_OK;
   int spin = 1 << 22;
   const RodDev* rods = c->d_rods;
@@ -656,7 +661,7 @@ rod_status launch_long(rod_ctx* c, float* x, float* v, float* q, float* w, int k
   float* pub = c->d_pub;
   int ps = c->pub_slots, nc = c->n_chunks;
   int* fl = c->d_flags;
-  void* args[] = {&rods, &chunks, &bc, &prm, &stride, &x, &v, &q, &w, &fe, &te, &ks, &done,
+  void* args[] = {&rods, &chunks, &bc, &prm, &stride, &sa, &fe, &te, &ks, &done,
                   &st, &pub, &ps, &nc, &fl, &spin};
   HIP_TRY(c, hipLaunchKernel((const void*)grid_kernel(), dim3(c->n_chunks), dim3(64 * kGridWaves),
                              args, 0, stream));
@@ -683,14 +688,17 @@ rod_status reset_flags(rod_ctx* c) {
   return ROD_OK;
 }
 
+// State arrays of a launch: the handle's own.
+StateArrays handle_state(rod_ctx* c) { return {c->d_x, c->d_v, c->d_q, c->d_w, c->d_xl, c->d_ql}; }
+
 rod_status launch_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long long done,
-                         hipStream_t stream) {
+                         hipStream_t stream, const StateArrays& sp) {
   const KernelEntry* k = find_kernel(b.waves, b.elems);
   const KernelFn fn = k ? k->fn[b.feat] : nullptr;
   if (!fn) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
   hipLaunchKernelGGL(fn, dim3(b.count), dim3(64 * k->waves), 0, stream, c->d_rods,
-                     c->d_rod_ids + b.first, c->d_prm, c->prm_stride, c->d_x, c->d_v, c->d_q,
-                     c->d_w, c->d_fext, c->d_text, ks, done, c->d_status, nullptr, 0LL,
+                     c->d_rod_ids + b.first, c->d_prm, c->prm_stride, sp, c->d_fext,
+                     c->d_text, ks, done, c->d_status, nullptr, 0LL,
                      c->total_pts, c->total_frames, nullptr, 0, 0LL, 0, 1);
   HIP_TRY(c, hipGetLastError());
   return ROD_OK;
@@ -705,7 +713,7 @@ rod_status launch_pair_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long
   hipLaunchKernelGGL(k->fn, dim3(b.count), dim3(128 * k->waves), 0, stream, c->d_rods,
                      c->d_groups + b.first, c->d_partner, c->d_rho, c->d_cbuild, c->d_ccand,
                      c->d_prm, c->prm_stride,
-                     c->d_x, c->d_v, c->d_q, c->d_w, c->d_fext, c->d_text, ks, done, c->d_status);
+                     handle_state(c), c->d_fext, c->d_text, ks, done, c->d_status);
   HIP_TRY(c, hipGetLastError());
   return ROD_OK;
 }
@@ -850,7 +858,8 @@ rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it, int buck
     for (int done = 0; done < n_steps; done += spl) {
       const int ks = std::min(spl, n_steps - done);
       rod_status rs =
-          gi < nb ? launch_bucket(c, c->buckets[bucket >= 0 ? bucket : gi], ks, c->steps_done + done, st)
+          gi < nb ? launch_bucket(c, c->buckets[bucket >= 0 ? bucket : gi], ks, c->steps_done + done, st,
+                                  handle_state(c))
                   : launch_pair_bucket(c, c->pair_buckets[gi - nb], ks, c->steps_done + done, st);
       if (rs != ROD_OK) return rs;
       ++launches;
@@ -871,7 +880,7 @@ rod_status launch_steps(rod_ctx* c, int n_steps, int spl, bool time_it, int buck
     if (g.rec[dev] && g.last[dev] != c->stream) HIP_TRY(c, hipStreamWaitEvent(c->stream, g.ev[dev], 0));
     for (int done = 0; done < n_steps; done += spl) {
       const int ks = std::min(spl, n_steps - done);
-      rod_status rs = launch_long(c, c->d_x, c->d_v, c->d_q, c->d_w, ks, c->steps_done + done,
+      rod_status rs = launch_long(c, handle_state(c), ks, c->steps_done + done,
                                   c->stream);
       if (rs != ROD_OK) return rs;
       ++launches;
@@ -897,8 +906,10 @@ const AdjointEntry* adjoint_shape(int max_n, int waves = 0, int elems = 0) {
   return nullptr;
 }
 
-// floats of one whole-handle state: x, v (3 per point), q (4 per frame), w (3 per frame)
-size_t state_floats(const rod_ctx* c) { return (size_t)6 * c->total_pts + (size_t)7 * c->total_frames; }
+// floats of one whole-handle state in the contiguous layout of corde::state_at
+size_t state_floats(const rod_ctx* c) {
+  return (size_t)corde::state_floats(c->total_pts, c->total_frames);
+}
 
 void free_adjoint(rod_ctx* c) {
   for (float** p : {&c->d_ckpt, &c->d_traj, &c->d_tips, &c->d_dtips, &c->d_adj}) {
@@ -947,7 +958,7 @@ bool ensure_adjoint(rod_ctx* c, int n_steps, int ck) {
 }
 
 // Launches the forward kernel of every bucket on the given state arrays.
-rod_status launch_forward_on(rod_ctx* c, float* x, float* v, float* q, float* w, int ks,
+rod_status launch_forward_on(rod_ctx* c, StateArrays sa, int ks,
                              long long step, float* traj, float* tips, long long tip_base,
                              int traj_steps, int store_final, hipStream_t stream = nullptr) {
   if (!stream) stream = c->stream;
@@ -957,7 +968,7 @@ rod_status launch_forward_on(rod_ctx* c, float* x, float* v, float* q, float* w,
     if (!k) return fail(c, ROD_E_UNSUPPORTED, "kernel shape not built");
     if (b.feat) return fail(c, ROD_E_UNSUPPORTED, "the adjoint steps plain rods only");
     hipLaunchKernelGGL(k->fn[0], dim3(b.count), dim3(64 * k->waves), 0, stream, c->d_rods,
-                       c->d_rod_ids + b.first, c->d_prm, c->prm_stride, x, v, q, w, c->d_fext,
+                       c->d_rod_ids + b.first, c->d_prm, c->prm_stride, sa, c->d_fext,
                        c->d_text, ks, step, c->d_status, traj, S, c->total_pts, c->total_frames,
                        tips, c->adj_steps, tip_base, traj_steps, store_final);
     HIP_TRY(c, hipGetLastError());
@@ -1095,8 +1106,10 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
   if (!dmalloc((void**)&c->d_rods, sizeof(RodDev) * n_rods) ||
       !dmalloc((void**)&c->d_prm, sizeof(float) * rows.size()) ||
       !dmalloc((void**)&c->d_x, sizeof(float) * 3 * pts) ||
+      !dmalloc((void**)&c->d_xl, sizeof(float) * 3 * pts) ||
       !dmalloc((void**)&c->d_v, sizeof(float) * 3 * pts) ||
       !dmalloc((void**)&c->d_q, sizeof(float) * 4 * frames) ||
+      !dmalloc((void**)&c->d_ql, sizeof(float) * 4 * frames) ||
       !dmalloc((void**)&c->d_w, sizeof(float) * 3 * frames) ||
       !dmalloc((void**)&c->d_status, sizeof(int)) ||
       !dmalloc((void**)&c->d_rod_ids, sizeof(int) * n_rods) ||
@@ -1114,8 +1127,10 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
     if (e == hipSuccess) e = hipMemcpy(c->d_text, text.data(), sizeof(float) * text.size(), hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = hipMemset(c->d_x, 0, sizeof(float) * 3 * pts);
+  if (e == hipSuccess) e = hipMemset(c->d_xl, 0, sizeof(float) * 3 * pts);
   if (e == hipSuccess) e = hipMemset(c->d_v, 0, sizeof(float) * 3 * pts);
   if (e == hipSuccess) e = hipMemset(c->d_q, 0, sizeof(float) * 4 * frames);
+  if (e == hipSuccess) e = hipMemset(c->d_ql, 0, sizeof(float) * 4 * frames);
   if (e == hipSuccess) e = hipMemset(c->d_w, 0, sizeof(float) * 3 * frames);
   if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(int));
   if (e == hipSuccess) e = hipEventCreate(&c->ev0);
@@ -1135,7 +1150,8 @@ rod_status rod_destroy(rod_ctx* c) {
   if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
-  for (void* p : {(void*)c->d_rods, (void*)c->d_prm, (void*)c->d_x, (void*)c->d_v,
+  for (void* p : {(void*)c->d_rods, (void*)c->d_prm, (void*)c->d_x, (void*)c->d_xl,
+                  (void*)c->d_ql, (void*)c->d_v,
                   (void*)c->d_q, (void*)c->d_w, (void*)c->d_fext, (void*)c->d_text,
                   (void*)c->d_status, (void*)c->d_rod_ids, (void*)c->d_ckpt, (void*)c->d_traj,
                   (void*)c->d_tips, (void*)c->d_dtips, (void*)c->d_adj,
@@ -1172,8 +1188,10 @@ rod_status rod_set_state(rod_ctx* c, const float* x, const float* v, const float
   if (!std::isfinite(t0)) return fail(c, ROD_E_INVALID, "t0 must be finite");
   const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   HIP_TRY(c, hipMemcpyAsync(c->d_x, x, sizeof(float) * 3 * c->total_pts, k, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_xl, 0, sizeof(float) * 3 * c->total_pts, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->d_v, v, sizeof(float) * 3 * c->total_pts, k, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->d_q, q, sizeof(float) * 4 * c->total_frames, k, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_ql, 0, sizeof(float) * 4 * c->total_frames, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->d_w, w, sizeof(float) * 3 * c->total_frames, k, c->stream));
   if (!on_device) HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->t0 = t0;
@@ -1668,17 +1686,19 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
   // save the state, probe the candidate shapes of every bucket, restore
   const size_t bx = sizeof(float) * 3 * c->total_pts, bq = sizeof(float) * 4 * c->total_frames,
                bw = sizeof(float) * 3 * c->total_frames;
-  float *sx = nullptr, *sv = nullptr, *sq = nullptr, *sw = nullptr;
-  if (hipMalloc(&sx, bx) != hipSuccess || hipMalloc(&sv, bx) != hipSuccess ||
-      hipMalloc(&sq, bq) != hipSuccess || hipMalloc(&sw, bw) != hipSuccess) {
-    for (float* p : {sx, sv, sq, sw}) if (p) (void)hipFree(p);
+  float *sx = nullptr, *sxl = nullptr, *sv = nullptr, *sq = nullptr, *sql = nullptr, *sw = nullptr;
+  if (hipMalloc(&sx, bx) != hipSuccess || hipMalloc(&sxl, bx) != hipSuccess ||
+      hipMalloc(&sv, bx) != hipSuccess || hipMalloc(&sq, bq) != hipSuccess ||
+      hipMalloc(&sql, bq) != hipSuccess || hipMalloc(&sw, bw) != hipSuccess) {
+    for (float* p : {sx, sxl, sv, sq, sql, sw}) if (p) (void)hipFree(p);
     return fail(c, ROD_E_NOMEM, "autotune scratch allocation failed");
   }
-  auto free_all = [&]() { for (float* p : {sx, sv, sq, sw}) (void)hipFree(p); };
+  auto free_all = [&]() { for (float* p : {sx, sxl, sv, sq, sql, sw}) (void)hipFree(p); };
   auto copy = [&](float* d, const float* s, size_t b) {
     return hipMemcpyAsync(d, s, b, hipMemcpyDeviceToDevice, c->stream);
   };
-  if (copy(sx, c->d_x, bx) || copy(sv, c->d_v, bx) || copy(sq, c->d_q, bq) || copy(sw, c->d_w, bw)) {
+  if (copy(sx, c->d_x, bx) || copy(sxl, c->d_xl, bx) || copy(sv, c->d_v, bx) ||
+      copy(sq, c->d_q, bq) || copy(sql, c->d_ql, bq) || copy(sw, c->d_w, bw)) {
     free_all();
     return fail(c, ROD_E_DEVICE, "autotune state save failed");
   }
@@ -1791,7 +1811,8 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
   c->steps_per_launch = steps_per_launch;
   c->steps_done = saved_steps;
   (void)reset_flags(c);
-  if (copy(c->d_x, sx, bx) || copy(c->d_v, sv, bx) || copy(c->d_q, sq, bq) || copy(c->d_w, sw, bw)) {
+  if (copy(c->d_x, sx, bx) || copy(c->d_xl, sxl, bx) || copy(c->d_v, sv, bx) ||
+      copy(c->d_q, sq, bq) || copy(c->d_ql, sql, bq) || copy(c->d_w, sw, bw)) {
     free_all();
     return fail(c, ROD_E_DEVICE, "autotune state restore failed");
   }
@@ -1819,7 +1840,7 @@ rod_status rod_set_stiffness_mult(rod_ctx* c, const float* bend, const float* tw
 }
 
 rod_status rod_adjoint_forward(rod_ctx* c, int32_t n_steps, int32_t ckpt_every, float* tips,
-                               int32_t on_device) {
+                               int32_t on_device, int64_t* rollout) {
   if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
   if (!c->have_state) return fail(c, ROD_E_ORDER, "rod_adjoint_forward before rod_set_state");
   if (n_steps < 1 || ckpt_every < 1) return fail(c, ROD_E_INVALID, "n_steps and ckpt_every must be >= 1");
@@ -1852,8 +1873,8 @@ rod_status rod_adjoint_forward(rod_ctx* c, int32_t n_steps, int32_t ckpt_every, 
     const int len = std::min(ck, n_steps - seg * ck);
     // the launch writes its initial state: the checkpoint (or, with ck = 1, the stored step)
     float* traj = (ck == 1 ? c->d_traj : c->d_ckpt) + (size_t)seg * S;
-    rod_status st = launch_forward_on(c, c->d_x, c->d_v, c->d_q, c->d_w, len, c->steps_done, traj,
-                                      c->d_tips, c->adj_step0, 1, 1);
+    rod_status st = launch_forward_on(c, handle_state(c), len, c->steps_done, traj, c->d_tips,
+                                      c->adj_step0, 1, 1);
     if (st != ROD_OK) return st;
     c->steps_done += len;
   }
@@ -1863,14 +1884,19 @@ rod_status rod_adjoint_forward(rod_ctx* c, int32_t n_steps, int32_t ckpt_every, 
     if (!on_device) HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
   c->adj_ready = true;
+  c->adj_serial = ++c->adj_count;
+  if (rollout) *rollout = c->adj_serial;
   return ROD_OK;
 }
 
-rod_status rod_adjoint_backward(rod_ctx* c, const float* dl_dtips, float* dl_dbend,
-                                float* dl_dtwist, float* dl_dx, float* dl_dv, float* dl_dq,
-                                float* dl_dw, int32_t on_device) {
+rod_status rod_adjoint_backward(rod_ctx* c, int64_t rollout, const float* dl_dtips,
+                                float* dl_dbend, float* dl_dtwist, float* dl_dx, float* dl_dv,
+                                float* dl_dq, float* dl_dw, int32_t on_device) {
   if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
   if (!c->adj_ready) return fail(c, ROD_E_ORDER, "rod_adjoint_backward without rod_adjoint_forward");
+  if (rollout != 0 && rollout != c->adj_serial)
+    return fail(c, ROD_E_ORDER, "rollout " + std::to_string(rollout) +
+                " is no longer held (the handle holds rollout " + std::to_string(c->adj_serial) + ")");
   if (c->n_chunks)
     return fail(c, ROD_E_UNSUPPORTED,
                 "chunked rods are not differentiated (rod_set_chunking(ctx, 2048, 0) restores the default split)");
@@ -1913,8 +1939,8 @@ rod_status rod_adjoint_backward(rod_ctx* c, const float* dl_dtips, float* dl_dbe
       const int len = std::min(ck, c->adj_steps - seg * ck);
       const long long tstep0 = c->adj_step0 + (long long)seg * ck;
       float* cp = c->d_ckpt + (size_t)seg * S;
-      rod_status st = launch_forward_on(c, cp, cp + P3, cp + 2 * P3, cp + 2 * P3 + F4, len, tstep0,
-                                        tb[seg & 1], nullptr, 0, len, 0, c->aux);
+      rod_status st = launch_forward_on(c, corde::state_at(cp, c->total_pts, c->total_frames), len,
+                                        tstep0, tb[seg & 1], nullptr, 0, len, 0, c->aux);
       if (st != ROD_OK) return st;
       HIP_TRY(c, hipEventRecord(c->ev_rec[seg & 1], c->aux));
       return ROD_OK;

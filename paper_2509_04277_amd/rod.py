@@ -85,8 +85,10 @@ _SIGS = {
     "rod_stable_dt": (C.c_int, [C.POINTER(rod_params), _DP]),
     "rod_last_step_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     "rod_set_stiffness_mult": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
-    "rod_adjoint_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _FP, C.c_int32]),
-    "rod_adjoint_backward": (C.c_int, [C.c_void_p, _FP, _FP, _FP, _FP, _FP, _FP, _FP, C.c_int32]),
+    "rod_adjoint_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _FP, C.c_int32,
+                                     C.POINTER(C.c_int64)]),
+    "rod_adjoint_backward": (C.c_int, [C.c_void_p, C.c_int64, _FP, _FP, _FP, _FP, _FP, _FP, _FP,
+                                       C.c_int32]),
     "rod_status_str": (C.c_char_p, [C.c_int]),
     "rod_last_error": (C.c_char_p, [C.c_void_p]),
 }
@@ -291,16 +293,20 @@ class RodBatch:
                                             t.ctypes.data_as(C.POINTER(C.c_float))), self.h)
 
     def adjoint_forward(self, n_steps: int, ckpt_every: int = 20, tips=None):
-        """Rollout with checkpoints; returns the tip trajectory (rods, n_steps, 3)."""
+        """Rollout with checkpoints; returns the tip trajectory (rods, n_steps, 3).  The
+        rollout's number is kept in ``self.rollout``."""
         if tips is None:
             tips = np.empty((len(self.n), int(n_steps), 3), np.float32)
         p, dev = _ptr(tips)
+        rid = C.c_int64(0)
         _check(lib().rod_adjoint_forward(self.h, int(n_steps), int(ckpt_every), C.c_void_p(p),
-                                         dev), self.h)
+                                         dev, C.byref(rid)), self.h)
+        self.rollout = int(rid.value)
         return tips
 
-    def adjoint_backward(self, dl_dtips, out=None):
-        """Gradients for dL/dtip: dict bend, twist (per rod) and x, v, q, w (state layout)."""
+    def adjoint_backward(self, dl_dtips, out=None, rollout: int = 0):
+        """Gradients for dL/dtip: dict bend, twist (per rod) and x, v, q, w (state layout).
+        rollout: the number of the rollout to reverse (0: the one the handle holds)."""
         if out is None:
             out = dict(bend=np.empty(len(self.n), np.float32), twist=np.empty(len(self.n), np.float32),
                        x=np.empty(3 * self.n_points, np.float32), v=np.empty(3 * self.n_points, np.float32),
@@ -309,8 +315,8 @@ class RodBatch:
         ptrs = [_ptr(out[k]) for k in ("bend", "twist", "x", "v", "q", "w")]
         if any(d != dev for _, d in ptrs):
             raise ValueError("dL/dtip and the outputs must be on the same side")
-        _check(lib().rod_adjoint_backward(self.h, C.c_void_p(pd), *[C.c_void_p(p) for p, _ in ptrs],
-                                          dev), self.h)
+        _check(lib().rod_adjoint_backward(self.h, int(rollout), C.c_void_p(pd),
+                                          *[C.c_void_p(p) for p, _ in ptrs], dev), self.h)
         return out
 
     # ---- kernel shape ---------------------------------------------------------------
@@ -425,6 +431,7 @@ def rollout_function():
             batch.adjoint_forward(int(n_steps), int(ckpt_every), tips)
             torch.cuda.synchronize(x0.device)
             ctx.batch = batch
+            ctx.rollout = batch.rollout   # a later forward on the handle makes backward refuse
             return tips
 
         @staticmethod
@@ -434,7 +441,7 @@ def rollout_function():
             out = dict(bend=torch.empty(len(b.n), device=dev), twist=torch.empty(len(b.n), device=dev),
                        x=torch.empty(3 * b.n_points, device=dev), v=torch.empty(3 * b.n_points, device=dev),
                        q=torch.empty(4 * b.n_frames, device=dev), w=torch.empty(3 * b.n_frames, device=dev))
-            b.adjoint_backward(grad_tips.contiguous().float(), out)
+            b.adjoint_backward(grad_tips.contiguous().float(), out, rollout=ctx.rollout)
             torch.cuda.synchronize(dev)
             return (None, out["bend"], out["twist"], out["x"], out["v"], out["q"], out["w"], None, None)
 

@@ -117,8 +117,8 @@ int main(void) {
     expect("autotune", rod_autotune(NULL, 10, 10, &t), ROD_E_INVALID);
     expect("last_step_time", rod_last_step_time(NULL, f, &k), ROD_E_INVALID);
     expect("stiffness_mult", rod_set_stiffness_mult(NULL, f, f), ROD_E_INVALID);
-    expect("adjoint_forward", rod_adjoint_forward(NULL, 10, 5, f, 0), ROD_E_INVALID);
-    expect("adjoint_backward", rod_adjoint_backward(NULL, f, f, f, f, f, f, f, 0), ROD_E_INVALID);
+    expect("adjoint_forward", rod_adjoint_forward(NULL, 10, 5, f, 0, NULL), ROD_E_INVALID);
+    expect("adjoint_backward", rod_adjoint_backward(NULL, 0, f, f, f, f, f, f, f, 0), ROD_E_INVALID);
 
     /* one valid handle: without a GPU rod_create fails cleanly (and frees what it made) */
     int rc = rod_create(&p, 1, NULL, &h);

@@ -2,7 +2,8 @@
 curved rod of N elements, static clamp, 5000 steps) for N = 16384 and 65536, inextensible and
 extensible, 10 steps before the end and at the end, on 32 pieces of 8 consecutive elements
 (9 points, 8 frames) spread along the rod, the last one ending at the tip; plus the largest
-displacement of any point over the run (the position bar's scale).
+displacement of any point over the run (the position bar's scale).  The rollouts start from
+the initial state rounded to FP32, the values the GPU receives.
 
 Run:  python tests/golden/make_c2_golden.py      (a few minutes: four rollouts in parallel)
 """
@@ -22,6 +23,14 @@ WINDOW = 10        # steps between the two stored states
 PIECES, PIECE = 32, 8
 
 
+def fp32(st):
+    """The state rounded to FP32 (kept as doubles): the values the GPU receives."""
+    out = st.copy()
+    for k in ("x", "v", "q", "w"):
+        setattr(out, k, np.asarray(getattr(st, k), dtype=np.float32).astype(np.float64))
+    return out
+
+
 def piece_starts(n):
     return np.unique(np.rint(np.linspace(0, n - PIECE, PIECES)).astype(np.int64))
 
@@ -33,7 +42,7 @@ def path(n, inext):
 def main():
     cases = [(n, inext) for n in SIZES for inext in (True, False)]
     wls = [W.config2(n, inext) for n, inext in cases]
-    rods = [wl.rods[0] for wl in wls]
+    rods = [(s, fp32(st)) for s, st in (wl.rods[0] for wl in wls)]
     n_steps = wls[0].n_steps
     dt = rods[0][0].dt
     assert all(wl.n_steps == n_steps and wl.rods[0][0].dt == dt for wl in wls)

@@ -9,6 +9,7 @@ import pytest
 from oracle import oracle as O
 from paper_2509_04277_amd import rod as R
 from paper_2509_04277_amd import workloads as W
+import parity_metrics as PM
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +44,8 @@ def _gpu(rods, pairs, one_way, n_steps, spl=10, shape=None):
 
 def _oracle(rods, pairs, one_way, n_steps):
     (sa, sta), (sb, stb) = rods[pairs[0, 0]], rods[pairs[0, 2]]
-    A, B = O.rollout_pair(sa, sb, sta, stb, pairs[:, 1], pairs[:, 3], one_way, n_steps)
+    A, B = O.rollout_pair(sa, sb, PM.fp32_input(sta), PM.fp32_input(stb), pairs[:, 1], pairs[:, 3],
+                          one_way, n_steps)
     out = [None, None]
     out[pairs[0, 0]], out[pairs[0, 2]] = A, B
     return out
@@ -118,7 +120,7 @@ def test_bound_pair_beside_other_rods():
     for (x, _, _, _), o in zip(gpu[:2], ref):
         assert np.abs(x - o.x).max() <= 1e-4
     for (x, _, _, _), (s, st) in zip(gpu[2:], extra):
-        o, _ = O.Rod(s).rollout(st, 500)
+        o, _ = O.Rod(s).rollout(PM.fp32_input(st), 500)
         assert np.abs(x - o.x).max() <= 1e-4 * float(np.sum(s.seg_len))
 
 

@@ -9,6 +9,7 @@ import pytest
 from oracle import oracle as O
 from paper_2509_04277_amd import rod as R
 from paper_2509_04277_amd import workloads as W
+import parity_metrics as PM
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +64,7 @@ def test_crossing_rods_vs_oracle(mu):
     gpu, info = _gpu(rods, [[0, 1]], mu, n_steps)
     _say("buckets %s" % info)
     assert info == [(1, 2, 2, 0.0)]
-    ref, most = O.rollout_group([s for s, _ in rods], [st for _, st in rods], n_steps, mu=mu)
+    ref, most = O.rollout_group([s for s, _ in rods], [PM.fp32_input(st) for _, st in rods], n_steps, mu=mu)
     assert most >= 1
     _compare(gpu, ref, rods, "c6")
     # the falling rod rests on the bar: their middles a contact distance apart, not through
@@ -97,7 +98,7 @@ def test_coiled_rod_self_contact_vs_oracle():
     gpu, info = _gpu([(spec, st)], [[0, -1]], 0.2, 200)
     _say("coiled rod, self contact, 200 steps; buckets %s" % info)
     assert info == [(1, 2, 1, 0.0)]
-    ref, most = O.rollout_group([spec], [st], 200, mu=0.2)
+    ref, most = O.rollout_group([spec], [PM.fp32_input(st)], 200, mu=0.2)
     assert most >= 1
     _compare(gpu, ref, [(spec, st)], "coiled")
     x = gpu[0][0]
@@ -122,7 +123,7 @@ def test_contact_lists_across_launches_and_new_states():
     b.sync()
     outs.append(b.get_state_rods())
     b.close()
-    ref, most = O.rollout_group([s for s, _ in rods], [st for _, st in rods], 2000, mu=0.3)
+    ref, most = O.rollout_group([s for s, _ in rods], [PM.fp32_input(st) for _, st in rods], 2000, mu=0.3)
     _say("crossing rods, 2000 steps at 1 / 7 / 100 per launch and after a reset; contacts %d" % most)
     assert most >= 1
     for o in outs[1:]:
@@ -151,7 +152,7 @@ def test_dense_side_by_side_contact_vs_oracle():
     rods = [(a.replace(dt=dt), sa), (b.replace(dt=dt), sb)]
     n_steps = 400
     gpu, info = _gpu(rods, [[0, 1]], 0.2, n_steps)
-    ref, most = O.rollout_group([s for s, _ in rods], [st for _, st in rods], n_steps, mu=0.2)
+    ref, most = O.rollout_group([s for s, _ in rods], [PM.fp32_input(st) for _, st in rods], n_steps, mu=0.2)
     _say("side by side 2x%d, l = 0.08 r, %d steps: most contacts of a point %d" % (n, n_steps, most))
     assert 1 <= most <= 8
     _compare(gpu, ref, rods, "side by side")
@@ -185,7 +186,7 @@ def test_rods_of_different_lengths_vs_oracle():
     rods = _unequal()
     n_steps = 1500
     gpu, info = _gpu(rods, [[0, 1]], 0.2, n_steps)
-    ref, most = O.rollout_group([s for s, _ in rods], [st for _, st in rods], n_steps, mu=0.2)
+    ref, most = O.rollout_group([s for s, _ in rods], [PM.fp32_input(st) for _, st in rods], n_steps, mu=0.2)
     _say("300 + 60 elements crossing, %d steps: buckets %s, contacts %d" % (n_steps, info, most))
     assert info == [(4, 2, 2, 0.0)]
     assert most >= 1

@@ -9,6 +9,7 @@ import pytest
 from oracle import oracle as O
 from paper_2509_04277_amd import rod as R
 from paper_2509_04277_amd import workloads as W
+import parity_metrics as PM
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +59,7 @@ def test_damped_rod_vs_oracle(inext, n):
     spec, st = _curved(n, inext, 20.0)
     n_steps = 600
     (x, v, q, w), = _gpu([(spec, st)], n_steps)[0]
-    ref, _ = O.Rod(spec).rollout(st, n_steps)
+    ref, _ = O.Rod(spec).rollout(PM.fp32_input(st), n_steps)
     L = float(np.sum(spec.seg_len))
     ex = float(np.abs(x - ref.x).max())
     _say("%s N=%d tau_d %.2e dt %.2e: max|dx| %.2e (tol %.1e)"
@@ -66,7 +67,7 @@ def test_damped_rod_vs_oracle(inext, n):
     assert np.isfinite(x).all()
     assert ex <= 1e-4 * L
     # the friction acted: the undamped rod (same dt) ends elsewhere
-    free, _ = O.Rod(spec.replace(damp_int=0.0)).rollout(st, n_steps)
+    free, _ = O.Rod(spec.replace(damp_int=0.0)).rollout(PM.fp32_input(st), n_steps)
     assert np.abs(free.x - ref.x).max() > 10 * max(ex, 1e-6)
 
 
@@ -82,7 +83,7 @@ def test_damped_and_plain_rods_in_one_handle():
     alone, _ = _gpu([b], 300)
     for u, v in zip(out[1], alone[0]):
         assert np.array_equal(u, v)
-    ref, _ = O.Rod(a[0]).rollout(a[1], 300)
+    ref, _ = O.Rod(a[0]).rollout(PM.fp32_input(a[1]), 300)
     assert np.abs(out[0][0] - ref.x).max() <= 1e-4
 
 

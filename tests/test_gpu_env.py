@@ -12,6 +12,7 @@ import pytest
 from oracle import oracle as O
 from paper_2509_04277_amd import rod as R
 from paper_2509_04277_amd import workloads as W
+import parity_metrics as PM
 
 pytestmark = pytest.mark.gpu
 
@@ -51,12 +52,13 @@ def _gpu(spec, st, n_steps, tris=None, mu=0.0, spl=10, haptic=False):
 
 
 def _fp32_storage_dev(spec, st, n_steps, env):
-    """max |dx| between the oracle's run and the same run with the state rounded to FP32 after
-    every step (FP64 arithmetic otherwise)."""
+    """max |dx| between the oracle's run and the same run with v and w rounded to FP32 after
+    every step (FP64 arithmetic otherwise; the GPU keeps x and q as pairs of floats)."""
+    st = PM.fp32_input(st)
     ref, _ = O.rollout_env(spec, st, n_steps, env)
     r = st.copy()
     for k in range(n_steps):
-        for a in "xvqw":
+        for a in "vw":
             setattr(r, a, getattr(r, a).astype(np.float32).astype(np.float64))
         r, _ = O.rollout_env(spec, r, 1, env, t0=k * spec.dt)
     return float(np.abs(r.x - ref.x).max())
@@ -76,7 +78,7 @@ def test_rod_in_bent_tube_vs_oracle(mu):
     _say("  tree: %d nodes, %d triangles" % info)
     assert info[1] == len(tris) and info[0] >= len(tris) // 2
     env = O.Env(tris, mu)
-    ref, most = O.rollout_env(spec, st, n_steps, env)
+    ref, most = O.rollout_env(spec, PM.fp32_input(st), n_steps, env)
     ex = float(np.abs(x - ref.x).max())
     tol = max(1e-4, 3 * _fp32_storage_dev(spec, st, n_steps, env))
     _say("  max|dx| %.2e (tol %.2e), colliding points (oracle, most) %d" % (ex, tol, most))
@@ -97,7 +99,7 @@ def test_rod_falls_onto_a_floor_vs_oracle(inext):
     n_steps = 1500
     (x, v, q, w), _ = _gpu(spec, st, n_steps, tris, 0.4)
     env = O.Env(tris, 0.4)
-    ref, most = O.rollout_env(spec, st, n_steps, env)
+    ref, most = O.rollout_env(spec, PM.fp32_input(st), n_steps, env)
     ex = float(np.abs(x - ref.x).max())
     tol = max(1e-4 * 0.5, 3 * _fp32_storage_dev(spec, st, n_steps, env))
     _say("floor, %s: max|dx| %.2e (tol %.2e), lowest point %.5f (floor + radius %.5f), colliding %d"

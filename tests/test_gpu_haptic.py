@@ -12,6 +12,7 @@ import pytest
 from oracle import oracle as O
 from paper_2509_04277_amd import rod as R
 from paper_2509_04277_amd import workloads as W
+import parity_metrics as PM
 
 pytestmark = pytest.mark.gpu
 
@@ -111,7 +112,7 @@ def test_force_matches_oracle(inext):
     spec, st = _swinging(64, inext)
     n_steps, win = 300, 50
     gpu, _ = _gpu_forces(spec, st, n_steps)
-    _, ref = O.Rod(spec).rollout_fb(st, n_steps)
+    _, ref = O.Rod(spec).rollout_fb(PM.fp32_input(st), n_steps)
     err = np.abs(gpu - ref).max()
     werr = np.abs(gpu.reshape(-1, win, 3).mean(axis=1) - ref.reshape(-1, win, 3).mean(axis=1)).max()
     if inext:
@@ -144,7 +145,7 @@ def test_windowed_records_vs_oracle():
         assert s == done and p == 0 and m == (n % k or k)
         recs.append((done, m, f))
     b.close()
-    _, ref = O.Rod(spec).rollout_fb(st, done)
+    _, ref = O.Rod(spec).rollout_fb(PM.fp32_input(st), done)
     _, wtol = _fp32_arith_bounds(spec, 1.0, k)
     for end, m, f in recs:
         want = ref[end - m:end].mean(axis=0)
@@ -198,7 +199,7 @@ def test_pose_between_launches_vs_oracle():
     f, s, p = b.haptic_get_force(0)
     b.close()
     assert s == k1 + k2 and p == 2
-    mid, _ = O.Rod(spec).rollout(st, k1)
+    mid, _ = O.Rod(spec).rollout(PM.fp32_input(st), k1)
     ref, _ = O.Rod(spec.replace(clamp_x0=tuple(x1), clamp_q0=tuple(q1))).rollout(mid, k2, t0=k1 * spec.dt)
     ex = np.abs(x - ref.x).max()
     _say("pose change: max|dx| %.2e (tol 1e-4), base %s" % (ex, x[0]))

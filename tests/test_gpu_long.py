@@ -1,8 +1,9 @@
 """GPU parity of the chunked long-rod kernel (one workgroup per chunk of about 500 elements,
-halo exchange through HBM once per step) against the FP64 oracle and against the
-single-workgroup kernel on the same rod.  Tolerance from the method's target: tip (and every
-point) within 1e-4 x rod length after the workload's step count.
+halo exchange through global memory every few steps) against the FP64 oracle and against the
+single-workgroup kernel on the same rod.  Runs are compared as whole states (parity_metrics):
+positions, tip within 1e-4 x rod length, frames, Darboux vectors and window-mean velocities.
 """
+import os
 import sys
 
 import numpy as np
@@ -10,8 +11,10 @@ import pytest
 
 from paper_2509_04277_amd import rod as R
 from paper_2509_04277_amd import workloads as W
+import parity_metrics as PM
 
 pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def _say(msg):
@@ -27,36 +30,41 @@ def _device():
     yield
 
 
-def _run(rods, n_steps, spl, chunk_above=None, chunk=0, splits=None, shape=None):
+def _run(rods, n_steps, spl, chunk_above=None, chunk=0, splits=None, shape=None, window=0):
+    """GPU run; with window = k > 0 also the state k steps before the end (returned as the
+    pair (before, end) in place of the end state)."""
     b = R.RodBatch([s for s, _ in rods])
     if shape is not None:
         b.set_tuning(shape[0], shape[1], spl)
     if chunk_above is not None:
         b.set_chunking(chunk_above, chunk)
     b.set_state_rods([st for _, st in rods])
-    for k in (splits or [n_steps]):
-        b.step(k, spl)
+    if window:
+        b.step(n_steps - window, spl)
+        before = b.get_state_rods()
+        b.step(window, spl)
+    else:
+        for k in (splits or [n_steps]):
+            b.step(k, spl)
     b.sync()
     out = b.get_state_rods()
     info = b.buckets()
     b.close()
-    return out, info
+    return ((before, out) if window else out), info
 
 
-def _vs_oracle(oracle, rods, gpu, n_steps, label):
-    for (s, st), (x, v, q, w) in zip(rods, gpu):
-        o = oracle.Rod(s).rollout(st, n_steps)[0]
-        L = float(np.sum(s.seg_len))
-        tip = float(np.linalg.norm(x[-1] - o.x[-1]))
-        ex = float(np.abs(x - o.x).max())
-        qn = float(np.abs(np.linalg.norm(q.astype(np.float64), axis=1) - 1).max())
-        _say("%s N=%d %s: tip=%.2e max|dx|=%.2e (tol %.1e) max|dv|=%.2e (|v|max %.2e) |q|-1=%.1e"
-             % (label, s.n, "inext" if s.inextensible else "ext", tip, ex, 1e-4 * L,
-                np.abs(v - o.v).max(), np.abs(o.v).max(), qn))
-        assert np.isfinite(x).all() and np.isfinite(q).all() and np.isfinite(v).all()
-        assert tip <= 1e-4 * L
-        assert ex <= 1e-4 * L
-        assert qn <= 1e-6
+def _vs_oracle(oracle, rods, gpu, n_steps, k, label, tol=None):
+    """Whole-state comparison (parity_metrics) of a windowed GPU run with the oracle."""
+    errs = []
+    for r, (s, st) in enumerate(rods):
+        a = oracle.Rod(s).rollout(PM.fp32_input(st), n_steps - k)[0]
+        c = oracle.Rod(s).rollout(a, k, t0=(n_steps - k) * s.dt)[0]
+        assert all(np.isfinite(v).all() for v in gpu[1][r])
+        e = PM.errors(s, st.x, gpu[0][r], gpu[1][r], (a.x, a.v, a.q, a.w), (c.x, c.v, c.q, c.w), k)
+        _say("%s N=%d %s: %s" % (label, s.n, "inext" if s.inextensible else "ext", PM.fmt(e)))
+        errs.append(e)
+    bad = PM.violations(PM.worst(errs), tol)
+    assert not bad, "%s: above the bars: %s" % (label, bad)
 
 
 @pytest.mark.parametrize("case", ["c2-500-inext", "c2-500-ext", "c1-2x512-driven"])
@@ -91,7 +99,7 @@ def test_chunked_matches_wider_single_workgroup(oracle, inext, chunk):
     L = float(np.sum(wl.rods[0][0].seg_len))
     n_steps = 300
     one, info1 = _run(wl.rods, n_steps, 10)
-    many, info2 = _run(wl.rods, n_steps, 10, chunk_above=1024, chunk=chunk)
+    (many_a, many), info2 = _run(wl.rods, n_steps, 10, chunk_above=1024, chunk=chunk, window=10)
     _say("1x2000 %s, %d steps, chunk %d; buckets single %s, chunked %s"
          % ("inext" if inext else "ext", n_steps, chunk, info1, info2))
     assert info2 == [(4, 2, 1, 0.0)]
@@ -101,7 +109,7 @@ def test_chunked_matches_wider_single_workgroup(oracle, inext, chunk):
         dx, L, dq, np.abs(v1 - v2).max(), np.abs(w1 - w2).max()))
     for u, v in zip(one[0], many[0]):
         assert np.array_equal(u, v)
-    _vs_oracle(oracle, wl.rods, many, n_steps, "chunked-2000")
+    _vs_oracle(oracle, wl.rods, (many_a, many), n_steps, 10, "chunked-2000", PM.BARS["c2"])
 
 
 def test_every_kernel_shape_is_bitwise():
@@ -123,17 +131,38 @@ def test_c2_4096_full_run(oracle, inext):
     wl = W.config2(4096, inext)
     _say("c2 full: 1x4096 %s, %d steps at %d per launch"
          % ("inext" if inext else "ext", wl.n_steps, wl.steps_per_launch))
-    gpu, info = _run(wl.rods, wl.n_steps, wl.steps_per_launch)
+    gpu, info = _run(wl.rods, wl.n_steps, wl.steps_per_launch, window=10)
     assert info == [(4, 2, 1, 0.0)]
-    _vs_oracle(oracle, wl.rods, gpu, wl.n_steps, "c2-4096")
+    _vs_oracle(oracle, wl.rods, gpu, wl.n_steps, 10, "c2-4096", PM.BARS["c2"])
 
 
-def test_c2_65536_short_run(oracle):
-    """Largest rod of the long-rod workload (142 chunks), 200 steps at 100 per launch."""
-    wl = W.config2(65536, True)
-    _say("c2 largest: 1x65536 inext, 200 steps at 100 per launch")
-    gpu, _ = _run(wl.rods, 200, 100)
-    _vs_oracle(oracle, wl.rods, gpu, 200, "c2-65536")
+@pytest.mark.parametrize("n", [16384, 65536])
+@pytest.mark.parametrize("inext", [True, False])
+def test_c2_full_run_against_stored_oracle(n, inext):
+    """The long-rod workload at 16384 and 65536 elements over its 5000 steps (chunked, 100 steps
+    per launch) against the stored FP64 oracle (tests/golden/make_c2_golden.py): 32 pieces of
+    8 consecutive elements along the rod, the last at the tip, compared as whole states."""
+    g = np.load(os.path.join(HERE, "golden", "c2_oracle_%d_%s.npz" % (n, "inext" if inext else "ext")))
+    wl = W.config2(n, inext)
+    spec, st = wl.rods[0]
+    k = int(g["window"])
+    assert int(g["n_steps"]) == wl.n_steps and float(g["dt"]) == spec.dt and int(g["n"]) == n
+    _say("c2 full: 1x%d %s, %d steps at 100 per launch" % (n, "inext" if inext else "ext", wl.n_steps))
+    (before, end), _ = _run(wl.rods, wl.n_steps, 100, window=k)
+    L = float(np.sum(spec.seg_len))
+    errs = []
+    for i, p0 in enumerate(g["starts"]):
+        pt, fr = slice(p0, p0 + 9), slice(p0, p0 + 8)
+        got = [(x[pt], v[pt], q[fr], w[fr]) for x, v, q, w in (before[0], end[0])]
+        ref = [(g["xa"][i], None, g["qa"][i], None), (g["xb"][i], None, g["qb"][i], None)]
+        errs.append(PM.errors(spec, st.x[pt], got[0], got[1], ref[0], ref[1], k,
+                              seg_len=spec.seg_len[fr], disp=float(g["disp"]), length=L))
+    tip = float(np.linalg.norm(end[0][0][-1] - g["xb"][-1][-1])) / L
+    w = PM.worst(errs)
+    w["tip"] = tip
+    _say("c2-%d %s (32 pieces): %s" % (n, "inext" if inext else "ext", PM.fmt(w)))
+    bad = PM.violations(w, PM.BARS["c2"])
+    assert not bad, bad
 
 
 def test_longest_accepted_rod_short_run(oracle):
@@ -141,9 +170,9 @@ def test_longest_accepted_rod_short_run(oracle):
     at 25 per launch, every point against the oracle."""
     wl = W.config2(1 << 17, True)
     _say("longest rod: 1x131072 inext, 50 steps at 25 per launch")
-    gpu, info = _run(wl.rods, 50, 25)
+    gpu, info = _run(wl.rods, 50, 25, window=25)
     assert info == [(4, 2, 1, 0.0)]
-    _vs_oracle(oracle, wl.rods, gpu, 50, "c2-131072")
+    _vs_oracle(oracle, wl.rods, gpu, 50, 25, "c2-131072", PM.BARS["c2"])
 
 
 def test_autotune_chunks_a_lone_long_rod(oracle):
@@ -162,11 +191,13 @@ def test_autotune_chunks_a_lone_long_rod(oracle):
     assert b.time()[1] == 0
     for u, v in zip(before, b.get_state()):
         assert np.array_equal(u, v)
-    b.step(300)
+    b.step(290)
+    gpu_a = b.get_state_rods()
+    b.step(10)
     b.sync()
     gpu = b.get_state_rods()
     b.close()
-    _vs_oracle(oracle, wl.rods, gpu, 300, "autotuned-2048")
+    _vs_oracle(oracle, wl.rods, (gpu_a, gpu), 300, 10, "autotuned-2048", PM.BARS["c2"])
 
 
 def test_launch_split_and_restart_are_bitwise():
@@ -218,10 +249,10 @@ def test_mixed_handle_long_and_short(oracle):
     """One handle holding resident rods and a chunked rod: one rod_step advances all."""
     rods = W.config0().rods + W.config2(3000, True).rods + W.config2(700, False).rods
     _say("mixed handle: N=64 ext, N=3000 inext (chunked), N=700 ext; 500 steps")
-    gpu, info = _run(rods, 500, 10)
+    gpu, info = _run(rods, 500, 10, window=10)
     _say("buckets %s" % info)
     assert info[-1][:3] == (4, 2, 1)
-    _vs_oracle(oracle, rods, gpu, 500, "mixed")
+    _vs_oracle(oracle, rods, gpu, 500, 10, "mixed", PM.BARS["c2"])
 
 
 def test_set_chunking_arguments():

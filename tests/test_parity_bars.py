@@ -12,6 +12,7 @@ configuration covers that coefficient.  Every step of the method is covered some
   velocity integration (the time step)                                  Sec. 2.1
 """
 import dataclasses
+import math
 
 import numpy as np
 import pytest
@@ -53,12 +54,16 @@ def _configs(oracle):
         "c0-swing": (W.config0(dt=1e-4).rods, 3000, 50, "c0-swing",
                      ("gravity", "damp_lin", "K_s", "K_p", "bend", "twist", "mass", "dt")),
         "c1-2000": (W.config1().rods, 2000, 10, "c1", ("twist", "mass", "n_iter", "dt", "drive")),
+        "c1-full": (W.config1().rods, 20000, 10, "c1-full",
+                    ("bend", "twist", "mass", "n_iter", "dt", "drive")),
         "edge": (parity_cases.edge_rods(oracle), 400, 37, "edge", ALL),
+        "c2-4096": (W.config2(4096, True).rods + W.config2(4096, False).rods, 5000, 10, "c2", ()),
     }
 
 
 def _window(oracle, rods, n, k):
-    a = [oracle.Rod(s).rollout(st, n - k)[0] for s, st in rods]
+    """States k steps before the end and at the end (the rods on the oracle's threads)."""
+    a = oracle.rollout_many_threads(rods, n - k)
     b = [oracle.Rod(s).rollout(sa, k, t0=(n - k) * s.dt)[0] for (s, _), sa in zip(rods, a)]
     return a, b
 
@@ -86,22 +91,60 @@ def test_every_step_is_covered(oracle):
     assert covered == set(CHANGES)
 
 
-@pytest.mark.parametrize("name", ["c0", "c0-swing", "c1-2000", "edge"])
+NAMES = ["c0", "c0-swing", "c1-2000", "c1-full", "edge"]
+
+
+@pytest.mark.parametrize("name", NAMES)
 def test_bars_fail_on_changed_coefficients(oracle, name):
     rods, n, k, bars, must = _configs(oracle)[name]
+    rods = PM.fp32_rods(rods)
     a, b = _window(oracle, rods, n, k)
     same = _worst(rods, a, b, a, b, k)
     same.pop("unit")
     assert all(v == 0.0 for v in same.values())
-    missed = []
+    changed = []
     for coef in must:
         prods = [(CHANGES[coef](s), st) for s, st in rods]
         assert any(_differs(ps, s) for (ps, _), (s, _) in zip(prods, rods)), coef
-        pa, pb = _window(oracle, prods, n, k)
-        w = _worst(rods, pa, pb, a, b, k)
+        changed += prods
+    pa = oracle.rollout_many_threads(changed, n - k)
+    missed = []
+    for i, coef in enumerate(must):
+        sl = slice(i * len(rods), (i + 1) * len(rods))
+        pb = [oracle.Rod(s).rollout(x, k, t0=(n - k) * s.dt)[0] for (s, _), x in zip(changed[sl], pa[sl])]
+        w = _worst(rods, pa[sl], pb, a, b, k)
         w.pop("unit")   # an FP64 oracle keeps unit quaternions whatever its coefficients
         bad = PM.violations(w, PM.BARS[bars])
         print("%s, %s x1.1: %s -> above the bars: %s" % (name, coef, PM.fmt(w), sorted(bad)))
         if not bad:
             missed.append(coef)
     assert not missed, "%s: a 10 %% change of %s passes every bar" % (name, missed)
+
+
+def _up2(v):
+    """v rounded up to two significant digits."""
+    e = math.floor(math.log10(v))
+    return math.ceil(v / 10 ** (e - 1) - 1e-9) * 10 ** (e - 1)
+
+
+@pytest.mark.parametrize("name", NAMES + ["c2-4096"])
+def test_bars_follow_the_fp32_floor(oracle, name):
+    """Each bar is max(base bar, FLOOR_FACTOR x the configuration's FP32 floor), the floor
+    being the oracle against itself with v, q and w rounded to FP32 after every step."""
+    rods, n, k, bars, _ = _configs(oracle)[name]
+    rods = PM.fp32_rods(rods)
+    a, b = _window(oracle, rods, n, k)
+    fl = []
+    for (s, st), sa, sb in zip(rods, a, b):
+        r = oracle.Rod(s)
+        ra = r.rollout_rounded(st, n - k, 14)
+        rb = r.rollout_rounded(ra, k, 14, t0=(n - k) * s.dt)
+        fl.append(PM.errors(s, st.x, _t(ra), _t(rb), _t(sa), _t(sb), k))
+    floor = PM.worst(fl)
+    floor.pop("unit")
+    print("%s: FP32 floor %s" % (name, PM.fmt(floor)))
+    for m, f in floor.items():
+        want = max(PM.TOL[m], _up2(PM.FLOOR_FACTOR * f)) if f > 0 else PM.TOL[m]
+        got = PM.BARS[bars][m]
+        # the floors move in their last digits between machines: allow 20 % either way
+        assert 0.8 * want <= got <= 1.2 * want, (name, m, got, want)
