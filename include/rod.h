@@ -312,6 +312,26 @@ rod_status rod_autotune(rod_ctx* ctx, int32_t probe_steps, int32_t steps_per_lau
  * extensible variant, penalty shear, penalty rotation, bending, twisting) of 2 / omega. */
 rod_status rod_stable_dt(const rod_params* p, double* dt_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): rod_step on caller-owned state instead of the
+ * handle's.  x, v, q, w are device arrays on the handle's device in the handle's layout (as for
+ * rod_set_state with on_device = 1), read and written in place; the handle's own state, step
+ * counter and tuning are left as they are.  Steps are numbered from first_step (a driven
+ * clamp is evaluated at t0 + (first_step + s + 1) dt, t0 from the last rod_set_state, else 0).
+ * Positions and quaternions are compensated within the call only (their low parts start at 0
+ * and are dropped at its end), so a run split over several calls rounds them to FP32 at each
+ * call's end; one call gives bitwise the state of rod_set_state + rod_step from the same state
+ * and time.  steps_per_launch = 0 uses the handle's.  The call allocates nothing and creates no
+ * stream: its one scratch buffer (those low parts, 3 floats per point and 4 per frame) is a
+ * fixed array in device memory that each GPU holds from the first rod_create on it until the
+ * process ends (56 MiB); every bucket steps on the handle's stream.  Calls on one GPU share that array, so
+ * calls that overlap on one GPU (other streams, other threads) race: order them.  Stream-
+ * ordered like rod_step; a non-finite state is reported by rod_sync.  Errors: INVALID (null
+ * pointer, negative count, more than 2^21 points), UNSUPPORTED (handles with chunked rods,
+ * bindings, contact, a haptic mailbox or an environment), DEVICE. */
+rod_status rod_step_state_noalloc(rod_ctx* ctx, float* x, float* v, float* q, float* w,
+                                  int64_t first_step, int32_t n_steps, int32_t steps_per_launch);
+
 /* Device time of the last rod_step() call measured with HIP events on the handle's stream
  * [ms], and the number of kernel launches it made. */
 rod_status rod_last_step_time(rod_ctx* ctx, float* ms, int32_t* launches);

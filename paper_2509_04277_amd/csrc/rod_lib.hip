@@ -688,7 +688,50 @@ rod_status reset_flags(rod_ctx* c) {
   return ROD_OK;
 }
 
-// State arrays of a launch: the handle's own.
+// ---- scratch of rod_step_state_noalloc -----------------------------------------------------
+// The low parts of the positions and quaternions of one call (3 floats per point, 4 per frame;
+// a handle has fewer frames than points).  Every GPU the library runs
+// on holds its own copy of this array until the process ends.  In host code its name is not a
+// device address: the address of each GPU's copy is looked up once per device, with that
+// device current (scratch_address), and only that address is passed to kernels.
+constexpr long long kNoAllocMaxPoints = 1LL << 21;   // 56 MiB
+static __device__ __align__(256) float scratch[7 * kNoAllocMaxPoints];
+
+struct ScratchTable {
+  std::mutex m;
+  float* ptr[kMaxDevices] = {};
+};
+ScratchTable& scratch_table() {
+  static ScratchTable* t = new ScratchTable;   // never destroyed, like the device copies
+  return *t;
+}
+
+// Device address of device dev's copy of the scratch array (dev must be current).
+rod_status scratch_address(rod_ctx* c, int dev, float** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, ROD_E_DEVICE, "device index out of range");
+  ScratchTable& t = scratch_table();
+  std::lock_guard<std::mutex> lock(t.m);
+  if (!t.ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, ROD_E_DEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") +
+                                       hipGetErrorString(e));
+    t.ptr[dev] = static_cast<float*>(p);
+  }
+  *out = t.ptr[dev];
+  return ROD_OK;
+}
+
+// Clears n floats with a kernel (a fill that also works where a caller captures the stream).
+__global__ void zero_floats(float* __restrict__ p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+
+// State arrays of a launch: the handle's own, or (rod_step_state_noalloc) the caller's with
+// the low parts in the device's scratch array.
 StateArrays handle_state(rod_ctx* c) { return {c->d_x, c->d_v, c->d_q, c->d_w, c->d_xl, c->d_ql}; }
 
 rod_status launch_bucket(rod_ctx* c, const rod_ctx::Bucket& b, int ks, long long done,
@@ -1142,6 +1185,11 @@ rod_status rod_create(const rod_params* params, int32_t n_rods, void* hip_stream
     st = make_buckets(c, [&](int r, int* w, int* e) { default_shape(c->n[r], w, e); });
     if (st != ROD_OK) return cleanup(st);
   }
+  {
+    // set-up of rod_step_state_noalloc on this device (a failure is reported by that call)
+    float* sp = nullptr;
+    if (scratch_address(c, c->device, &sp) != ROD_OK) c->err.clear();
+  }
   *out = c;
   return ROD_OK;
 }
@@ -1249,6 +1297,45 @@ rod_status rod_set_clamp(rod_ctx* c, int32_t rod, const double* x0, const double
   for (int k = 0; k < 4; ++k) d.cq0[k] = (float)q0[k];
   HIP_TRY(c, hipMemcpyAsync(c->d_rods + rod, &d, sizeof(RodDev), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return ROD_OK;
+}
+
+rod_status rod_step_state_noalloc(rod_ctx* c, float* x, float* v, float* q, float* w,
+                                  int64_t first_step, int32_t n_steps, int32_t steps_per_launch) {
+  if (!c) return fail(nullptr, ROD_E_INVALID, "null handle");
+  if (!x || !v || !q || !w) return fail(c, ROD_E_INVALID, "null state pointer");
+  if (n_steps < 0 || steps_per_launch < 0 || first_step < 0)
+    return fail(c, ROD_E_INVALID, "n_steps, steps_per_launch and first_step must be >= 0");
+  if (c->n_chunks || !c->pair_buckets.empty() || c->n_haptic || c->env_nodes)
+    return fail(c, ROD_E_UNSUPPORTED, "rod_step_state_noalloc steps handles without chunked rods, "
+                                      "bindings, contact, haptic mailboxes or an environment");
+  if ((long long)c->total_pts > kNoAllocMaxPoints)
+    return fail(c, ROD_E_INVALID, "rod_step_state_noalloc holds at most " +
+                                      std::to_string(kNoAllocMaxPoints) + " points; the handle has " +
+                                      std::to_string(c->total_pts));
+  int dev = -1;
+  HIP_TRY(c, hipGetDevice(&dev));
+  if (dev != c->device)
+    return fail(c, ROD_E_DEVICE, "the handle's device (" + std::to_string(c->device) +
+                ") is not the current device (" + std::to_string(dev) + ")");
+  if (n_steps == 0) return ROD_OK;
+  float* lo = nullptr;
+  {
+    rod_status st = scratch_address(c, dev, &lo);
+    if (st != ROD_OK) return st;
+  }
+  const long long nl = 3LL * c->total_pts + 4LL * c->total_frames;
+  hipLaunchKernelGGL(zero_floats, dim3((unsigned)std::min<long long>((nl + 255) / 256, 1024)),
+                     dim3(256), 0, c->stream, lo, nl);
+  HIP_TRY(c, hipGetLastError());
+  const int spl = steps_per_launch > 0 ? steps_per_launch : c->steps_per_launch;
+  const StateArrays sp = {x, v, q, w, lo, lo + 3LL * c->total_pts};
+  for (const auto& b : c->buckets)   // all on the handle's stream: no stream is created
+    for (int done = 0; done < n_steps; done += spl) {
+      const int ks = std::min(spl, n_steps - done);
+      rod_status rs = launch_bucket(c, b, ks, (long long)first_step + done, c->stream, sp);
+      if (rs != ROD_OK) return rs;
+    }
   return ROD_OK;
 }
 

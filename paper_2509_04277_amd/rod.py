@@ -85,6 +85,8 @@ _SIGS = {
     "rod_stable_dt": (C.c_int, [C.POINTER(rod_params), _DP]),
     "rod_last_step_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_int32)]),
     "rod_set_stiffness_mult": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "rod_step_state_noalloc": (C.c_int, [C.c_void_p, _FP, _FP, _FP, _FP, C.c_int64, C.c_int32,
+                                        C.c_int32]),
     "rod_adjoint_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _FP, C.c_int32,
                                      C.POINTER(C.c_int64)]),
     "rod_adjoint_backward": (C.c_int, [C.c_void_p, C.c_int64, _FP, _FP, _FP, _FP, _FP, _FP, _FP,
@@ -281,6 +283,17 @@ class RodBatch:
     def set_clamp(self, rod: int, x0, q0):
         a, b = _f64(x0, 3), _f64(q0, 4)
         _check(lib().rod_set_clamp(self.h, int(rod), a.ctypes.data_as(_DP), b.ctypes.data_as(_DP)),
+               self.h)
+
+    def step_state_noalloc(self, x, v, q, w, first_step: int, n_steps: int,
+                           steps_per_launch: int = 0):
+        """rod_step_state_noalloc: steps caller-owned device state (float32 tensors in the
+        handle's layout) in place, allocating nothing."""
+        ptrs = [_ptr(a) for a in (x, v, q, w)]
+        if any(not d for _, d in ptrs):
+            raise ValueError("device arrays expected")
+        _check(lib().rod_step_state_noalloc(self.h, *[C.c_void_p(p) for p, _ in ptrs],
+                                            int(first_step), int(n_steps), int(steps_per_launch)),
                self.h)
 
     # ---- adjoint --------------------------------------------------------------------
