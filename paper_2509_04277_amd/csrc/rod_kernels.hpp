@@ -269,23 +269,22 @@ __device__ __forceinline__ void add_pair(float& hi, float& lo, float d) {
 }
 
 // q <- normalize(q + dt/2 q (x) (0, omega)) on a quaternion held as the pair (h, l) (the
-// rotation increment per step is far below the ulp of a unit quaternion's components): the
-// increment, from the high part, is added to the pair; the normalisation then enters as the
-// correction (1/|q| - 1) q, added the same way.  That correction only changes the norm, where
-// the FP32 rounding of the factor does not touch the rotation.
+// rotation increment per step is far below the ulp of a unit quaternion's components).  The
+// increment d, from the high part, is orthogonal to it (a rotation), so |h + d|^2 = |h|^2 +
+// |d|^2 and the normalised result is (h + d)(1 + eps) with eps = 1/|h + d| - 1: the increment
+// and the normalisation enter as one correction d + eps (h + d), added to the pair with
+// Fast2Sum per component.  The FP32 rounding of eps only changes the norm, not the rotation.
 __device__ __forceinline__ void advance_quat(Q4& h, Q4& l, V3 o, float dt) {
   const float hdt = 0.5f * dt;
   const Q4 d = {hdt * (-h.x * o.x - h.y * o.y - h.z * o.z), hdt * (h.w * o.x + h.y * o.z - h.z * o.y),
                 hdt * (h.w * o.y - h.x * o.z + h.z * o.x), hdt * (h.w * o.z + h.x * o.y - h.y * o.x)};
-  add_pair(h.w, l.w, d.w);
-  add_pair(h.x, l.x, d.x);
-  add_pair(h.y, l.y, d.y);
-  add_pair(h.z, l.z, d.z);
-  const float eps = rsqrtf(h.w * h.w + h.x * h.x + h.y * h.y + h.z * h.z) - 1.f;
-  add_pair(h.w, l.w, eps * h.w);
-  add_pair(h.x, l.x, eps * h.x);
-  add_pair(h.y, l.y, eps * h.y);
-  add_pair(h.z, l.z, eps * h.z);
+  const float n2 = (h.w * h.w + h.x * h.x + h.y * h.y + h.z * h.z) +
+                   (d.w * d.w + d.x * d.x + d.y * d.y + d.z * d.z);
+  const float eps = rsqrtf(n2) - 1.f;
+  add_pair(h.w, l.w, __builtin_fmaf(eps, h.w, __builtin_fmaf(eps, d.w, d.w)));
+  add_pair(h.x, l.x, __builtin_fmaf(eps, h.x, __builtin_fmaf(eps, d.x, d.x)));
+  add_pair(h.y, l.y, __builtin_fmaf(eps, h.y, __builtin_fmaf(eps, d.y, d.y)));
+  add_pair(h.z, l.z, __builtin_fmaf(eps, h.z, __builtin_fmaf(eps, d.z, d.z)));
 }
 
 __device__ __forceinline__ Q4 qmul(Q4 a, Q4 b) {
