@@ -756,6 +756,34 @@ void oracle_step_group(const oracle_rod* const* rods, int32_t n_rods, const orac
     }
 }
 
+/* Rounds n values to the nearest FP32 number (kept as doubles). */
+static void round_fp32(double* a, int n) {
+    for (int i = 0; i < n; ++i) a[i] = (double)(float)a[i];
+}
+
+/* The fields of one rod's state named by the bits of mask (1 x, 2 v, 4 q, 8 w), rounded. */
+static void round_state(int n, double* x, double* v, double* q, double* w, int32_t mask) {
+    if (mask & 1) round_fp32(x, 3 * (n + 1));
+    if (mask & 2) round_fp32(v, 3 * (n + 1));
+    if (mask & 4) round_fp32(q, 4 * n);
+    if (mask & 8) round_fp32(w, 3 * n);
+}
+
+void oracle_rollout_group_rounded(const oracle_rod* const* rods, int32_t n_rods,
+                                  const oracle_binding* bind, const oracle_contact* contact,
+                                  double t0, int32_t n_steps, double* const* x,
+                                  double* const* v, double* const* q, double* const* w,
+                                  int32_t mask, int32_t* max_contacts) {
+    int32_t most = 0;
+    for (int s = 0; s < n_steps; ++s) {
+        int32_t m = 0;
+        oracle_step_group(rods, n_rods, bind, contact, t0 + s * rods[0]->dt, x, v, q, w, &m);
+        if (m > most) most = m;
+        for (int r = 0; r < n_rods; ++r) round_state(rods[r]->n, x[r], v[r], q[r], w[r], mask);
+    }
+    if (max_contacts) *max_contacts = most;
+}
+
 void oracle_rollout_group(const oracle_rod* const* rods, int32_t n_rods,
                           const oracle_binding* bind, const oracle_contact* contact, double t0,
                           int32_t n_steps, double* const* x, double* const* v, double* const* q,
@@ -948,20 +976,12 @@ void oracle_rollout(const oracle_rod* rod, double t0, int32_t n_steps, double* x
     }
 }
 
-/* Rounds n values to the nearest FP32 number (kept as doubles). */
-static void round_fp32(double* a, int n) {
-    for (int i = 0; i < n; ++i) a[i] = (double)(float)a[i];
-}
 
 void oracle_rollout_rounded(const oracle_rod* rod, double t0, int32_t n_steps, double* x,
                             double* v, double* q, double* w, int32_t mask) {
-    const int n = rod->n;
     for (int s = 0; s < n_steps; ++s) {
         oracle_step(rod, t0 + s * rod->dt, x, v, q, w);
-        if (mask & 1) round_fp32(x, 3 * (n + 1));
-        if (mask & 2) round_fp32(v, 3 * (n + 1));
-        if (mask & 4) round_fp32(q, 4 * n);
-        if (mask & 8) round_fp32(w, 3 * n);
+        round_state(rod->n, x, v, q, w, mask);
     }
 }
 

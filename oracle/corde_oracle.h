@@ -208,6 +208,14 @@ void oracle_step_group(const oracle_rod* const* rods, int32_t n_rods, const orac
                        const oracle_contact* contact, double t, double* const* x, double* const* v,
                        double* const* q, double* const* w, int32_t* max_contacts);
 
+/* oracle_rollout_group with every rod's state fields named by mask (as for
+ * oracle_rollout_rounded) rounded to FP32 after every step. */
+void oracle_rollout_group_rounded(const oracle_rod* const* rods, int32_t n_rods,
+                                  const oracle_binding* bind, const oracle_contact* contact,
+                                  double t0, int32_t n_steps, double* const* x,
+                                  double* const* v, double* const* q, double* const* w,
+                                  int32_t mask, int32_t* max_contacts);
+
 /* n_steps of oracle_step_group from time t0; max_contacts over all steps. */
 void oracle_rollout_group(const oracle_rod* const* rods, int32_t n_rods,
                           const oracle_binding* bind, const oracle_contact* contact, double t0,

@@ -117,6 +117,10 @@ def lib():
         L.oracle_rollout_group.argtypes = [C.POINTER(C.POINTER(_Rod)), C.c_int32,
                                            C.POINTER(_Binding), C.POINTER(_Contact), C.c_double,
                                            C.c_int32] + [C.POINTER(_DP)] * 4 + [C.POINTER(C.c_int32)]
+        L.oracle_rollout_group_rounded.restype = None
+        L.oracle_rollout_group_rounded.argtypes = [
+            C.POINTER(C.POINTER(_Rod)), C.c_int32, C.POINTER(_Binding), C.POINTER(_Contact),
+            C.c_double, C.c_int32] + [C.POINTER(_DP)] * 4 + [C.c_int32, C.POINTER(C.c_int32)]
         L.oracle_self_skip.restype = C.c_int32
         L.oracle_self_skip.argtypes = [C.POINTER(_Rod)]
         L.oracle_rollout_pair.restype = None
@@ -463,10 +467,12 @@ def self_skip(spec):
     return int(lib().oracle_self_skip(C.byref(Rod(spec).c)))
 
 
-def rollout_group(specs, states, n_steps, mu=None, pairs=None, one_way=False, t0=0.0):
+def rollout_group(specs, states, n_steps, mu=None, pairs=None, one_way=False, t0=0.0,
+                  round_mask=0):
     """One or two rods stepped together: optional bindings (pairs: (k, 2) point indices of
     rod 0 and rod 1, rod 1 the master if one_way) and optional contact with friction
-    coefficient mu.  Returns (new states, largest number of contacts of one point)."""
+    coefficient mu.  round_mask (1 x, 2 v, 4 q, 8 w): those fields rounded to FP32 after every
+    step.  Returns (new states, largest number of contacts of one point)."""
     rods = [Rod(s) for s in specs]
     outs, keep = [], []
     for r, st in zip(rods, states):
@@ -485,9 +491,15 @@ def rollout_group(specs, states, n_steps, mu=None, pairs=None, one_way=False, t0
                       ib.ctypes.data_as(C.POINTER(C.c_int32)), int(bool(one_way)))
     ct = _Contact(float(mu)) if mu is not None else None
     most = C.c_int32(0)
-    lib().oracle_rollout_group(rp, len(rods), C.byref(bd) if bd is not None else None,
-                               C.byref(ct) if ct is not None else None, float(t0), int(n_steps),
-                               arr("x"), arr("v"), arr("q"), arr("w"), C.byref(most))
+    bp = C.byref(bd) if bd is not None else None
+    cp = C.byref(ct) if ct is not None else None
+    if round_mask:
+        lib().oracle_rollout_group_rounded(rp, len(rods), bp, cp, float(t0), int(n_steps),
+                                           arr("x"), arr("v"), arr("q"), arr("w"),
+                                           int(round_mask), C.byref(most))
+    else:
+        lib().oracle_rollout_group(rp, len(rods), bp, cp, float(t0), int(n_steps), arr("x"),
+                                   arr("v"), arr("q"), arr("w"), C.byref(most))
     return outs, int(most.value)
 
 

@@ -260,6 +260,12 @@ __device__ __forceinline__ void advance_position(V3& hi, V3& lo, V3 v, float dt)
   add_compensated(hi.z, lo.z, v.z, dt);
 }
 
+// Rounding error of s = fl(a + b) (Knuth's TwoSum): a + b = s + two_sum_err(a, b, s) exactly.
+__device__ __forceinline__ float two_sum_err(float a, float b, float s) {
+  const float bb = s - a;
+  return (a - (s - bb)) + (b - bb);
+}
+
 // hi + lo <- hi + lo + d with the Fast2Sum of hi and lo + d.
 __device__ __forceinline__ void add_pair(float& hi, float& lo, float d) {
   const float y = lo + d;
@@ -320,32 +326,35 @@ __device__ __forceinline__ void clamp_pose(const RodDev& rd, double t, V3& xc, Q
 }
 
 
-// Nearest point of triangle t to p, by the Voronoi region of p (vertex, edge or face) found
-// from the signs of dot products with the edges (Ericson, Real-Time Collision Detection, 5.1.5).
-__device__ __forceinline__ V3 tri_closest(const EnvTri& t, V3 p) {
-  const V3 a = {t.a[0], t.a[1], t.a[2]};
+// Nearest point of triangle t to the point a + ap (a its first vertex), as its offset from
+// a, by the Voronoi region of the point (vertex, edge or face) found from the signs of dot
+// products with the edges (Ericson, Real-Time Collision Detection, 5.1.5).  Working from a
+// keeps every quantity at the scale of the triangle and the sphere, not of the coordinates.
+// face: set when the nearest point lies inside the face (the point projects onto it).
+__device__ __forceinline__ V3 tri_closest(const EnvTri& t, V3 ap, bool& face) {
+  face = false;
   const V3 ab = {t.e1[0], t.e1[1], t.e1[2]};
   const V3 ac = {t.e2[0], t.e2[1], t.e2[2]};
-  const V3 ap = p - a;
   const float d1 = dot(ab, ap), d2 = dot(ac, ap);
-  if (d1 <= 0.f && d2 <= 0.f) return a;
+  if (d1 <= 0.f && d2 <= 0.f) return {0.f, 0.f, 0.f};
   const V3 bp = ap - ab;
   const float d3 = dot(ab, bp), d4 = dot(ac, bp);
-  if (d3 >= 0.f && d4 <= d3) return a + ab;
+  if (d3 >= 0.f && d4 <= d3) return ab;
   const float vc = d1 * d4 - d3 * d2;
-  if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) return fma3(d1 / (d1 - d3), ab, a);
+  if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) return (d1 / (d1 - d3)) * ab;
   const V3 cp = ap - ac;
   const float d5 = dot(ab, cp), d6 = dot(ac, cp);
-  if (d6 >= 0.f && d5 <= d6) return a + ac;
+  if (d6 >= 0.f && d5 <= d6) return ac;
   const float vb = d5 * d2 - d1 * d6;
-  if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) return fma3(d2 / (d2 - d6), ac, a);
+  if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) return (d2 / (d2 - d6)) * ac;
   const float va = d3 * d6 - d5 * d4;
   if (va <= 0.f && d4 - d3 >= 0.f && d5 - d6 >= 0.f) {
     const float u = (d4 - d3) / ((d4 - d3) + (d5 - d6));
-    return fma3(u, ac - ab, a + ab);
+    return fma3(u, ac - ab, ab);
   }
+  face = true;
   const float den = 1.0f / (va + vb + vc);
-  return fma3(vc * den, ac, fma3(vb * den, ab, a));
+  return fma3(vc * den, ac, (vb * den) * ab);
 }
 
 // Walks the environment's tree for a sphere of centre c and radius reach, calling leaf(k) for
@@ -368,18 +377,45 @@ __device__ __forceinline__ void env_walk(const RodDev& rd, V3 c, float reach, Le
   }
 }
 
-// Narrow phase of one triangle against a sphere (centre c, radius r): a triangle collides when
-// its nearest point is closer than r; its depth is r - dist with the centre in front of the
-// face, r + dist behind it; acc gathers depth x face normal, dmax the largest depth.  Returns
-// the distance.
-__device__ __forceinline__ float env_hit(const EnvTri& t, V3 c, float r, V3& acc, float& dmax) {
-  const V3 q = tri_closest(t, c);
-  const V3 d = c - q;
-  const float dist = sqrtf(dot(d, d));
+// Narrow phase of one triangle against a sphere (centre c + cl, a compensated position;
+// radius r): a triangle collides when its nearest point is closer than r; its depth is r - dist
+// with the centre in front of the face, r + dist behind it; acc gathers depth x face normal,
+// dmax the largest depth.  Returns the distance.  Where the nearest point is inside the face,
+// the signed distance is the centre's height over the face's plane, dot(c + cl - a, n), taken
+// in double-float arithmetic (the error-free difference c - a, products by fma), and the
+// depth is r minus that height on either side: resting contact keeps the height within a
+// step's sinking of r, far below the ulp of the coordinates.
+__device__ __forceinline__ float env_hit(const EnvTri& t, V3 c, V3 cl, float r, V3& acc,
+                                         float& dmax) {
+  const float a[3] = {t.a[0], t.a[1], t.a[2]}, cc[3] = {c.x, c.y, c.z}, ll[3] = {cl.x, cl.y, cl.z};
+  const float nn[3] = {t.n[0], t.n[1], t.n[2]};
+  float ch[3], ce[3];   // c + cl - a = ch + ce per coordinate
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    ch[k] = cc[k] - a[k];
+    ce[k] = two_sum_err(cc[k], -a[k], ch[k]) + ll[k];
+  }
+  const V3 ca = {ch[0] + ce[0], ch[1] + ce[1], ch[2] + ce[2]};
+  bool face;
+  const V3 d = ca - tri_closest(t, ca, face);
+  float dist, dep;
+  if (face) {
+    float H = 0.f, L = 0.f;   // height over the plane: H + L
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float p = ch[k] * nn[k];
+      const float s = H + p;
+      L += two_sum_err(H, p, s) + __builtin_fmaf(ch[k], nn[k], -p) + ce[k] * nn[k];
+      H = s;
+    }
+    dep = (r - H) - L;
+    dist = fabsf(H + L);
+  } else {
+    dist = sqrtf(dot(d, d));
+    dep = dot(ca, V3{nn[0], nn[1], nn[2]}) >= 0.f ? r - dist : r + dist;
+  }
   if (dist < r) {
-    const V3 nf = {t.n[0], t.n[1], t.n[2]};
-    const V3 ca = {c.x - t.a[0], c.y - t.a[1], c.z - t.a[2]};
-    const float dep = dot(ca, nf) >= 0.f ? r - dist : r + dist;
+    const V3 nf = {nn[0], nn[1], nn[2]};
     acc = fma3(dep, nf, acc);
     dmax = fmaxf(dmax, dep);
   }
@@ -851,7 +887,7 @@ struct RodLane {
       if (!ok[e]) continue;
       const int slot = rd.slot_off + off + j0 + e;
       const float r = lr[j0 + e];
-      const V3 c = X[e];
+      const V3 c = X[e], cl = XL[e];
       int2* list = rd.env_cand + (size_t)slot * kEnvCand;
       V3 acc = {0.f, 0.f, 0.f};
       float dmax = 0.f;
@@ -863,7 +899,7 @@ struct RodLane {
         const float reach = (1.f + kEnvMargin) * r;
         int cnt = 0;
         env_walk(rd, c, reach, [&](int k) {
-          const float dist = env_hit(rd.env_tris[k], c, r, acc, dmax);
+          const float dist = env_hit(rd.env_tris[k], c, cl, r, acc, dmax);
           if (dist < reach) {
             if (cnt < kEnvCand) list[cnt] = make_int2(k, __float_as_int(dist));
             ++cnt;
@@ -890,10 +926,10 @@ struct RodLane {
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u)
-            if (near[u]) env_hit(t[u], c, r, acc, dmax);
+            if (near[u]) env_hit(t[u], c, cl, r, acc, dmax);
         }
       } else {
-        env_walk(rd, c, r, [&](int k) { env_hit(rd.env_tris[k], c, r, acc, dmax); });
+        env_walk(rd, c, r, [&](int k) { env_hit(rd.env_tris[k], c, cl, r, acc, dmax); });
       }
       env_finish(acc, dmax, en[e], ed[e]);
     }
@@ -1097,7 +1133,10 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
 // group's first rod and [64 W, 128 W) the second, each exactly as rod_resident_kernel steps
 // one rod; a single rod leaves the second half idle (a rod of no elements taking the same
 // barriers).  Both rods have the same number of constraint iterations.
-//   Step start: every point writes its position and sphere radius to LDS.  With contact
+//   Step start: every point writes its position (both floats of the pair) and sphere radius
+//   to LDS; separations between points of the group are taken as (x_i - x_j) + (l_i - l_j),
+//   and the contact test and separation from them by sphere_gap, so that the compensated
+//   positions decide contacts, alike on both sides of a pair.  With contact
 //   (compiled in when CT), every point then lists (in (rod, point) order, at most
 //   kMaxContacts) the points whose spheres overlap its own, leaving out points of its own rod
 //   within self_skip of it.  It takes them from a candidate list (at most kContactCand
@@ -1118,6 +1157,8 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
 constexpr int kMaxContacts = 8;    // contacts per point (more sets status bit 8)
 constexpr int kContactCand = 16;   // candidate partners per point kept between list builds
 constexpr int kSphereSize = 8;     // points per bounding sphere
+// slack [m] of the fallback's FP32 candidate test over the exact contact test (sphere_gap)
+constexpr float kExactSlack = 1e-6f;
 
 struct GroupDev {
   int32_t rod[2];      // rod[1] = -1: a single rod
@@ -1137,6 +1178,35 @@ __device__ __forceinline__ void quad_put(uint2& q, int k, uint32_t v) {
   w = (k & 1) ? ((w & 0xffffu) | (v << 16)) : ((w & 0xffff0000u) | v);
 }
 
+// Gap |d| - D between two spheres whose radii sum to D (ri + rj) and whose centres are the
+// compensated positions xi + li and xj + lj; d returns the centre difference (rounded, for
+// the normal).  Resting contact keeps |d| within a step's sinking (g dt^2, often below
+// 1e-8 m) of D, where the difference of two FP32 lengths would carry an error of ulp(D):
+// instead |d|^2 - D^2 is formed in double-float arithmetic (error-free sums and products,
+// two_sum_err and fma) and divided by |d| + D, which gives the gap to FP32 precision of the
+// gap itself; both the contact test and the separation of the impulses use it.
+__device__ __forceinline__ float sphere_gap(V3 xi, V3 li, V3 xj, V3 lj, float ri, float rj,
+                                            V3& d) {
+  const float a[3] = {xi.x, xi.y, xi.z}, b[3] = {xj.x, xj.y, xj.z};
+  const float la[3] = {li.x, li.y, li.z}, lb[3] = {lj.x, lj.y, lj.z};
+  float S = 0.f, T = 0.f, dc[3];   // |d|^2 = S + T
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float sh = a[c] - b[c];
+    const float se = two_sum_err(a[c], -b[c], sh) + (la[c] - lb[c]);   // d_c = sh + se
+    const float p = sh * sh;
+    const float t = S + p;
+    T += two_sum_err(S, p, t) + __builtin_fmaf(sh, sh, -p) + __builtin_fmaf(2.f * sh, se, se * se);
+    S = t;
+    dc[c] = sh + se;
+  }
+  d = {dc[0], dc[1], dc[2]};
+  const float Dh = ri + rj, Dl = two_sum_err(ri, rj, Dh);
+  const float D2 = Dh * Dh;
+  const float D2e = __builtin_fmaf(Dh, Dh, -D2) + 2.f * Dh * Dl;
+  return ((S - D2) + (T - D2e)) / (sqrtf(S) + Dh);
+}
+
 template <int W, int E, bool CT>
 __global__ __launch_bounds__(128 * W) void rod_group_kernel(
     const RodDev* __restrict__ rods, const GroupDev* __restrict__ groups,
@@ -1151,9 +1221,11 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
   constexpr int SW = (SMAX + 31) / 32;
   __shared__ Mailbox<W> mb[2];
   __shared__ float cbuf[2][kClampChunk][10];
-  // step-start position and sphere radius, double-buffered by step parity: a wavefront that
-  // starts the next step does not overwrite what another still reads for this one
-  __shared__ float4 xs[2][2][CAP];
+  // step-start position and sphere radius, and the low parts of the position (the positions
+  // are pairs of floats; separations between points take both); rewritten at every step start
+  // after a barrier, so that no wavefront still reads the previous step's
+  __shared__ float4 xs[2][CAP];
+  __shared__ float4 xsl[2][CAP];
   // velocity and inverse mass, double-buffered by publication parity: the reads after one
   // publication and the writes two publications later are separated by a barrier
   __shared__ float4 vw[2][2][CAP];
@@ -1209,7 +1281,7 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
   const float reb2 = (0.45f * gp.margin) * (0.45f * gp.margin);
   const int s0 = (nrod[0] + kSphereSize - 1) / kSphereSize;
   const int ns = s0 + (nrod[1] + kSphereSize - 1) / kSphereSize;
-  int par = 0, xp = 0;
+  int par = 0;
   V3 xc = {rd.cx0[0], rd.cx0[1], rd.cx0[2]}, wc = {0.f, 0.f, 0.f};
   Q4 qc = {rd.cq0[0], rd.cq0[1], rd.cq0[2], rd.cq0[3]};
   const float dt = rd.dt;
@@ -1227,7 +1299,7 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
   auto scan = [&](int e, float mm) {
     const int i = L.j0 + e;
     const int own = sub * s0 + i / kSphereSize;
-    const V3 xi = L.X[e];
+    const V3 xi = L.X[e], li = L.XL[e];
     int n = 0;
     for (int wd = 0; wd < SW; ++wd) {
       uint32_t bits = wd * 32 < ns ? sov[own][wd] : 0u;
@@ -1238,9 +1310,11 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
         const int a = kk * kSphereSize, b = min(a + kSphereSize, nrod[r]);
         for (int j = a; j < b; ++j) {
           if (r == sub && abs(j - i) <= skip) continue;
-          const float4 p = xs[xp][r][j];
-          const float dx = xi.x - p.x, dy = xi.y - p.y, dz = xi.z - p.z, D = rho[e] + p.w + mm;
-          const float d2 = dx * dx + dy * dy + dz * dz;
+          const float4 p = xs[r][j], pl = xsl[r][j];
+          const V3 lj = {pl.x, pl.y, pl.z};
+          const float dx = (xi.x - p.x) + (li.x - lj.x), dy = (xi.y - p.y) + (li.y - lj.y);
+          const float dz = (xi.z - p.z) + (li.z - lj.z), D = rho[e] + p.w + mm;
+          const float d2 = dx * dx + dy * dy + dz * dz;   // (the listing takes the exact test)
           if (!(d2 < D * D) || !(d2 > 0.f)) continue;
           if (n < kContactCand) quad_put(cand[sub][n >> 2][i], n & 3, (uint32_t)(r * CAP + j));
           ++n;
@@ -1252,10 +1326,13 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
 
   for (int s = 0; s < n_steps; ++s) {
     // ---- step start: positions and radii; contact lists
-    xp = s & 1;
+    __syncthreads();   // every wavefront is done with the previous step's xs and xsl
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      if (L.ok[e]) xs[xp][sub][L.j0 + e] = make_float4(L.X[e].x, L.X[e].y, L.X[e].z, rho[e]);
+    for (int e = 0; e < E; ++e) {
+      if (!L.ok[e]) continue;
+      xs[sub][L.j0 + e] = make_float4(L.X[e].x, L.X[e].y, L.X[e].z, rho[e]);
+      xsl[sub][L.j0 + e] = make_float4(L.XL[e].x, L.XL[e].y, L.XL[e].z, 0.f);
+    }
     if (contact) {
       bool mv = false;
 #pragma unroll
@@ -1280,7 +1357,7 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
           const int a = k * kSphereSize, b = min(a + kSphereSize, nrod[r]);
           float cx = 0.f, cy = 0.f, cz = 0.f, rm = 0.f;
           for (int j = a; j < b; ++j) {
-            const float4 p = xs[xp][r][j];
+            const float4 p = xs[r][j];
             cx += p.x; cy += p.y; cz += p.z;
             rm = fmaxf(rm, p.w);
           }
@@ -1288,7 +1365,7 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
           cx *= inv; cy *= inv; cz *= inv;
           float d2 = 0.f;
           for (int j = a; j < b; ++j) {
-            const float4 p = xs[xp][r][j];
+            const float4 p = xs[r][j];
             d2 = fmaxf(d2, (p.x - cx) * (p.x - cx) + (p.y - cy) * (p.y - cy) + (p.z - cz) * (p.z - cz));
           }
           sph[t] = make_float4(cx, cy, cz, sqrtf(d2) + rm);
@@ -1318,7 +1395,7 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
           int n = scan(e, gp.margin);
           float4 b = make_float4(L.X[e].x, L.X[e].y, L.X[e].z, 0.f);
           if (n > kContactCand) {   // too many candidates: this step's exact contacts only
-            n = min(scan(e, 0.f), kContactCand);
+            n = min(scan(e, kExactSlack), kContactCand);
             b.x = __int_as_float(0x7fc00000);   // build again next step
           }
           ncand[e] = n;
@@ -1331,8 +1408,9 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
         cnt[e] = 0;
         if (!L.ok[e]) continue;
         const int i = L.j0 + e;
-        const V3 xi = L.X[e];
-        const float4* xsp = &xs[xp][0][0];   // indexed by sub * CAP + slot
+        const V3 xi = L.X[e], li = L.XL[e];
+        const float4* xsp = &xs[0][0];   // indexed by sub * CAP + slot
+        const float4* xlp = &xsl[0][0];
         // four candidates at a time: one quad read, then their four position reads together
 #pragma unroll
         for (int q = 0; q < kContactCand; q += 4) {
@@ -1340,16 +1418,21 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
           const uint2 w = cand[sub][q >> 2][i];
           int g[4];
           float4 p[4];
+          float4 pl[4];
 #pragma unroll
           for (int k = 0; k < 4; ++k) g[k] = q + k < ncand[e] ? quad_get(w, k) : quad_get(w, 0);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) p[k] = xsp[g[k]];
+          for (int k = 0; k < 4; ++k) {
+            p[k] = xsp[g[k]];
+            pl[k] = xlp[g[k]];
+          }
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             if (q + k >= ncand[e]) break;
-            const float dx = xi.x - p[k].x, dy = xi.y - p[k].y, dz = xi.z - p[k].z, D = rho[e] + p[k].w;
-            const float d2 = dx * dx + dy * dy + dz * dz;
-            if (!(d2 < D * D) || !(d2 > 0.f)) continue;
+            const V3 lj = {pl[k].x, pl[k].y, pl[k].z};
+            V3 d;
+            const float gap = sphere_gap(xi, li, V3{p[k].x, p[k].y, p[k].z}, lj, rho[e], p[k].w, d);
+            if (!(gap < 0.f) || !(dot(d, d) > 0.f)) continue;
             if (cnt[e] < kMaxContacts) {
               quad_put(lst[sub][cnt[e] >> 2][i], cnt[e] & 3, (uint32_t)g[k]);
               ++cnt[e];
@@ -1388,11 +1471,13 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           if (part[e] >= 0 && moved_rod) {
-            const float4 ox = xs[xp][1 - sub][part[e]];
+            const float4 ox = xs[1 - sub][part[e]];
             const float4 ov = vw[bpar][1 - sub][part[e]];
-            const V3 p = fma3(dt, L.Vv[e], L.X[e]);
-            const V3 po = fma3(dt, V3{ov.x, ov.y, ov.z}, V3{ox.x, ox.y, ox.z});
-            const V3 d = p - po;
+            const float4 ol = xsl[1 - sub][part[e]];
+            const V3 lo = {ol.x, ol.y, ol.z};
+            // predicted separation: (x - xo) + (l - lo) + dt (v - vo)
+            const V3 d0 = (L.X[e] - V3{ox.x, ox.y, ox.z}) + (L.XL[e] - lo);
+            const V3 d = fma3(dt, L.Vv[e] - V3{ov.x, ov.y, ov.z}, d0);
             const float wm = L.P[P_WINV][e];
             const float ws = gp.bind_mode == 2 ? wm + ov.w : wm;
             if (ws > 0.f) L.Vv[e] = fnma3(wm / (dt * ws), d, L.Vv[e]);
@@ -1406,23 +1491,25 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
         for (int e = 0; e < E; ++e) {
           if (!cnt[e]) continue;
           const int i = L.j0 + e;
-          const V3 xi = L.X[e], vi = L.Vv[e];
-          const V3 pi = fma3(dt, vi, xi);
+          const V3 xi = L.X[e], vi = L.Vv[e], li = L.XL[e];
           const float wi = L.P[P_WINV][e];
-          const float4* xsp = &xs[xp][0][0];     // indexed by sub * CAP + slot
+          const float4* xsp = &xs[0][0];     // indexed by sub * CAP + slot
+          const float4* xlp = &xsl[0][0];
           const float4* vwp = &vw[bpar][0][0];
-          // the impulse on this point from partner (ox, ov); false if that contact is inactive
-          auto impulse = [&](float4 ox, float4 ov, V3& imp) {
+          // the impulse on this point from partner (ox + its low parts oxl, ov); false if that
+          // contact is inactive
+          auto impulse = [&](float4 ox, float4 oxl, float4 ov, V3& imp) {
             const V3 xj = {ox.x, ox.y, ox.z}, vj = {ov.x, ov.y, ov.z};
             const float wsum = wi + ov.w;
             if (!(wsum > 0.f)) return false;
-            const V3 d0 = xi - xj;
+            V3 d0;
+            const float gap = sphere_gap(xi, li, xj, V3{oxl.x, oxl.y, oxl.z}, rho[e], ox.w, d0);
             const V3 nrm = rsqrtf(dot(d0, d0)) * d0;        // step-start normal, towards i
-            const V3 pj = fma3(dt, vj, xj);
-            const float sep = dot(pi - pj, nrm) - (rho[e] + ox.w);
+            const V3 vr = vi - vj;
+            // predicted separation along the normal: |d0| - D + dt (vi - vj).n
+            const float sep = __builtin_fmaf(dt, dot(vr, nrm), gap);
             if (!(sep < 0.f)) return false;
             const float lam = -sep / (dt * wsum);
-            const V3 vr = vi - vj;
             const V3 vt = fnma3(dot(vr, nrm), nrm, vr);
             const float vtl = sqrtf(dot(vt, vt));
             imp = (wi * lam) * nrm;
@@ -1439,12 +1526,13 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
             const int ga = quad_get(w, c & 3);
             const int gb = c + 1 < cnt[e] ? quad_get(w, (c & 3) + 1) : ga;
             const float4 oxa = xsp[ga], ova = vwp[ga], oxb = xsp[gb], ovb = vwp[gb];
+            const float4 la = xlp[ga], lb = xlp[gb];
             V3 imp;
-            if (impulse(oxa, ova, imp)) {
+            if (impulse(oxa, la, ova, imp)) {
               acc = acc + imp;
               ++act;
             }
-            if (c + 1 < cnt[e] && impulse(oxb, ovb, imp)) {
+            if (c + 1 < cnt[e] && impulse(oxb, lb, ovb, imp)) {
               acc = acc + imp;
               ++act;
             }

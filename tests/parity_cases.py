@@ -31,3 +31,262 @@ def edge_rods(oracle):
             st.q[0] = qc
         rods.append((spec, st))
     return rods
+
+
+# ---------------------------------------------------------------- bound and touching rods --
+
+class GroupCase:
+    """Rods stepped together through bindings or contact (Sec. 3.4, Sec. 2.3): the handle's
+    rods, how the handle is set up, and the same problem for the oracle's group step, whose
+    rods come in `order` (for bindings the dependent rod first, the master second)."""
+
+    def __init__(self, rods, n_steps, window, bars, bind=None, contact=None):
+        self.rods = [(fp32_radius(s), st) for s, st in rods]
+        self.n_steps, self.window, self.bars = n_steps, window, bars
+        self.bind, self.contact = bind, contact
+        if bind is not None:
+            pairs, one_way = bind
+            self.order = [int(pairs[0, 0]), int(pairs[0, 2])]
+            self.oracle_kw = dict(pairs=np.stack([pairs[:, 1], pairs[:, 3]], 1), one_way=one_way)
+        else:
+            self.order = list(range(len(rods)))
+            self.oracle_kw = dict(mu=contact[1])
+
+    def setup(self, batch):
+        """Bindings or contact on a RodBatch of self.rods."""
+        if self.bind is not None:
+            batch.set_bindings(*self.bind)
+        else:
+            batch.set_contact(*self.contact)
+
+
+def fp32_radius(spec):
+    """The spec with its element radii rounded to FP32 (kept as doubles), as the GPU receives
+    them: contact decides on distances against sums of radii, and where touching rods rest a
+    radius rounding (a few 1e-10 m) is not small against a step's sinking."""
+    return spec.replace(radius=np.asarray(spec.radius, dtype=np.float32).astype(np.float64))
+
+
+def _dt_shared(oracle, rods):
+    """The stricter of the rods' stable time steps (the oracle's rule), given to all of them."""
+    dt = min(oracle.Rod(s.replace(dt=1.0)).dt_rule() for s, _ in rods)
+    return [(s.replace(dt=dt), st) for s, st in rods]
+
+
+def bound_pair(one_way):
+    """The catheter / guidewire pair (both 512 elements, 384 bound points)."""
+    wl, pairs = W.config5(one_way)
+    return GroupCase(wl.rods, 500, 10, "c5", bind=(pairs, one_way))
+
+
+def crossing(oracle, mu):
+    """Two crossing 128-element rods: a stiff bar and a soft rod falling across its middle."""
+    return GroupCase(_dt_shared(oracle, W.config6().rods), 1500, 10, "c6", contact=([[0, 1]], mu))
+
+
+def coiled(oracle, n=48, turns=2, L=1.0, r=0.01, rise=0.5):
+    """Two flat turns of a circle with a slight helical rise (the second turn rise x 2r above
+    the first); the rest shape is this shape.  Self-contact, friction 0.2."""
+    R_ = L / (2 * np.pi * turns)
+    s = np.linspace(0.0, L, n + 1)
+    x = np.stack([R_ * np.sin(s / R_), R_ * (1 - np.cos(s / R_)), rise * 2 * r * s / (L / turns)], 1)
+    q = W.frames_from_polyline(x)
+    spec, st = W.straight_rod(n, L=L, radius=r, inextensible=True, dt=1e-5, gravity=(0, 0, 0),
+                              damp=5.0)
+    rod = oracle.Rod(spec)
+    u_hat = np.array([rod.darboux(q, j) for j in range(n - 1)])
+    lens = np.linalg.norm(x[1:] - x[:-1], axis=1)
+    spec = spec.replace(u_hat=u_hat, seg_len=lens, clamp_x0=tuple(x[0]), clamp_q0=tuple(q[0]))
+    st = st.copy()
+    st.x, st.q = x, q
+    return GroupCase(_dt_shared(oracle, [(spec, st)]), 200, 10, "coiled", contact=([[0, -1]], 0.2))
+
+
+def side_by_side(oracle, n=64, r=0.01):
+    """Two parallel rods whose elements are much shorter than their radius (l = 0.08 r), one
+    pressed sideways onto the other by gravity; friction 0.2."""
+    L = n * 0.08 * r
+    a, sa = W.straight_rod(n, L=L, radius=r, young=1e7, inextensible=True, gravity=(0, 0, 0),
+                           damp=0.5)
+    b, sb = W.straight_rod(n, L=L, radius=r, young=1e6, inextensible=True,
+                           gravity=(0, -9.81, 0), damp=0.5)
+    off = np.array([0.0, 1.99 * r, 0.0])
+    sb = sb.copy()
+    sb.x = sb.x + off
+    b = b.replace(clamp_x0=tuple(np.asarray(b.clamp_x0) + off))
+    return GroupCase(_dt_shared(oracle, [(a, sa), (b, sb)]), 400, 10, "side",
+                     contact=([[0, 1]], 0.2))
+
+
+def unequal(oracle, gap=1e-3):
+    """A 300-element bar along x (1 m, no gravity) and a 60-element rod along y (0.5 m) that
+    falls across its middle from gap above; both radius 4 mm, inextensible, static clamps,
+    friction 0.2."""
+    import math
+    r = 0.004
+    out = []
+    q_y = (math.cos(math.pi / 4), -math.sin(math.pi / 4), 0.0, 0.0)
+    for n, L, base, d3, q0, young, grav in (
+            (300, 1.0, (0.0, 0.0, 0.0), (1.0, 0.0, 0.0), W.Q_ALONG_X, 1e7, (0.0, 0.0, 0.0)),
+            (60, 0.5, (0.5, -0.25, 2 * r + gap), (0.0, 1.0, 0.0), q_y, 1e6, (0.0, 0.0, -9.81))):
+        l = L / n
+        x = np.asarray(base)[None, :] + np.outer(np.arange(n + 1) * l, d3)
+        q = np.tile(np.asarray(q0, dtype=np.float64), (n, 1))
+        spec = W.RodSpec(n=n, inextensible=True, n_iter=10, clamp=True, dt=1e-5, gravity=grav,
+                         damp_lin=0.5, damp_ang=0.5, poisson=0.5, density=1000.0,
+                         seg_len=np.full(n, l), radius=np.full(n, r), young=np.full(n, young),
+                         clamp_x0=tuple(base), clamp_q0=tuple(q0))
+        out.append((spec, W.RodState(x=x, v=np.zeros_like(x), q=q, w=np.zeros((n, 3)))))
+    return GroupCase(_dt_shared(oracle, out), 1500, 10, "unequal", contact=([[0, 1]], 0.2))
+
+
+def group_cases(oracle):
+    """The bound and touching configurations of the parity tests, by name."""
+    return {"c5-one": bound_pair(True), "c5-two": bound_pair(False),
+            "c6-mu0": crossing(oracle, 0.0), "c6-mu0.3": crossing(oracle, 0.3),
+            "coiled": coiled(oracle), "side": side_by_side(oracle), "unequal": unequal(oracle)}
+
+
+def group_run(oracle, case, n_steps, states=None, t0=0.0, round_mask=0, specs=None, **kw):
+    """The oracle's group step over n_steps from `states` (default: the FP32 input), in the
+    handle's rod order; returns (states, largest number of contacts of one point).  specs and
+    kw replace the case's rods' specs and group arguments."""
+    specs = [s for s, _ in case.rods] if specs is None else specs
+    if states is None:
+        states = [_fp32(st) for _, st in case.rods]
+    okw = dict(case.oracle_kw, **kw)
+    o = case.order
+    out, most = oracle.rollout_group([specs[i] for i in o], [states[i] for i in o], n_steps,
+                                     t0=t0, round_mask=round_mask, **okw)
+    res = [None] * len(o)
+    for j, i in enumerate(o):
+        res[i] = out[j]
+    return res, most
+
+
+def group_window(oracle, case, n_steps, k, round_mask=0, specs=None, **kw):
+    """Oracle states after n_steps - k and n_steps steps (handle order), and the most
+    contacts of one point over the run."""
+    specs = [s for s, _ in case.rods] if specs is None else specs
+    a, most_a = group_run(oracle, case, n_steps - k, round_mask=round_mask, specs=specs, **kw)
+    b, most_b = group_run(oracle, case, k, states=a, t0=(n_steps - k) * specs[0].dt,
+                          round_mask=round_mask, specs=specs, **kw)
+    return a, b, max(most_a, most_b)
+
+
+def _fp32(st):
+    out = st.copy()
+    for f in ("x", "v", "q", "w"):
+        setattr(out, f, np.asarray(getattr(st, f), dtype=np.float32).astype(np.float64))
+    return out
+
+
+# ------------------------------------------------------------------ environment collision --
+
+class EnvCase:
+    """One rod against a static triangle mesh (Sec. 2.2) with friction mu; the mesh as both
+    sides receive it (vertices rounded to FP32)."""
+
+    def __init__(self, spec, state, tris, mu, n_steps, window, bars):
+        self.rods = [(fp32_radius(spec), state)]
+        self.tris = np.asarray(tris, dtype=np.float32).astype(np.float64)
+        self.mu, self.n_steps, self.window, self.bars = mu, n_steps, window, bars
+
+
+def tube(oracle, mu):
+    """The environment workload: a 64-element rod laid along a bent tube's axis, clamped at
+    its entrance, pressed onto the wall by gravity and its own stiffness."""
+    wl, tris = W.config7(n=64)
+    (spec, st), = _dt_shared(oracle, wl.rods)
+    return EnvCase(spec, st, tris, mu, 1200, 10, "tube")
+
+
+def floor_plane(z=0.0, size=2.0):
+    a, b, c, d = ([-size, -size, z], [size, -size, z], [size, size, z], [-size, size, z])
+    return np.array([[a, b, c], [a, c, d]], dtype=np.float64)
+
+
+def on_floor(oracle, inext):
+    """A clamped 32-element rod that sags onto a floor just below it and slides on it with
+    friction 0.4."""
+    spec, st = W.straight_rod(32, L=0.5, radius=0.01, inextensible=inext, dt=1e-5, damp=0.5)
+    (spec, st), = _dt_shared(oracle, [(spec, st)])
+    return EnvCase(spec, st, floor_plane(z=-0.02), 0.4, 1500, 10, "floor")
+
+
+def env_run(oracle, case, n_steps, state=None, t0=0.0, round_mask=0):
+    """The oracle's rod against the case's mesh over n_steps from `state` (default: the FP32
+    input); with round_mask, the fields of the mask rounded to FP32 after every step."""
+    spec = case.rods[0][0]
+    env = oracle.Env(case.tris, case.mu)
+    st = _fp32(case.rods[0][1]) if state is None else state
+    if not round_mask:
+        return oracle.rollout_env(spec, st, n_steps, env, t0=t0)
+    most = 0
+    for k in range(n_steps):
+        st, m = oracle.rollout_env(spec, st, 1, env, t0=t0 + k * spec.dt)
+        st = _round(st, round_mask)
+        most = max(most, m)
+    return st, most
+
+
+def env_window(oracle, case, n_steps, k, round_mask=0):
+    """Oracle states after n_steps - k and n_steps steps, and the most colliding points."""
+    spec = case.rods[0][0]
+    a, m1 = env_run(oracle, case, n_steps - k, round_mask=round_mask)
+    b, m2 = env_run(oracle, case, k, state=a, t0=(n_steps - k) * spec.dt, round_mask=round_mask)
+    return [a], [b], max(m1, m2)
+
+
+def _round(st, mask):
+    out = st.copy()
+    for f, bit in (("x", 1), ("v", 2), ("q", 4), ("w", 8)):
+        if mask & bit:
+            setattr(out, f, np.asarray(getattr(st, f), dtype=np.float32).astype(np.float64))
+    return out
+
+
+def env_restarts(oracle, case, states, stops, k=10):
+    """From each state states[i] (taken at step stops[i] of a run), k steps of the oracle: the
+    plain run, and two runs that show how far FP32-sized differences carry over the window
+    (its floor): v, q and w rounded to FP32 after every step, and a start whose v, q and w are
+    moved by 2^-22 relative, signs seeded by the step.  Contact decisions (touching or not,
+    sticking or slipping) make some windows far more sensitive than others; the moved start
+    shows that where the rounding alone does not.  Returns [(start, plain, rounded, moved)]."""
+    spec = case.rods[0][0]
+    out = []
+    for st, s in zip(states, stops):
+        st = _round(st, 15)
+        b, _ = env_run(oracle, case, k, state=st, t0=s * spec.dt)
+        r, _ = env_run(oracle, case, k, state=st, t0=s * spec.dt, round_mask=14)
+        m, _ = env_run(oracle, case, k, state=_moved(st, s), t0=s * spec.dt)
+        out.append((st, b, r, m))
+    return out
+
+
+def _moved(st, seed):
+    rng = np.random.default_rng(seed)
+    out = st.copy()
+    for f in ("v", "q", "w"):
+        a = np.asarray(getattr(st, f), dtype=np.float64)
+        setattr(out, f, a * (1.0 + rng.choice([-1.0, 1.0], a.shape) * 2.0 ** -22))
+    return out
+
+
+def env_floor(spec, x0, start, plain, rounded, moved, k, errors):
+    """Floor of one restart window: per quantity the larger of the rounded and the moved
+    run's difference from the plain run (errors: parity_metrics.errors)."""
+    t = lambda u: (u.x, u.v, u.q, u.w)
+    fr = errors(spec, x0, t(start), t(rounded), t(start), t(plain), k)
+    fm = errors(spec, x0, t(start), t(moved), t(start), t(plain), k)
+    out = {m: max(fr[m], fm[m]) for m in fr}
+    out.pop("unit")
+    return out
+
+
+def env_changed(case, spec=None, mu=None):
+    """The case with another spec or friction coefficient (same input and mesh)."""
+    c = EnvCase(case.rods[0][0] if spec is None else spec, case.rods[0][1], case.tris,
+                case.mu if mu is None else mu, case.n_steps, case.window, case.bars)
+    c.tris = case.tris
+    return c

@@ -76,22 +76,9 @@ def run_oracle_window(oracle, rods, n_steps, k):
     return a, c
 
 
-def _tuple(st):
-    return (st.x, st.v, st.q, st.w)
-
-
 def compare_window(gpu, ref, rods, k, label, tol=None):
     """Whole-state comparison (parity_metrics) of every rod; returns the worst values."""
-    errs = []
-    for r, (spec, st) in enumerate(rods):
-        e = PM.errors(spec, st.x, gpu[0][r], gpu[1][r], _tuple(ref[0][r]), _tuple(ref[1][r]), k)
-        assert all(np.isfinite(a).all() for a in gpu[1][r])
-        _say("%s rod %d N=%d: %s" % (label, r, spec.n, PM.fmt(e)))
-        errs.append(e)
-    w = PM.worst(errs)
-    bad = PM.violations(w, tol)
-    assert not bad, "%s: above the bars: %s" % (label, bad)
-    return w
+    return PM.check_window(gpu, ref, rods, k, label, tol, _say)
 
 
 def compare(gpu, ref, specs, label):

@@ -10,6 +10,13 @@ configuration covers that coefficient.  Every step of the method is covered some
   force integration (masses and inertias: the density)                  Sec. 2.1
   distance constraints (the number of constraint iterations)            Sec. 2.1
   velocity integration (the time step)                                  Sec. 2.1
+  binding constraints (a tenth of the bound points released)           Sec. 3.4
+  contact friction (the Coulomb coefficient)                            Sec. 2.3
+
+The bound and touching configurations (parity_cases.group_cases) are held to the same rules:
+their bars follow their FP32 floors, and they detect the changes listed for them.  So are the
+restart windows of the environment-collision tests (10 steps from states along a run, bars
+from each window's own floor).
 """
 import dataclasses
 import math
@@ -43,8 +50,25 @@ CHANGES = {
     "dt": lambda s: s.replace(dt=1.1 * s.dt),
 }
 
+# changes of the group step's own arguments (the oracle's rollout_group keywords)
+GROUP_CHANGES = {
+    "bind": lambda kw: dict(kw, pairs=kw["pairs"][len(kw["pairs"]) // 10:]),
+    "mu": lambda kw: dict(kw, mu=1.1 * kw["mu"]),
+}
+
 # configuration: (rods, steps, window, bar set, coefficients it must detect)
 ALL = tuple(CHANGES)
+
+# group configuration: coefficients it must detect
+GROUP_MUST = {
+    "c5-one": ("drive", "twist", "mass", "dt", "bind"),
+    "c5-two": ("drive", "twist", "mass", "n_iter", "dt", "bind"),
+    "c6-mu0": ("gravity", "damp_lin", "K_p", "bend", "mass", "n_iter", "dt"),
+    "c6-mu0.3": ("gravity", "damp_lin", "K_p", "bend", "mass", "n_iter", "dt", "mu"),
+    "coiled": ("damp_lin", "damp_ang", "K_p", "bend", "twist", "mass", "n_iter", "dt", "mu"),
+    "side": ("K_p", "bend", "mass", "n_iter", "dt", "mu"),
+    "unequal": ("gravity", "K_p", "bend", "mass", "dt"),
+}
 
 
 def _configs(oracle):
@@ -88,7 +112,12 @@ def test_every_step_is_covered(oracle):
     covered = set()
     for _, _, _, _, must in _configs(oracle).values():
         covered |= set(must)
-    assert covered == set(CHANGES)
+    for must in GROUP_MUST.values():
+        covered |= set(must)
+    for _, _, must in ENV.values():
+        covered |= set(must)
+    assert covered == set(CHANGES) | set(GROUP_CHANGES)
+    assert set(GROUP_MUST) == set(parity_cases.group_cases(oracle))
 
 
 NAMES = ["c0", "c0-swing", "c1-2000", "c1-full", "edge"]
@@ -143,8 +172,108 @@ def test_bars_follow_the_fp32_floor(oracle, name):
     floor = PM.worst(fl)
     floor.pop("unit")
     print("%s: FP32 floor %s" % (name, PM.fmt(floor)))
+    _check_bars(name, floor, PM.BARS[bars])
+
+
+def _check_bars(name, floor, bars):
+    """Each bar within 20 % of max(base bar, FLOOR_FACTOR x floor) rounded up to two digits
+    (the floors move in their last digits between machines)."""
     for m, f in floor.items():
         want = max(PM.TOL[m], _up2(PM.FLOOR_FACTOR * f)) if f > 0 else PM.TOL[m]
-        got = PM.BARS[bars][m]
-        # the floors move in their last digits between machines: allow 20 % either way
+        got = bars[m]
         assert 0.8 * want <= got <= 1.2 * want, (name, m, got, want)
+
+
+def _group_worst(case, pa, pb, a, b):
+    return PM.worst([PM.errors(s, st.x, _t(x), _t(y), _t(u), _t(v), case.window)
+                     for (s, st), x, y, u, v in zip(case.rods, pa, pb, a, b)])
+
+
+@pytest.mark.parametrize("name", sorted(GROUP_MUST))
+def test_group_bars_fail_on_changed_coefficients(oracle, name):
+    case = parity_cases.group_cases(oracle)[name]
+    n, k = case.n_steps, case.window
+    a, b, _ = parity_cases.group_window(oracle, case, n, k)
+    specs = [s for s, _ in case.rods]
+    missed = []
+    for coef in GROUP_MUST[name]:
+        if coef in CHANGES:
+            cs = [CHANGES[coef](s) for s in specs]
+            assert any(_differs(c, s) for c, s in zip(cs, specs)), coef
+            pa, pb, _ = parity_cases.group_window(oracle, case, n, k, specs=cs)
+        else:
+            kw = GROUP_CHANGES[coef](dict(case.oracle_kw))
+            pa, pb, _ = parity_cases.group_window(oracle, case, n, k, **kw)
+        w = _group_worst(case, pa, pb, a, b)
+        w.pop("unit")
+        bad = PM.violations(w, PM.BARS[case.bars])
+        print("%s, %s changed: %s -> above the bars: %s" % (name, coef, PM.fmt(w), sorted(bad)))
+        if not bad:
+            missed.append(coef)
+    assert not missed, "%s: a change of %s passes every bar" % (name, missed)
+
+
+@pytest.mark.parametrize("bars", ["c5", "c6", "coiled", "side", "unequal"])
+def test_group_bars_follow_the_fp32_floor(oracle, bars):
+    """As test_bars_follow_the_fp32_floor, for the bound and touching configurations (every
+    rod of the group rounded after every group step); a bar set that several configurations
+    share follows the largest of their floors."""
+    cases = [c for c in parity_cases.group_cases(oracle).values() if c.bars == bars]
+    assert cases
+    fl = []
+    for case in cases:
+        n, k = case.n_steps, case.window
+        a, b, _ = parity_cases.group_window(oracle, case, n, k)
+        ra, rb, _ = parity_cases.group_window(oracle, case, n, k, round_mask=14)
+        fl.append(_group_worst(case, ra, rb, a, b))
+    floor = PM.worst(fl)
+    floor.pop("unit")
+    print("%s: FP32 floor %s" % (bars, PM.fmt(floor)))
+    _check_bars(bars, floor, PM.BARS[bars])
+
+
+# environment collision: restart steps along the run, and the changes those windows detect
+ENV = {
+    "tube-0.0": (lambda o: parity_cases.tube(o, 0.0), (400, 600, 800, 1000, 1190),
+                 ("gravity", "K_p", "bend", "twist", "mass", "n_iter", "dt")),
+    "tube-0.3": (lambda o: parity_cases.tube(o, 0.3), (400, 600, 800, 1000, 1190),
+                 ("gravity", "K_p", "bend", "twist", "mass", "dt")),
+    "floor-inext": (lambda o: parity_cases.on_floor(o, True), (200, 500, 1000, 1490),
+                    ("gravity", "K_p", "bend", "mass", "n_iter", "dt", "mu")),
+    "floor-ext": (lambda o: parity_cases.on_floor(o, False), (200, 500, 1000, 1490),
+                  ("gravity", "K_s", "K_p", "bend", "mass", "dt")),
+}
+
+
+@pytest.mark.parametrize("name", sorted(ENV))
+def test_env_restart_bars_fail_on_changed_coefficients(oracle, name):
+    make, stops, must = ENV[name]
+    case = make(oracle)
+    spec, st0 = case.rods[0]
+    states, st, prev = [], None, 0
+    for s in stops:
+        st, _ = parity_cases.env_run(oracle, case, s - prev, state=st, t0=prev * spec.dt)
+        prev = s
+        states.append(st)
+    base = parity_cases.env_restarts(oracle, case, states, stops)
+    bars = [PM.floor_bars(parity_cases.env_floor(spec, st0.x, S, b, r, m, 10, PM.errors))
+            for S, b, r, m in base]
+    missed = []
+    for coef in must:
+        if coef == "mu":
+            ch = parity_cases.env_changed(case, mu=1.1 * case.mu)
+        else:
+            ns = CHANGES[coef](spec)
+            assert _differs(ns, spec), coef
+            ch = parity_cases.env_changed(case, spec=ns)
+        hit = []
+        for (S, b, _, _), (_, pb, _, _), bb, s in zip(base, parity_cases.env_restarts(oracle, ch, states, stops),
+                                                       bars, stops):
+            e = PM.errors(spec, st0.x, _t(S), _t(pb), _t(S), _t(b), 10)
+            e.pop("unit")
+            if PM.violations(e, bb):
+                hit.append(s)
+        print("%s, %s changed: windows above their bars start at %s" % (name, coef, hit))
+        if not hit:
+            missed.append(coef)
+    assert not missed, "%s: a change of %s passes every window" % (name, missed)
