@@ -273,7 +273,20 @@ def _moved(st, seed):
     return out
 
 
-def env_floor(spec, x0, start, plain, rounded, moved, k, errors):
+def rod_restarts(oracle, spec, states, stops, k=10):
+    """As env_restarts, for a rod on its own."""
+    r = oracle.Rod(spec)
+    out = []
+    for st, s in zip(states, stops):
+        st = _round(st, 15)
+        b = r.rollout(st, k, t0=s * spec.dt)[0]
+        rr = r.rollout_rounded(st, k, 14, t0=s * spec.dt)
+        m = r.rollout(_moved(st, s), k, t0=s * spec.dt)[0]
+        out.append((st, b, rr, m))
+    return out
+
+
+def window_floor(spec, x0, start, plain, rounded, moved, k, errors):
     """Floor of one restart window: per quantity the larger of the rounded and the moved
     run's difference from the plain run (errors: parity_metrics.errors)."""
     t = lambda u: (u.x, u.v, u.q, u.w)
@@ -290,3 +303,49 @@ def env_changed(case, spec=None, mu=None):
                 case.mu if mu is None else mu, case.n_steps, case.window, case.bars)
     c.tris = case.tris
     return c
+
+
+# ------------------------------------------------------- internal friction, haptic pose --
+
+def damped(oracle, n, inext, td_over_dt, seed=6):
+    """A curved, twisted clamped rod released under gravity with internal friction tau_d a
+    multiple of the stable dt (the dashpots then take part in the stability rule)."""
+    rng = np.random.default_rng(seed)
+    x, q = W.curved_rod(n, 1.0 / n, rng, 0.05, twist_sigma=0.05)
+    spec, _ = W.straight_rod(n, inextensible=inext, dt=1e-5)
+    spec = spec.replace(seg_len=np.linalg.norm(np.diff(x, axis=0), axis=1), clamp_x0=tuple(x[0]),
+                        clamp_q0=tuple(q[0]))
+    dt0 = oracle.Rod(spec.replace(dt=1.0)).dt_rule()
+    spec = spec.replace(damp_int=td_over_dt * dt0)
+    spec = spec.replace(dt=oracle.Rod(spec.replace(dt=1.0)).dt_rule())
+    return spec, W.RodState(x=x, v=np.zeros_like(x), q=q, w=np.zeros((n, 3)))
+
+
+def swinging(oracle, n, inext, seed=3):
+    """A clamped horizontal rod released under gravity, slightly perturbed."""
+    spec, st = W.straight_rod(n, inextensible=inext, dt=1e-5, damp=0.3)
+    spec = spec.replace(dt=oracle.Rod(spec.replace(dt=1.0)).dt_rule())
+    rng = np.random.default_rng(seed)
+    st = st.copy()
+    st.x = st.x + rng.normal(0, 1e-4, st.x.shape) * np.r_[0.0, np.ones(n)][:, None]
+    return spec, st
+
+
+# ----------------------------------------------------------------------- uneven batches --
+
+def with_rule_dt(oracle, rods):
+    """Each rod at its own stable time step (the oracle's rule)."""
+    return [(s.replace(dt=oracle.Rod(s.replace(dt=1.0)).dt_rule()), st) for s, st in rods]
+
+
+def batch48(oracle):
+    """48 uneven rods (N 8..700, both variants), per-rod dt: several kernel-shape buckets."""
+    return with_rule_dt(oracle, W.config3(n_rods=48, n_min=8, n_max=700).rods)
+
+
+def c3_pick(rods):
+    """Sampled rods of the 4096-rod batch: every 256th, the costliest (longest inextensible)
+    and the shortest."""
+    ns = np.array([s.n for s, _ in rods])
+    cost = ns * np.array([4 + s.n_iter for s, _ in rods])
+    return sorted(set(range(0, len(rods), 256)) | {int(np.argmax(cost)), int(np.argmin(ns))})

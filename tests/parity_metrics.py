@@ -44,6 +44,9 @@ BARS = {
     "c1-full": dict(TOL, x=1.6e-2, q=1.8e-3, u=5.4e-1, wbar=1.1e-1),          # 20000 steps
     "edge": dict(TOL, q=1.2e-4),
     "c2": dict(TOL, wbar=1.9e-3),                                              # 4096, 5000 steps
+    "damped": dict(TOL, wbar=1.5e-3),                                          # 600 steps
+    "batch": dict(TOL, wbar=8.1e-3),                                           # 48 rods, 150
+    "c3": dict(TOL, wbar=9.6e-3),                                              # sampled, 1000
     "c5": dict(TOL, u=1.2e-2, wbar=1.5e-2),                                   # bound pair, 500
     "c6": dict(TOL, u=6.3e-3, wbar=2.9e-2),                                   # crossing, 1500
     "coiled": TOL,

@@ -10,6 +10,7 @@ configuration covers that coefficient.  Every step of the method is covered some
   force integration (masses and inertias: the density)                  Sec. 2.1
   distance constraints (the number of constraint iterations)            Sec. 2.1
   velocity integration (the time step)                                  Sec. 2.1
+  internal friction (the retardation time of the Kelvin-Voigt dashpots)  Sec. 2.1
   binding constraints (a tenth of the bound points released)           Sec. 3.4
   contact friction (the Coulomb coefficient)                            Sec. 2.3
 
@@ -20,6 +21,8 @@ from each window's own floor).
 """
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -48,6 +51,7 @@ CHANGES = {
     "mass": lambda s: s.replace(density=1.1 * s.density),
     "n_iter": lambda s: s.replace(n_iter=s.n_iter - max(1, s.n_iter // 10)) if s.inextensible else s,
     "dt": lambda s: s.replace(dt=1.1 * s.dt),
+    "damp_int": lambda s: s.replace(damp_int=1.1 * s.damp_int),
 }
 
 # changes of the group step's own arguments (the oracle's rollout_group keywords)
@@ -80,9 +84,21 @@ def _configs(oracle):
         "c1-2000": (W.config1().rods, 2000, 10, "c1", ("twist", "mass", "n_iter", "dt", "drive")),
         "c1-full": (W.config1().rods, 20000, 10, "c1-full",
                     ("bend", "twist", "mass", "n_iter", "dt", "drive")),
-        "edge": (parity_cases.edge_rods(oracle), 400, 37, "edge", ALL),
+        "edge": (parity_cases.edge_rods(oracle), 400, 37, "edge",
+                 tuple(c for c in ALL if c != "damp_int")),   # (no internal friction there)
         "c2-4096": (W.config2(4096, True).rods + W.config2(4096, False).rods, 5000, 10, "c2", ()),
+        "c0-300": (W.config0(n=64).rods, 300, 10, "c0", ()),
+        "batch": (parity_cases.batch48(oracle), 150, 10, "batch", ()),
+        "c3-sampled": (_c3_sample(oracle), 1000, 10, "c3", ()),
+        "damped": ([parity_cases.damped(oracle, n, inext, 20.0) for n in (64, 700)
+                    for inext in (False, True)], 600, 10, "damped",
+                   ("gravity", "K_s", "K_p", "bend", "twist", "mass", "dt", "damp_int")),
     }
+
+
+def _c3_sample(oracle):
+    rods = parity_cases.with_rule_dt(oracle, W.config3().rods)
+    return [rods[i] for i in parity_cases.c3_pick(rods)]
 
 
 def _window(oracle, rods, n, k):
@@ -120,7 +136,7 @@ def test_every_step_is_covered(oracle):
     assert set(GROUP_MUST) == set(parity_cases.group_cases(oracle))
 
 
-NAMES = ["c0", "c0-swing", "c1-2000", "c1-full", "edge"]
+NAMES = ["c0", "c0-swing", "c1-2000", "c1-full", "edge", "damped"]
 
 
 @pytest.mark.parametrize("name", NAMES)
@@ -156,19 +172,21 @@ def _up2(v):
     return math.ceil(v / 10 ** (e - 1) - 1e-9) * 10 ** (e - 1)
 
 
-@pytest.mark.parametrize("name", NAMES + ["c2-4096"])
+@pytest.mark.parametrize("name", NAMES + ["c2-4096", "c0-300", "batch", "c3-sampled"])
 def test_bars_follow_the_fp32_floor(oracle, name):
     """Each bar is max(base bar, FLOOR_FACTOR x the configuration's FP32 floor), the floor
     being the oracle against itself with v, q and w rounded to FP32 after every step."""
     rods, n, k, bars, _ = _configs(oracle)[name]
     rods = PM.fp32_rods(rods)
     a, b = _window(oracle, rods, n, k)
-    fl = []
-    for (s, st), sa, sb in zip(rods, a, b):
+    def one(args):
+        (s, st), sa, sb = args
         r = oracle.Rod(s)
         ra = r.rollout_rounded(st, n - k, 14)
         rb = r.rollout_rounded(ra, k, 14, t0=(n - k) * s.dt)
-        fl.append(PM.errors(s, st.x, _t(ra), _t(rb), _t(sa), _t(sb), k))
+        return PM.errors(s, st.x, _t(ra), _t(rb), _t(sa), _t(sb), k)
+    with ThreadPoolExecutor(max(1, min(8, os.cpu_count() or 1))) as ex:   # ctypes drops the GIL
+        fl = list(ex.map(one, zip(rods, a, b)))
     floor = PM.worst(fl)
     floor.pop("unit")
     print("%s: FP32 floor %s" % (name, PM.fmt(floor)))
@@ -256,7 +274,7 @@ def test_env_restart_bars_fail_on_changed_coefficients(oracle, name):
         prev = s
         states.append(st)
     base = parity_cases.env_restarts(oracle, case, states, stops)
-    bars = [PM.floor_bars(parity_cases.env_floor(spec, st0.x, S, b, r, m, 10, PM.errors))
+    bars = [PM.floor_bars(parity_cases.window_floor(spec, st0.x, S, b, r, m, 10, PM.errors))
             for S, b, r, m in base]
     missed = []
     for coef in must:
