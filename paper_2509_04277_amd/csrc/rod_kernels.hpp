@@ -260,12 +260,6 @@ __device__ __forceinline__ void advance_position(V3& hi, V3& lo, V3 v, float dt)
   add_compensated(hi.z, lo.z, v.z, dt);
 }
 
-// Rounding error of s = fl(a + b) (Knuth's TwoSum): a + b = s + two_sum_err(a, b, s) exactly.
-__device__ __forceinline__ float two_sum_err(float a, float b, float s) {
-  const float bb = s - a;
-  return (a - (s - bb)) + (b - bb);
-}
-
 // hi + lo <- hi + lo + d with the Fast2Sum of hi and lo + d.
 __device__ __forceinline__ void add_pair(float& hi, float& lo, float d) {
   const float y = lo + d;
@@ -380,42 +374,30 @@ __device__ __forceinline__ void env_walk(const RodDev& rd, V3 c, float reach, Le
 // Narrow phase of one triangle against a sphere (centre c + cl, a compensated position;
 // radius r): a triangle collides when its nearest point is closer than r; its depth is r - dist
 // with the centre in front of the face, r + dist behind it; acc gathers depth x face normal,
-// dmax the largest depth.  Returns the distance.  Where the nearest point is inside the face,
-// the signed distance is the centre's height over the face's plane, dot(c + cl - a, n), taken
-// in double-float arithmetic (the error-free difference c - a, products by fma), and the
-// depth is r minus that height on either side: resting contact keeps the height within a
-// step's sinking of r, far below the ulp of the coordinates.
+// dmax the largest depth.  Returns the distance.  The centre is taken relative to the
+// triangle's first vertex in FP64 (exact for these float operands); where the nearest point
+// is inside the face the signed distance is the height over the face's plane, dot(c + cl - a,
+// n) in FP64, and the depth is r minus that height on either side: resting contact keeps the
+// height within a step's sinking of r, far below the ulp of the coordinates.
 __device__ __forceinline__ float env_hit(const EnvTri& t, V3 c, V3 cl, float r, V3& acc,
                                          float& dmax) {
-  const float a[3] = {t.a[0], t.a[1], t.a[2]}, cc[3] = {c.x, c.y, c.z}, ll[3] = {cl.x, cl.y, cl.z};
-  const float nn[3] = {t.n[0], t.n[1], t.n[2]};
-  float ch[3], ce[3];   // c + cl - a = ch + ce per coordinate
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    ch[k] = cc[k] - a[k];
-    ce[k] = two_sum_err(cc[k], -a[k], ch[k]) + ll[k];
-  }
-  const V3 ca = {ch[0] + ce[0], ch[1] + ce[1], ch[2] + ce[2]};
+  const double hx = ((double)c.x - (double)t.a[0]) + (double)cl.x;
+  const double hy = ((double)c.y - (double)t.a[1]) + (double)cl.y;
+  const double hz = ((double)c.z - (double)t.a[2]) + (double)cl.z;
+  const V3 ca = {(float)hx, (float)hy, (float)hz};
+  const V3 nf = {t.n[0], t.n[1], t.n[2]};
   bool face;
   const V3 d = ca - tri_closest(t, ca, face);
   float dist, dep;
   if (face) {
-    float H = 0.f, L = 0.f;   // height over the plane: H + L
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const float p = ch[k] * nn[k];
-      const float s = H + p;
-      L += two_sum_err(H, p, s) + __builtin_fmaf(ch[k], nn[k], -p) + ce[k] * nn[k];
-      H = s;
-    }
-    dep = (r - H) - L;
-    dist = fabsf(H + L);
+    const double H = __builtin_fma(hx, (double)nf.x, __builtin_fma(hy, (double)nf.y, hz * (double)nf.z));
+    dep = (float)((double)r - H);
+    dist = fabsf((float)H);
   } else {
     dist = sqrtf(dot(d, d));
-    dep = dot(ca, V3{nn[0], nn[1], nn[2]}) >= 0.f ? r - dist : r + dist;
+    dep = dot(ca, nf) >= 0.f ? r - dist : r + dist;
   }
   if (dist < r) {
-    const V3 nf = {nn[0], nn[1], nn[2]};
     acc = fma3(dep, nf, acc);
     dmax = fmaxf(dmax, dep);
   }
@@ -1182,29 +1164,18 @@ __device__ __forceinline__ void quad_put(uint2& q, int k, uint32_t v) {
 // compensated positions xi + li and xj + lj; d returns the centre difference (rounded, for
 // the normal).  Resting contact keeps |d| within a step's sinking (g dt^2, often below
 // 1e-8 m) of D, where the difference of two FP32 lengths would carry an error of ulp(D):
-// instead |d|^2 - D^2 is formed in double-float arithmetic (error-free sums and products,
-// two_sum_err and fma) and divided by |d| + D, which gives the gap to FP32 precision of the
-// gap itself; both the contact test and the separation of the impulses use it.
+// instead the centre difference is formed in FP64 (exact for these float operands), |d|^2 -
+// D^2 in FP64, and the gap is that over |d| + D, to FP32 precision of the gap itself.  (FP64
+// fused multiply-adds issue at the rate of the unpacked FP32 ones this library uses.)
 __device__ __forceinline__ float sphere_gap(V3 xi, V3 li, V3 xj, V3 lj, float ri, float rj,
                                             V3& d) {
-  const float a[3] = {xi.x, xi.y, xi.z}, b[3] = {xj.x, xj.y, xj.z};
-  const float la[3] = {li.x, li.y, li.z}, lb[3] = {lj.x, lj.y, lj.z};
-  float S = 0.f, T = 0.f, dc[3];   // |d|^2 = S + T
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const float sh = a[c] - b[c];
-    const float se = two_sum_err(a[c], -b[c], sh) + (la[c] - lb[c]);   // d_c = sh + se
-    const float p = sh * sh;
-    const float t = S + p;
-    T += two_sum_err(S, p, t) + __builtin_fmaf(sh, sh, -p) + __builtin_fmaf(2.f * sh, se, se * se);
-    S = t;
-    dc[c] = sh + se;
-  }
-  d = {dc[0], dc[1], dc[2]};
-  const float Dh = ri + rj, Dl = two_sum_err(ri, rj, Dh);
-  const float D2 = Dh * Dh;
-  const float D2e = __builtin_fmaf(Dh, Dh, -D2) + 2.f * Dh * Dl;
-  return ((S - D2) + (T - D2e)) / (sqrtf(S) + Dh);
+  const double dx = ((double)xi.x - (double)xj.x) + ((double)li.x - (double)lj.x);
+  const double dy = ((double)xi.y - (double)xj.y) + ((double)li.y - (double)lj.y);
+  const double dz = ((double)xi.z - (double)xj.z) + ((double)li.z - (double)lj.z);
+  d = {(float)dx, (float)dy, (float)dz};
+  const double S = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+  const double D = (double)ri + (double)rj;
+  return (float)__builtin_fma(-D, D, S) / (sqrtf((float)S) + (float)D);
 }
 
 template <int W, int E, bool CT>

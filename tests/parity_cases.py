@@ -81,7 +81,7 @@ def bound_pair(one_way):
 
 def crossing(oracle, mu):
     """Two crossing 128-element rods: a stiff bar and a soft rod falling across its middle."""
-    return GroupCase(_dt_shared(oracle, W.config6().rods), 1500, 10, "c6", contact=([[0, 1]], mu))
+    return GroupCase(_dt_shared(oracle, W.config6().rods), 2000, 10, None, contact=([[0, 1]], mu))
 
 
 def coiled(oracle, n=48, turns=2, L=1.0, r=0.01, rise=0.5):
@@ -99,7 +99,7 @@ def coiled(oracle, n=48, turns=2, L=1.0, r=0.01, rise=0.5):
     spec = spec.replace(u_hat=u_hat, seg_len=lens, clamp_x0=tuple(x[0]), clamp_q0=tuple(q[0]))
     st = st.copy()
     st.x, st.q = x, q
-    return GroupCase(_dt_shared(oracle, [(spec, st)]), 200, 10, "coiled", contact=([[0, -1]], 0.2))
+    return GroupCase(_dt_shared(oracle, [(spec, st)]), 200, 10, None, contact=([[0, -1]], 0.2))
 
 
 def side_by_side(oracle, n=64, r=0.01):
@@ -114,7 +114,7 @@ def side_by_side(oracle, n=64, r=0.01):
     sb = sb.copy()
     sb.x = sb.x + off
     b = b.replace(clamp_x0=tuple(np.asarray(b.clamp_x0) + off))
-    return GroupCase(_dt_shared(oracle, [(a, sa), (b, sb)]), 400, 10, "side",
+    return GroupCase(_dt_shared(oracle, [(a, sa), (b, sb)]), 400, 10, None,
                      contact=([[0, 1]], 0.2))
 
 
@@ -137,7 +137,7 @@ def unequal(oracle, gap=1e-3):
                          seg_len=np.full(n, l), radius=np.full(n, r), young=np.full(n, young),
                          clamp_x0=tuple(base), clamp_q0=tuple(q0))
         out.append((spec, W.RodState(x=x, v=np.zeros_like(x), q=q, w=np.zeros((n, 3)))))
-    return GroupCase(_dt_shared(oracle, out), 1500, 10, "unequal", contact=([[0, 1]], 0.2))
+    return GroupCase(_dt_shared(oracle, out), 1500, 10, None, contact=([[0, 1]], 0.2))
 
 
 def group_cases(oracle):
@@ -248,29 +248,36 @@ def _round(st, mask):
 
 def env_restarts(oracle, case, states, stops, k=10):
     """From each state states[i] (taken at step stops[i] of a run), k steps of the oracle: the
-    plain run, and two runs that show how far FP32-sized differences carry over the window
-    (its floor): v, q and w rounded to FP32 after every step, and a start whose v, q and w are
-    moved by 2^-22 relative, signs seeded by the step.  Contact decisions (touching or not,
-    sticking or slipping) make some windows far more sensitive than others; the moved start
-    shows that where the rounding alone does not.  Returns [(start, plain, rounded, moved)]."""
+    plain run, and runs that show how far FP32-sized differences of the state carry over the
+    window (its floor): v, q and w rounded to FP32 after every step; a start whose v, q and w
+    are moved by 2^-22 relative; a start whose positions are moved by 2^-24 relative (half an
+    FP32 ulp).  Signs are seeded by the step.  Contacts (touching or not, sticking or slipping)
+    make some windows far more sensitive than others, and stiff rods answer a position change
+    far more than a velocity change; the moved starts show that where the rounding alone does
+    not.  Returns [(start, plain, [perturbed runs])]."""
     spec = case.rods[0][0]
     out = []
     for st, s in zip(states, stops):
         st = _round(st, 15)
         b, _ = env_run(oracle, case, k, state=st, t0=s * spec.dt)
-        r, _ = env_run(oracle, case, k, state=st, t0=s * spec.dt, round_mask=14)
-        m, _ = env_run(oracle, case, k, state=_moved(st, s), t0=s * spec.dt)
-        out.append((st, b, r, m))
+        pert = [env_run(oracle, case, k, state=st, t0=s * spec.dt, round_mask=14)[0]]
+        for m in _moved_starts(st, s):
+            pert.append(env_run(oracle, case, k, state=m, t0=s * spec.dt)[0])
+        out.append((st, b, pert))
     return out
 
 
-def _moved(st, seed):
+def _moved(st, seed, fields=("v", "q", "w"), scale=2.0 ** -22):
     rng = np.random.default_rng(seed)
     out = st.copy()
-    for f in ("v", "q", "w"):
+    for f in fields:
         a = np.asarray(getattr(st, f), dtype=np.float64)
-        setattr(out, f, a * (1.0 + rng.choice([-1.0, 1.0], a.shape) * 2.0 ** -22))
+        setattr(out, f, a * (1.0 + rng.choice([-1.0, 1.0], a.shape) * scale))
     return out
+
+
+def _moved_starts(st, seed):
+    return [_moved(st, seed), _moved(st, seed + 1, ("x",), 2.0 ** -24)]
 
 
 def rod_restarts(oracle, spec, states, stops, k=10):
@@ -280,19 +287,18 @@ def rod_restarts(oracle, spec, states, stops, k=10):
     for st, s in zip(states, stops):
         st = _round(st, 15)
         b = r.rollout(st, k, t0=s * spec.dt)[0]
-        rr = r.rollout_rounded(st, k, 14, t0=s * spec.dt)
-        m = r.rollout(_moved(st, s), k, t0=s * spec.dt)[0]
-        out.append((st, b, rr, m))
+        pert = [r.rollout_rounded(st, k, 14, t0=s * spec.dt)]
+        pert += [r.rollout(m, k, t0=s * spec.dt)[0] for m in _moved_starts(st, s)]
+        out.append((st, b, pert))
     return out
 
 
-def window_floor(spec, x0, start, plain, rounded, moved, k, errors):
-    """Floor of one restart window: per quantity the larger of the rounded and the moved
-    run's difference from the plain run (errors: parity_metrics.errors)."""
+def window_floor(spec, x0, start, plain, perturbed, k, errors):
+    """Floor of one restart window: per quantity the largest difference of a perturbed run
+    from the plain run (errors: parity_metrics.errors)."""
     t = lambda u: (u.x, u.v, u.q, u.w)
-    fr = errors(spec, x0, t(start), t(rounded), t(start), t(plain), k)
-    fm = errors(spec, x0, t(start), t(moved), t(start), t(plain), k)
-    out = {m: max(fr[m], fm[m]) for m in fr}
+    fl = [errors(spec, x0, t(start), t(p), t(start), t(plain), k) for p in perturbed]
+    out = {m: max(f[m] for f in fl) for m in fl[0]}
     out.pop("unit")
     return out
 
@@ -349,3 +355,33 @@ def c3_pick(rods):
     ns = np.array([s.n for s, _ in rods])
     cost = ns * np.array([4 + s.n_iter for s, _ in rods])
     return sorted(set(range(0, len(rods), 256)) | {int(np.argmax(cost)), int(np.argmin(ns))})
+
+
+def group_restarts(oracle, case, states, stops, k=10):
+    """As env_restarts, for rods stepped together: states[i] holds the rods' states (handle
+    order) at step stops[i]; returns [(starts, plain, rounded, moved)], each a list over the
+    rods."""
+    dt = case.rods[0][0].dt
+    out = []
+    for sts, s in zip(states, stops):
+        sts = [_round(st, 15) for st in sts]
+        b, _ = group_run(oracle, case, k, states=sts, t0=s * dt)
+        pert = [group_run(oracle, case, k, states=sts, t0=s * dt, round_mask=14)[0]]
+        moved = [_moved_starts(st, 97 * s + 2 * i) for i, st in enumerate(sts)]
+        for j in range(len(moved[0])):
+            pert.append(group_run(oracle, case, k, states=[m[j] for m in moved], t0=s * dt)[0])
+        out.append((sts, b, pert))
+    return out
+
+
+def group_floor(case, x0s, start, plain, perturbed, k, errors):
+    """Floor of one restart window of a group: per quantity the largest over the rods of
+    window_floor (perturbed: the perturbed runs, each a list over the rods)."""
+    fl = [window_floor(spec, x0, a, b, [p[r] for p in perturbed], k, errors)
+          for r, ((spec, _), x0, a, b) in enumerate(zip(case.rods, x0s, start, plain))]
+    return {m: max(f[m] for f in fl) for m in fl[0]}
+
+
+# restart steps of the touching configurations (their runs' lengths: the stops' last + 10)
+TOUCHING_STOPS = {"c6-mu0": (500, 1000, 1500, 1990), "c6-mu0.3": (500, 1000, 1500, 1990),
+                  "coiled": (100, 190), "side": (200, 390), "unequal": (500, 1000, 1490)}

