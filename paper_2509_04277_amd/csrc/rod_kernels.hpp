@@ -1206,6 +1206,10 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
   // quad-major so that a wavefront reads consecutive quads
   __shared__ uint2 cand[2][kContactCand / 4][CC];
   __shared__ uint2 lst[2][kMaxContacts / 4][CC];
+  // the gap |d| - D of each listed contact, stored once per step where LDS has room (a group
+  // of one or two wavefronts per rod); the larger shape recomputes it in every iteration
+  constexpr bool GC = CT && W <= 2;
+  __shared__ float gapc[2][GC ? kMaxContacts : 1][GC ? CC : 1];
   __shared__ float4 xbl[2][CC];      // each point's position when its candidates were listed
   __shared__ int moved[2][2 * W];                         // per wavefront and step parity
   __shared__ int touching[2][2 * W];                      // ditto: some point has a contact
@@ -1406,6 +1410,7 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
             if (!(gap < 0.f) || !(dot(d, d) > 0.f)) continue;
             if (cnt[e] < kMaxContacts) {
               quad_put(lst[sub][cnt[e] >> 2][i], cnt[e] & 3, (uint32_t)g[k]);
+              if constexpr (GC) gapc[sub][cnt[e]][i] = gap;
               ++cnt[e];
             } else {
               overflow = true;
@@ -1469,12 +1474,21 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
           const float4* vwp = &vw[bpar][0][0];
           // the impulse on this point from partner (ox + its low parts oxl, ov); false if that
           // contact is inactive
-          auto impulse = [&](float4 ox, float4 oxl, float4 ov, V3& imp) {
+          auto impulse = [&](float4 ox, float4 oxl, float4 ov, int c, V3& imp) {
             const V3 xj = {ox.x, ox.y, ox.z}, vj = {ov.x, ov.y, ov.z};
             const float wsum = wi + ov.w;
             if (!(wsum > 0.f)) return false;
-            V3 d0;
-            const float gap = sphere_gap(xi, li, xj, V3{oxl.x, oxl.y, oxl.z}, rho[e], ox.w, d0);
+            const V3 lj = {oxl.x, oxl.y, oxl.z};
+            // the listing's gap (stored, or formed again alike); the normal from the centre
+            // difference in FP32, the same in every shape and exactly opposite for the partner
+            float gap;
+            if constexpr (GC) {
+              gap = gapc[sub][c][i];
+            } else {
+              V3 dd;
+              gap = sphere_gap(xi, li, xj, lj, rho[e], ox.w, dd);
+            }
+            const V3 d0 = (xi - xj) + (li - lj);
             const V3 nrm = rsqrtf(dot(d0, d0)) * d0;        // step-start normal, towards i
             const V3 vr = vi - vj;
             // predicted separation along the normal: |d0| - D + dt (vi - vj).n
@@ -1499,11 +1513,11 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
             const float4 oxa = xsp[ga], ova = vwp[ga], oxb = xsp[gb], ovb = vwp[gb];
             const float4 la = xlp[ga], lb = xlp[gb];
             V3 imp;
-            if (impulse(oxa, la, ova, imp)) {
+            if (impulse(oxa, la, ova, c, imp)) {
               acc = acc + imp;
               ++act;
             }
-            if (c + 1 < cnt[e] && impulse(oxb, lb, ovb, imp)) {
+            if (c + 1 < cnt[e] && impulse(oxb, lb, ovb, c + 1, imp)) {
               acc = acc + imp;
               ++act;
             }
