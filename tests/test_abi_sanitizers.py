@@ -3,7 +3,6 @@ pass only; the device code is built as usual) and driven through the C ABI's arg
 and refusal paths by tests/abi_sanitize_driver.c: the documented status for every refusal,
 no sanitizer finding.  Runs without a GPU."""
 import os
-import shutil
 import subprocess
 
 import pytest

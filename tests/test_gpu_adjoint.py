@@ -2,7 +2,6 @@
 (through the C ABI) against FP64 central finite differences of the oracle rollout on the same
 inputs and targets.  Loss: L = mean over (rods, steps, xyz) of (tip - target)^2, targets from
 the oracle with perturbed stiffness and initial velocity."""
-import sys
 
 import numpy as np
 import pytest

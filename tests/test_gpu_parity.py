@@ -6,7 +6,6 @@ quaternions unit to FP32 precision.  A CPU test (test_parity_bars) shows that a 
 each coefficient of the method breaks these bars on the configurations run here.
 """
 import json
-import math
 import os
 import sys
 
