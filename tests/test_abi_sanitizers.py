@@ -18,7 +18,10 @@ def test_abi_host_code_under_asan_and_ubsan(tmp_path):
     san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
     lib_o, drv_o, exe = (str(tmp_path / n) for n in ("rod_lib.o", "driver.o", "abi_sanitized"))
     steps = [
-        [HIPCC, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-Xclang", "-target-feature",
+        # (the device code, never run here, is built without optimisation or debug information:
+        # it is the slow part of the build)
+        [HIPCC, "--offload-arch=gfx950", "-parallel-jobs=2", "-O1", "-Xarch_device", "-O0",
+         "-Xarch_host", "-g", "-std=c++17", "-Xclang", "-target-feature",
          "-Xclang", "-packed-fp32-ops", *san, "-I", inc, "-c",
          os.path.join(REPO, "paper_2509_04277_amd", "csrc", "rod_lib.hip"), "-o", lib_o],
         [HIPCC, "-x", "c", "-I", inc, "-c", os.path.join(HERE, "abi_sanitize_driver.c"), "-o", drv_o],

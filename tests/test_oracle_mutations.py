@@ -100,7 +100,7 @@ def test_every_planted_mistake_fails_a_pin(tmp_path):
             paths[f].write_text(text)
         libs.append(O.build(force=True, src=str(paths[SRC]), grad_src=str(paths[GRAD_SRC]),
                             lib=str(tmp_path / ("m%02d.so" % k))))
-    with ThreadPoolExecutor(max_workers=4) as ex:
+    with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1))) as ex:
         results = list(ex.map(lambda a: _run_pins(*a),
                               [(lib, str(tmp_path / ("m%02d.log" % k))) for k, lib in enumerate(libs)]))
     rc0, out0 = results[0]
