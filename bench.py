@@ -23,6 +23,33 @@ sys.path.insert(0, REPO)
 BYTES_PER_ELEMENT_STEP = 104          # 13 FP32 state values read + written per element
 HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E
 
+# Floating-point operations of the method per element (one segment, point, frame and joint)
+# and step, by part of the step (add, subtract, multiply: 1; a multiply-add: 2; division,
+# square root, reciprocal square root: 1), with shared subexpressions evaluated once and
+# per-element material coefficients computed once per rod (Sec. 2.1):
+#   segment   segment vector, tangent, directors d1..d3 of the frame, penalty force and torque
+#             (eqs. (7)-(8)); stretch: the extensible variant's stretch force (eq. (2));
+#   joint     relative rotation of neighbouring frames, moment K (u - u_hat) (eqs. (3), (5),
+#             (6)) and the torques on both frames;
+#   accumulate  the net force on a point and torque on a frame from their neighbours;
+#   point, frame  force and torque integration with damping and the gyroscopic term;
+#   impulse   one distance-constraint impulse per segment and constraint iteration;
+#   advance   the velocity integration of the point and of the frame's quaternion, renormalised.
+# The per-rod clamp pose is not counted.
+FLOPS_PER_ROW = {"segment": 70, "stretch": 9, "joint": 52, "accumulate": 8, "point": 18,
+                 "frame": 21, "advance": 46, "impulse": 32}
+# MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (multiply-add) x 2.4 GHz = 78.6
+# TFLOP/s, twice that with packed FP32 instructions (the published 157.3; the kernels here are
+# built without packed FP32).
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_UNPACKED_PEAK_TFLOPS = 78.6
+
+
+def flops_per_element_step(inextensible, n_iter):
+    r = FLOPS_PER_ROW
+    base = r["segment"] + r["joint"] + r["accumulate"] + r["point"] + r["frame"] + r["advance"]
+    return base + (r["impulse"] * n_iter if inextensible else r["stretch"])
+
 
 def kernel_source_hash():
     h = hashlib.sha256()
@@ -46,6 +73,27 @@ def _counters(kernel_name, elements, spl):
     return e
 
 
+def measured_batch_issue(wl, ms, buckets):
+    """VALU issue of the batched rollout: the wave-level VALU instructions that the committed
+    counter run of this workload counted (same kernel sources and buckets), each 4 cycles of a
+    16-lane SIMD, over the chip's 1024 SIMDs at 2.4 GHz, as a fraction of the rollout time;
+    with the executed FP32 operations (a multiply-add counted twice).  None without counters."""
+    path = os.path.join(REPO, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    e = json.load(open(path)).get("c3_batch")
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    if e.get("elements") != wl.n_elements or e.get("steps") != wl.n_steps:
+        return None
+    if [list(b) for b in e["buckets"]] != [[w, k, n] for w, k, n, _ in buckets]:
+        return None
+    issue_s = e["valu_insts_per_rollout"] * 4 / (256 * 4) / 2.4e9
+    return {"valu_issue_frac": issue_s / (ms / 1e3),
+            "valu_insts_per_rollout": e["valu_insts_per_rollout"],
+            "executed_fp32_tflops": e["fp32_flops_per_rollout"] / (ms / 1e3) / 1e12}
+
+
 def measured_traffic(kernel_name, elements, spl):
     """HBM bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE), or None."""
     e = _counters(kernel_name, elements, spl)
@@ -60,7 +108,8 @@ def measured_wave_shares(kernel_name, elements, spl):
     if e is None or "valu_active_share" not in e:
         return None
     return {"valu_issue_frac": e["valu_active_share"], "barrier_share": e["wait_any_share"],
-            "valu_insts_per_wave_step": e.get("valu_insts_per_wave_step")}
+            "valu_insts_per_wave_step": e.get("valu_insts_per_wave_step"),
+            "fp32_flops_per_element_step": e.get("fp32_flops_per_element_step")}
 
 
 def host_cpu():
@@ -199,12 +248,23 @@ def batch_extras(R, W):
     for h in handles:
         h.close()
     achieved = BYTES_PER_ELEMENT_STEP * elements * wl.n_steps / (ms / 1e3) / 1e9
+    tflops = (sum(s.n * flops_per_element_step(s.inextensible, s.n_iter) for s, _ in rods)
+              * wl.n_steps / (ms / 1e3) / 1e12)
+    issue = measured_batch_issue(wl, ms, buckets)
     return {
         "workload": "4096 rods, N log-uniform [32, 2048] (sum %d), half inextensible, per-rod dt, "
                     "%d steps" % (elements, wl.n_steps),
         "element_steps_per_s": value, "ms": ms, "runs_ms": runs_ms, "launches": launches,
         "buckets": [{"waves": w, "elems_per_lane": e, "rods": n} for w, e, n, _ in buckets],
         "hbm_roofline_frac": achieved / HBM_PEAK_GBS,
+        # many rods per compute unit: the launches are bound by VALU issue, so the method's
+        # floating-point rate against the FP32 vector peak (packed, and without packed FP32)
+        "alu_roofline": {"bound": "alu", "achieved": tflops, "unit": "TFLOP/s",
+                         "peak": FP32_VECTOR_PEAK_TFLOPS, "frac": tflops / FP32_VECTOR_PEAK_TFLOPS,
+                         "peak_unpacked": FP32_UNPACKED_PEAK_TFLOPS,
+                         "frac_unpacked": tflops / FP32_UNPACKED_PEAK_TFLOPS,
+                         "valu_issue_frac": issue and issue["valu_issue_frac"],
+                         "executed_fp32_tflops": issue and issue["executed_fp32_tflops"]},
         "one_rod_per_launch": {"element_steps_per_s": elements * wl.n_steps / (single_ms / 1e3),
                                "ms_extrapolated": single_ms, "sampled_rods": len(sample),
                                "hbm_roofline_frac": BYTES_PER_ELEMENT_STEP * elements * wl.n_steps
@@ -531,6 +591,8 @@ def main():
     achieved = bytes_per_launch / launch_s / 1e9
     traffic = measured_traffic(kernel, elements, spl)
     shares = measured_wave_shares(kernel, elements, spl)
+    flops = sum(s.n * flops_per_element_step(s.inextensible, s.n_iter) for s, _ in wl.rods)
+    tflops = flops * spl / launch_s / 1e12
     out = {
         "metric": "element-steps/s",
         "value": value,
@@ -563,7 +625,14 @@ def main():
                      # of wavefront time from SQ counters of the same kernel and workload
                      "valu_issue_frac": shares and shares["valu_issue_frac"],
                      "barrier_share": shares and shares["barrier_share"],
-                     "valu_insts_per_wave_step": shares and shares["valu_insts_per_wave_step"]},
+                     "valu_insts_per_wave_step": shares and shares["valu_insts_per_wave_step"],
+                     # the method's floating-point operations per element-step and the rate
+                     # of the same launches against the chip's FP32 vector peak
+                     "flops_per_element_step": flops / elements,
+                     "executed_fp32_flops_per_element_step":
+                         shares and shares["fp32_flops_per_element_step"],
+                     "alu": {"achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": tflops / FP32_VECTOR_PEAK_TFLOPS}},
     }
     if not args.no_extras:
         sizes = tuple(int(v) for v in args.long_sizes.split(",") if v)
