@@ -52,7 +52,8 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
     float* __restrict__ ax, float* __restrict__ av, float* __restrict__ aq, float* __restrict__ aw,
     double* __restrict__ gacc, const float* __restrict__ fext, const float* __restrict__ text,
     int* __restrict__ status) {
-  __shared__ Mailbox<W> mb;
+  __shared__ Mailbox<W, kMergedExchange<W, E>> mb;
+  mailbox_init(mb);
   const int rod = rod_ids[blockIdx.x];
   const RodDev rd = rods[rod];
   RodLane<W, E> L;
@@ -229,11 +230,12 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
             if (cross_lanes) {
               float mh[3] = {AVc[E - 1].x, AVc[E - 1].y, AVc[E - 1].z};
               float ml[3] = {AVc[0].x, AVc[0].y, AVc[0].z};
+              const float base[3] = {abvc.x, abvc.y, abvc.z};
               float lo[3], hi[3];
-              exchange<W, E, 3, 3>(mh, lo, ml, hi, mb, par);
+              exchange<W, E, 3, 3, true, kMergedExchange<W, E>>(mh, lo, ml, hi, base, mb, par);
               glo = {lo[0], lo[1], lo[2]};
               ghi = {hi[0], hi[1], hi[2]};
-              if (g == 0) glo = abvc;
+              if (!kMergedExchange<W, E> && g == 0) glo = abvc;
             }
             V3 nv[E];
             V3 dbase = {0.f, 0.f, 0.f};
@@ -325,11 +327,12 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
       {
         float mh[3] = {FB[E - 1].x, FB[E - 1].y, FB[E - 1].z};
         float ml[3] = {TB[0].x, TB[0].y, TB[0].z};
+        const float base[3] = {fb0.x, fb0.y, fb0.z};
         float lo[3], hi[3];
-        exchange<W, E, 3, 3>(mh, lo, ml, hi, mb, par);
+        exchange<W, E, 3, 3, true, kMergedExchange<W, E>>(mh, lo, ml, hi, base, mb, par);
         fb_lo = {lo[0], lo[1], lo[2]};
         tb_hi = {hi[0], hi[1], hi[2]};
-        if (g == 0) fb_lo = fb0;
+        if (!kMergedExchange<W, E> && g == 0) fb_lo = fb0;
       }
       V3 dneg_first = {0.f, 0.f, 0.f};
       Q4 qb_last = {0.f, 0.f, 0.f, 0.f};
@@ -414,8 +417,9 @@ __global__ __launch_bounds__(64 * W) void rod_adjoint_kernel(
       {
         float mh[4] = {qb_last.w, qb_last.x, qb_last.y, qb_last.z};
         float ml[3] = {dneg_first.x, dneg_first.y, dneg_first.z};
+        const float base[4] = {0.f, 0.f, 0.f, 0.f};   // frame 0 has no joint below
         float lo[4], hi[3];
-        exchange<W, E, 4, 3>(mh, lo, ml, hi, mb, par);
+        exchange<W, E, 4, 3, false, kMergedExchange<W, E>>(mh, lo, ml, hi, base, mb, par);
         // joint j-1's adjoint for frame j (from below); segment j+1's -d for point j+1 (above)
         const Q4 qfrom = {lo[0], lo[1], lo[2], lo[3]};
         const V3 dfrom = {hi[0], hi[1], hi[2]};

@@ -153,36 +153,108 @@ __device__ __forceinline__ Q4 sel4(bool c, Q4 a, Q4 b) {
   return {c ? a.w : b.w, c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
 }
 
-// DPP whole-wavefront shifts; the lane without a source receives 0 (bound_ctrl).
+// DPP whole-wavefront shifts.  from_lower_lane / from_upper_lane: the lane without a source
+// (lane 0 / lane 63) receives 0 (bound_ctrl).  The `_or` forms leave that lane's destination
+// unwritten, so it keeps `edge`: one instruction moves the neighbour's value and merges what the
+// wavefront's edge lane takes from elsewhere.
 __device__ __forceinline__ float from_lower_lane(float v) {  // lane i <- lane i-1
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float from_upper_lane(float v) {  // lane i <- lane i+1
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
+__device__ __forceinline__ float from_lower_lane_or(float edge, float v) {  // lane i <- lane i-1
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_upper_lane_or(float edge, float v) {  // lane i <- lane i+1
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
 
 // Neighbour exchange across the rod's lanes.  `lo` receives the KL values `mine_hi` of the
 // lane below (its last slot), `hi` receives the KH values `mine_lo` of the lane above (its
-// first slot).  Global lane 0 and the last lane receive 0 (the caller substitutes).  E (the
-// elements per lane) only sets how much register room the reads may use.
+// first slot).  The rod's last lane receives 0.  Its first lane (g = 0) receives `base` (B:
+// values that stand for what lies below the rod, such as its base point) in the merged form;
+// otherwise 0, and the caller substitutes (the substitution inside the plain form kept a lane
+// mask live across the step loop, which spilled scalar registers).  E (the elements per lane)
+// only sets how much register room the reads may use.
 constexpr int kMailboxWords = 11;  // the widest exchange: quaternion (two parts), angular velocity
-template <int W>
+// buf: what each wavefront's edge lanes publish ([0]: lane 0's, [1]: lane 63's), per parity.
+// edge (merged form, M): [1] is what lane 0 of wavefront 0 reads from below (written by that
+// lane at every exchange: the base values, or zeros), [0] what the last wavefront's lane 63
+// reads from above (zero, set once by mailbox_init and never written).
+template <int W, bool M = false>
 struct Mailbox {
   float buf[2][W][2][kMailboxWords];
+  float edge[2][2][kMailboxWords];
 };
 
-template <int W, int E, int KL, int KH>
+// Two forms of the exchange move the same values (the states are bitwise the same).  The
+// merged form (M) reads the mailbox words into the DPP moves' kept operand (one instruction per
+// word, the base values travelling through the mailbox); the plain form moves before the
+// barrier and selects the mailbox words into the edge lanes afterwards.  Measured (device time
+// per step, 2 rods and 2048 rods per launch, every shape): the merged form is faster for four
+// wavefronts of 2 or 4 elements per lane, one per SIMD, and slower for every other shape, for
+// two rods of four wavefronts in one workgroup (two wavefronts per SIMD), and in the chunked
+// long-rod kernel's extensible steps (two exchanges per step); those use the plain form.
+template <int W, int E>
+constexpr bool kMergedExchange = (W == 4) && (E == 2 || E == 4);
+
+// Zeroes the words above the last wavefront (merged form only); must run before the kernel's
+// first exchange (whose barrier orders it before the reads).  It touches no word that an
+// exchange writes.
+template <int W, bool M>
+__device__ __forceinline__ void mailbox_init(Mailbox<W, M>& mb) {
+  if constexpr (M) {
+    if (threadIdx.x < kMailboxWords) {
+      mb.edge[0][0][threadIdx.x] = 0.f;
+      mb.edge[1][0][threadIdx.x] = 0.f;
+    }
+  }
+}
+
+template <int W, int E, int KL, int KH, bool B, bool M>
 __device__ __forceinline__ void exchange(const float (&mine_hi)[KL], float (&lo)[KL],
                                          const float (&mine_lo)[KH], float (&hi)[KH],
-                                         Mailbox<W>& mb, int& parity) {
+                                         const float (&base)[KL], Mailbox<W, M>& mb, int& parity) {
   static_assert(KL <= kMailboxWords && KH <= kMailboxWords, "exchange wider than the mailbox");
   const int lane = threadIdx.x & 63;
+  if constexpr (W == 1) {
 #pragma unroll
-  for (int k = 0; k < KL; ++k) lo[k] = from_lower_lane(mine_hi[k]);
+    for (int k = 0; k < KL; ++k) lo[k] = from_lower_lane(mine_hi[k]);
 #pragma unroll
-  for (int k = 0; k < KH; ++k) hi[k] = from_upper_lane(mine_lo[k]);
-  if constexpr (W > 1) {
+    for (int k = 0; k < KH; ++k) hi[k] = from_upper_lane(mine_lo[k]);
+  } else if constexpr (M) {
+    const int wave = (threadIdx.x >> 6) & (W - 1);   // wavefront within the rod's W
+    if (lane == 63) {
+#pragma unroll
+      for (int k = 0; k < KL; ++k) mb.buf[parity][wave][1][k] = mine_hi[k];
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < KH; ++k) mb.buf[parity][wave][0][k] = mine_lo[k];
+      if (wave == 0) {   // (zeros without B: faster on c1 than reading the zero words)
+#pragma unroll
+        for (int k = 0; k < KL; ++k) mb.edge[parity][1][k] = B ? base[k] : 0.f;
+      }
+    }
+    __syncthreads();
+    // every lane reads the same (broadcast) words; the DPP move keeps them only in the
+    // wavefront's edge lane, which has no source inside the wavefront
+    const float* from_lo = wave > 0 ? mb.buf[parity][wave - 1][1] : mb.edge[parity][1];
+    const float* from_hi = wave < W - 1 ? mb.buf[parity][wave + 1][0] : mb.edge[parity][0];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) lo[k] = from_lower_lane_or(from_lo[k], mine_hi[k]);
+#pragma unroll
+    for (int k = 0; k < KH; ++k) hi[k] = from_upper_lane_or(from_hi[k], mine_lo[k]);
+    parity ^= 1;
+  } else {
     static_assert((W & (W - 1)) == 0, "W must be a power of two");
+#pragma unroll
+    for (int k = 0; k < KL; ++k) lo[k] = from_lower_lane(mine_hi[k]);
+#pragma unroll
+    for (int k = 0; k < KH; ++k) hi[k] = from_upper_lane(mine_lo[k]);
     const int wave = (threadIdx.x >> 6) & (W - 1);   // wavefront within the rod's W
     if (lane == 63) {
 #pragma unroll
@@ -593,8 +665,8 @@ struct RodLane {
   // Exchange A: the left neighbour point's position (both parts: xl, xll; the base point for
   // lane 0) and the next frame's quaternion (both parts: qn, qnl; from the lane above); with
   // internal friction (D) also that point's velocity vl and that frame's angular velocity wn.
-  template <bool D>
-  __device__ __forceinline__ void exchange_a(Mailbox<W>& mb, int& par, V3& xl, V3& xll, Q4& qn,
+  template <bool D, bool M>
+  __device__ __forceinline__ void exchange_a(Mailbox<W, M>& mb, int& par, V3& xl, V3& xll, Q4& qn,
                                              Q4& qnl, V3& vl, V3& wn) const {
     const V3 a = X[E - 1], al = XL[E - 1];
     const Q4 b = Qf[0], bl = QL[0];
@@ -602,12 +674,13 @@ struct RodLane {
       const V3 c = Vv[E - 1], o = Om[0];
       float mh[9] = {a.x, a.y, a.z, al.x, al.y, al.z, c.x, c.y, c.z};
       float ml[11] = {b.w, b.x, b.y, b.z, bl.w, bl.x, bl.y, bl.z, o.x, o.y, o.z};
+      const float base[9] = {bx.x, bx.y, bx.z, bxl.x, bxl.y, bxl.z, bv.x, bv.y, bv.z};
       float lo[9], hi[11];
-      exchange<W, E, 9, 11>(mh, lo, ml, hi, mb, par);
+      exchange<W, E, 9, 11, true, M>(mh, lo, ml, hi, base, mb, par);
       xl = {lo[0], lo[1], lo[2]};
       xll = {lo[3], lo[4], lo[5]};
       vl = {lo[6], lo[7], lo[8]};
-      if (g == 0) {
+      if (!M && g == 0) {
         xl = bx;
         xll = bxl;
         vl = bv;
@@ -618,11 +691,12 @@ struct RodLane {
     } else {
       float mh[6] = {a.x, a.y, a.z, al.x, al.y, al.z};
       float ml[8] = {b.w, b.x, b.y, b.z, bl.w, bl.x, bl.y, bl.z};
+      const float base[6] = {bx.x, bx.y, bx.z, bxl.x, bxl.y, bxl.z};
       float lo[6], hi[8];
-      exchange<W, E, 6, 8>(mh, lo, ml, hi, mb, par);
+      exchange<W, E, 6, 8, true, M>(mh, lo, ml, hi, base, mb, par);
       xl = {lo[0], lo[1], lo[2]};
       xll = {lo[3], lo[4], lo[5]};
-      if (g == 0) {
+      if (!M && g == 0) {
         xl = bx;
         xll = bxl;
       }
@@ -632,7 +706,8 @@ struct RodLane {
       wn = {0.f, 0.f, 0.f};
     }
   }
-  __device__ __forceinline__ void exchange_a(Mailbox<W>& mb, int& par, V3& xl, V3& xll, Q4& qn,
+  template <bool M>
+  __device__ __forceinline__ void exchange_a(Mailbox<W, M>& mb, int& par, V3& xl, V3& xll, Q4& qn,
                                              Q4& qnl) const {
     V3 vl, wn;
     exchange_a<false>(mb, par, xl, xll, qn, qnl, vl, wn);
@@ -646,8 +721,8 @@ struct RodLane {
   // (len - l) + td d(len)/dt and a joint's moment K (u - uhat + td du/dt), where
   // du/dt = (rw (w_{j+1} - w_j) + rv x (w_{j+1} + w_j)) / lbar for the relative rotation
   // r = conj(q_j) q_{j+1}; vl and wn are the exchanged neighbour velocities.
-  template <bool D = false>
-  __device__ __forceinline__ void forces(Mailbox<W>& mb, int& par, V3 xl, V3 xll, Q4 qn, Q4 qnl,
+  template <bool D = false, bool M = false>
+  __device__ __forceinline__ void forces(Mailbox<W, M>& mb, int& par, V3 xl, V3 xll, Q4 qn, Q4 qnl,
                                          V3 (&F)[E],
                                          V3 (&T)[E], V3 (&Ev)[E], V3& fs0, V3& enext,
                                          float td = 0.f, V3 vl = {0.f, 0.f, 0.f},
@@ -713,8 +788,9 @@ struct RodLane {
     }
     float mh[3] = {tn_prev.x, tn_prev.y, tn_prev.z};
     float ml[6] = {fs0.x, fs0.y, fs0.z, Ev[0].x, Ev[0].y, Ev[0].z};
+    const float base[3] = {0.f, 0.f, 0.f};   // no joint below frame 0
     float lo[3], hi[6];
-    exchange<W, E, 3, 6>(mh, lo, ml, hi, mb, par);
+    exchange<W, E, 3, 6, false, M>(mh, lo, ml, hi, base, mb, par);
     T[0] = T[0] + V3{lo[0], lo[1], lo[2]};
     F[E - 1] = F[E - 1] - V3{hi[0], hi[1], hi[2]};
     enext = {hi[3], hi[4], hi[5]};
@@ -764,18 +840,20 @@ struct RodLane {
 
   // One red-black half-sweep h of the distance impulses.  If dsnap is given, the segment
   // vector d of the slot's segment in this half-sweep is saved (for the adjoint).
-  __device__ __forceinline__ void half_sweep(const RodDev& rd, Mailbox<W>& mb, int& par, int h,
+  template <bool M>
+  __device__ __forceinline__ void half_sweep(const RodDev& rd, Mailbox<W, M>& mb, int& par, int h,
                                              const V3 (&Ev)[E], V3 enext, V3* dsnap) {
     const bool cross_lanes = (E % 2 == 1) || (h == 0);
     V3 vlo = {0.f, 0.f, 0.f}, vhi = {0.f, 0.f, 0.f};
     if (cross_lanes) {
       float mh[3] = {Vv[E - 1].x, Vv[E - 1].y, Vv[E - 1].z};
       float ml[3] = {Vv[0].x, Vv[0].y, Vv[0].z};
+      const float base[3] = {bv.x, bv.y, bv.z};
       float lo[3], hi[3];
-      exchange<W, E, 3, 3>(mh, lo, ml, hi, mb, par);
+      exchange<W, E, 3, 3, true, M>(mh, lo, ml, hi, base, mb, par);
       vlo = {lo[0], lo[1], lo[2]};
       vhi = {hi[0], hi[1], hi[2]};
-      if (g == 0) vlo = bv;
+      if (!M && g == 0) vlo = bv;
     }
     V3 dvb = {0.f, 0.f, 0.f};
     V3 nv[E];
@@ -1013,7 +1091,8 @@ __global__ __launch_bounds__(64 * W) void rod_resident_kernel(
     float* __restrict__ traj,
     long long traj_stride, int n_pts, int n_frames, float* __restrict__ tips, int tip_steps,
     long long tip_base, int traj_steps, int store_final) {
-  __shared__ Mailbox<W> mb;
+  __shared__ Mailbox<W, kMergedExchange<W, E>> mb;
+  mailbox_init(mb);
   __shared__ float cbuf[kClampChunk][10];
   const int rod = rod_ids[blockIdx.x];
   const RodDev rd = rods[rod];
@@ -1190,7 +1269,7 @@ __global__ __launch_bounds__(128 * W) void rod_group_kernel(
   constexpr int CC = CT ? CAP : 1;                                  // contact-list slots
   constexpr int SMAX = CT ? 2 * ((CAP + kSphereSize - 1) / kSphereSize) : 1;  // spheres
   constexpr int SW = (SMAX + 31) / 32;
-  __shared__ Mailbox<W> mb[2];
+  __shared__ Mailbox<W, false> mb[2];   // two rods per workgroup: the plain exchange
   __shared__ float cbuf[2][kClampChunk][10];
   // step-start position and sphere radius, and the low parts of the position (the positions
   // are pairs of floats; separations between points take both); rewritten at every step start
@@ -1588,7 +1667,7 @@ __global__ __launch_bounds__(64 * W) void rod_grid_kernel(
     StateArrays st, const float* __restrict__ fext, const float* __restrict__ text, int n_steps,
     long long steps_done, int* __restrict__ status, float* pub, int pub_slots, int n_chunks,
     int* flags, int spin_limit) {
-  __shared__ Mailbox<W> mb;
+  __shared__ Mailbox<W, false> mb;   // the plain exchange (see kMergedExchange)
   __shared__ float cbuf[kClampChunk][10];
   __shared__ int abort_flag;
   const int ci = block_chunk[blockIdx.x];
