@@ -296,8 +296,9 @@ rod_status rod_haptic_get_force(rod_ctx* ctx, int32_t rod, rod_haptic_force* out
 /* The autotuner of the batched form (kernel shape per bucket and steps per launch picked by
  * measuring; the paper fixes them by hand, Sec. 3.1).
  * Per bucket, time every built shape that holds its longest rod on probe_steps steps (the
- * state is saved and restored, the step counter unchanged) and keep the fastest; sets the
- * handle's steps_per_launch.  steps_per_launch = 0: first, while the long-rod split is the
+ * state is saved and restored, the step counter unchanged) and keep the fastest, or a shape
+ * that another bucket keeps if it is within 2 % of the fastest (the buckets then share one
+ * launch); sets the handle's steps_per_launch.  steps_per_launch = 0: first, while the long-rod split is the
  * default one, the whole handle is timed with its rods of more than 512 elements in one
  * workgroup each and chunked as by rod_set_chunking(ctx, 512, 0), and the faster split is kept
  * (a chunked rod is not differentiated by the adjoint); then the shapes are timed at 10 steps

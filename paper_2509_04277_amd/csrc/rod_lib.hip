@@ -1823,6 +1823,7 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
   }
   // per bucket: time every built shape that holds its longest rod without idling most lanes
   std::vector<rod_ctx::Bucket> chosen = c->buckets;
+  std::vector<std::vector<std::pair<int, float>>> tried(chosen.size());   // (shape, us) per bucket
   for (size_t bi = 0; bi < chosen.size() && st == ROD_OK; ++bi) {
     rod_ctx::Bucket& best = chosen[bi];
     best.us_per_step = INFINITY;
@@ -1842,6 +1843,7 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
       }
       if (st != ROD_OK) break;
       const float us = 1000.f * ms_best / probe_steps;
+      tried[bi].push_back({k.waves * 16 + k.elems, us});
       if (us < best.us_per_step) {
         best.us_per_step = us;
         best.waves = k.waves;
@@ -1850,6 +1852,29 @@ rod_status rod_autotune(rod_ctx* c, int32_t probe_steps, int32_t steps_per_launc
     }
   }
   if (st == ROD_OK) {
+    // Near ties go to a shape that another bucket (same kernel features) already uses: the
+    // buckets step side by side, one launch each, and the shared shape saves a launch.  (The
+    // shortest rods' bucket timed 1 x 1 and 1 x 2 within noise; split, the 4096-rod batch took
+    // 38.6 ms against 37.4 merged.)
+    auto key_of = [](const rod_ctx::Bucket& b) { return b.waves * 16 + b.elems; };
+    auto used_elsewhere = [&](size_t bi, int key) {
+      for (size_t o = 0; o < chosen.size(); ++o)
+        if (o != bi && chosen[o].feat == chosen[bi].feat && key_of(chosen[o]) == key) return true;
+      return false;
+    };
+    for (size_t bi = 0; bi < chosen.size(); ++bi) {
+      rod_ctx::Bucket& b = chosen[bi];
+      if (used_elsewhere(bi, key_of(b))) continue;
+      for (const auto& t : tried[bi]) {
+        if (t.first == key_of(b) || !(t.second <= 1.02f * b.us_per_step)) continue;
+        if (used_elsewhere(bi, t.first)) {
+          b.waves = t.first / 16;
+          b.elems = t.first % 16;
+          b.us_per_step = t.second;
+          break;
+        }
+      }
+    }
     // re-bucket: rods keep their bucket's chosen shape (equal shapes merge)
     std::vector<int> shape_of(c->n_rods);
     for (size_t bi = 0; bi < chosen.size(); ++bi)
