@@ -390,3 +390,34 @@ def test_stale_rollout_is_refused():
     t2.sum().backward()
     assert bend2.grad is not None and torch.isfinite(bend2.grad).all()
     b.close()
+
+
+def test_adjoint_in_two_exchange_forms():
+    """Rods of 300 elements: the adjoint in four wavefronts of two elements per lane (whose
+    exchanges merge the mailbox word into the lane move) and in eight wavefronts of one (plain
+    exchanges) sees the same forward tips, bitwise, and returns the same gradients up to the
+    rounding of the reverse pass's shape (two elements per lane share one impulse adjoint per
+    in-lane segment): measured at most 2e-5 of the largest entry of a block (the same before
+    the exchange had two forms), asserted at the adjoint's 1e-4 target; a lost base-point value
+    or neighbour word moves a block by far more."""
+    rods = [(s.replace(dt=R.stable_dt(s)), st) for s, st in W.config4(n_rods=2, n=300).rods]
+    n_steps = 40
+    rng = np.random.default_rng(71)
+    targets = np.stack([st.x[-1] + rng.normal(0, 1e-3, (n_steps, 3)) for _, st in rods])
+    res = []
+    for shape in ((4, 2), (8, 1)):
+        b = R.RodBatch([s for s, _ in rods])
+        b.set_tuning(shape[0], shape[1], 10)
+        b.set_state_rods([st for _, st in rods])
+        tips = b.adjoint_forward(n_steps, 20)
+        M = len(rods) * n_steps * 3
+        dtips = np.ascontiguousarray((2.0 / M) * (tips.astype(np.float64) - targets), dtype=np.float32)
+        g = b.adjoint_backward(dtips)
+        b.close()
+        res.append((tips, g))
+    assert np.array_equal(res[0][0], res[1][0])
+    for k in ("x", "v", "q", "w", "bend", "twist"):
+        a, c = (np.asarray(r[1][k], dtype=np.float64) for r in res)
+        rel = float(np.abs(a - c).max() / max(np.abs(a).max(), 1e-30))
+        _say("(4, 2) against (8, 1), %s: largest difference %.2e of the largest entry" % (k, rel))
+        assert rel <= 1e-4, k
